@@ -1,0 +1,101 @@
+"""Six-ray diffuse-UV transfer, shielding, effective column and CR attenuation (Secs. 5.1-5.3), FP64.
+
+For a uniform cubic grid of cell size dx, rays enter from the six domain
+faces along +-x, +-y, +-z with luminosity c E_0 dx^2, E_0 = chi0 E^Draine / 6
+(Sec. 5.2).  With Eq. e:Erad and Delta s = dx, a cell's energy density in band
+b is the sum over the six rays of
+
+    (chi0 / 6) exp(-sigma_b N_in) (1 - exp(-dtau)) / dtau,   dtau = sigma_b n dx,
+
+where N_in is the hydrogen column from the face to the cell's entry face.
+chi_H2 additionally weights each ray by f_shld,H2(N_H2,in + n x_H2 dx / 2)
+(Eq. e:Erad_H2, Eq. e:fshld_H2_DB; half the cell's own column, reading of the
+footnote on the shielding column), chi_C by the C shielding function of
+(N_C, N_H2) at the same mid-cell columns.  N_eff = -ln(chi_PE / chi0) /
+(1e-21 Z'_d) (Eq. e:tau_eff); xi_cr follows Eq. e:cratt.
+
+All six faces are open (no periodic wrap).  Arrays are indexed [k, j, i]
+(x fastest in memory, linear index i + nx (j + ny k)).
+"""
+import numpy as np
+
+from . import constants as C
+from . import micro
+
+
+def f_shld_H2(N_H2, b5=C.B5):
+    """Eq. e:fshld_H2_DB."""
+    x = N_H2 / 5.0e14
+    s = np.sqrt(1.0 + x)
+    return 0.965 / (1.0 + x / b5) ** 2 + 0.035 / s * np.exp(-8.5e-4 * s)
+
+
+def f_shld_C(N_C, N_H2):
+    """C self- and H2 cross-shielding -- stand-in table (Sec. 5.1)."""
+    lc = np.log10(np.maximum(N_C, 1.0e-300))
+    lh = np.log10(np.maximum(N_H2, 1.0e-300))
+    return np.exp(micro.LN10 * micro.table2d("cshield", lc, lh, 0))
+
+
+def g_slab(y):
+    """(1 - exp(-y)) / y, the cell average of exp(-tau) over a cell of optical depth y."""
+    small = y < 1.0e-4
+    ys = np.where(small, 1.0, y)
+    return np.where(small, 1.0 - y / 2.0 + y * y / 6.0, -np.expm1(-ys) / ys)
+
+
+def upstream_columns(q, axis, forward):
+    """Exclusive sum of q along axis from the face the ray enters."""
+    if forward:
+        c = np.cumsum(q, axis=axis)
+        return c - q
+    r = np.flip(q, axis=axis)
+    c = np.cumsum(r, axis=axis) - r
+    return np.flip(c, axis=axis)
+
+
+def columns6(n, xH2, xC, dx, par, xi_in=None):
+    """Returns dict chi_PE, chi_LW, chi_H2, chi_C, N_eff, xi (arrays shaped like n [nz, ny, nx]).
+
+    par.cr_mode: 0 -> xi = xi_cr0; 1 -> Eq. e:cratt on N_eff; 2 -> xi_in returned unchanged.
+    """
+    n = np.asarray(n, dtype=np.float64)
+    xH2 = np.asarray(xH2, dtype=np.float64)
+    xC = np.zeros_like(n) if xC is None else np.asarray(xC, dtype=np.float64)
+    Zd, chi0 = par.Zd, par.chi0
+    sPE, sLW = C.SIG_D_PE * Zd, C.SIG_D_LW * Zd
+    qH, qH2, qC = n * dx, n * xH2 * dx, n * xC * dx
+    gPE, gLW = g_slab(sPE * qH), g_slab(sLW * qH)
+    chiPE = np.zeros_like(n)
+    chiLW = np.zeros_like(n)
+    chiH2 = np.zeros_like(n)
+    chiC = np.zeros_like(n)
+    for axis in (2, 1, 0):          # x, y, z
+        for fwd in (True, False):   # + then - direction
+            NH = upstream_columns(qH, axis, fwd)
+            NH2m = upstream_columns(qH2, axis, fwd) + 0.5 * qH2
+            NCm = upstream_columns(qC, axis, fwd) + 0.5 * qC
+            wPE = np.exp(-sPE * NH) * gPE
+            wLW = np.exp(-sLW * NH) * gLW
+            chiPE += wPE
+            chiLW += wLW
+            chiH2 += wLW * f_shld_H2(NH2m)
+            chiC += wLW * f_shld_C(NCm, NH2m)
+    f = chi0 / 6.0
+    chiPE, chiLW, chiH2, chiC = f * chiPE, f * chiLW, f * chiH2, f * chiC
+    if chi0 > 0.0:
+        Neff = -np.log(chiPE / chi0) / (C.SIG_D_NEFF * Zd)
+    else:
+        Neff = np.zeros_like(n)
+    if par.cr_mode == 0:
+        xi = np.full_like(n, par.xi_cr0)
+    elif par.cr_mode == 1:
+        xi = cr_attenuation(Neff, par.xi_cr0)
+    else:
+        xi = np.asarray(xi_in, dtype=np.float64)
+    return dict(chi_PE=chiPE, chi_LW=chiLW, chi_H2=chiH2, chi_C=chiC, N_eff=Neff, xi=xi)
+
+
+def cr_attenuation(Neff, xi0):
+    """Eq. e:cratt: xi0 for N_eff <= N0, xi0 (N_eff / N0)^-1 beyond."""
+    return np.where(Neff <= C.N0_CR, xi0, xi0 * C.N0_CR / np.maximum(Neff, C.N0_CR))
