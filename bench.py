@@ -1,0 +1,174 @@
+"""Throughput of the ISM chemistry + cooling source step on one MI355X.
+
+A step is one pass of the hot path over the 128^3 lognormal-GRF workload
+(4 pc cells, Z' = 1, CR attenuation by N_eff, dt = 1e4 yr): six-ray columns, then
+the subcycled chem+cool step of every cell.  The cell state is restored from a
+device copy before each step so every step does the same work.  Prints one JSON
+line (see the fields below); `value` is cell-updates/s of the whole step with the
+inputs resident in HBM.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--path f64|mixed] [--no-cpu]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--path", choices=("f64", "mixed"), default="f64")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-cells", type=int, default=4096)
+    return ap.parse_args()
+
+
+def cpu_baseline(state, cfg, ncell_sample, par_o):
+    """The CPU oracle on a seeded sample of the same workload (columns for the sampled cells + the step)."""
+    from oracle import columns as ocol
+    from oracle import step as ostep
+    from oracle.constants import PC, YR
+    rng = np.random.default_rng(7)
+    shape = state["n"].shape
+    idx = rng.choice(state["n"].size, ncell_sample, replace=False)
+    cells = np.stack(np.unravel_index(idx, shape), 1)
+    t0 = time.perf_counter()
+    rc = ocol.columns6_cells(state["n"], state["xH2"], None, cfg["dx_pc"] * PC, par_o, cells)
+    t1 = time.perf_counter()
+    rad = dict(chi_PE=rc["chi_PE"], chi_LW=rc["chi_LW"], chi_H2=rc["chi_H2"], chi_C=rc["chi_C"],
+               phi=np.zeros(len(idx)), xi=rc["xi"], Neff=rc["N_eff"])
+    sel = lambda a: a.ravel()[idx]
+    ostep.chem_cool_step(sel(state["n"]), sel(state["T"]), sel(state["xH2"]), sel(state["xHp"]), rad,
+                         cfg["dt_yr"] * YR, par_o)
+    t2 = time.perf_counter()
+    try:
+        threads = len(os.sched_getaffinity(0))
+    except Exception:
+        threads = os.cpu_count()
+    return {"value": ncell_sample / (t2 - t0), "unit": "cell-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{ncell_sample} seeded random cells of the 128^3 grid: oracle six-ray columns for those cells "
+                      f"({t1 - t0:.1f} s) + oracle step ({t2 - t1:.1f} s), numpy single-threaded; host has {threads} "
+                      f"threads"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported "
+                                   "(the source step is per-cell independent; see the sharding notes)"}))
+        sys.exit(2)
+    import torch
+    from paper_2210_08024_amd import ism, workloads
+    from oracle.census import substep_census
+    from oracle.constants import Params as OParams
+
+    state, cfg = workloads.make("grf128")
+    shape = state["n"].shape
+    N = state["n"].size
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ism.init(0)
+    prec = ism.F64 if args.path == "f64" else ism.MIXED
+    rd = torch.float64 if prec == ism.F64 else torch.float32
+    par = ism.Params(Zg=cfg["Zg"], Zd=cfg["Zg"], cr_mode=cfg["cr_mode"])
+    dx = cfg["dx_pc"] * 3.0856775814913673e18
+    dt = cfg["dt_yr"] * 3.15576e7
+    init = {k: torch.from_numpy(np.ascontiguousarray(state[k]).ravel()).to(dev) for k in ("n", "T", "xH2", "xHp")}
+    n = init["n"]
+    T, xH2, xHp = (torch.empty_like(init[k]) for k in ("T", "xH2", "xHp"))
+    rad = {k: torch.empty(N, dtype=rd, device=dev) for k in ("chi_PE", "chi_LW", "chi_H2", "chi_C", "N_eff", "xi")}
+    outs = {"xCp": torch.empty(N, dtype=rd, device=dev), "xCO": torch.empty(N, dtype=rd, device=dev),
+            "xe": torch.empty(N, dtype=rd, device=dev), "nsub": torch.empty(N, dtype=torch.int32, device=dev),
+            "status": torch.empty(N, dtype=torch.uint8, device=dev)}
+    radv = {k: v.view(shape) for k, v in rad.items()}
+    stepr = dict(rad)
+    stepr["phi"] = None
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+
+    def one_step(times=None):
+        T.copy_(init["T"])
+        xH2.copy_(init["xH2"])
+        xHp.copy_(init["xHp"])
+        if times is not None:
+            ev[0].record()
+        ism.columns6(n.view(shape), xH2.view(shape), None, dx, par, prec, out=radv)
+        if times is not None:
+            ev[1].record()
+        ism.chem_cool_step(n, T, xH2, xHp, stepr, dt, par, prec, out=outs)
+        if times is not None:
+            ev[2].record()
+            torch.cuda.synchronize()
+            times["columns"].append(ev[0].elapsed_time(ev[1]) * 1e-3)
+            times["step"].append(ev[1].elapsed_time(ev[2]) * 1e-3)
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one_step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    times = {"columns": [], "step": []}
+    for _ in range(max(3, min(args.steps, 5))):
+        one_step(times)
+    nsub = outs["nsub"].to(torch.int64)
+    tot_sub = int(nsub.sum().item())
+    st = outs["status"].cpu().numpy()
+    t_step = float(np.mean(times["step"]))
+    t_cols = float(np.mean(times["columns"]))
+    arith, trans = substep_census(OParams())
+    flops = float(tot_sub) * (arith + trans)
+    peak = FP64_PEAK_TFLOPS if prec == ism.F64 else FP32_PEAK_TFLOPS
+    achieved = flops / t_step / 1e12
+    ms = wall / args.steps * 1e3
+    value = N / (wall / args.steps)
+    out = {
+        "metric": "cell-updates/s per chem+cool step (columns6 + subcycled step)",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == ism.F64 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "grf128: 128^3 lognormal GRF (sigma_ln 1.5, 2 pc smoothing), 4 pc cells, "
+                               "P/k = 3e3 K cm^-3, Z' = 1, chi0 = 1 six-ray, xi_cr0 = 2e-16 attenuated by N_eff, "
+                               "dt = 1e4 yr", "cells": N, "path": args.path},
+        "roofline": {"bound": "alu", "kernel": "step_simple_kernel", "achieved": achieved, "peak": peak,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "work": f"{tot_sub} substeps x ({arith} flops + {trans} transcendentals counted as 1) "
+                             f"per launch; census of the oracle's substep"},
+        "detail": {"step_kernel_ms": t_step * 1e3, "columns_ms": t_cols * 1e3,
+                   "step_only_cell_updates_per_s": N / t_step,
+                   "nsub_mean": tot_sub / N, "nsub_max": int(nsub.max().item()),
+                   "nsub_p99": float(np.percentile(outs["nsub"].cpu().numpy(), 99)),
+                   "status_nonzero": int((st != 0).sum()),
+                   "columns_hbm_GBs_algorithmic": N * (24 + (48 if prec == ism.F64 else 24)) / t_cols / 1e9},
+    }
+    if not args.no_cpu:
+        from oracle.constants import Params as OP
+        out["cpu_baseline"] = cpu_baseline(state, cfg, args.cpu_cells, OP(Zg=1.0, Zd=1.0, cr_mode=1))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

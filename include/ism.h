@@ -1,0 +1,150 @@
+/*
+ * ism.h -- C ABI of the MI355X ISM photochemistry + heating/cooling source step.
+ *
+ * Method: Kim, Gong, Kim & Ostriker, "Photochemistry and Heating/Cooling of the
+ * Multiphase Interstellar Medium with UV Radiative Transfer for Magnetohydrodynamic
+ * Simulations" (arXiv:2210.08024).  Each entry point names the passage that defines
+ * the operation it performs.
+ *
+ * Conventions (all entry points):
+ *  - Pointers named as arrays are DEVICE pointers (hipMalloc / torch CUDA tensors),
+ *    contiguous, owned by the caller, at least 8-byte aligned; the library never
+ *    frees or retains them.  Scalars and structs are passed by host pointer.
+ *  - Units are cgs: n [cm^-3], T [K], dt [s], dx [cm], chi in Draine-field units,
+ *    phi_LyC [photons cm^-2 s^-1], xi_cr [s^-1], columns [cm^-2].
+ *  - Grids are indexed idx = i + nx * (j + ny * k), x fastest.
+ *  - ISM_PREC_F64: every floating array is double.  ISM_PREC_MIXED: the cell state
+ *    (n, T, x_H2, x_H+) stays double; radiation inputs/outputs and the derived
+ *    abundance outputs (x_C+, x_CO, x_e) are float.
+ *  - Work is enqueued asynchronously on the given stream (NULL = default stream);
+ *    nothing synchronises except where stated.
+ *  - Argument errors are detected before anything is enqueued and return ISM_E_ARG;
+ *    launch/runtime errors return ISM_E_DEVICE.  ism_last_error() gives the message
+ *    (thread-local).  Per-cell numerical trouble never fails a call: it is reported
+ *    in the per-cell status bits below and the call returns ISM_OK.
+ *  - Thread safety: concurrent calls on different streams are safe after ism_init.
+ */
+#ifndef ISM_H
+#define ISM_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ISM_OK = 0,
+  ISM_E_ARG = -1,     /* invalid argument (null, size, range)            */
+  ISM_E_DEVICE = -2,  /* HIP runtime / launch failure                    */
+  ISM_E_NOMEM = -3,   /* device allocation failed                        */
+  ISM_E_STATE = -4,   /* library not initialised on this device          */
+  ISM_E_TABLE = -5    /* coefficient file missing, unreadable or invalid */
+} ism_status;
+
+typedef enum { ISM_PREC_F64 = 0, ISM_PREC_MIXED = 1 } ism_precision;
+
+/* Per-cell status bits written by the step entry points. */
+enum {
+  ISM_ST_SUBSTEP_CAP = 1,   /* max_substeps reached before t = dt                 */
+  ISM_ST_NONFINITE = 2,     /* a non-finite value appeared; the cell stopped      */
+  ISM_ST_T_FLOOR = 4,       /* the temperature floor was applied                  */
+  ISM_ST_DENOM_GUARD = 8,   /* T-update denominator guard fired                   */
+  ISM_ST_FALLBACK = 16,     /* surrogate rejected, plain solver used              */
+  ISM_ST_TD_UNBRACKETED = 32 /* dust-temperature root not bracketed, T_d = 1e4 K  */
+};
+
+/* Uniform Cartesian grid (Sec. 5.2): nx*ny*nz cells of side dx_cm. */
+typedef struct {
+  int32_t nx, ny, nz;
+  int32_t pad_;
+  double dx_cm;
+} ism_grid;
+
+/* Parameters of the source step (Table t:param, Sec. 6.1, Sec. 7.1.2). */
+typedef struct {
+  double Zg;            /* scaled gas metallicity Z'_g (> 0)                              */
+  double Zd;            /* scaled dust abundance Z'_d (> 0)                               */
+  double chi0;          /* unattenuated FUV at the domain faces, Draine units (Sec. 5.2)  */
+  double xi_cr0;        /* unattenuated primary CR ionisation rate [s^-1] (Sec. 2.4)      */
+  double dvdr_kms_pc;   /* |dv/dr| for the CO LVG column (Sec. 4.2.2, default 1)          */
+  double eps_sub;       /* substep limiter factor (Sec. 6.1, 0.1)                         */
+  double fd_rel;        /* relative step of the forward difference dH/dT_mu (1e-3)        */
+  double T_floor;       /* temperature floor [K] (1)                                       */
+  double T_bb;          /* dust bath blackbody temperature [K] (Sec. 7.1.2, 6)            */
+  double tau_opt_ratio; /* tau_PE,eff / tau_OPT (Sec. 7.1.2, 1.87)                        */
+  int32_t cr_mode;      /* columns6: 0 xi = xi_cr0, 1 Eq. e:cratt on N_eff, 2 leave xi_cr  */
+  int32_t kgr_const;    /* 1: k_gr = 3e-17 Z'_d (Sec. 7); 0: Eq. e:H2form                 */
+  int32_t h2_rovib;     /* 1: include H2 ro-vibrational cooling                           */
+  int32_t max_substeps; /* substep cap per cell (100000)                                   */
+} ism_params;
+
+/* Fill *p with the defaults listed above (Z'_g = Z'_d = chi0 = 1, xi_cr0 = 2e-16). */
+void ism_params_default(ism_params *p);
+
+/* Initialise the library on HIP device `device`: parse the coefficient file
+ * (JSON: printed constants, stand-in coefficients and tables) and upload it.
+ * Must precede every other call on that device; may be called again to reload.
+ * Returns ISM_E_TABLE if the file is missing or invalid, ISM_E_DEVICE on HIP errors. */
+ism_status ism_init(int device, const char *coefficients_json_path);
+
+/* Release the library's device memory on every initialised device. */
+ism_status ism_shutdown(void);
+
+/* Message of the last error on the calling thread ("" if none).  Library-owned. */
+const char *ism_last_error(void);
+
+/* Number of per-cell diagnostics written by ism_rates, and the name of diagnostic k
+ * (NULL if k is out of range).  Library-owned strings. */
+int32_t ism_ndiag(void);
+const char *ism_diag_name(int32_t k);
+
+/* Six-ray diffuse-UV transfer (Secs. 5.1-5.3; Eqs. e:Erad, e:Erad_H2, e:fshld_H2_DB,
+ * e:tau_eff, e:cratt).  For every cell, rays from the six faces give
+ *   chi_b   = chi0/6 sum_d exp(-sigma_b N_in,d) (1 - exp(-dtau_b)) / dtau_b,  b = PE, LW
+ *   chi_H2  = same LW sum weighted by f_shld,H2(N_H2,in,d + n x_H2 dx / 2)
+ *   chi_C   = same LW sum weighted by f_shld,C(N_C,in,d + n x_C dx/2, N_H2 mid-cell)
+ *   N_eff   = -ln(chi_PE / chi0) / (1e-21 Z'_d)   (0 when chi0 = 0)
+ *   xi_cr   = per p->cr_mode (not written when cr_mode = 2)
+ * with upstream columns accumulated in double.
+ * In: n, xH2 (double, ncell), xC (double or NULL = 0).  Out: chi_PE, chi_LW, chi_H2,
+ * chi_C, N_eff, xi_cr (double for F64, float for MIXED).  Requires nx, ny, nz >= 1. */
+ism_status ism_columns6(const ism_grid *g, const ism_params *p, ism_precision prec,
+                        const double *n, const double *xH2, const double *xC,
+                        void *chi_PE, void *chi_LW, void *chi_H2, void *chi_C,
+                        void *N_eff, void *xi_cr, hipStream_t stream);
+
+/* Per-cell diagnostics of the microphysics at the given state (Secs. 3-4): every rate
+ * coefficient, heating and cooling term, T_d, the equilibrium x_C+, x_CO, x_e, the
+ * net volumetric rate H = n Gamma - n^2 Lambda and C_H2, C_H+ (Eqs. e:HH, e:HII,
+ * e:ODE1).  `out` is SoA: diagnostic k of cell i at out[k * ncell + i], ism_ndiag()
+ * arrays of double (F64) or float (MIXED).  Radiation inputs as for the step;
+ * phi_LyC may be NULL (= 0). */
+ism_status ism_rates(const ism_params *p, ism_precision prec, int64_t ncell,
+                     const double *n, const double *T, const double *xH2, const double *xHp,
+                     const void *chi_PE, const void *chi_LW, const void *chi_H2, const void *chi_C,
+                     const void *phi_LyC, const void *xi_cr, const void *N_eff,
+                     void *out, hipStream_t stream);
+
+/* The subcycled heating/cooling + chemistry source step (Sec. 6.1, Eqs. e:ODE1,
+ * e:ODE2): advances every cell by dt_s with n and radiation fixed.  Per substep:
+ * dt_sub = min(dt - t, eps e/|H|, eps/|C_H2|, eps/|C_H+|); semi-implicit T_mu update
+ * with a forward-difference dH/dT_mu; backward-Euler update of (x_H2, x_H+) with rate
+ * coefficients at the new temperature; equilibrium C/O/e closure (Secs. 3.2-3.3).
+ * In/out: T, xH2, xHp (double).  In: n (double) and radiation (precision as above;
+ * phi_LyC may be NULL = 0).  Optional outputs (NULL to skip): xCp, xCO, xe, nsub
+ * (int32 substeps taken), status (uint8 bits above).  F64 evaluates everything in
+ * double; MIXED evaluates rates, heating, cooling and the closure in float and keeps
+ * the net H, the T update and the abundance update in double. */
+ism_status ism_chem_cool_step(const ism_params *p, ism_precision prec, int64_t ncell, double dt_s,
+                              const double *n, double *T, double *xH2, double *xHp,
+                              const void *chi_PE, const void *chi_LW, const void *chi_H2,
+                              const void *chi_C, const void *phi_LyC, const void *xi_cr,
+                              const void *N_eff, void *xCp, void *xCO, void *xe,
+                              int32_t *nsub, uint8_t *status, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ISM_H */

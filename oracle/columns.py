@@ -45,13 +45,22 @@ def g_slab(y):
 
 
 def upstream_columns(q, axis, forward):
-    """Exclusive sum of q along axis from the face the ray enters."""
-    if forward:
-        c = np.cumsum(q, axis=axis)
-        return c - q
-    r = np.flip(q, axis=axis)
-    c = np.cumsum(r, axis=axis) - r
-    return np.flip(c, axis=axis)
+    """Exclusive running sum of q along axis, starting from the face the ray enters.
+
+    Accumulated cell by cell (no inclusive-minus-self subtraction), so a small
+    upstream column next to a very dense cell keeps its relative precision.
+    """
+    qq = np.moveaxis(q, axis, 0)
+    if not forward:
+        qq = qq[::-1]
+    out = np.empty_like(qq)
+    run = np.zeros_like(qq[0])
+    for k in range(qq.shape[0]):
+        out[k] = run
+        run = run + qq[k]
+    if not forward:
+        out = out[::-1]
+    return np.moveaxis(out, 0, axis)
 
 
 def columns6(n, xH2, xC, dx, par, xi_in=None):
@@ -99,3 +108,43 @@ def columns6(n, xH2, xC, dx, par, xi_in=None):
 def cr_attenuation(Neff, xi0):
     """Eq. e:cratt: xi0 for N_eff <= N0, xi0 (N_eff / N0)^-1 beyond."""
     return np.where(Neff <= C.N0_CR, xi0, xi0 * C.N0_CR / np.maximum(Neff, C.N0_CR))
+
+
+def columns6_cells(n, xH2, xC, dx, par, cells):
+    """The six-ray result for selected cells only, by direct summation along each ray.
+
+    cells: int array [m, 3] of (k, j, i).  Same definition as columns6, evaluated
+    one cell at a time (used to check full-size grids on samples).
+    """
+    n = np.asarray(n, dtype=np.float64)
+    xH2 = np.asarray(xH2, dtype=np.float64)
+    xC = np.zeros_like(n) if xC is None else np.asarray(xC, dtype=np.float64)
+    Zd, chi0 = par.Zd, par.chi0
+    sPE, sLW = C.SIG_D_PE * Zd, C.SIG_D_LW * Zd
+    out = {k: np.zeros(len(cells)) for k in ("chi_PE", "chi_LW", "chi_H2", "chi_C", "N_eff", "xi")}
+    for m, (k, j, i) in enumerate(np.asarray(cells)):
+        lines = ((n[k, j, :], xH2[k, j, :], xC[k, j, :], i), (n[k, :, i], xH2[k, :, i], xC[k, :, i], j),
+                 (n[:, j, i], xH2[:, j, i], xC[:, j, i], k))
+        acc = np.zeros(4)
+        qH = n[k, j, i] * dx
+        qH2 = n[k, j, i] * xH2[k, j, i] * dx
+        qC = n[k, j, i] * xC[k, j, i] * dx
+        for ln, lx, lc, p in lines:
+            for up in (slice(0, p), slice(p + 1, None)):
+                NH = np.sum(ln[up] * dx)
+                NH2 = np.sum(ln[up] * lx[up] * dx)
+                NC = np.sum(ln[up] * lc[up] * dx)
+                wPE = np.exp(-sPE * NH) * g_slab(np.array([sPE * qH]))[0]
+                wLW = np.exp(-sLW * NH) * g_slab(np.array([sLW * qH]))[0]
+                mH2 = NH2 + 0.5 * qH2
+                mC = NC + 0.5 * qC
+                acc += (wPE, wLW, wLW * f_shld_H2(np.array([mH2]))[0],
+                        wLW * f_shld_C(np.array([mC]), np.array([mH2]))[0])
+        f = chi0 / 6.0
+        out["chi_PE"][m], out["chi_LW"][m], out["chi_H2"][m], out["chi_C"][m] = f * acc
+        out["N_eff"][m] = -np.log(out["chi_PE"][m] / chi0) / (C.SIG_D_NEFF * Zd) if chi0 > 0 else 0.0
+    if par.cr_mode == 0:
+        out["xi"][:] = par.xi_cr0
+    elif par.cr_mode == 1:
+        out["xi"] = cr_attenuation(out["N_eff"], par.xi_cr0)
+    return out

@@ -244,23 +244,25 @@ def _two_level(g0, g1, E10, A10, C10, T):
 
 
 def _three_level(g, E, A10, A20, A21, C10, C20, C21, T):
-    """Steady populations (p0, p1, p2) of a 3-level atom, solved as a linear system."""
+    """Steady populations (p0, p1, p2) of a 3-level atom.
+
+    Statistical equilibrium of levels 1 and 2 with p0 set to 1,
+      p1 (R10 + R12) - p2 R21 = R01,   -p1 R12 + p2 (R20 + R21) = R02,
+    solved by Cramer's rule (determinant R10 R20 + R10 R21 + R12 R20, all terms
+    positive), then normalised to p0 + p1 + p2 = 1.  Upward collision rates
+    follow detailed balance, C_lu = C_ul (g_u / g_l) exp(-(E_u - E_l) / T).
+    """
     g0, g1, g2 = g
     E1, E2 = E
-    C01 = C10 * (g1 / g0) * np.exp(-E1 / T)
-    C02 = C20 * (g2 / g0) * np.exp(-E2 / T)
-    C12 = C21 * (g2 / g1) * np.exp(-(E2 - E1) / T)
-    R01, R02, R12 = C01, C02, C12
+    R01 = C10 * (g1 / g0) * np.exp(-E1 / T)
+    R02 = C20 * (g2 / g0) * np.exp(-E2 / T)
+    R12 = C21 * (g2 / g1) * np.exp(-(E2 - E1) / T)
     R10, R20, R21 = C10 + A10, C20 + A20, C21 + A21
-    N = np.broadcast(T, C10).shape
-    M = np.zeros(N + (3, 3))
-    M[..., 0, 0], M[..., 0, 1], M[..., 0, 2] = R01, -(R10 + R12), R21
-    M[..., 1, 0], M[..., 1, 1], M[..., 1, 2] = R02, R12, -(R20 + R21)
-    M[..., 2, :] = 1.0
-    rhs = np.zeros(N + (3,))
-    rhs[..., 2] = 1.0
-    p = np.linalg.solve(M, rhs[..., None])[..., 0]
-    return p[..., 0], p[..., 1], p[..., 2]
+    det = R10 * R20 + R10 * R21 + R12 * R20
+    p1 = (R01 * (R20 + R21) + R21 * R02) / det
+    p2 = (R02 * (R10 + R12) + R12 * R01) / det
+    s = 1.0 + p1 + p2
+    return 1.0 / s, p1 / s, p2 / s
 
 
 def fine_structure(T, n, xH, xH2, xe, xCp, xC, xO):

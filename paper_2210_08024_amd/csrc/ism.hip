@@ -1,0 +1,403 @@
+// libism: C ABI of the MI355X ISM photochemistry + heating/cooling source step.
+// Host side: coefficient loading, argument validation, per-device state, launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/ism.h"
+#include "coef.h"
+#include "json_mini.h"
+#include "kernels_step.h"
+#include "kernels_columns.h"
+
+using namespace ism;
+
+namespace {
+
+thread_local std::string g_err;
+
+ism_status fail(ism_status s, const std::string &msg) {
+  g_err = msg;
+  return s;
+}
+
+struct DevState {
+  bool ready = false;
+  double *tab64 = nullptr;
+  float *tab32 = nullptr;
+  void *scratch = nullptr;
+  size_t scratch_bytes = 0;
+  int num_cu = 0;
+};
+
+std::mutex g_mu;
+std::map<int, DevState> g_dev;
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(ISM_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+// ---------------------------------------------------------------- coefficient binding
+struct Binder {
+  const ismjson::Value *sec;
+  std::string err;
+  bool get(const char *name, double *dst, size_t n) {
+    const ismjson::Value *e = sec ? sec->get(name) : nullptr;
+    const ismjson::Value *v = e ? e->get("value") : nullptr;
+    std::vector<double> vals;
+    if (!v || !v->numbers(vals)) { err = std::string("missing coefficient '") + name + "'"; return false; }
+    if (vals.size() != n) {
+      err = std::string("coefficient '") + name + "' has " + std::to_string(vals.size()) + " values, expected " +
+            std::to_string(n);
+      return false;
+    }
+    for (size_t k = 0; k < n; ++k) dst[k] = vals[k];
+    return true;
+  }
+};
+
+#define BIND(b, name, field) ok = ok && b.get(name, &(field), 1)
+#define BINDA(b, name, field) ok = ok && b.get(name, field, sizeof(field) / sizeof(field[0]))
+
+bool bind_table(const ismjson::Value &tables, const char *name, const std::vector<int> &dims, int ncol,
+                std::vector<double> &tab, size_t offset, double *x0, double *dx, std::string &err) {
+  const ismjson::Value *t = tables.get(name);
+  const ismjson::Value *axes = t ? t->get("axes") : nullptr;
+  const ismjson::Value *vals = t ? t->get("values") : nullptr;
+  if (!t || !axes || axes->kind != ismjson::Value::Arr || axes->arr.size() != dims.size() || !vals) {
+    err = std::string("table '") + name + "' missing or malformed";
+    return false;
+  }
+  size_t total = (size_t)ncol;
+  for (size_t d = 0; d < dims.size(); ++d) {
+    const ismjson::Value &ax = axes->arr[d];
+    const ismjson::Value *n = ax.get("n"), *a0 = ax.get("x0"), *ad = ax.get("dx");
+    if (!n || !a0 || !ad || (int)n->num != dims[d] || !(ad->num > 0)) {
+      err = std::string("table '") + name + "' axis " + std::to_string(d) + " does not match the expected grid";
+      return false;
+    }
+    x0[d] = a0->num;
+    dx[d] = ad->num;
+    total *= (size_t)dims[d];
+  }
+  std::vector<double> v;
+  if (!vals->numbers(v) || v.size() != total) {
+    err = std::string("table '") + name + "' has the wrong number of values";
+    return false;
+  }
+  for (size_t k = 0; k < total; ++k) tab[offset + k] = v[k];
+  return true;
+}
+
+bool load_coefficients(const char *path, CoefT<double> &c, std::vector<double> &tab, std::string &err) {
+  std::ifstream f(path);
+  if (!f) { err = std::string("cannot open coefficient file '") + (path ? path : "(null)") + "'"; return false; }
+  std::stringstream ss;
+  ss << f.rdbuf();
+  std::string text = ss.str();
+  ismjson::Value doc;
+  ismjson::Parser parser(text);
+  if (!parser.parse(doc, err)) return false;
+  const ismjson::Value *pr = doc.get("printed"), *sd = doc.get("standin"), *tb = doc.get("tables");
+  if (!pr || !sd || !tb) { err = "coefficient file lacks printed/standin/tables sections"; return false; }
+  std::memset(&c, 0, sizeof(c));
+  Binder P{pr, ""}, S{sd, ""};
+  bool ok = true;
+  BIND(P, "xC_tot_per_Zg", c.xCt_per_Zg); BIND(P, "xO_tot_per_Zg", c.xOt_per_Zg); BIND(P, "muH_0", c.muH0);
+  BIND(P, "muH_slope", c.muH_slope); BIND(P, "gamma", c.gamma); BIND(P, "kgr_0", c.kgr0);
+  BINDA(P, "kgr_shape", c.kgr_shape); BINDA(P, "cr_H2_coef", c.cr_coef); BIND(P, "cr_H2_destr_factor", c.cr_destr);
+  BIND(P, "zeta_pd_ISRF", c.zeta_pd); BIND(P, "sigma_pi_H2", c.sig_pi_H2); BIND(P, "sigma_pi_H", c.sig_pi_H);
+  BIND(P, "hnu_LyC_eV", c.hnu_LyC_eV); BIND(P, "zeta_pi_C_ISRF", c.zeta_pi_C);
+  BIND(P, "zeta_pi_C_cr_factor", c.zeta_pi_C_cr); BIND(P, "zeta_cr_C_factor", c.zeta_cr_C);
+  BINDA(P, "co_fit", c.co_fit); BIND(P, "xe_T_switch", c.xe_T_switch); BIND(P, "J_PE_Draine", c.J_PE);
+  BIND(P, "J_LW_Draine", c.J_LW); BIND(P, "J_FUV_norm", c.J_FUV); BIND(P, "G0_per_chiFUV", c.G0_per_chi);
+  BIND(P, "pe_prefactor", c.pe_pref); BINDA(P, "pe_C", c.pe_C); BIND(P, "psi_offset", c.psi_off);
+  BIND(P, "q_pi_H_eV", c.q_pi_H_eV); BIND(P, "q_pi_H2_eV", c.q_pi_H2_eV); BINDA(P, "h2form_heat_eV", c.h2form_eV);
+  BIND(P, "f_pump", c.f_pump); BIND(P, "pump_heat_eV", c.pump_eV); BIND(P, "pd_heat_eV", c.pd_eV);
+  BIND(P, "A_eff", c.A_eff); BINDA(P, "sigmoid", c.sigmoid); BINDA(P, "lya_k12", c.lya);
+  BIND(P, "lya_E21_K", c.lya_E21); BIND(P, "ci_H_eV", c.ci_eV); BIND(P, "cd_H2_eV", c.cd_eV);
+  BINDA(P, "neb", c.neb); BINDA(P, "neb_a", c.neb_a); BIND(P, "alpha_gd", c.alpha_gd);
+  BIND(P, "sigma_IR_10K", c.sigma_IR10); BIND(P, "a_rad", c.a_rad); BIND(P, "cp_ncrit_e", c.cp_ncrit_e);
+  BINDA(P, "cp_ncrit_H", c.cp_ncrit_H); BINDA(P, "o_ncrit_H", c.o_ncrit_H); BINDA(P, "c_ncrit_H", c.c_ncrit_H);
+  BINDA(P, "sigma_d_abs", c.sig_d_abs); BIND(P, "sigma_d_Neff", c.sig_d_Neff); BIND(P, "N0_cr", c.N0_cr);
+  BINDA(P, "fshld_H2", c.fshld); BIND(P, "b5", c.b5);
+  BINDA(S, "alpha_B", c.alpha_B); BINDA(S, "k_ci_H", c.k_ci_H); BINDA(S, "k_cd_H", c.k_cd_H);
+  BINDA(S, "k_cd_H2", c.k_cd_H2); BINDA(S, "alpha_gr_Hp", c.agr_Hp); BINDA(S, "alpha_gr_Cp", c.agr_Cp);
+  BINDA(S, "alpha_rrdr_Cp", c.arrdr_Cp); BINDA(S, "k_CpH2", c.k_CpH2); BINDA(S, "x_MH", c.x_MH);
+  BINDA(S, "q_cr_H", c.q_cr_H); BINDA(S, "q_cr_H2", c.q_cr_H2); BINDA(S, "k_H2_H", c.k_H2_H);
+  BINDA(S, "k_H2_H2", c.k_H2_H2); BINDA(S, "ff", c.ff); BINDA(S, "rr_energy", c.rr_energy);
+  BINDA(S, "grrec", c.grrec); BINDA(S, "rovib_lte", c.rovib_lte); BINDA(S, "rovib_low", c.rovib_low);
+  BINDA(S, "cp_levels", c.cp_levels); BIND(S, "cp_h2_over_h", c.cp_h2_over_h); BINDA(S, "c_levels", c.c_levels);
+  BINDA(S, "c_coll", c.c_coll); BINDA(S, "o_levels", c.o_levels); BINDA(S, "o_coll", c.o_coll);
+  if (!ok) { err = !P.err.empty() ? P.err : S.err; return false; }
+  tab.assign(TAB_TOTAL, 0.0);
+  double x0[2], dx[2];
+  if (!bind_table(*tb, "cie", {CIE_N}, CIE_NC, tab, TAB_CIE, x0, dx, err)) return false;
+  c.cie_x0 = x0[0]; c.cie_dx = dx[0];
+  if (!bind_table(*tb, "co", {CO_NX, CO_NY}, CO_NC, tab, TAB_CO, x0, dx, err)) return false;
+  c.co_x0 = x0[0]; c.co_dx = dx[0]; c.co_y0 = x0[1]; c.co_dy = dx[1];
+  if (!bind_table(*tb, "cshield", {CS_NX, CS_NY}, 1, tab, TAB_CS, x0, dx, err)) return false;
+  c.cs_x0 = x0[0]; c.cs_dx = dx[0]; c.cs_y0 = x0[1]; c.cs_dy = dx[1];
+  return true;
+}
+
+// Every field of CoefT is R or an array of R: convert member-wise through a flat view.
+void coef_to_f32(const CoefT<double> &d, CoefT<float> &f) {
+  static_assert(sizeof(CoefT<double>) % sizeof(double) == 0, "CoefT must hold only doubles");
+  static_assert(sizeof(CoefT<double>) / sizeof(double) == sizeof(CoefT<float>) / sizeof(float), "layout");
+  const double *s = reinterpret_cast<const double *>(&d);
+  float *t = reinterpret_cast<float *>(&f);
+  for (size_t k = 0; k < sizeof(CoefT<double>) / sizeof(double); ++k) t[k] = (float)s[k];
+}
+
+ism_status current_state(DevState **out, int *dev_out = nullptr) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_dev.find(dev);
+  if (it == g_dev.end() || !it->second.ready)
+    return fail(ISM_E_STATE, "ism_init has not been called for device " + std::to_string(dev));
+  *out = &it->second;
+  if (dev_out) *dev_out = dev;
+  return ISM_OK;
+}
+
+ism_status check_params(const ism_params *p) {
+  if (!p) return fail(ISM_E_ARG, "params is NULL");
+  if (!(p->Zg > 0.0) || !std::isfinite(p->Zg)) return fail(ISM_E_ARG, "Zg must be finite and > 0");
+  if (!(p->Zd > 0.0) || !std::isfinite(p->Zd)) return fail(ISM_E_ARG, "Zd must be finite and > 0");
+  if (!(p->chi0 >= 0.0) || !std::isfinite(p->chi0)) return fail(ISM_E_ARG, "chi0 must be finite and >= 0");
+  if (!(p->xi_cr0 >= 0.0) || !std::isfinite(p->xi_cr0)) return fail(ISM_E_ARG, "xi_cr0 must be finite and >= 0");
+  if (!(p->dvdr_kms_pc > 0.0)) return fail(ISM_E_ARG, "dvdr_kms_pc must be > 0");
+  if (!(p->eps_sub > 0.0 && p->eps_sub <= 1.0)) return fail(ISM_E_ARG, "eps_sub must be in (0, 1]");
+  if (!(p->fd_rel > 0.0 && p->fd_rel < 0.5)) return fail(ISM_E_ARG, "fd_rel must be in (0, 0.5)");
+  if (!(p->T_floor > 0.0)) return fail(ISM_E_ARG, "T_floor must be > 0");
+  if (!(p->T_bb > 0.0 && p->T_bb < 1e4)) return fail(ISM_E_ARG, "T_bb must be in (0, 1e4)");
+  if (!(p->tau_opt_ratio > 0.0)) return fail(ISM_E_ARG, "tau_opt_ratio must be > 0");
+  if (p->cr_mode < 0 || p->cr_mode > 2) return fail(ISM_E_ARG, "cr_mode must be 0, 1 or 2");
+  if (p->max_substeps < 1) return fail(ISM_E_ARG, "max_substeps must be >= 1");
+  return ISM_OK;
+}
+
+template <class R>
+ParT<R> make_par(const ism_params *p, const CoefT<double> &c) {
+  ParT<R> q;
+  q.Zg = (R)p->Zg; q.Zd = (R)p->Zd; q.chi0 = (R)p->chi0; q.dvdr = (R)p->dvdr_kms_pc;
+  q.eps_sub = (R)p->eps_sub; q.fd_rel = (R)p->fd_rel; q.T_floor = (R)p->T_floor; q.T_bb = (R)p->T_bb;
+  q.tau_ratio = (R)p->tau_opt_ratio;
+  q.xCt = (R)(c.xCt_per_Zg * p->Zg);
+  q.xOt = (R)(c.xOt_per_Zg * p->Zg);
+  q.muH = (R)(c.muH0 - c.muH_slope * (p->Zg - 1.0));
+  q.kgr_const = p->kgr_const; q.h2_rovib = p->h2_rovib; q.max_sub = p->max_substeps; q.cr_mode = p->cr_mode;
+  return q;
+}
+
+CoefT<double> g_host_coef;  // last loaded coefficients (host copy for make_par)
+
+ism_status scratch(DevState *st, size_t bytes, void **out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (st->scratch_bytes < bytes) {
+    if (st->scratch) (void)hipFree(st->scratch);
+    st->scratch = nullptr;
+    st->scratch_bytes = 0;
+    hipError_t e = hipMalloc(&st->scratch, bytes);
+    if (e != hipSuccess) return fail(ISM_E_NOMEM, std::string("scratch allocation failed: ") + hipGetErrorString(e));
+    st->scratch_bytes = bytes;
+  }
+  *out = st->scratch;
+  return ISM_OK;
+}
+
+const char *kDiagNames[NDIAG] = {
+    "xCp", "xCO", "xe", "Td", "kgr", "zcrH2", "zpd", "zpiH2", "zcd", "zpiH", "zcrH", "zci", "aB",
+    "agrH", "psi", "G_pe", "G_cr", "G_pi", "G_h2", "Gamma", "L_lya", "L_ci", "L_rovib", "L_cd", "L_ff", "L_rr",
+    "L_cp", "L_c", "L_o", "L_co", "L_grrec", "L_neb", "L_gd", "L_cie", "S", "Lambda", "H", "C_H2", "C_Hp"};
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+void ism_params_default(ism_params *p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->Zg = 1.0; p->Zd = 1.0; p->chi0 = 1.0; p->xi_cr0 = 2.0e-16; p->dvdr_kms_pc = 1.0; p->eps_sub = 0.1;
+  p->fd_rel = 1.0e-3; p->T_floor = 1.0; p->T_bb = 6.0; p->tau_opt_ratio = 1.87;
+  p->cr_mode = 0; p->kgr_const = 0; p->h2_rovib = 1; p->max_substeps = 100000;
+}
+
+const char *ism_last_error(void) { return g_err.c_str(); }
+
+int32_t ism_ndiag(void) { return NDIAG; }
+
+const char *ism_diag_name(int32_t k) { return (k >= 0 && k < NDIAG) ? kDiagNames[k] : nullptr; }
+
+ism_status ism_init(int device, const char *path) {
+  g_err.clear();
+  CoefT<double> c64;
+  std::vector<double> tab;
+  std::string err;
+  if (!path) return fail(ISM_E_ARG, "coefficient path is NULL");
+  if (!load_coefficients(path, c64, tab, err)) return fail(ISM_E_TABLE, err);
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(ISM_E_ARG, "device index out of range");
+  int prev = 0;
+  HIP_TRY(hipGetDevice(&prev));
+  HIP_TRY(hipSetDevice(device));
+  CoefT<float> c32;
+  coef_to_f32(c64, c32);
+  std::vector<float> tab32(tab.begin(), tab.end());
+  ism_status rc = ISM_OK;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevState &st = g_dev[device];
+    hipError_t e = hipSuccess;
+    if (!st.tab64) e = hipMalloc(&st.tab64, TAB_TOTAL * sizeof(double));
+    if (e == hipSuccess && !st.tab32) e = hipMalloc(&st.tab32, TAB_TOTAL * sizeof(float));
+    if (e == hipSuccess) e = hipMemcpy(st.tab64, tab.data(), TAB_TOTAL * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(st.tab32, tab32.data(), TAB_TOTAL * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(g_coef64), &c64, sizeof(c64));
+    if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(g_coef32), &c32, sizeof(c32));
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&st.num_cu, hipDeviceAttributeMultiprocessorCount, device);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) rc = fail(ISM_E_DEVICE, std::string("ism_init: ") + hipGetErrorString(e));
+    else { st.ready = true; g_host_coef = c64; }
+  }
+  (void)hipSetDevice(prev);
+  return rc;
+}
+
+ism_status ism_shutdown(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  for (auto &kv : g_dev) {
+    if (hipSetDevice(kv.first) != hipSuccess) continue;
+    (void)hipDeviceSynchronize();
+    if (kv.second.tab64) (void)hipFree(kv.second.tab64);
+    if (kv.second.tab32) (void)hipFree(kv.second.tab32);
+    if (kv.second.scratch) (void)hipFree(kv.second.scratch);
+  }
+  g_dev.clear();
+  (void)hipSetDevice(prev);
+  return ISM_OK;
+}
+
+ism_status ism_columns6(const ism_grid *g, const ism_params *p, ism_precision prec, const double *n,
+                        const double *xH2, const double *xC, void *chi_PE, void *chi_LW, void *chi_H2, void *chi_C,
+                        void *N_eff, void *xi_cr, hipStream_t stream) {
+  g_err.clear();
+  if (!g) return fail(ISM_E_ARG, "grid is NULL");
+  if (ism_status s = check_params(p)) return s;
+  if (prec != ISM_PREC_F64 && prec != ISM_PREC_MIXED) return fail(ISM_E_ARG, "invalid precision");
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1) return fail(ISM_E_ARG, "grid dimensions must be >= 1");
+  if (!(g->dx_cm > 0.0) || !std::isfinite(g->dx_cm)) return fail(ISM_E_ARG, "dx_cm must be finite and > 0");
+  if ((int64_t)g->ny * g->nz > (int64_t)INT32_MAX * 4 || g->nx > (1 << 24))
+    return fail(ISM_E_ARG, "grid too large");
+  if (!n || !xH2 || !chi_PE || !chi_LW || !chi_H2 || !chi_C || !N_eff)
+    return fail(ISM_E_ARG, "n, xH2 and all chi/N_eff outputs must be non-NULL");
+  if (p->cr_mode != 2 && !xi_cr) return fail(ISM_E_ARG, "xi_cr output is NULL (cr_mode 0/1 writes it)");
+  DevState *st;
+  if (ism_status s = current_state(&st)) return s;
+  const int64_t ncell = (int64_t)g->nx * g->ny * g->nz;
+  void *acc;
+  if (ism_status s = scratch(st, (size_t)ncell * sizeof(double4), &acc)) return s;
+  ColArgs a;
+  a.nx = g->nx; a.ny = g->ny; a.nz = g->nz; a.dx = g->dx_cm;
+  a.n = n; a.xH2 = xH2; a.xC = xC; a.acc = (double4 *)acc;
+  a.chiPE = chi_PE; a.chiLW = chi_LW; a.chiH2 = chi_H2; a.chiC = chi_C; a.Neff = N_eff; a.xi = xi_cr;
+  a.out_f32 = prec == ISM_PREC_MIXED; a.cr_mode = p->cr_mode;
+  a.chi0 = p->chi0; a.Zd = p->Zd; a.xi0 = p->xi_cr0;
+  a.sPE = g_host_coef.sig_d_abs[2] * p->Zd;
+  a.sLW = g_host_coef.sig_d_abs[1] * p->Zd;
+  a.tab = st->tab64;
+  const int64_t rows = (int64_t)g->ny * g->nz;
+  hipLaunchKernelGGL(columns_x_kernel, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, stream, a);
+  HIP_TRY(hipGetLastError());
+  const unsigned bx = (unsigned)((g->nx + 63) / 64);
+  hipLaunchKernelGGL(columns_yz_kernel<1>, dim3(bx, (unsigned)g->nz), dim3(64), 0, stream, a);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(columns_yz_kernel<2>, dim3(bx, (unsigned)g->ny), dim3(64), 0, stream, a);
+  HIP_TRY(hipGetLastError());
+  return ISM_OK;
+}
+
+ism_status ism_rates(const ism_params *p, ism_precision prec, int64_t ncell, const double *n, const double *T,
+                     const double *xH2, const double *xHp, const void *chi_PE, const void *chi_LW,
+                     const void *chi_H2, const void *chi_C, const void *phi_LyC, const void *xi_cr,
+                     const void *N_eff, void *out, hipStream_t stream) {
+  g_err.clear();
+  if (ism_status s = check_params(p)) return s;
+  if (prec != ISM_PREC_F64 && prec != ISM_PREC_MIXED) return fail(ISM_E_ARG, "invalid precision");
+  if (ncell < 0) return fail(ISM_E_ARG, "ncell must be >= 0");
+  if (ncell == 0) return ISM_OK;
+  if (!n || !T || !xH2 || !xHp || !chi_PE || !chi_LW || !chi_H2 || !chi_C || !xi_cr || !N_eff || !out)
+    return fail(ISM_E_ARG, "a required array is NULL");
+  DevState *st;
+  if (ism_status s = current_state(&st)) return s;
+  const unsigned blocks = (unsigned)((ncell + 127) / 128);
+  if (prec == ISM_PREC_F64) {
+    RatesArgs<double> a{ncell, n, T, xH2, xHp, (const double *)chi_PE, (const double *)chi_LW,
+                        (const double *)chi_H2, (const double *)chi_C, (const double *)phi_LyC,
+                        (const double *)xi_cr, (const double *)N_eff, (double *)out, st->tab64,
+                        make_par<double>(p, g_host_coef)};
+    hipLaunchKernelGGL(rates_kernel<double>, dim3(blocks), dim3(128), 0, stream, a);
+  } else {
+    RatesArgs<float> a{ncell, n, T, xH2, xHp, (const float *)chi_PE, (const float *)chi_LW,
+                       (const float *)chi_H2, (const float *)chi_C, (const float *)phi_LyC,
+                       (const float *)xi_cr, (const float *)N_eff, (float *)out, st->tab32,
+                       make_par<float>(p, g_host_coef)};
+    hipLaunchKernelGGL(rates_kernel<float>, dim3(blocks), dim3(128), 0, stream, a);
+  }
+  HIP_TRY(hipGetLastError());
+  return ISM_OK;
+}
+
+ism_status ism_chem_cool_step(const ism_params *p, ism_precision prec, int64_t ncell, double dt_s, const double *n,
+                              double *T, double *xH2, double *xHp, const void *chi_PE, const void *chi_LW,
+                              const void *chi_H2, const void *chi_C, const void *phi_LyC, const void *xi_cr,
+                              const void *N_eff, void *xCp, void *xCO, void *xe, int32_t *nsub, uint8_t *status,
+                              hipStream_t stream) {
+  g_err.clear();
+  if (ism_status s = check_params(p)) return s;
+  if (prec != ISM_PREC_F64 && prec != ISM_PREC_MIXED) return fail(ISM_E_ARG, "invalid precision");
+  if (ncell < 0) return fail(ISM_E_ARG, "ncell must be >= 0");
+  if (!(dt_s >= 0.0) || !std::isfinite(dt_s)) return fail(ISM_E_ARG, "dt_s must be finite and >= 0");
+  if (ncell == 0) return ISM_OK;
+  if (!n || !T || !xH2 || !xHp || !chi_PE || !chi_LW || !chi_H2 || !chi_C || !xi_cr || !N_eff)
+    return fail(ISM_E_ARG, "a required array is NULL");
+  DevState *st;
+  if (ism_status s = current_state(&st)) return s;
+  const unsigned blocks = (unsigned)((ncell + 255) / 256);
+  if (prec == ISM_PREC_F64) {
+    StepArgs<double> a{ncell, dt_s, n, T, xH2, xHp, (const double *)chi_PE, (const double *)chi_LW,
+                       (const double *)chi_H2, (const double *)chi_C, (const double *)phi_LyC,
+                       (const double *)xi_cr, (const double *)N_eff, (double *)xCp, (double *)xCO, (double *)xe,
+                       nsub, status, st->tab64, make_par<double>(p, g_host_coef), make_par<double>(p, g_host_coef),
+                       nullptr};
+    hipLaunchKernelGGL(step_simple_kernel<double>, dim3(blocks), dim3(256), 0, stream, a);
+  } else {
+    StepArgs<float> a{ncell, dt_s, n, T, xH2, xHp, (const float *)chi_PE, (const float *)chi_LW,
+                      (const float *)chi_H2, (const float *)chi_C, (const float *)phi_LyC,
+                      (const float *)xi_cr, (const float *)N_eff, (float *)xCp, (float *)xCO, (float *)xe,
+                      nsub, status, st->tab32, make_par<float>(p, g_host_coef), make_par<double>(p, g_host_coef),
+                      nullptr};
+    hipLaunchKernelGGL(step_simple_kernel<float>, dim3(blocks), dim3(256), 0, stream, a);
+  }
+  HIP_TRY(hipGetLastError());
+  return ISM_OK;
+}
+
+}  // extern "C"

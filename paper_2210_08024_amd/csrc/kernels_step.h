@@ -1,0 +1,185 @@
+// Source-step kernels: the subcycled heating/cooling + chemistry update (Sec. 6.1)
+// and the per-cell diagnostics of the microphysics.
+#pragma once
+#include "physics.h"
+
+namespace ism {
+
+__constant__ CoefT<double> g_coef64;
+__constant__ CoefT<float> g_coef32;
+
+template <class R> __device__ __forceinline__ const CoefT<R> &coef();
+template <> __device__ __forceinline__ const CoefT<double> &coef<double>() { return g_coef64; }
+template <> __device__ __forceinline__ const CoefT<float> &coef<float>() { return g_coef32; }
+
+template <class R> struct CloseTol;
+template <> struct CloseTol<double> { static constexpr double v = 1e-12; };
+template <> struct CloseTol<float> { static constexpr float v = 1e-6f; };
+
+template <class R>
+struct StepArgs {
+  int64_t ncell;
+  double dt;
+  const double *n;
+  double *T, *xH2, *xHp;
+  const R *chiPE, *chiLW, *chiH2, *chiC, *phi, *xi, *Neff;
+  R *xCp, *xCO, *xe;
+  int32_t *nsub;
+  uint8_t *status;
+  const R *tab;
+  ParT<R> pr;
+  ParT<double> pd;
+  int64_t *queue;  // persistent variant: next unclaimed cell (device counter), else unused
+};
+
+// Per-lane state of one cell while it is being subcycled.
+template <class R>
+struct CellState {
+  double nd, K, Tmu, xH2, xHp, t;
+  Rad<R> r;
+  EqS<R> e;
+  R tdg;
+  int32_t ns;
+  uint32_t st;
+};
+
+template <class R>
+__device__ __forceinline__ void cell_begin(const StepArgs<R> &a, int64_t i, CellState<R> &s, const R *tab) {
+  const CoefT<R> &c = coef<R>();
+  s.nd = a.n[i];
+  s.r.chiPE = a.chiPE[i];
+  s.r.chiLW = a.chiLW[i];
+  s.r.chiH2 = a.chiH2[i];
+  s.r.chiC = a.chiC[i];
+  s.r.phi = a.phi ? a.phi[i] : R(0);
+  s.r.xi = a.xi[i];
+  s.r.Neff = a.Neff[i];
+  const double T0 = a.T[i];
+  s.xH2 = a.xH2[i];
+  s.xHp = a.xHp[i];
+  const double muH = a.pd.muH;
+  s.K = s.nd * muH * K_B / (g_coef64.gamma - 1.0);
+  s.e = eq_species<R>(R(T0), R(s.nd), R(s.xH2), R(s.xHp), s.r, c, a.pr, tab, CloseTol<R>::v, 50);
+  s.Tmu = T0 * (1.1 + (double)s.e.xe - s.xH2) / muH;
+  s.t = 0.0;
+  s.ns = 0;
+  s.st = 0;
+  s.tdg = R(0);
+}
+
+// One substep of Sec. 6.1 for the lane's cell; returns true when the cell is finished.
+template <class R>
+__device__ __forceinline__ bool cell_substep(const StepArgs<R> &a, CellState<R> &s, const R *tab) {
+  const CoefT<R> &c = coef<R>();
+  const ParT<R> &p = a.pr;
+  const double muH = a.pd.muH, eps = a.pd.eps_sub, delta = a.pd.fd_rel, dt = a.dt;
+  const double mu_den = 1.1 + (double)s.e.xe - s.xH2;
+  const double Ta = muH * s.Tmu / mu_den;
+  Eval<R> v = evaluate<R, false, false>(R(Ta), s.nd, R(s.xH2), R(s.xHp), s.e, s.r, c, p, tab, s.tdg, nullptr);
+  s.tdg = v.Td;
+  const double H = v.H;
+  const double en = s.K * s.Tmu;
+  const double rem = dt - s.t;
+  double dts = rem;
+  const double aH = fabs(H), a1 = fabs((double)v.CH2), a2 = fabs((double)v.CHp);
+  if (aH > 0.0) dts = fmin(dts, eps * en / aH);
+  if (a1 > 0.0) dts = fmin(dts, eps / a1);
+  if (a2 > 0.0) dts = fmin(dts, eps / a2);
+  Eval<R> v2 =
+      evaluate<R, false, false>(R(Ta * (1.0 + delta)), s.nd, R(s.xH2), R(s.xHp), s.e, s.r, c, p, tab, s.tdg, nullptr);
+  const double dH = (v2.H - H) / (delta * s.Tmu);
+  double den = s.K - dts * dH;
+  if (den <= 0.1 * s.K) { den = s.K; s.st |= ISM_ST_DENOM_GUARD; }
+  if (v.td_bad || v2.td_bad) s.st |= ISM_ST_TD_UNBRACKETED;
+  double Tmu_new = s.Tmu + dts * H / den;
+  const double Tmu_min = a.pd.T_floor * mu_den / muH;
+  if (Tmu_new < Tmu_min) { Tmu_new = Tmu_min; s.st |= ISM_ST_T_FLOOR; }
+  // abundances: rate coefficients at T^{n+1} = mu^n T_mu^{n+1}, abundance factors frozen at step n
+  const double Tp = muH * Tmu_new / mu_den;
+  Eval<R> vc = evaluate<R, true, false>(R(Tp), s.nd, R(s.xH2), R(s.xHp), s.e, s.r, c, p, tab, s.tdg, nullptr);
+  const double F = vc.F, D = vc.D, I = vc.I, Rr = vc.Rr;
+  const double det = 1.0 + dts * (2.0 * F + D + I + Rr) + dts * dts * (2.0 * F * Rr + D * I + D * Rr);
+  const double xa = (s.xH2 * (1.0 + dts * (I + Rr)) + F * dts * (1.0 - s.xHp) + F * dts * dts * Rr) / det;
+  const double xb = (s.xHp * (1.0 + dts * (2.0 * F + D)) + I * dts * (1.0 - 2.0 * s.xH2) + I * dts * dts * D) / det;
+  s.e = eq_species<R>(R(Tp), R(s.nd), R(xa), R(xb), s.r, c, p, tab, CloseTol<R>::v, 50);
+  const bool fin = isfinite(Tmu_new) && isfinite(xa) && isfinite(xb);
+  if (!fin) s.st |= ISM_ST_NONFINITE;
+  const bool last = (dts == rem);
+  s.t = last ? dt : s.t + dts;
+  s.ns += 1;
+  const bool cap = (s.ns >= a.pd.max_sub) && !last;
+  if (cap) s.st |= ISM_ST_SUBSTEP_CAP;
+  s.Tmu = Tmu_new;
+  s.xH2 = xa;
+  s.xHp = xb;
+  return last || cap || !fin;
+}
+
+template <class R>
+__device__ __forceinline__ void cell_end(const StepArgs<R> &a, int64_t i, const CellState<R> &s) {
+  a.T[i] = a.pd.muH * s.Tmu / (1.1 + (double)s.e.xe - s.xH2);
+  a.xH2[i] = s.xH2;
+  a.xHp[i] = s.xHp;
+  if (a.xCp) a.xCp[i] = s.e.xCp;
+  if (a.xCO) a.xCO[i] = s.e.xCO;
+  if (a.xe) a.xe[i] = s.e.xe;
+  if (a.nsub) a.nsub[i] = s.ns;
+  if (a.status) a.status[i] = (uint8_t)s.st;
+}
+
+template <class R>
+__device__ __forceinline__ void stage_tables(const R *g, R *s_tab) {
+  for (int k = threadIdx.x; k < TAB_STEP; k += blockDim.x) s_tab[k] = g[k];
+  __syncthreads();
+}
+
+// One lane per cell, a plain 1-D grid.
+template <class R>
+__global__ __launch_bounds__(256) void step_simple_kernel(StepArgs<R> a) {
+  __shared__ R s_tab[TAB_STEP];
+  stage_tables(a.tab, s_tab);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.ncell) return;
+  CellState<R> s;
+  cell_begin(a, i, s, s_tab);
+  while (!cell_substep(a, s, s_tab)) {
+  }
+  cell_end(a, i, s);
+}
+
+// Per-cell diagnostics (ism_rates).
+template <class R>
+struct RatesArgs {
+  int64_t ncell;
+  const double *n, *T, *xH2, *xHp;
+  const R *chiPE, *chiLW, *chiH2, *chiC, *phi, *xi, *Neff;
+  R *out;
+  const R *tab;
+  ParT<R> pr;
+};
+
+template <class R>
+__global__ __launch_bounds__(128) void rates_kernel(RatesArgs<R> a) {
+  __shared__ R s_tab[TAB_STEP];
+  stage_tables(a.tab, s_tab);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.ncell) return;
+  const CoefT<R> &c = coef<R>();
+  Rad<R> r;
+  r.chiPE = a.chiPE[i];
+  r.chiLW = a.chiLW[i];
+  r.chiH2 = a.chiH2[i];
+  r.chiC = a.chiC[i];
+  r.phi = a.phi ? a.phi[i] : R(0);
+  r.xi = a.xi[i];
+  r.Neff = a.Neff[i];
+  const double nd = a.n[i];
+  const R T = R(a.T[i]), xH2 = R(a.xH2[i]), xHp = R(a.xHp[i]);
+  EqS<R> e = eq_species<R>(T, R(nd), xH2, xHp, r, c, a.pr, s_tab, CloseTol<R>::v, 50);
+  R d[NDIAG];
+  evaluate<R, false, true>(T, nd, xH2, xHp, e, r, c, a.pr, s_tab, R(0), d);
+#pragma unroll
+  for (int k = 0; k < NDIAG; ++k) a.out[(int64_t)k * a.ncell + i] = d[k];
+}
+
+}  // namespace ism

@@ -1,0 +1,208 @@
+"""Python binding of libism (include/ism.h): argument marshalling only.
+
+Every computation runs in the HIP library; torch provides device memory and the
+stream.  The binding raises if the built library is missing -- there is no CPU
+fallback.  Function names follow the C entry points without the ``ism_`` prefix.
+"""
+import ctypes
+import os
+from dataclasses import dataclass, fields
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+LIB_PATH = os.path.join(HERE, "libism.so")
+COEFF_PATH = os.path.join(ROOT, "data", "ism_coefficients.json")
+
+F64, MIXED = 0, 1
+
+ST_SUBSTEP_CAP, ST_NONFINITE, ST_T_FLOOR, ST_DENOM_GUARD, ST_FALLBACK, ST_TD_UNBRACKETED = 1, 2, 4, 8, 16, 32
+
+
+class IsmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ism error {code}: {msg}")
+        self.code = code
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("dx_cm", ctypes.c_double)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in ("Zg", "Zd", "chi0", "xi_cr0", "dvdr_kms_pc", "eps_sub", "fd_rel",
+                                                "T_floor", "T_bb", "tau_opt_ratio")] + \
+               [(k, ctypes.c_int32) for k in ("cr_mode", "kgr_const", "h2_rovib", "max_substeps")]
+
+
+@dataclass
+class Params:
+    """Mirror of ism_params (defaults of ism_params_default)."""
+    Zg: float = 1.0
+    Zd: float = 1.0
+    chi0: float = 1.0
+    xi_cr0: float = 2.0e-16
+    dvdr_kms_pc: float = 1.0
+    eps_sub: float = 0.1
+    fd_rel: float = 1.0e-3
+    T_floor: float = 1.0
+    T_bb: float = 6.0
+    tau_opt_ratio: float = 1.87
+    cr_mode: int = 0
+    kgr_const: int = 0
+    h2_rovib: int = 1
+    max_substeps: int = 100000
+
+    def _c(self):
+        return _Params(**{f.name: getattr(self, f.name) for f in fields(self)})
+
+
+_lib = None
+_inited = set()
+
+_vp, _dp, _i64, _i32 = ctypes.c_void_p, ctypes.c_double, ctypes.c_int64, ctypes.c_int32
+
+
+def lib():
+    """Load libism.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2210_08024_amd.build` "
+                              "(there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        L.ism_init.argtypes = [ctypes.c_int, ctypes.c_char_p]
+        L.ism_last_error.restype = ctypes.c_char_p
+        L.ism_ndiag.restype = _i32
+        L.ism_diag_name.argtypes = [_i32]
+        L.ism_diag_name.restype = ctypes.c_char_p
+        L.ism_params_default.argtypes = [ctypes.POINTER(_Params)]
+        L.ism_columns6.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Params), ctypes.c_int] + [_vp] * 10
+        L.ism_rates.argtypes = [ctypes.POINTER(_Params), ctypes.c_int, _i64] + [_vp] * 13
+        L.ism_chem_cool_step.argtypes = [ctypes.POINTER(_Params), ctypes.c_int, _i64, _dp] + [_vp] * 17
+        for name in ("ism_init", "ism_shutdown", "ism_columns6", "ism_rates", "ism_chem_cool_step"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return ["ism_params_default", "ism_init", "ism_shutdown", "ism_last_error", "ism_ndiag", "ism_diag_name",
+            "ism_columns6", "ism_rates", "ism_chem_cool_step"]
+
+
+def _check(rc):
+    if rc != 0:
+        raise IsmError(rc, lib().ism_last_error().decode())
+
+
+def init(device=None, path=COEFF_PATH):
+    """ism_init on `device` (default: torch's current device)."""
+    dev = torch.cuda.current_device() if device is None else int(device)
+    _check(lib().ism_init(dev, path.encode()))
+    _inited.add(dev)
+
+
+def _ensure_init(t):
+    dev = t.device.index if t.device.index is not None else torch.cuda.current_device()
+    if dev not in _inited:
+        init(dev)
+
+
+def _ptr(t, dtype, n=None, name="array", allow_none=False):
+    if t is None:
+        if allow_none:
+            return None
+        raise ValueError(f"{name} is required")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def _rdt(prec):
+    return torch.float64 if prec == F64 else torch.float32
+
+
+def ndiag():
+    return lib().ism_ndiag()
+
+
+def diag_names():
+    return [lib().ism_diag_name(k).decode() for k in range(ndiag())]
+
+
+def columns6(n, xH2, xC, dx_cm, params, prec=F64, out=None, stream=None):
+    """Six-ray columns on an [nz, ny, nx] grid.  Returns dict chi_PE, chi_LW, chi_H2, chi_C, N_eff, xi."""
+    _ensure_init(n)
+    nz, ny, nx = n.shape
+    N = n.numel()
+    rd = _rdt(prec)
+    if out is None:
+        out = {k: torch.empty_like(n, dtype=rd) for k in ("chi_PE", "chi_LW", "chi_H2", "chi_C", "N_eff", "xi")}
+    g = _Grid(nx, ny, nz, 0, float(dx_cm))
+    p = params._c()
+    _check(lib().ism_columns6(ctypes.byref(g), ctypes.byref(p), prec, _ptr(n, torch.float64, N, "n"),
+                              _ptr(xH2, torch.float64, N, "xH2"),
+                              _ptr(xC, torch.float64, N, "xC", allow_none=True),
+                              *[_ptr(out[k], rd, N, k) for k in ("chi_PE", "chi_LW", "chi_H2", "chi_C", "N_eff")],
+                              _ptr(out["xi"], rd, N, "xi", allow_none=True), _stream(stream)))
+    return out
+
+
+RAD_KEYS = ("chi_PE", "chi_LW", "chi_H2", "chi_C", "phi", "xi", "N_eff")
+
+
+def rates(n, T, xH2, xHp, rad, params, prec=F64, out=None, stream=None):
+    """Per-cell diagnostics [ndiag, ncell] (see diag_names())."""
+    _ensure_init(n)
+    N = n.numel()
+    rd = _rdt(prec)
+    if out is None:
+        out = torch.empty((ndiag(), N), dtype=rd, device=n.device)
+    p = params._c()
+    _check(lib().ism_rates(ctypes.byref(p), prec, N, _ptr(n, torch.float64, N, "n"), _ptr(T, torch.float64, N, "T"),
+                           _ptr(xH2, torch.float64, N, "xH2"), _ptr(xHp, torch.float64, N, "xHp"),
+                           _ptr(rad["chi_PE"], rd, N, "chi_PE"), _ptr(rad["chi_LW"], rd, N, "chi_LW"),
+                           _ptr(rad["chi_H2"], rd, N, "chi_H2"), _ptr(rad["chi_C"], rd, N, "chi_C"),
+                           _ptr(rad.get("phi"), rd, N, "phi", allow_none=True), _ptr(rad["xi"], rd, N, "xi"),
+                           _ptr(rad["N_eff"], rd, N, "N_eff"), _ptr(out, rd, None, "out"), _stream(stream)))
+    return out
+
+
+def chem_cool_step(n, T, xH2, xHp, rad, dt_s, params, prec=F64, want=("xCp", "xCO", "xe", "nsub", "status"),
+                   out=None, stream=None):
+    """In-place step of T, xH2, xHp (float64 device tensors).  Returns dict of the requested extra outputs."""
+    _ensure_init(n)
+    N = n.numel()
+    rd = _rdt(prec)
+    if out is None:
+        out = {}
+        for k in want:
+            dt = torch.int32 if k == "nsub" else (torch.uint8 if k == "status" else rd)
+            out[k] = torch.empty(N, dtype=dt, device=n.device)
+    p = params._c()
+    g = out.get
+    _check(lib().ism_chem_cool_step(
+        ctypes.byref(p), prec, N, float(dt_s), _ptr(n, torch.float64, N, "n"), _ptr(T, torch.float64, N, "T"),
+        _ptr(xH2, torch.float64, N, "xH2"), _ptr(xHp, torch.float64, N, "xHp"),
+        _ptr(rad["chi_PE"], rd, N, "chi_PE"), _ptr(rad["chi_LW"], rd, N, "chi_LW"),
+        _ptr(rad["chi_H2"], rd, N, "chi_H2"), _ptr(rad["chi_C"], rd, N, "chi_C"),
+        _ptr(rad.get("phi"), rd, N, "phi", allow_none=True), _ptr(rad["xi"], rd, N, "xi"),
+        _ptr(rad["N_eff"], rd, N, "N_eff"),
+        _ptr(g("xCp"), rd, N, "xCp", True), _ptr(g("xCO"), rd, N, "xCO", True), _ptr(g("xe"), rd, N, "xe", True),
+        _ptr(g("nsub"), torch.int32, N, "nsub", True), _ptr(g("status"), torch.uint8, N, "status", True),
+        _stream(stream)))
+    return out

@@ -1,0 +1,84 @@
+"""Shared test helpers: seeded inputs, oracle runs and the relative-error check."""
+import numpy as np
+
+from oracle import columns as ocol
+from oracle import constants as OC
+from oracle import step as ostep
+
+YR = OC.YR
+
+# |a - b| <= tol * max(|b|, floor): floors for near-zero abundances (x_H2, x_H+, x_e: absolute;
+# C-bearing species: relative to x_C,tot).
+FLOORS_F64 = dict(T=0.0, xH2=1e-10, xHp=1e-10, xe=1e-10, xCp=1e-10, xCO=1e-10)
+FLOORS_MIX = dict(T=0.0, xH2=1e-7, xHp=1e-7, xe=1e-7, xCp=1e-7, xCO=1e-7)
+
+
+def rel_err(a, b, floor=0.0):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.abs(a - b) / np.maximum(np.abs(b), floor)
+
+
+def check_fields(gpu, ref, tol, floors, xCt, fields=("T", "xH2", "xHp", "xe", "xCp", "xCO"), label=""):
+    report = {}
+    for k in fields:
+        fl = floors[k] * (xCt if k in ("xCp", "xCO") else 1.0)
+        e = rel_err(gpu[k], ref[k], fl)
+        report[k] = (float(e.max()), float(np.percentile(e, 99)))
+        bad = np.nonzero(e > tol)[0]
+        assert bad.size == 0, (f"{label} {k}: {bad.size} cells over {tol}; worst {e.max():.3e} at cell "
+                               f"{int(np.argmax(e))}: gpu {np.asarray(gpu[k])[np.argmax(e)]!r} "
+                               f"ref {np.asarray(ref[k])[np.argmax(e)]!r}")
+    return report
+
+
+def oracle_rad(state, dx_cm, par, xC=None):
+    r = ocol.columns6(state["n"], state["xH2"], xC, dx_cm, par)
+    N = state["n"].size
+    return dict(chi_PE=r["chi_PE"].ravel(), chi_LW=r["chi_LW"].ravel(), chi_H2=r["chi_H2"].ravel(),
+                chi_C=r["chi_C"].ravel(), phi=np.zeros(N), xi=r["xi"].ravel(), Neff=r["N_eff"].ravel())
+
+
+def oracle_step(state, rad, dt_s, par, idx=None):
+    sel = (lambda a: a.ravel()) if idx is None else (lambda a: a.ravel()[idx])
+    radi = {k: sel(v) for k, v in rad.items()}
+    return ostep.chem_cool_step(sel(state["n"]), sel(state["T"]), sel(state["xH2"]), sel(state["xHp"]), radi,
+                                dt_s, par)
+
+
+def to_dev(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a).ravel())
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def gpu_rad(rad, dtype):
+    return dict(chi_PE=to_dev(rad["chi_PE"], dtype), chi_LW=to_dev(rad["chi_LW"], dtype),
+                chi_H2=to_dev(rad["chi_H2"], dtype), chi_C=to_dev(rad["chi_C"], dtype),
+                phi=to_dev(rad["phi"], dtype), xi=to_dev(rad["xi"], dtype), N_eff=to_dev(rad["Neff"], dtype))
+
+
+def ism_params_from(par):
+    from paper_2210_08024_amd import ism
+    return ism.Params(Zg=par.Zg, Zd=par.Zd, chi0=par.chi0, xi_cr0=par.xi_cr0, cr_mode=par.cr_mode,
+                      kgr_const=par.kgr_const, h2_rovib=par.h2_rovib, eps_sub=par.eps_sub, fd_rel=par.fd_rel,
+                      max_substeps=par.max_substeps, T_floor=par.T_floor, T_bb=par.T_bb,
+                      tau_opt_ratio=par.tau_opt_ratio, dvdr_kms_pc=par.dvdr_kms_pc)
+
+
+def gpu_step(state, rad, dt_s, par, prec):
+    import torch
+    from paper_2210_08024_amd import ism
+    rd = torch.float64 if prec == ism.F64 else torch.float32
+    n = to_dev(state["n"])
+    T = to_dev(state["T"])
+    xH2 = to_dev(state["xH2"])
+    xHp = to_dev(state["xHp"])
+    out = ism.chem_cool_step(n, T, xH2, xHp, gpu_rad(rad, rd), dt_s, ism_params_from(par), prec)
+    torch.cuda.synchronize()
+    res = dict(T=T.cpu().numpy(), xH2=xH2.cpu().numpy(), xHp=xHp.cpu().numpy())
+    for k, v in out.items():
+        res[k] = v.cpu().numpy()
+    return res

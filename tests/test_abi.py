@@ -1,0 +1,98 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every symbol the
+header declares, and rejects bad arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2210_08024_amd import ism
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(ism_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    L = ism.lib()
+    decl = declared_functions()
+    assert "ism_chem_cool_step" in decl and "ism_columns6" in decl and "ism_rates" in decl
+    for name in decl:
+        assert hasattr(L, name), f"libism.so does not export {name}"
+
+
+def test_params_default_matches_binding_defaults():
+    p = ism._Params()
+    ism.lib().ism_params_default(ctypes.byref(p))
+    d = ism.Params()
+    for f, _ in ism._Params._fields_:
+        assert getattr(p, f) == getattr(d, f), f
+
+
+def test_param_struct_layout():
+    assert ctypes.sizeof(ism._Params) == 10 * 8 + 4 * 4
+    assert ctypes.sizeof(ism._Grid) == 24
+
+
+def test_diag_names():
+    names = ism.diag_names()
+    assert len(names) == ism.ndiag() == 39
+    assert names[0] == "xCp" and names[-1] == "C_Hp" and "Lambda" in names
+    assert ism.lib().ism_diag_name(99) is None
+
+
+def _bad(p=None, prec=0):
+    p = p or ism.Params()
+    cp = p._c()
+    rc = ism.lib().ism_chem_cool_step(ctypes.byref(cp), prec, 10, 1.0, *([None] * 17))
+    return rc, ism.lib().ism_last_error().decode()
+
+
+@pytest.mark.parametrize("field,value,msg", [("Zg", 0.0, "Zg"), ("Zd", -1.0, "Zd"), ("eps_sub", 0.0, "eps_sub"),
+                                             ("fd_rel", 0.7, "fd_rel"), ("cr_mode", 5, "cr_mode"),
+                                             ("max_substeps", 0, "max_substeps"), ("T_floor", 0.0, "T_floor")])
+def test_invalid_params_rejected_before_launch(field, value, msg):
+    p = ism.Params()
+    setattr(p, field, value)
+    rc, err = _bad(p)
+    assert rc == -1 and msg in err
+
+
+def test_invalid_precision_and_null_arrays():
+    rc, err = _bad(prec=7)
+    assert rc == -1 and "precision" in err
+    rc, err = _bad()
+    assert rc == -1 and "NULL" in err
+    cp = ism.Params()._c()
+    assert ism.lib().ism_chem_cool_step(ctypes.byref(cp), 0, -1, 1.0, *([None] * 17)) == -1
+    assert ism.lib().ism_chem_cool_step(ctypes.byref(cp), 0, 10, float("nan"), *([None] * 17)) == -1
+    # zero cells is a no-op that succeeds without touching the device
+    assert ism.lib().ism_chem_cool_step(ctypes.byref(cp), 0, 0, 1.0, *([None] * 17)) == 0
+
+
+def test_columns6_argument_checks():
+    cp = ism.Params()._c()
+    g = ism._Grid(0, 4, 4, 0, 1.0)
+    assert ism.lib().ism_columns6(ctypes.byref(g), ctypes.byref(cp), 0, *([None] * 10)) == -1
+    assert "grid" in ism.lib().ism_last_error().decode()
+    g = ism._Grid(4, 4, 4, 0, -1.0)
+    assert ism.lib().ism_columns6(ctypes.byref(g), ctypes.byref(cp), 0, *([None] * 10)) == -1
+    g = ism._Grid(4, 4, 4, 0, 1.0)
+    assert ism.lib().ism_columns6(ctypes.byref(g), ctypes.byref(cp), 0, *([None] * 10)) == -1
+    assert "NULL" in ism.lib().ism_last_error().decode()
+
+
+def test_init_rejects_missing_or_bad_coefficient_file(tmp_path):
+    assert ism.lib().ism_init(0, b"/nonexistent/coeffs.json") == -5
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"printed": {}, "standin": {}, "tables": {}}')
+    assert ism.lib().ism_init(0, str(bad).encode()) == -5
+    assert "missing coefficient" in ism.lib().ism_last_error().decode()

@@ -1,0 +1,280 @@
+"""Parity of the HIP path (through the C ABI) with the CPU FP64 oracle.
+
+Bar: plain FP64 path within 1e-9 relative of the oracle in T and every abundance;
+mixed FP32/FP64 path within 1e-3 relative, with hydrogen/carbon/oxygen closure held
+to 1e-6.  Near-zero abundances use the floors in helpers.py.
+"""
+import numpy as np
+import pytest
+
+import helpers as H
+from oracle import columns as ocol
+from oracle import constants as OC
+from oracle import micro as omicro
+from oracle.constants import Params
+
+pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
+
+
+@pytest.fixture(scope="module")
+def ism():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2210_08024_amd import ism as m
+    m.init()
+    return m
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+# ------------------------------------------------------------------ six-ray columns
+def _grid_case(shape, seed, xc=True):
+    rng = np.random.default_rng(seed)
+    n = 10 ** rng.uniform(-2, 3.5, shape)
+    xH2 = rng.uniform(0, 0.5, shape)
+    xC = rng.uniform(0, 1.6e-4, shape) if xc else None
+    return n, xH2, xC
+
+
+@pytest.mark.parametrize("shape,seed", [((16, 16, 16), 1), ((9, 5, 67), 2), ((3, 130, 7), 3), ((1, 1, 1), 4)])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_columns6_parity(ism, shape, seed, prec):
+    import torch
+    _print("columns6", shape, seed, prec)
+    n, xH2, xC = _grid_case(shape, seed)
+    par = Params(chi0=1.7, Zd=0.8, cr_mode=1)
+    dx = 2.0 * OC.PC
+    ref = ocol.columns6(n, xH2, xC, dx, par)
+    out = ism.columns6(H.to_dev(n).view(shape), H.to_dev(xH2).view(shape), H.to_dev(xC).view(shape), dx,
+                       H.ism_params_from(par), prec)
+    torch.cuda.synchronize()
+    tol = 1e-12 if prec == 0 else 2e-6
+    for k in ("chi_PE", "chi_LW", "chi_H2", "chi_C", "N_eff", "xi"):
+        g = out[k].cpu().numpy().astype(np.float64)
+        r = ref[k]
+        fl = 1e-30 if k != "N_eff" else 1e14     # N_eff is compared on a column scale for near-vacuum cells
+        e = H.rel_err(g, r, fl)
+        assert e.max() <= tol, (k, e.max(), np.unravel_index(np.argmax(e), shape))
+
+
+def test_columns6_vacuum_and_modes(ism):
+    import torch
+    shape = (4, 4, 4)
+    n = np.zeros(shape)
+    x = np.zeros(shape)
+    for mode in (0, 1, 2):
+        par = Params(chi0=2.5, cr_mode=mode, xi_cr0=3e-16)
+        xi = torch.full((64,), 7e-17, dtype=torch.float64, device="cuda").view(shape)
+        out = ism.columns6(H.to_dev(n).view(shape), H.to_dev(x).view(shape), None, OC.PC,
+                           H.ism_params_from(par), 0,
+                           out={k: torch.empty(shape, dtype=torch.float64, device="cuda") for k in
+                                ("chi_PE", "chi_LW", "chi_H2", "chi_C", "N_eff")} | {"xi": xi})
+        torch.cuda.synchronize()
+        assert torch.allclose(out["chi_PE"], torch.tensor(2.5, dtype=torch.float64, device="cuda"), rtol=1e-15)
+        expect_xi = 7e-17 if mode == 2 else 3e-16
+        assert torch.all(out["xi"] == expect_xi)
+
+
+# ------------------------------------------------------------------ rates
+def _random_states(N, seed):
+    rng = np.random.default_rng(seed)
+    n = 10 ** rng.uniform(-2, 4, N)
+    T = 10 ** rng.uniform(0.5, 7.5, N)
+    d = rng.dirichlet([1, 1, 1], N)
+    rad = dict(chi_PE=10 ** rng.uniform(-4, 3, N), chi_LW=10 ** rng.uniform(-4, 3, N),
+               chi_H2=10 ** rng.uniform(-6, 3, N), chi_C=10 ** rng.uniform(-6, 3, N),
+               phi=np.where(rng.uniform(size=N) < 0.3, 10 ** rng.uniform(0, 13, N), 0.0),
+               xi=10 ** rng.uniform(-17.5, -15, N), Neff=10 ** rng.uniform(18, 23, N))
+    return n, T, 0.5 * d[:, 0], d[:, 1], rad
+
+
+@pytest.mark.parametrize("kgr_const,rovib", [(0, 1), (1, 0)])
+def test_rates_parity_f64(ism, kgr_const, rovib):
+    import torch
+    _print("rates f64", kgr_const, rovib)
+    N = 3001
+    n, T, xH2, xHp, rad = _random_states(N, 11 + kgr_const)
+    par = Params(Zg=0.7, Zd=1.3, chi0=1.0, kgr_const=kgr_const, h2_rovib=rovib)
+    eq = omicro.eq_species(T, n, xH2, xHp, rad["chi_PE"], rad["chi_LW"], rad["chi_C"], rad["xi"], par)
+    ev = omicro.evaluate(T, n, xH2, xHp, eq, rad, par)
+    out = ism.rates(H.to_dev(n), H.to_dev(T), H.to_dev(xH2), H.to_dev(xHp), H.gpu_rad(rad, torch.float64),
+                    H.ism_params_from(par), 0).cpu().numpy()
+    names = ism.diag_names()
+    ref = dict(ev)
+    ref.update(eq)
+    worst = {}
+    for k, name in enumerate(names):
+        r = np.asarray(ref[name], dtype=np.float64) * np.ones(N)
+        e = H.rel_err(out[k], r, 1e-300)
+        e[(r == 0) & (out[k] == 0)] = 0.0
+        worst[name] = e.max()
+    # H = n Gamma - n^2 Lambda can cancel: compare it on the scale of its two terms
+    scale = np.maximum(n * np.abs(ev["Gamma"]), n * n * np.abs(ev["Lambda"]))
+    worst["H"] = (np.abs(out[names.index("H")] - ev["H"]) / scale).max()
+    bad = {k: v for k, v in worst.items() if not v <= 1e-9}
+    assert not bad, bad
+
+
+def test_rates_parity_mixed(ism):
+    import torch
+    N = 2048
+    n, T, xH2, xHp, rad = _random_states(N, 5)
+    par = Params()
+    eq = omicro.eq_species(T, n, xH2, xHp, rad["chi_PE"], rad["chi_LW"], rad["chi_C"], rad["xi"], par)
+    ev = omicro.evaluate(T, n, xH2, xHp, eq, rad, par)
+    out = ism.rates(H.to_dev(n), H.to_dev(T), H.to_dev(xH2), H.to_dev(xHp), H.gpu_rad(rad, torch.float32),
+                    H.ism_params_from(par), 1).cpu().numpy().astype(np.float64)
+    names = ism.diag_names()
+    for name in ("Gamma", "Lambda", "xe", "xCp", "Td", "C_H2", "C_Hp"):
+        r = np.asarray({**ev, **eq}[name]) * np.ones(N)
+        scale = np.abs(r)
+        if name in ("C_H2", "C_Hp"):
+            F = ev["F"] * np.maximum(1 - 2 * xH2 - xHp, 0) + ev["D"] * xH2 if name == "C_H2" else \
+                ev["I"] * np.maximum(1 - 2 * xH2 - xHp, 0) + ev["Rr"] * xHp
+            scale = np.abs(F)
+        fl = 1e-7 if name in ("xe",) else (1e-7 * 1.6e-4 if name == "xCp" else 1e-300)
+        e = np.abs(out[names.index(name)] - r) / np.maximum(scale, fl)
+        assert np.nanmax(e) < 2e-3, (name, np.nanmax(e))
+
+
+# ------------------------------------------------------------------ the step
+def _c0():
+    from paper_2210_08024_amd import workloads
+    s, cfg = workloads.make("tiny16")
+    par = Params(Zg=1.0, Zd=1.0, cr_mode=0)
+    rad = H.oracle_rad(s, cfg["dx_pc"] * OC.PC, par)
+    return s, rad, par, cfg["dt_yr"] * OC.YR
+
+
+@pytest.fixture(scope="module")
+def c0_oracle():
+    s, rad, par, dt = _c0()
+    return s, rad, par, dt, H.oracle_step(s, rad, dt, par)
+
+
+def test_step_parity_f64_small_grid(ism, c0_oracle):
+    _print("step f64 16^3")
+    s, rad, par, dt, ref = c0_oracle
+    g = H.gpu_step(s, rad, dt, par, ism.F64)
+    rep = H.check_fields(g, ref, 1e-9, H.FLOORS_F64, par.xCtot, label="f64 16^3")
+    _print("f64 16^3 max/p99 rel err", rep)
+    assert np.all(g["status"] == 0)
+    assert np.mean(g["nsub"] == ref["nsub"]) > 0.99
+    # closure: x_C = x_C,tot - x_C+ - x_CO >= 0, hydrogen 2 x_H2 + x_H+ <= 1
+    assert np.all(par.xCtot - g["xCp"] - g["xCO"] >= -1e-18)
+    assert np.all(2 * g["xH2"] + g["xHp"] <= 1 + 1e-15)
+
+
+def test_step_parity_mixed_small_grid(ism, c0_oracle):
+    _print("step mixed 16^3")
+    s, rad, par, dt, ref = c0_oracle
+    g = H.gpu_step(s, rad, dt, par, ism.MIXED)
+    rep = H.check_fields(g, ref, 1e-3, H.FLOORS_MIX, par.xCtot, label="mixed 16^3")
+    _print("mixed 16^3 max/p99 rel err", rep)
+    assert np.all(2 * g["xH2"] + g["xHp"] <= 1 + 1e-6)
+    assert np.all(par.xCtot - g["xCp"] - g["xCO"] >= -1e-6 * par.xCtot)
+    assert np.all(g["xCp"] >= 0) and np.all(g["xCO"] >= 0)
+
+
+def test_step_parity_f64_irradiated_ragged(ism):
+    """EUV-irradiated, strongly and weakly FUV-lit cells, ragged count, several Z'."""
+    _print("step f64 ragged EUV")
+    N = 999
+    n, T, xH2, xHp, rad = _random_states(N, 21)
+    T = np.clip(T, 10, 1e6)
+    n = np.clip(n, 1e-2, 1e3)
+    for Z in (0.1, 3.0):
+        par = Params(Zg=Z, Zd=Z)
+        s = dict(n=n, T=T, xH2=xH2, xHp=xHp)
+        ref = H.oracle_step(s, rad, 1e3 * OC.YR, par)
+        g = H.gpu_step(s, rad, 1e3 * OC.YR, par, ism.F64)
+        H.check_fields(g, ref, 1e-9, H.FLOORS_F64, par.xCtot, label=f"ragged Z={Z}")
+
+
+def test_step_edge_cases(ism):
+    _print("step edges")
+    par = Params()
+    s = dict(n=np.array([1.0]), T=np.array([5000.0]), xH2=np.array([0.1]), xHp=np.array([0.2]))
+    rad = {k: np.array([v]) for k, v in dict(chi_PE=1.0, chi_LW=1.0, chi_H2=0.3, chi_C=0.9, phi=0.0, xi=2e-16,
+                                                Neff=1e20).items()}
+    # dt = 0: one zero-length substep, state unchanged up to the T <-> T_mu round trip
+    g = H.gpu_step(s, rad, 0.0, par, ism.F64)
+    ref = H.oracle_step(s, rad, 0.0, par)
+    assert g["nsub"][0] == 1 and ref["nsub"][0] == 1
+    H.check_fields(g, ref, 1e-12, H.FLOORS_F64, par.xCtot, label="dt=0")
+    assert g["xH2"][0] == 0.1 and g["xHp"][0] == 0.2
+    # a single cell with a long step, and a dark cell (chi = 0)
+    for rr in (rad, {**rad, "chi_PE": np.array([0.0]), "chi_LW": np.array([0.0]), "chi_H2": np.array([0.0]),
+                      "chi_C": np.array([0.0])}):
+        g = H.gpu_step(s, rr, 1e7 * OC.YR, par, ism.F64)
+        ref = H.oracle_step(s, rr, 1e7 * OC.YR, par)
+        H.check_fields(g, ref, 1e-9, H.FLOORS_F64, par.xCtot, label="single")
+    # substep cap fires and is reported
+    pc = Params(max_substeps=2)
+    g = H.gpu_step(s, rad, 1e7 * OC.YR, pc, ism.F64)
+    ref = H.oracle_step(s, rad, 1e7 * OC.YR, pc)
+    assert g["status"][0] & ism.ST_SUBSTEP_CAP and ref["status"][0] & ism.ST_SUBSTEP_CAP
+    assert g["nsub"][0] == 2
+    H.check_fields(g, ref, 1e-9, H.FLOORS_F64, par.xCtot, label="cap")
+
+
+def test_step_deterministic(ism, c0_oracle):
+    s, rad, par, dt, _ = c0_oracle
+    a = H.gpu_step(s, rad, dt, par, ism.F64)
+    b = H.gpu_step(s, rad, dt, par, ism.F64)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
+# ------------------------------------------------------------------ full-size 128^3, sampled
+@pytest.fixture(scope="module")
+def grf128():
+    from paper_2210_08024_amd import workloads
+    s, cfg = workloads.make("grf128")
+    return s, cfg
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_end_to_end_128_sampled(ism, grf128, prec):
+    """Full 128^3 grid (4 pc cells, lognormal GRF density, CR attenuation): GPU columns6 + step
+    over the whole grid, the oracle on 600 sampled cells computed one by one."""
+    import torch
+    _print("end-to-end 128^3 prec", prec)
+    s, cfg = grf128
+    shape = s["n"].shape
+    par = Params(Zg=1.0, Zd=1.0, cr_mode=1)
+    dx = cfg["dx_pc"] * OC.PC
+    dt = cfg["dt_yr"] * OC.YR
+    rd = torch.float64 if prec == 0 else torch.float32
+    n = H.to_dev(s["n"])
+    T = H.to_dev(s["T"])
+    xH2 = H.to_dev(s["xH2"])
+    xHp = H.to_dev(s["xHp"])
+    rad = ism.columns6(n.view(shape), xH2.view(shape), None, dx, H.ism_params_from(par), prec)
+    radf = {k: v.view(-1) for k, v in rad.items()}
+    radf["phi"] = None
+    out = ism.chem_cool_step(n, T, xH2, xHp, radf, dt, H.ism_params_from(par), prec)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(99)
+    N = s["n"].size
+    idx = np.concatenate([rng.choice(N, 597, replace=False), [0, N - 1, N // 2]])
+    cells = np.stack(np.unravel_index(idx, shape), 1)
+    rc = ocol.columns6_cells(s["n"], s["xH2"], None, dx, par, cells)
+    for k, gk in (("chi_PE", "chi_PE"), ("chi_H2", "chi_H2"), ("N_eff", "N_eff"), ("xi", "xi")):
+        g = rad[gk].view(-1)[torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.float64)
+        tol = 1e-11 if prec == 0 else 2e-6
+        assert H.rel_err(g, rc[k], 1e14 if k == "N_eff" else 1e-30).max() < tol, k
+    radi = dict(chi_PE=rc["chi_PE"], chi_LW=rc["chi_LW"], chi_H2=rc["chi_H2"], chi_C=rc["chi_C"],
+                phi=np.zeros(len(idx)), xi=rc["xi"], Neff=rc["N_eff"])
+    ref = H.oracle_step(s, radi, dt, par, idx=idx)
+    tid = torch.from_numpy(idx).cuda()
+    g = dict(T=T[tid].cpu().numpy(), xH2=xH2[tid].cpu().numpy(), xHp=xHp[tid].cpu().numpy())
+    for k in ("xCp", "xCO", "xe"):
+        g[k] = out[k][tid].cpu().numpy()
+    tol, fl = (1e-9, H.FLOORS_F64) if prec == 0 else (1e-3, H.FLOORS_MIX)
+    rep = H.check_fields(g, ref, tol, fl, par.xCtot, label=f"128^3 prec {prec}")
+    _print("128^3 sampled max/p99 rel err", rep)
+    st = out["status"].cpu().numpy()
+    assert np.all(st == 0), np.bincount(st)

@@ -169,6 +169,25 @@ def test_three_level_limits():
     assert p1[0] == pytest.approx(1e-20 * (3.0 / 5.0) * np.exp(-227.7 / 100) / 8.91e-5, rel=1e-6)
 
 
+def test_three_level_vs_lapack():
+    """The closed form equals a LAPACK solve of the full balance + normalisation system."""
+    rng = np.random.default_rng(7)
+    T = 10 ** rng.uniform(1.5, 4, 50)
+    C10, C20, C21 = (10 ** rng.uniform(-8, -2, 50) for _ in range(3))
+    g, E, A = (5.0, 3.0, 1.0), (227.7, 326.6), (8.91e-5, 1.34e-10, 1.75e-5)
+    p = np.stack(micro._three_level(g, E, *A, C10, C20, C21, T), 1)
+    R01 = C10 * 3 / 5 * np.exp(-E[0] / T)
+    R02 = C20 * 1 / 5 * np.exp(-E[1] / T)
+    R12 = C21 * 1 / 3 * np.exp(-(E[1] - E[0]) / T)
+    R10, R20, R21 = C10 + A[0], C20 + A[1], C21 + A[2]
+    M = np.zeros((50, 3, 3))
+    M[:, 0] = np.stack([R01, -(R10 + R12), R21], 1)
+    M[:, 1] = np.stack([R02, R12, -(R20 + R21)], 1)
+    M[:, 2] = 1.0
+    ref = np.linalg.solve(M, np.tile([0.0, 0.0, 1.0], (50, 1))[..., None])[..., 0]
+    np.testing.assert_allclose(p, ref, rtol=1e-9, atol=1e-15)
+
+
 def test_table_interpolation_rule():
     axes, vals = C.standins().tables["cie"]
     ax = axes[0]
