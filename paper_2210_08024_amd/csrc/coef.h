@@ -26,6 +26,10 @@ constexpr int TAB_CS = TAB_CO + CO_NX * CO_NY * CO_NC;     // 794
 constexpr int CS_NX = 23, CS_NY = 29;
 constexpr int TAB_TOTAL = TAB_CS + CS_NX * CS_NY;          // 1461
 constexpr int TAB_STEP = TAB_CS;                           // CIE + CO, staged in LDS by the step
+// The device copies of the log10 cooling columns (CIE columns 0-1, CO column 0) hold
+// log10(value) + TAB_LOG_OFFSET; lookups multiply 10^(entry) by TAB_LOG_SCALE.
+constexpr double TAB_LOG_OFFSET = 24.0;
+constexpr double TAB_LOG_SCALE = 1e-24;
 
 template <class R>
 struct CoefT {
@@ -44,6 +48,8 @@ struct CoefT {
   R alpha_B[3], k_ci_H[3], k_cd_H[2], k_cd_H2[5], agr_Hp[7], agr_Cp[7], arrdr_Cp[3], k_CpH2[3], x_MH[4];
   R q_cr_H[3], q_cr_H2[8], k_H2_H[2], k_H2_H2[3], ff[2], rr_energy[2], grrec[4];
   R rovib_lte[11], rovib_low[7], cp_levels[4], cp_h2_over_h, c_levels[8], c_coll[5], o_levels[8], o_coll[5];
+  // ---- derived on the host after loading (logs of constants used inside exponents) ----
+  R ln_arrdr_T0, ln_xMH_T0, fs_slope_C, fs_slope_O, ln_lya_T, ln_co0;
   // ---- table axes ----
   R cie_x0, cie_dx;
   R co_x0, co_dx, co_y0, co_dy;
@@ -54,7 +60,7 @@ struct CoefT {
 template <class R>
 struct ParT {
   R Zg, Zd, chi0, dvdr, eps_sub, fd_rel, T_floor, T_bb, tau_ratio;
-  R xCt, xOt, muH;
+  R xCt, xOt, muH, lnZd;
   int32_t kgr_const, h2_rovib, max_sub, cr_mode;
 };
 

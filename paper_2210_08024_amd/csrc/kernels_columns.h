@@ -37,7 +37,8 @@ __device__ __forceinline__ double f_shld_H2(double N) {
   return c.fshld[0] / (u * u) + c.fshld[1] / s * ::exp(-c.fshld[2] * s);
 }
 
-__device__ __forceinline__ double f_shld_C(double NC, double NH2, const double *tab) {
+// cs: the C-shielding table itself ([CS_NX][CS_NY], log10 f), e.g. its LDS copy.
+__device__ __forceinline__ double f_shld_C(double NC, double NH2, const double *cs) {
   const CoefT<double> &c = g_coef64;
   const double lc = ::log10(NC > 1e-300 ? NC : 1e-300);
   const double lh = ::log10(NH2 > 1e-300 ? NH2 : 1e-300);
@@ -45,7 +46,7 @@ __device__ __forceinline__ double f_shld_C(double NC, double NH2, const double *
   double f, g;
   axis_pos(lc, c.cs_x0, c.cs_dx, CS_NX, i, f);
   axis_pos(lh, c.cs_y0, c.cs_dy, CS_NY, j, g);
-  const double *v = tab + TAB_CS;
+  const double *v = cs;
   const double v00 = v[i * CS_NY + j], v01 = v[i * CS_NY + j + 1];
   const double v10 = v[(i + 1) * CS_NY + j], v11 = v[(i + 1) * CS_NY + j + 1];
   return ::exp(LN10 * ((v00 * (1.0 - g) + v01 * g) * (1.0 - f) + (v10 * (1.0 - g) + v11 * g) * f));

@@ -8,13 +8,15 @@ namespace ism {
 __constant__ CoefT<double> g_coef64;
 __constant__ CoefT<float> g_coef32;
 
+__device__ __forceinline__ const CoefT<double> &coef64() { return g_coef64; }
+
 template <class R> __device__ __forceinline__ const CoefT<R> &coef();
 template <> __device__ __forceinline__ const CoefT<double> &coef<double>() { return g_coef64; }
 template <> __device__ __forceinline__ const CoefT<float> &coef<float>() { return g_coef32; }
 
 template <class R> struct CloseTol;
 template <> struct CloseTol<double> { static constexpr double v = 1e-12; };
-template <> struct CloseTol<float> { static constexpr float v = 1e-6f; };
+template <> struct CloseTol<float> { static constexpr float v = 2.5e-7f; };
 
 template <class R>
 struct StepArgs {
@@ -59,7 +61,7 @@ __device__ __forceinline__ void cell_begin(const StepArgs<R> &a, int64_t i, Cell
   s.xHp = a.xHp[i];
   const double muH = a.pd.muH;
   s.K = s.nd * muH * K_B / (g_coef64.gamma - 1.0);
-  s.e = eq_species<R>(R(T0), R(s.nd), R(s.xH2), R(s.xHp), s.r, c, a.pr, tab, CloseTol<R>::v, 50);
+  s.e = eq_species<R>(T0, R(s.nd), s.xH2, s.xHp, s.r, c, a.pr, tab, CloseTol<R>::v, 50);
   s.Tmu = T0 * (1.1 + (double)s.e.xe - s.xH2) / muH;
   s.t = 0.0;
   s.ns = 0;
@@ -75,7 +77,7 @@ __device__ __forceinline__ bool cell_substep(const StepArgs<R> &a, CellState<R> 
   const double muH = a.pd.muH, eps = a.pd.eps_sub, delta = a.pd.fd_rel, dt = a.dt;
   const double mu_den = 1.1 + (double)s.e.xe - s.xH2;
   const double Ta = muH * s.Tmu / mu_den;
-  Eval<R> v = evaluate<R, false, false>(R(Ta), s.nd, R(s.xH2), R(s.xHp), s.e, s.r, c, p, tab, s.tdg, nullptr);
+  Eval<R> v = evaluate<R, false, false>(Ta, s.nd, s.xH2, s.xHp, s.e, s.r, c, p, tab, s.tdg, nullptr);
   s.tdg = v.Td;
   const double H = v.H;
   const double en = s.K * s.Tmu;
@@ -86,7 +88,7 @@ __device__ __forceinline__ bool cell_substep(const StepArgs<R> &a, CellState<R> 
   if (a1 > 0.0) dts = fmin(dts, eps / a1);
   if (a2 > 0.0) dts = fmin(dts, eps / a2);
   Eval<R> v2 =
-      evaluate<R, false, false>(R(Ta * (1.0 + delta)), s.nd, R(s.xH2), R(s.xHp), s.e, s.r, c, p, tab, s.tdg, nullptr);
+      evaluate<R, false, false>(Ta * (1.0 + delta), s.nd, s.xH2, s.xHp, s.e, s.r, c, p, tab, s.tdg, nullptr);
   const double dH = (v2.H - H) / (delta * s.Tmu);
   double den = s.K - dts * dH;
   if (den <= 0.1 * s.K) { den = s.K; s.st |= ISM_ST_DENOM_GUARD; }
@@ -96,12 +98,12 @@ __device__ __forceinline__ bool cell_substep(const StepArgs<R> &a, CellState<R> 
   if (Tmu_new < Tmu_min) { Tmu_new = Tmu_min; s.st |= ISM_ST_T_FLOOR; }
   // abundances: rate coefficients at T^{n+1} = mu^n T_mu^{n+1}, abundance factors frozen at step n
   const double Tp = muH * Tmu_new / mu_den;
-  Eval<R> vc = evaluate<R, true, false>(R(Tp), s.nd, R(s.xH2), R(s.xHp), s.e, s.r, c, p, tab, s.tdg, nullptr);
+  Eval<R> vc = evaluate<R, true, false>(Tp, s.nd, s.xH2, s.xHp, s.e, s.r, c, p, tab, s.tdg, nullptr);
   const double F = vc.F, D = vc.D, I = vc.I, Rr = vc.Rr;
   const double det = 1.0 + dts * (2.0 * F + D + I + Rr) + dts * dts * (2.0 * F * Rr + D * I + D * Rr);
   const double xa = (s.xH2 * (1.0 + dts * (I + Rr)) + F * dts * (1.0 - s.xHp) + F * dts * dts * Rr) / det;
   const double xb = (s.xHp * (1.0 + dts * (2.0 * F + D)) + I * dts * (1.0 - 2.0 * s.xH2) + I * dts * dts * D) / det;
-  s.e = eq_species<R>(R(Tp), R(s.nd), R(xa), R(xb), s.r, c, p, tab, CloseTol<R>::v, 50);
+  s.e = eq_species<R>(Tp, R(s.nd), xa, xb, s.r, c, p, tab, CloseTol<R>::v, 50);
   const bool fin = isfinite(Tmu_new) && isfinite(xa) && isfinite(xb);
   if (!fin) s.st |= ISM_ST_NONFINITE;
   const bool last = (dts == rem);
@@ -174,7 +176,8 @@ __global__ __launch_bounds__(128) void rates_kernel(RatesArgs<R> a) {
   r.xi = a.xi[i];
   r.Neff = a.Neff[i];
   const double nd = a.n[i];
-  const R T = R(a.T[i]), xH2 = R(a.xH2[i]), xHp = R(a.xHp[i]);
+  const double T = a.T[i];
+  const double xH2 = a.xH2[i], xHp = a.xHp[i];
   EqS<R> e = eq_species<R>(T, R(nd), xH2, xHp, r, c, a.pr, s_tab, CloseTol<R>::v, 50);
   R d[NDIAG];
   evaluate<R, false, true>(T, nd, xH2, xHp, e, r, c, a.pr, s_tab, R(0), d);

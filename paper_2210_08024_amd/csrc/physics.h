@@ -1,6 +1,14 @@
-// Device microphysics of the ISM source step (Secs. 3-4 of arXiv:2210.08024),
-// templated on the evaluation type R (double: plain path, float: mixed path).
-// One lane evaluates one cell; nothing here touches memory except the LDS tables.
+// Device microphysics of the ISM source step (Secs. 3-4 of arXiv:2210.08024).
+//
+// One lane evaluates one cell.  Templated on R, the type the terms are formed and
+// stored in: double on the plain path, float on the mixed path.  On both paths the
+// temperature stays double and every exponent (E/T, p ln T, p ln psi, table values)
+// is formed in double; Mx<R>::ex turns a double exponent into an R result.  For float
+// that is a 2^k 2^f split with |f| <= 1/2 and the hardware exp2 on f only, so the
+// result carries ~1 float ulp whatever the size of the exponent; the algebra around
+// the transcendentals runs in R, and the few cancelling differences (x_H, x_O, the
+// fit polynomials) in double.  FP64 FMA issues at the FP32 rate on CDNA4, so the
+// double pieces cost little; what float saves are the transcendental sequences.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -8,62 +16,81 @@
 
 namespace ism {
 
-// ---------------------------------------------------------------- math wrappers
-// double: ROCm device libm; float: hardware transcendentals (v_exp_f32 / v_log_f32).
-__device__ __forceinline__ double m_exp(double x) { return ::exp(x); }
-__device__ __forceinline__ float m_exp(float x) { return __expf(x); }
-__device__ __forceinline__ double m_log(double x) { return ::log(x); }
-__device__ __forceinline__ float m_log(float x) { return __logf(x); }
-__device__ __forceinline__ double m_log10(double x) { return ::log10(x); }
-__device__ __forceinline__ float m_log10(float x) { return __log10f(x); }
-__device__ __forceinline__ double m_pow(double x, double y) { return ::pow(x, y); }
-__device__ __forceinline__ float m_pow(float x, float y) { return __powf(x, y); }
-__device__ __forceinline__ double m_sqrt(double x) { return ::sqrt(x); }
-__device__ __forceinline__ float m_sqrt(float x) { return __fsqrt_rn(x); }
-__device__ __forceinline__ double m_cbrt(double x) { return ::cbrt(x); }
-__device__ __forceinline__ float m_cbrt(float x) { return ::cbrtf(x); }
-__device__ __forceinline__ double m_expm1(double x) { return ::expm1(x); }
-__device__ __forceinline__ float m_expm1(float x) { return ::expm1f(x); }
-template <class R> __device__ __forceinline__ R m_pow10(R x) { return m_exp(R(LN10) * x); }
+// The double copy of the coefficients (constant memory, defined with the kernels).
+__device__ __forceinline__ const CoefT<double> &coef64();
+
+constexpr double LOG2E = 1.4426950408889634074;
+constexpr double LN2 = 0.69314718055994530942;
+constexpr double LN100 = 4.6051701859880913680;
+constexpr double LN1E3 = 6.9077552789821370520;
+constexpr double LN1E4 = 9.2103403719761827361;
+constexpr double LN10D = 2.3025850929940456840;
+
+// ---------------------------------------------------------------- math policies
+template <class R> struct Mx;
+
+template <> struct Mx<double> {
+  static __device__ __forceinline__ double ex(double x) { return ::exp(x); }
+  static __device__ __forceinline__ double ln(double x) { return ::log(x); }
+  static __device__ __forceinline__ double sq(double x) { return ::sqrt(x); }
+  static __device__ __forceinline__ double cb(double x) { return ::cbrt(x); }
+};
+
+template <> struct Mx<float> {
+  // exp of a double exponent: x log2(e) = k + f, |f| <= 1/2, result 2^f (hardware) scaled by 2^k.
+  static __device__ __forceinline__ float ex(double x) {
+    double y = x * LOG2E;
+    y = y < -200.0 ? -200.0 : (y > 200.0 ? 200.0 : y);
+    const double k = ::rint(y);
+    const float r = __builtin_amdgcn_exp2f((float)(y - k));
+    return ::ldexpf(r, (int)k);
+  }
+  // natural log as a double: exponent from frexp, mantissa in [0.5, 1) through the hardware log2.
+  static __device__ __forceinline__ double ln(double x) {
+    const int e = __builtin_amdgcn_frexp_exp(x);
+    const float m = (float)__builtin_amdgcn_frexp_mant(x);
+    return ((double)e + (double)__builtin_amdgcn_logf(m)) * LN2;
+  }
+  static __device__ __forceinline__ float sq(float x) { return __fsqrt_rn(x); }
+  static __device__ __forceinline__ float cb(float x) { return ::cbrtf(x); }
+};
+
 template <class R> __device__ __forceinline__ R rmax(R a, R b) { return a > b ? a : b; }
 template <class R> __device__ __forceinline__ R rmin(R a, R b) { return a < b ? a : b; }
 
-template <class R> struct Tiny;
-template <> struct Tiny<double> { static constexpr double v = 1e-300; };
-template <> struct Tiny<float> { static constexpr float v = 1e-37f; };
-
 // ---------------------------------------------------------------- tables
-// Clamp x to the grid [x0, x0 + (n-1) dx]; lower node index and fraction.
-template <class R>
-__device__ __forceinline__ void axis_pos(R x, R x0, R dx, int n, int &i, R &f) {
-  R hi = x0 + R(n - 1) * dx;
-  R xc = x < x0 ? x0 : (x > hi ? hi : x);
-  R u = (xc - x0) / dx;
+// Clamp x to the grid [x0, x0 + (n-1) dx]; lower node index and fraction (in double).
+__device__ __forceinline__ void axis_pos(double x, double x0, double dx, int n, int &i, double &f) {
+  const double hi = x0 + (double)(n - 1) * dx;
+  const double xc = x < x0 ? x0 : (x > hi ? hi : x);
+  const double u = (xc - x0) / dx;
   int k = (int)floor(u);
   k = k > 0 ? k : 0;  // also maps a NaN argument to node 0
   i = k < n - 2 ? k : n - 2;
-  f = u - R(i);
+  f = u - (double)i;
 }
 
 template <class R>
-__device__ __forceinline__ R cie_lookup(const R *tab, const CoefT<R> &c, R lgT, int col) {
+__device__ __forceinline__ double cie_lookup(const R *tab, double lgT, int col) {
+  const CoefT<double> &c = coef64();
   int i;
-  R f;
+  double f;
   axis_pos(lgT, c.cie_x0, c.cie_dx, CIE_N, i, f);
   const R *v = tab + TAB_CIE;
-  return v[i * CIE_NC + col] * (R(1) - f) + v[(i + 1) * CIE_NC + col] * f;
+  return (double)v[i * CIE_NC + col] * (1.0 - f) + (double)v[(i + 1) * CIE_NC + col] * f;
 }
 
 template <class R>
-__device__ __forceinline__ R co_lookup(const R *tab, const CoefT<R> &c, R lT, R lN, int col) {
+__device__ __forceinline__ double co_lookup(const R *tab, double lT, double lN, int col) {
+  const CoefT<double> &c = coef64();
   int i, j;
-  R f, g;
+  double f, g;
   axis_pos(lT, c.co_x0, c.co_dx, CO_NX, i, f);
   axis_pos(lN, c.co_y0, c.co_dy, CO_NY, j, g);
   const R *v = tab + TAB_CO;
-  R v00 = v[(i * CO_NY + j) * CO_NC + col], v01 = v[(i * CO_NY + j + 1) * CO_NC + col];
-  R v10 = v[((i + 1) * CO_NY + j) * CO_NC + col], v11 = v[((i + 1) * CO_NY + j + 1) * CO_NC + col];
-  return (v00 * (R(1) - g) + v01 * g) * (R(1) - f) + (v10 * (R(1) - g) + v11 * g) * f;
+  const double v00 = v[(i * CO_NY + j) * CO_NC + col], v01 = v[(i * CO_NY + j + 1) * CO_NC + col];
+  const double v10 = v[((i + 1) * CO_NY + j) * CO_NC + col], v11 = v[((i + 1) * CO_NY + j + 1) * CO_NC + col];
+  return (v00 * (1.0 - g) + v01 * g) * (1.0 - f) + (v10 * (1.0 - g) + v11 * g) * f;
 }
 
 // ---------------------------------------------------------------- per-cell inputs
@@ -85,48 +112,44 @@ struct Eval {
   bool td_bad;
 };
 
-// ---------------------------------------------------------------- rate coefficients
+// Temperature-derived quantities shared by every term of one evaluation.
+struct Tq {
+  double T, lnT, invT, lnT4;
+};
+
 template <class R>
-__device__ __forceinline__ R k_gr(R T, const CoefT<R> &c, const ParT<R> &p) {
+__device__ __forceinline__ Tq make_tq(double T) {
+  Tq q;
+  q.T = T;
+  q.lnT = Mx<R>::ln(T);
+  q.invT = 1.0 / T;
+  q.lnT4 = q.lnT - LN1E4;
+  return q;
+}
+
+// ---------------------------------------------------------------- rate coefficients (Sec. 3)
+template <class R>
+__device__ __forceinline__ R k_gr(const Tq &q, const CoefT<R> &c, const ParT<R> &p) {
   if (p.kgr_const) return c.kgr0 * p.Zd;
-  R T2 = T / R(100);
-  R s = m_sqrt(T2);
+  const R T2 = R(q.T * 0.01);
+  const R s = Mx<R>::sq(T2);
   return c.kgr0 * p.Zd * c.kgr_shape[0] * s /
          (R(1) + c.kgr_shape[1] * s + c.kgr_shape[2] * T2 + c.kgr_shape[3] * T2 * T2);
 }
 
+// Grain-assisted recombination 1e-14 C0 Z'_d / (1 + C1 psi^C2 (1 + C3 T^C4 psi^(-C5 - C6 ln T))).
 template <class R>
-__device__ __forceinline__ R alpha_B(R T, const CoefT<R> &c) {
-  R T4 = T / R(1e4);
-  return c.alpha_B[0] * m_pow(T4, c.alpha_B[1] + c.alpha_B[2] * m_log(T4));
+__device__ __forceinline__ R alpha_gr(const Tq &q, double lnpsi, const double *k, R Zd) {
+  const R a = Mx<R>::ex(k[2] * lnpsi);
+  const R b = Mx<R>::ex(k[4] * q.lnT + (-k[5] - k[6] * q.lnT) * lnpsi);
+  return R(1e-14 * k[0]) * Zd / (R(1) + R(k[1]) * a * (R(1) + R(k[3]) * b));
 }
 
+// Grain charging parameter G0 T^1/2 / n_e + 50 (Sec. 4.1.1), n_e floored at 1e-20 n.
 template <class R>
-__device__ __forceinline__ R k_ci_H(R T, const CoefT<R> &c) {
-  return c.k_ci_H[0] * m_sqrt(T) * m_exp(-c.k_ci_H[1] / T) / (R(1) + m_sqrt(T / c.k_ci_H[2]));
-}
-
-template <class R>
-__device__ __forceinline__ R k_cd_H(R T, const CoefT<R> &c) {
-  return c.k_cd_H[0] * m_sqrt(T) * m_exp(-(R(1) + c.k_cd_H[1] / T));
-}
-
-template <class R>
-__device__ __forceinline__ R k_cd_H2(R T, const CoefT<R> &c) {
-  return c.k_cd_H2[0] * m_pow(T, c.k_cd_H2[1]) * m_pow(R(1) + c.k_cd_H2[2] * T, -c.k_cd_H2[3]) *
-         m_exp(-c.k_cd_H2[4] / T);
-}
-
-template <class R>
-__device__ __forceinline__ R alpha_gr(R T, R psi, const R *k, R Zd) {
-  return R(1e-14) * k[0] * Zd /
-         (R(1) + k[1] * m_pow(psi, k[2]) * (R(1) + k[3] * m_pow(T, k[4]) * m_pow(psi, -k[5] - k[6] * m_log(T))));
-}
-
-template <class R>
-__device__ __forceinline__ R psi_charge(R T, R n, R xe, R chiPE, R chiLW, const CoefT<R> &c) {
-  R G0 = c.G0_per_chi * ((c.J_PE * chiPE + c.J_LW * chiLW) / c.J_FUV);
-  return G0 * m_sqrt(T) / (n * rmax(xe, R(1e-20))) + c.psi_off;
+__device__ __forceinline__ R psi_charge(R sqrtT, R n, R xe, R chiPE, R chiLW, const CoefT<R> &c) {
+  const R G0 = c.G0_per_chi * ((c.J_PE * chiPE + c.J_LW * chiLW) / c.J_FUV);
+  return G0 * sqrtT / (n * rmax(xe, R(1e-20))) + c.psi_off;
 }
 
 // ---------------------------------------------------------------- C / O / e closure
@@ -134,48 +157,56 @@ __device__ __forceinline__ R psi_charge(R T, R n, R xe, R chiPE, R chiLW, const 
 // (positive root of the quadratic, psi iterated to a fixed point in x_e) below 2e4 K,
 // Eq. e:xELhot above; CO from Eqs. e:CO, e:CO_fit with chi_CO = chi_LW.
 template <class R>
-__device__ EqS<R> eq_species(R T, R n, R xH2, R xHp, const Rad<R> &r, const CoefT<R> &c, const ParT<R> &p,
-                             const R *tab, R tol, int maxit) {
+__device__ EqS<R> eq_species(double T, R n, double xH2_d, double xHp_d, const Rad<R> &r, const CoefT<R> &c,
+                             const ParT<R> &p, const R *tab, R tol, int maxit) {
+  const CoefT<double> &cd = coef64();
   EqS<R> e;
+  const Tq q = make_tq<R>(T);
+  const R xH2 = R(xH2_d), xHp = R(xHp_d);
+  const R sqrtT = Mx<R>::sq(R(T));
   const R xCt = p.xCt, xOt = p.xOt, Zd = p.Zd;
   e.xOp = xOt * xHp;
   const R a = c.zeta_pi_C * r.chiC + c.zeta_pi_C_cr * R(2) * xH2 * r.xi + c.zeta_cr_C * r.xi;
-  const R cc = c.arrdr_Cp[0] * m_pow(T / c.arrdr_Cp[1], c.arrdr_Cp[2]) * n;
-  const R kch = c.k_CpH2[0] * m_pow(T, c.k_CpH2[1]) * m_exp(-c.k_CpH2[2] / T) * n * xH2;
+  const R cc = R(cd.arrdr_Cp[0]) * Mx<R>::ex(cd.arrdr_Cp[2] * (q.lnT - cd.ln_arrdr_T0)) * n;
+  const R kch = R(cd.k_CpH2[0]) * Mx<R>::ex(cd.k_CpH2[1] * q.lnT - cd.k_CpH2[2] * q.invT) * n * xH2;
   R y, xe;
-  if (T >= c.xe_T_switch) {
-    R lgT = m_log10(T);
-    xe = xHp + cie_lookup(tab, c, lgT, 2) + p.Zg * cie_lookup(tab, c, lgT, 3);
-    R psi = psi_charge(T, n, xe, r.chiPE, r.chiLW, c);
-    R B = alpha_gr(T, psi, c.agr_Cp, Zd) * n + kch;
-    R dh = a + B + cc * xe;
+  if (T >= cd.xe_T_switch) {
+    const double lgT = q.lnT / LN10D;
+    xe = xHp + R(cie_lookup(tab, lgT, 2)) + p.Zg * R(cie_lookup(tab, lgT, 3));
+    const R psi = psi_charge(sqrtT, n, xe, r.chiPE, r.chiLW, c);
+    const R B = alpha_gr<R>(q, Mx<R>::ln((double)psi), cd.agr_Cp, Zd) * n + kch;
+    const R dh = a + B + cc * xe;
     y = a > R(0) ? xCt * a / (dh > R(0) ? dh : R(1)) : R(0);
   } else {
-    const R xmh = R(2) * xH2 * m_sqrt(c.x_MH[0] * r.xi / (c.x_MH[1] * m_pow(T / c.x_MH[2], c.x_MH[3]) * n));
+    const R amh = R(cd.x_MH[1]) * Mx<R>::ex(cd.x_MH[3] * (q.lnT - cd.ln_xMH_T0));
+    const R xmh = R(2) * xH2 * Mx<R>::sq(c.x_MH[0] * r.xi / (amh * n));
     const R xe0 = xHp + e.xOp + xmh;
     xe = xe0 + xCt;
     y = R(0);
     for (int it = 0; it < maxit; ++it) {
-      R psi = psi_charge(T, n, xe, r.chiPE, r.chiLW, c);
-      R B = alpha_gr(T, psi, c.agr_Cp, Zd) * n + kch;
-      R pp = a + B + cc * xe0;
-      R den = pp + m_sqrt(pp * pp + R(4) * cc * xCt * a);
+      const R psi = psi_charge(sqrtT, n, xe, r.chiPE, r.chiLW, c);
+      const R B = alpha_gr<R>(q, Mx<R>::ln((double)psi), cd.agr_Cp, Zd) * n + kch;
+      const R pp = a + B + cc * xe0;
+      const R den = pp + Mx<R>::sq(pp * pp + R(4) * cc * xCt * a);
       y = a > R(0) ? R(2) * xCt * a / (den > R(0) ? den : R(1)) : R(0);
-      R xn = xe0 + y;
-      bool conv = fabs(xn - xe) <= tol * xn;
+      const R xn = xe0 + y;
+      const bool conv = fabs(xn - xe) <= tol * xn;
       xe = xn;
       if (conv) break;
     }
   }
   e.xCp = y;
   e.xe = xe;
-  R xi16 = rmax(r.xi / R(1e-16), R(1e-10));
-  R ncrit = m_pow(c.co_fit[0] * Zd / (xi16 * xi16), m_cbrt(r.chiLW)) * (c.co_fit[1] * xi16 / m_pow(Zd, c.co_fit[2]));
-  R frac = rmax(y / xCt, xHp);
-  R q = ncrit / n;
-  e.xCO = xCt * R(2) * xH2 * (R(1) - frac) / (R(1) + q * q);
+  const R xi16 = rmax(r.xi / R(1e-16), R(1e-10));
+  const double lxi = Mx<R>::ln((double)xi16);
+  // n_CO,crit = (4e3 Z'_d xi16^-2)^(chi^1/3) (50 xi16 / Z'_d^1.4)
+  const R ncrit = Mx<R>::ex((double)Mx<R>::cb(r.chiLW) * (cd.ln_co0 + (double)p.lnZd - 2.0 * lxi)) *
+                  (c.co_fit[1] * xi16 / Mx<R>::ex(cd.co_fit[2] * (double)p.lnZd));
+  const R frac = rmax(y / xCt, xHp);
+  const R qq = ncrit / n;
+  e.xCO = xCt * R(2) * xH2 * (R(1) - frac) / (R(1) + qq * qq);
   e.xC = xCt - y - e.xCO;
-  e.xO = xOt - e.xCO - e.xOp;
+  e.xO = R((double)xOt * (1.0 - xHp_d)) - e.xCO;  // x_O,tot - x_O+ formed in double (x_H+ -> 1)
   return e;
 }
 
@@ -187,10 +218,11 @@ __device__ EqS<R> eq_species(R T, R n, R xH2, R xHp, const Rad<R> &r, const Coef
 template <class R>
 __device__ __forceinline__ R dust_heating_per_Zd(const Rad<R> &r, const CoefT<R> &c, const ParT<R> &p) {
   const R fourpi = R(12.566370614359172954);
-  R uv = fourpi * (c.sig_d_abs[2] * c.J_PE * r.chiPE + c.sig_d_abs[1] * c.J_LW * r.chiLW) +
-         c.sig_d_abs[0] * r.phi * (c.hnu_LyC_eV * R(EV));
-  R tau = c.sig_d_Neff * p.Zd * r.Neff;
-  R opt = fourpi * (c.sig_d_abs[2] * c.J_PE + c.sig_d_abs[1] * c.J_LW) * p.chi0 * m_exp(-tau / p.tau_ratio);
+  const R uv = fourpi * (c.sig_d_abs[2] * c.J_PE * r.chiPE + c.sig_d_abs[1] * c.J_LW * r.chiLW) +
+               c.sig_d_abs[0] * r.phi * (c.hnu_LyC_eV * R(EV));
+  const R tau = c.sig_d_Neff * p.Zd * r.Neff;
+  const R opt = fourpi * (c.sig_d_abs[2] * c.J_PE + c.sig_d_abs[1] * c.J_LW) * p.chi0 *
+                Mx<R>::ex(-(double)tau / (double)p.tau_ratio);
   return uv + opt;
 }
 
@@ -199,24 +231,28 @@ template <> struct RootTol<double> { static constexpr double v = 1e-14; static c
 template <> struct RootTol<float> { static constexpr float v = 2e-7f; static constexpr int it = 40; };
 
 template <class R>
-__device__ R dust_T(R T, R n, R G, R guess, const CoefT<R> &c, const ParT<R> &p, bool &bad) {
+__device__ R dust_T(R T, R sqrtT, R n, R G, R guess, const CoefT<R> &c, const ParT<R> &p, bool &bad) {
   const R A = c.sigma_IR10 / R(100) * R(C_LIGHT) * c.a_rad;
-  const R B = n * c.alpha_gd * m_sqrt(T);
+  const R B = n * c.alpha_gd * sqrtT;
   const R Tbb2 = p.T_bb * p.T_bb, Tbb4 = Tbb2 * Tbb2;
   const R rhs = G + B * T;
   R lo = rmin(p.T_bb, T), hi = R(1e4);
-  R h2 = hi * hi;
+  const R h2 = hi * hi;
   if (A * h2 * (h2 * h2 - Tbb4) + B * hi - rhs < R(0)) { bad = true; return hi; }
   bad = false;
-  R x = (guess > lo && guess < hi) ? guess : R(0.5) * (lo + hi);
+  R x = guess;
+  if (!(x > lo && x < hi)) {  // cold start: radiative-equilibrium estimate (rhs / A)^(1/6)
+    x = Mx<R>::ex(Mx<R>::ln((double)(rhs / A)) / 6.0);
+    if (!(x > lo && x < hi)) x = R(0.5) * (lo + hi);
+  }
   for (int it = 0; it < RootTol<R>::it; ++it) {
-    R x2 = x * x;
-    R g = A * x2 * (x2 * x2 - Tbb4) + B * x - rhs;
+    const R x2 = x * x;
+    const R g = A * x2 * (x2 * x2 - Tbb4) + B * x - rhs;
     if (g >= R(0)) hi = x; else lo = x;
-    R dg = A * (R(6) * x2 * x2 * x - R(2) * Tbb4 * x) + B;
+    const R dg = A * (R(6) * x2 * x2 * x - R(2) * Tbb4 * x) + B;
     R xn = x - g / dg;
     if (!(xn > lo && xn < hi)) xn = R(0.5) * (lo + hi);
-    R dx = fabs(xn - x);
+    const R dx = fabs(xn - x);
     x = xn;
     if (dx <= RootTol<R>::v * x || hi - lo <= RootTol<R>::v * x) break;
   }
@@ -224,26 +260,29 @@ __device__ R dust_T(R T, R n, R G, R guess, const CoefT<R> &c, const ParT<R> &p,
 }
 
 // ---------------------------------------------------------------- fine structure (Sec. 4.2.2)
+// 3-level atom (levels 0, 1, 2); H-impact de-excitation k10 follows the printed critical
+// densities as a power law in T (slope precomputed on the host), other partners and
+// transitions are stand-in ratios.  Populations by Cramer's rule with p0 = 1, normalised.
 template <class R>
-__device__ __forceinline__ R three_level_cool(R T, R n, R xH, R xH2, R xe, const R *lv, const R *co, const R *nc,
-                                              const CoefT<R> &c) {
-  const R g0 = lv[0], g1 = lv[1], g2 = lv[2], E1 = lv[3], E2 = lv[4], A10 = lv[5], A20 = lv[6], A21 = lv[7];
-  const R s = m_log(nc[0] / nc[1]) / m_log(R(500));
-  R kH = (A10 / nc[0]) * m_pow(T / R(10), s);
-  R ke = co[3] * m_pow(T / R(1e4), co[4]);
-  R part = xH * kH + xH2 * co[2] * kH + xe * ke;
-  R C10 = n * part, C20 = n * co[0] * part, C21 = n * co[1] * part;
-  R R01 = C10 * (g1 / g0) * m_exp(-E1 / T);
-  R R02 = C20 * (g2 / g0) * m_exp(-E2 / T);
-  R R12 = C21 * (g2 / g1) * m_exp(-(E2 - E1) / T);
-  R R10 = C10 + A10, R20 = C20 + A20, R21 = C21 + A21;
-  R det = R10 * R20 + R10 * R21 + R12 * R20;
+__device__ __forceinline__ R three_level_cool(const Tq &q, R n, R xH, R xH2, R xe, const double *lv,
+                                              const double *co, const double *nc, double slope) {
+  const R g0 = R(lv[0]), g1 = R(lv[1]), g2 = R(lv[2]), A10 = R(lv[5]), A20 = R(lv[6]), A21 = R(lv[7]);
+  const double E1 = lv[3], E2 = lv[4];
+  const R kH = R(lv[5] / nc[0]) * Mx<R>::ex(slope * (q.lnT - LN10D));
+  const R ke = R(co[3]) * Mx<R>::ex(co[4] * q.lnT4);
+  const R part = xH * kH + xH2 * R(co[2]) * kH + xe * ke;
+  const R C10 = n * part, C20 = n * R(co[0]) * part, C21 = n * R(co[1]) * part;
+  const R R01 = C10 * (g1 / g0) * Mx<R>::ex(-E1 * q.invT);
+  const R R02 = C20 * (g2 / g0) * Mx<R>::ex(-E2 * q.invT);
+  const R R12 = C21 * (g2 / g1) * Mx<R>::ex(-(E2 - E1) * q.invT);
+  const R R10 = C10 + A10, R20 = C20 + A20, R21 = C21 + A21;
+  const R det = R10 * R20 + R10 * R21 + R12 * R20;
   R p1 = (R01 * (R20 + R21) + R21 * R02) / det;
   R p2 = (R02 * (R10 + R12) + R12 * R01) / det;
-  R sum = R(1) + p1 + p2;
+  const R sum = R(1) + p1 + p2;
   p1 /= sum;
   p2 /= sum;
-  return (p1 * A10 * E1 + p2 * (A20 * E2 + A21 * (E2 - E1))) * R(K_B) / n;
+  return (p1 * A10 * R(E1) + p2 * (A20 * R(E2) + A21 * R(E2 - E1))) * R(K_B) / n;
 }
 
 // ---------------------------------------------------------------- diagnostics layout
@@ -259,28 +298,38 @@ enum Diag {
 // abundances (xH2, xHp) and closure e.  CHEM_ONLY skips heating/cooling; DIAG writes
 // every term into diag[NDIAG].
 template <class R, bool CHEM_ONLY, bool DIAG>
-__device__ Eval<R> evaluate(R T, double n_d, R xH2, R xHp, const EqS<R> &e, const Rad<R> &r, const CoefT<R> &c,
-                            const ParT<R> &p, const R *tab, R td_guess, R *diag) {
+__device__ Eval<R> evaluate(double T, double n_d, double xH2_d, double xHp_d, const EqS<R> &e, const Rad<R> &r,
+                            const CoefT<R> &c, const ParT<R> &p, const R *tab, R td_guess, R *diag) {
+  const CoefT<double> &cd = coef64();
   Eval<R> v;
+  const Tq q = make_tq<R>(T);
+  const R Tr = R(T);
+  const R sqrtT = Mx<R>::sq(Tr);
   const R n = R(n_d);
   const R Zd = p.Zd, Zg = p.Zg;
   const R xe = e.xe;
-  R xH = R(1) - R(2) * xH2 - xHp;
-  xH = xH > R(0) ? xH : R(0);
-  const R psi = psi_charge(T, n, xe, r.chiPE, r.chiLW, c);
+  const R xH2 = R(xH2_d), xHp = R(xHp_d);
+  // x_H = 1 - 2 x_H2 - x_H+ cancels when hydrogen is nearly all molecular or ionised: formed in double
+  const double xHd = 1.0 - 2.0 * xH2_d - xHp_d;
+  const R xH = R(xHd > 0.0 ? xHd : 0.0);
+  const R psi = psi_charge(sqrtT, n, xe, r.chiPE, r.chiLW, c);
+  const double lnpsi = Mx<R>::ln((double)psi);
   // chemistry, Eqs. e:HH and e:HII
-  const R kgr = k_gr(T, c, p);
+  const R kgr = k_gr(q, c, p);
   const R zcrH2 = c.cr_coef[0] * r.xi * (c.cr_coef[1] * xH2 + c.cr_coef[2] * xH);
   const R zcrH = R(0.5) * zcrH2;
   const R zpd = c.zeta_pd * r.chiH2;
   const R zpiH2 = c.sig_pi_H2 * r.phi;
   const R zpiH = c.sig_pi_H * r.phi;
-  const R kcdH = k_cd_H(T, c), kcdH2 = k_cd_H2(T, c);
+  const R kcdH = c.k_cd_H[0] * sqrtT * Mx<R>::ex(-(1.0 + cd.k_cd_H[1] * q.invT));
+  // power laws and the Boltzmann factor in one exponent
+  const R kcdH2 = c.k_cd_H2[0] * Mx<R>::ex(cd.k_cd_H2[1] * q.lnT - cd.k_cd_H2[3] * Mx<R>::ln(1.0 + cd.k_cd_H2[2] * T) -
+                                           cd.k_cd_H2[4] * q.invT);
   const R zcd = n * (xH * kcdH + xH2 * kcdH2);
-  const R kci = k_ci_H(T, c);
+  const R kci = c.k_ci_H[0] * sqrtT * Mx<R>::ex(-cd.k_ci_H[1] * q.invT) / (R(1) + Mx<R>::sq(R(T / cd.k_ci_H[2])));
   const R zci = kci * n * xe;
-  const R aB = alpha_B(T, c);
-  const R agrH = alpha_gr(T, psi, c.agr_Hp, Zd);
+  const R aB = c.alpha_B[0] * Mx<R>::ex((cd.alpha_B[1] + cd.alpha_B[2] * q.lnT4) * q.lnT4);
+  const R agrH = alpha_gr<R>(q, lnpsi, cd.agr_Hp, Zd);
   v.F = kgr * n;
   v.D = c.cr_destr * zcrH2 + zpd + zpiH2 + zcd;
   v.I = zpiH + zcrH + zci;
@@ -300,100 +349,113 @@ __device__ Eval<R> evaluate(R T, double n_d, R xH2, R xHp, const EqS<R> &e, cons
   const R ev = R(EV);
   // heating, Sec. 4.1
   const R G0 = c.G0_per_chi * ((c.J_PE * r.chiPE + c.J_LW * r.chiLW) / c.J_FUV);
-  const R eps = (c.pe_C[0] + c.pe_C[1] * m_pow(T, c.pe_C[4])) /
-                (R(1) + c.pe_C[2] * m_pow(psi, c.pe_C[5]) * (R(1) + c.pe_C[3] * m_pow(psi, c.pe_C[6])));
+  const R eps = (c.pe_C[0] + c.pe_C[1] * Mx<R>::ex(cd.pe_C[4] * q.lnT)) /
+                (R(1) + c.pe_C[2] * Mx<R>::ex(cd.pe_C[5] * lnpsi) * (R(1) + c.pe_C[3] * Mx<R>::ex(cd.pe_C[6] * lnpsi)));
   const R g_pe = c.pe_pref * G0 * eps * Zd;
-  const R qH = (c.q_cr_H[0] + c.q_cr_H[1] * m_sqrt(xe / (xe + c.q_cr_H[2]))) * ev;
+  const R qH = (c.q_cr_H[0] + c.q_cr_H[1] * Mx<R>::sq(xe / (xe + c.q_cr_H[2]))) * ev;
   R qH2;
   {
-    const R *q = c.q_cr_H2;  // values q[0..3] at log10 n = q[4..7]
-    R ln = m_log10(n);
-    if (ln <= q[4]) qH2 = q[0];
-    else if (ln >= q[7]) qH2 = q[3];
-    else {
-      int j = ln < q[5] ? 0 : (ln < q[6] ? 1 : 2);
-      qH2 = (q[j + 1] - q[j]) / (q[j + 5] - q[j + 4]) * (ln - q[j + 4]) + q[j];
-    }
-    qH2 *= ev;
+    const double *qq = cd.q_cr_H2;  // values qq[0..3] at log10 n = qq[4..7], linear between, flat outside
+    const double ln = Mx<R>::ln(n_d) / LN10D;
+    double val;
+    if (ln <= qq[4]) val = qq[0];
+    else if (ln >= qq[7]) val = qq[3];
+    else if (ln < qq[5]) val = (qq[1] - qq[0]) / (qq[5] - qq[4]) * (ln - qq[4]) + qq[0];
+    else if (ln < qq[6]) val = (qq[2] - qq[1]) / (qq[6] - qq[5]) * (ln - qq[5]) + qq[1];
+    else val = (qq[3] - qq[2]) / (qq[7] - qq[6]) * (ln - qq[6]) + qq[2];
+    qH2 = R(val) * ev;
   }
   const R g_cr = r.xi * (xH * qH + R(2) * xH2 * qH2);
   const R g_pi = xH * (c.q_pi_H_eV * ev) * zpiH + xH2 * (c.q_pi_H2_eV * ev) * zpiH2;
-  const R kHH = c.k_H2_H[0] * m_sqrt(T) * m_exp(-c.k_H2_H[1] / T);
-  const R kHH2 = c.k_H2_H2[0] * m_sqrt(T) * m_exp(-c.k_H2_H2[1] / (T + c.k_H2_H2[2]));
+  const R kHH = c.k_H2_H[0] * sqrtT * Mx<R>::ex(-cd.k_H2_H[1] * q.invT);
+  const R kHH2 = c.k_H2_H2[0] * sqrtT * Mx<R>::ex(-cd.k_H2_H2[1] / (T + cd.k_H2_H2[2]));
   const R dcol = xH * kHH + xH2 * kHH2;
   const R eff = n * dcol / (n * dcol + c.A_eff + zpd);
   const R g_h2 = kgr * n * xH * (c.h2form_eV[0] * ev + c.h2form_eV[1] * ev * eff) +
                  zpd * xH2 * c.f_pump * (c.pump_eV * ev) * eff + zpd * xH2 * (c.pd_eV * ev);
   v.Gamma = (double)g_pe + (double)g_cr + (double)g_pi + (double)g_h2;
   // cooling, Sec. 4.2
-  const R T4 = T / R(1e4);
-  const R k12 = c.lya[0] * m_pow(T4, c.lya[1]) / (R(1) + m_pow(T4 / c.lya[2], c.lya[3])) * m_exp(-c.lya[4] / T4);
+  const R T4 = R(T * 1e-4);
+  const R k12 = c.lya[0] * Mx<R>::ex(cd.lya[1] * q.lnT4 - cd.lya[4] * 1e4 * q.invT) /
+                (R(1) + Mx<R>::ex(cd.lya[3] * (q.lnT4 - cd.ln_lya_T)));
   const R l_lya = xH * xe * R(K_B) * c.lya_E21 * k12;
   const R l_ci = (c.ci_eV * ev) * xH * xe * kci;
   const R l_cd = (c.cd_eV * ev) * xH2 * (xH * kcdH + xH2 * kcdH2);
   R l_rv = R(0);
   if (p.h2_rovib) {
-    const R *a = c.rovib_lte;
-    const R T3 = T / R(1e3);
-    const R q3 = a[4] / T3;
-    const R Lrot = a[0] * m_pow(T3, a[1]) / (R(1) + a[2] * m_pow(T3, a[3])) * m_exp(-(q3 * q3 * q3)) +
-                   a[5] * m_exp(-a[6] / T3);
-    const R Lvib = a[7] * m_exp(-a[8] / T3) + a[9] * m_exp(-a[10] / T3);
+    const double *a = cd.rovib_lte;
+    const double lnT3 = q.lnT - LN1E3;
+    const double iT3 = 1e3 * q.invT;
+    const double q3 = a[4] * iT3;
+    const R Lrot = R(a[0]) * Mx<R>::ex(a[1] * lnT3) / (R(1) + R(a[2]) * Mx<R>::ex(a[3] * lnT3)) *
+                       Mx<R>::ex(-(q3 * q3 * q3)) +
+                   R(a[5]) * Mx<R>::ex(-a[6] * iT3);
+    const R Lvib = R(a[7]) * Mx<R>::ex(-a[8] * iT3) + R(a[9]) * Mx<R>::ex(-a[10] * iT3);
     const R Llte = Lrot + Lvib;
-    const R *b = c.rovib_low;
-    R lg = m_log10(T);
+    // the quartic in log10 T cancels terms of ~1e2 down to ~-24: kept in double
+    const double *b = cd.rovib_low;
+    double lg = q.lnT / LN10D;
     lg = lg < b[5] ? b[5] : (lg > b[6] ? b[6] : lg);
-    const R L0 = m_pow10(b[0] + lg * (b[1] + lg * (b[2] + lg * (b[3] + lg * b[4]))));
+    const R L0 = Mx<R>::ex(LN10D * (b[0] + lg * (b[1] + lg * (b[2] + lg * (b[3] + lg * b[4])))));
     const R np_ = n * (xH + xH2);
-    const R L = Llte * np_ * L0 / (np_ * L0 + Llte);
+    const R nL0 = np_ * L0;
+    // = Llte n L0 / (n L0 + Llte) without forming the tiny product; 0 when either rate is 0
+    const R L = (nL0 > R(0) && Llte > R(0)) ? nL0 / (R(1) + nL0 / Llte) : R(0);
     l_rv = xH2 * L / n;
   }
-  const R l_ff = c.ff[0] * c.ff[1] * m_sqrt(T) * xe * xHp;
-  const R l_rr = aB * R(K_B) * T * (c.rr_energy[0] + c.rr_energy[1] * m_log(T4)) * xe * xHp;
+  const R l_ff = c.ff[0] * c.ff[1] * sqrtT * xe * xHp;
+  const R l_rr = aB * R(K_B) * Tr * R(cd.rr_energy[0] + cd.rr_energy[1] * q.lnT4) * xe * xHp;
   // C+ 2-level
   R l_cp;
   {
     const R g0 = c.cp_levels[0], g1 = c.cp_levels[1], E10 = c.cp_levels[2], A10 = c.cp_levels[3];
-    const R T2 = T / R(100);
-    const R k10H = (A10 / c.cp_ncrit_H[0]) * m_pow(T2, c.cp_ncrit_H[1] + c.cp_ncrit_H[2] * m_log(T2));
-    const R k10e = A10 / (c.cp_ncrit_e * m_sqrt(T4));
+    const double lnT2 = q.lnT - LN100;
+    const R k10H = (A10 / c.cp_ncrit_H[0]) * Mx<R>::ex((cd.cp_ncrit_H[1] + cd.cp_ncrit_H[2] * lnT2) * lnT2);
+    const R k10e = A10 / (c.cp_ncrit_e * Mx<R>::sq(T4));
     const R C10 = n * (xH * k10H + xH2 * c.cp_h2_over_h * k10H + xe * k10e);
-    const R C01 = C10 * (g1 / g0) * m_exp(-E10 / T);
+    const R C01 = C10 * (g1 / g0) * Mx<R>::ex(-cd.cp_levels[2] * q.invT);
     const R f1 = C01 / (C01 + C10 + A10);
     l_cp = e.xCp * f1 * A10 * R(K_B) * E10 / n;
   }
-  const R l_c = e.xC * three_level_cool(T, n, xH, xH2, xe, c.c_levels, c.c_coll, c.c_ncrit_H, c);
-  const R l_o = e.xO * three_level_cool(T, n, xH, xH2, xe, c.o_levels, c.o_coll, c.o_ncrit_H, c);
+  const R l_c = e.xC * three_level_cool<R>(q, n, xH, xH2, xe, cd.c_levels, cd.c_coll, cd.c_ncrit_H, cd.fs_slope_C);
+  const R l_o = e.xO * three_level_cool<R>(q, n, xH, xH2, xe, cd.o_levels, cd.o_coll, cd.o_ncrit_H, cd.fs_slope_O);
   R l_co;
   {
     const R Nt = n * e.xCO * R(PC_CM) / p.dvdr;
-    const R lT = m_log10(T);
-    const R lN = m_log10(rmax(Nt, Tiny<R>::v));
-    const R L0 = m_pow10(co_lookup(tab, c, lT, lN, 0));
-    const R nh = m_pow10(co_lookup(tab, c, lT, lN, 1));
+    const double lT = q.lnT / LN10D;
+    const double lN = Nt > R(0) ? Mx<R>::ln((double)Nt) / LN10D : -300.0;
+    // log10 columns are stored as log10(value) + TAB_LOG_OFFSET (see coef.h)
+    const R L0 = Mx<R>::ex(LN10D * (co_lookup(tab, lT, lN, 0) - TAB_LOG_OFFSET));
+    const R nh = Mx<R>::ex(LN10D * co_lookup(tab, lT, lN, 1));
     l_co = e.xCO * L0 / (R(1) + n / nh);
   }
-  const R l_gr = c.grrec[0] * m_pow(T, c.grrec[1]) * m_pow(psi, c.grrec[2] * m_pow(T, -c.grrec[3])) * xe * Zd;
+  const R l_gr =
+      c.grrec[0] * Mx<R>::ex(cd.grrec[1] * q.lnT + cd.grrec[2] * (double)Mx<R>::ex(-cd.grrec[3] * q.lnT) * lnpsi) *
+      xe * Zd;
   R l_neb;
   {
-    const R lnT4 = m_log(T4);
-    R f = R(0);
-    for (int k = 6; k >= 0; --k) f = f * lnT4 + c.neb_a[k];
-    f = m_pow10(f);
+    // the degree-6 fit cancels terms several times its value: Horner in double
+    double f = 0.0;
+    for (int k = 6; k >= 0; --k) f = f * q.lnT4 + cd.neb_a[k];
+    // exp(-E/T4) f_neb as one exponent: each factor alone can leave float range
+    const R ef = Mx<R>::ex(LN10D * f - cd.neb[1] * 1e4 * q.invT);
     const R ne2 = n * xe / R(100);
-    l_neb = Zg * xe * xHp * c.neb[0] * m_exp(-c.neb[1] / T4) * f /
-            (m_sqrt(T4) * (R(1) + c.neb[2] * m_pow(ne2, c.neb[3] - c.neb[4] * lnT4)));
+    const double expo = cd.neb[3] - cd.neb[4] * q.lnT4;
+    const R dens = ne2 > R(0) ? Mx<R>::ex(expo * Mx<R>::ln((double)ne2))
+                              : (expo > 0.0 ? R(0) : (expo < 0.0 ? R(INFINITY) : R(1)));
+    l_neb = Zg * xe * xHp * c.neb[0] * ef / (Mx<R>::sq(T4) * (R(1) + c.neb[2] * dens));
   }
   const R G = dust_heating_per_Zd(r, c, p);
   bool bad;
-  const R Td = dust_T(T, n, G, td_guess, c, p, bad);
+  const R Td = dust_T(Tr, sqrtT, n, G, td_guess, c, p, bad);
   v.Td = Td;
   v.td_bad = bad;
-  const R l_gd = c.alpha_gd * m_sqrt(T) * (T - Td) * Zd;
-  const R S = R(1) / (R(1) + m_exp(-c.sigmoid[0] * (T - R(0.5) * (c.sigmoid[1] + c.sigmoid[2])) /
-                                     (c.sigmoid[2] - c.sigmoid[1])));
-  const R lgT = m_log10(T);
-  const R l_cie = m_pow10(cie_lookup(tab, c, lgT, 0)) + Zg * m_pow10(cie_lookup(tab, c, lgT, 1));
+  const R l_gd = c.alpha_gd * sqrtT * (Tr - Td) * Zd;
+  const R S = R(1) / (R(1) + Mx<R>::ex(-cd.sigmoid[0] * (T - 0.5 * (cd.sigmoid[1] + cd.sigmoid[2])) /
+                                         (cd.sigmoid[2] - cd.sigmoid[1])));
+  const double lgT = q.lnT / LN10D;
+  const R l_cie = Mx<R>::ex(LN10D * (cie_lookup(tab, lgT, 0) - TAB_LOG_OFFSET)) +
+                  Zg * Mx<R>::ex(LN10D * (cie_lookup(tab, lgT, 1) - TAB_LOG_OFFSET));
   const double l_hyd = (double)l_lya + (double)l_ci + (double)l_rv + (double)l_cd + (double)l_ff + (double)l_rr;
   const double mid = (double)l_cp + (double)l_c + (double)l_o + (double)l_co + (double)l_gr + (double)l_neb +
                      (double)l_gd;

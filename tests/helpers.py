@@ -41,7 +41,9 @@ def oracle_rad(state, dx_cm, par, xC=None):
 
 def oracle_step(state, rad, dt_s, par, idx=None):
     sel = (lambda a: a.ravel()) if idx is None else (lambda a: a.ravel()[idx])
-    radi = {k: sel(v) for k, v in rad.items()}
+    N = np.size(state["n"])
+    # radiation may be given for the whole grid or already for the selected cells
+    radi = {k: (sel(v) if np.size(v) == N else np.asarray(v).ravel()) for k, v in rad.items()}
     return ostep.chem_cool_step(sel(state["n"]), sel(state["T"]), sel(state["xH2"]), sel(state["xHp"]), radi,
                                 dt_s, par)
 
