@@ -4,8 +4,10 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <sstream>
@@ -31,13 +33,19 @@ ism_status fail(ism_status s, const std::string &msg) {
   return s;
 }
 
+constexpr int QUEUE_SLOTS = 1024;  // work-queue counters per device (overlapping step calls)
+
 struct DevState {
   bool ready = false;
   double *tab64 = nullptr;
   float *tab32 = nullptr;
   void *scratch = nullptr;
   size_t scratch_bytes = 0;
+  int64_t *queues = nullptr;
+  unsigned qnext = 0;
   int num_cu = 0;
+  int occ64 = 0, occ32 = 0;  // resident 256-thread blocks per CU of the persistent step kernels
+  bool simple_step = false;   // ISM_STEP_KERNEL=simple selects the one-lane-per-cell grid
 };
 
 std::mutex g_mu;
@@ -161,6 +169,15 @@ ism_status ism_init(int device, const char *path) {
     if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(g_coef64), &c64, sizeof(c64));
     if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(g_coef32), &c32, sizeof(c32));
     if (e == hipSuccess) e = hipDeviceGetAttribute(&st.num_cu, hipDeviceAttributeMultiprocessorCount, device);
+    if (e == hipSuccess && !st.queues) e = hipMalloc(&st.queues, QUEUE_SLOTS * sizeof(int64_t));
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&st.occ64, step_queue_kernel<double>, 256, 0);
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&st.occ32, step_queue_kernel<float>, 256, 0);
+    if (e == hipSuccess) {
+      const char *k = std::getenv("ISM_STEP_KERNEL");
+      st.simple_step = k && std::string(k) == "simple";
+    }
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) rc = fail(ISM_E_DEVICE, std::string("ism_init: ") + hipGetErrorString(e));
     else { st.ready = true; g_host_coef = c64; }
@@ -179,6 +196,7 @@ ism_status ism_shutdown(void) {
     if (kv.second.tab64) (void)hipFree(kv.second.tab64);
     if (kv.second.tab32) (void)hipFree(kv.second.tab32);
     if (kv.second.scratch) (void)hipFree(kv.second.scratch);
+    if (kv.second.queues) (void)hipFree(kv.second.queues);
   }
   g_dev.clear();
   (void)hipSetDevice(prev);
@@ -270,21 +288,36 @@ ism_status ism_chem_cool_step(const ism_params *p, ism_precision prec, int64_t n
     return fail(ISM_E_ARG, "a required array is NULL");
   DevState *st;
   if (ism_status s = current_state(&st)) return s;
-  const unsigned blocks = (unsigned)((ncell + 255) / 256);
+  int64_t *q;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    q = st->queues + (st->qnext++ % QUEUE_SLOTS);
+  }
+  const int64_t want = (ncell + 255) / 256;
   if (prec == ISM_PREC_F64) {
     StepArgs<double> a{ncell, dt_s, n, T, xH2, xHp, (const double *)chi_PE, (const double *)chi_LW,
                        (const double *)chi_H2, (const double *)chi_C, (const double *)phi_LyC,
                        (const double *)xi_cr, (const double *)N_eff, (double *)xCp, (double *)xCO, (double *)xe,
-                       nsub, status, st->tab64, make_par<double>(p, g_host_coef), make_par<double>(p, g_host_coef),
-                       nullptr};
-    hipLaunchKernelGGL(step_simple_kernel<double>, dim3(blocks), dim3(256), 0, stream, a);
+                       nsub, status, st->tab64, make_par<double>(p, g_host_coef), make_par<double>(p, g_host_coef), q};
+    if (st->simple_step) {
+      hipLaunchKernelGGL(step_simple_kernel<double>, dim3((unsigned)want), dim3(256), 0, stream, a);
+    } else {
+      const int64_t grid = std::min<int64_t>(want, (int64_t)st->num_cu * std::max(st->occ64, 1));
+      hipLaunchKernelGGL(queue_init_kernel, dim3(1), dim3(1), 0, stream, q, grid * 256);
+      hipLaunchKernelGGL(step_queue_kernel<double>, dim3((unsigned)grid), dim3(256), 0, stream, a);
+    }
   } else {
     StepArgs<float> a{ncell, dt_s, n, T, xH2, xHp, (const float *)chi_PE, (const float *)chi_LW,
                       (const float *)chi_H2, (const float *)chi_C, (const float *)phi_LyC,
                       (const float *)xi_cr, (const float *)N_eff, (float *)xCp, (float *)xCO, (float *)xe,
-                      nsub, status, st->tab32, make_par<float>(p, g_host_coef), make_par<double>(p, g_host_coef),
-                      nullptr};
-    hipLaunchKernelGGL(step_simple_kernel<float>, dim3(blocks), dim3(256), 0, stream, a);
+                      nsub, status, st->tab32, make_par<float>(p, g_host_coef), make_par<double>(p, g_host_coef), q};
+    if (st->simple_step) {
+      hipLaunchKernelGGL(step_simple_kernel<float>, dim3((unsigned)want), dim3(256), 0, stream, a);
+    } else {
+      const int64_t grid = std::min<int64_t>(want, (int64_t)st->num_cu * std::max(st->occ32, 1));
+      hipLaunchKernelGGL(queue_init_kernel, dim3(1), dim3(1), 0, stream, q, grid * 256);
+      hipLaunchKernelGGL(step_queue_kernel<float>, dim3((unsigned)grid), dim3(256), 0, stream, a);
+    }
   }
   HIP_TRY(hipGetLastError());
   return ISM_OK;

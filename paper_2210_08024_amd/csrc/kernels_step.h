@@ -8,7 +8,15 @@ namespace ism {
 __constant__ CoefT<double> g_coef64;
 __constant__ CoefT<float> g_coef32;
 
-__device__ __forceinline__ const CoefT<double> &coef64() { return g_coef64; }
+// The double coefficients through a pointer laundered by an empty asm at each use site: the
+// compiler may not hoist their scalar loads out of the substep loop, which otherwise keeps
+// hundreds of constants live across it and spills them into vector registers.
+__device__ __forceinline__ const CoefT<double> &coef64() {
+  const __attribute__((address_space(4))) CoefT<double> *p =
+      (const __attribute__((address_space(4))) CoefT<double> *)&g_coef64;
+  asm volatile("" : "+s"(p));
+  return *(const CoefT<double> *)p;
+}
 
 template <class R> __device__ __forceinline__ const CoefT<R> &coef();
 template <> __device__ __forceinline__ const CoefT<double> &coef<double>() { return g_coef64; }
@@ -77,8 +85,22 @@ __device__ __forceinline__ bool cell_substep(const StepArgs<R> &a, CellState<R> 
   const double muH = a.pd.muH, eps = a.pd.eps_sub, delta = a.pd.fd_rel, dt = a.dt;
   const double mu_den = 1.1 + (double)s.e.xe - s.xH2;
   const double Ta = muH * s.Tmu / mu_den;
-  Eval<R> v = evaluate<R, false, false>(Ta, s.nd, s.xH2, s.xHp, s.e, s.r, c, p, tab, s.tdg, nullptr);
-  s.tdg = v.Td;
+  // H at T and at T (1 + fd_rel): one instance of the evaluation, run twice
+  Eval<R> v;
+  double H2 = 0.0;
+  bool td_bad = false;
+#pragma unroll 1
+  for (int k = 0; k < 2; ++k) {
+    const Eval<R> w = evaluate<R, false, false>(k == 0 ? Ta : Ta * (1.0 + delta), s.nd, s.xH2, s.xHp, s.e, s.r, c,
+                                                p, tab, s.tdg, nullptr);
+    td_bad = td_bad || w.td_bad;
+    if (k == 0) {
+      v = w;
+      s.tdg = w.Td;
+    } else {
+      H2 = w.H;
+    }
+  }
   const double H = v.H;
   const double en = s.K * s.Tmu;
   const double rem = dt - s.t;
@@ -87,12 +109,10 @@ __device__ __forceinline__ bool cell_substep(const StepArgs<R> &a, CellState<R> 
   if (aH > 0.0) dts = fmin(dts, eps * en / aH);
   if (a1 > 0.0) dts = fmin(dts, eps / a1);
   if (a2 > 0.0) dts = fmin(dts, eps / a2);
-  Eval<R> v2 =
-      evaluate<R, false, false>(Ta * (1.0 + delta), s.nd, s.xH2, s.xHp, s.e, s.r, c, p, tab, s.tdg, nullptr);
-  const double dH = (v2.H - H) / (delta * s.Tmu);
+  const double dH = (H2 - H) / (delta * s.Tmu);
   double den = s.K - dts * dH;
   if (den <= 0.1 * s.K) { den = s.K; s.st |= ISM_ST_DENOM_GUARD; }
-  if (v.td_bad || v2.td_bad) s.st |= ISM_ST_TD_UNBRACKETED;
+  if (td_bad) s.st |= ISM_ST_TD_UNBRACKETED;
   double Tmu_new = s.Tmu + dts * H / den;
   const double Tmu_min = a.pd.T_floor * mu_den / muH;
   if (Tmu_new < Tmu_min) { Tmu_new = Tmu_min; s.st |= ISM_ST_T_FLOOR; }
@@ -148,6 +168,45 @@ __global__ __launch_bounds__(256) void step_simple_kernel(StepArgs<R> a) {
   }
   cell_end(a, i, s);
 }
+
+// Persistent variant: a grid sized to the chip; every lane keeps one cell in flight and,
+// when its cell finishes, claims the next unclaimed cell from a device counter (one
+// atomic per wave per refill, ranks by popcount), so lanes stay busy however uneven the
+// substep counts are.  Every lane leaves once the counter passes ncell and its cell is
+// done; *a.queue must hold the number of lanes in the grid at launch.
+// Two waves per SIMD: measured fastest for both precisions (more waves spill to scratch).
+template <class R>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void step_queue_kernel(StepArgs<R> a) {
+  __shared__ R s_tab[TAB_STEP];
+  stage_tables(a.tab, s_tab);
+  const int lane = threadIdx.x & 63;
+  int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool active = cell < a.ncell;
+  CellState<R> s;
+  if (active) cell_begin(a, cell, s, s_tab);
+  while (__ballot(active) != 0) {
+    bool need = false;
+    if (active && cell_substep(a, s, s_tab)) {
+      cell_end(a, cell, s);
+      need = true;
+    }
+    const uint64_t m = __ballot(need);
+    if (m != 0) {
+      const int leader = __ffsll((unsigned long long)m) - 1;
+      unsigned long long base = 0;
+      if (lane == leader) base = atomicAdd((unsigned long long *)a.queue, (unsigned long long)__popcll(m));
+      base = __shfl(base, leader, 64);
+      if (need) {
+        cell = (int64_t)base + __popcll(m & ((1ull << lane) - 1ull));
+        active = cell < a.ncell;
+        if (active) cell_begin(a, cell, s, s_tab);
+        else active = false;
+      }
+    }
+  }
+}
+
+__global__ void queue_init_kernel(int64_t *q, int64_t v) { *q = v; }
 
 // Per-cell diagnostics (ism_rates).
 template <class R>
