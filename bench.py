@@ -32,7 +32,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--path", choices=("f64", "mixed"), default="f64")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-cells", type=int, default=4096)
+    ap.add_argument("--cpu-cells", type=int, default=65536)
     return ap.parse_args()
 
 
@@ -153,7 +153,7 @@ def main():
         "config": {"workload": "grf128: 128^3 lognormal GRF (sigma_ln 1.5, 2 pc smoothing), 4 pc cells, "
                                "P/k = 3e3 K cm^-3, Z' = 1, chi0 = 1 six-ray, xi_cr0 = 2e-16 attenuated by N_eff, "
                                "dt = 1e4 yr", "cells": N, "path": args.path},
-        "roofline": {"bound": "alu", "kernel": "step_simple_kernel", "achieved": achieved, "peak": peak,
+        "roofline": {"bound": "alu", "kernel": "step_queue_kernel", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
                      "work": f"{tot_sub} substeps x ({arith} flops + {trans} transcendentals counted as 1) "
                              f"per launch; census of the oracle's substep"},

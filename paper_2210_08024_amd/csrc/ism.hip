@@ -220,25 +220,52 @@ ism_status ism_columns6(const ism_grid *g, const ism_params *p, ism_precision pr
   DevState *st;
   if (ism_status s = current_state(&st)) return s;
   const int64_t ncell = (int64_t)g->nx * g->ny * g->nz;
-  void *acc;
-  if (ism_status s = scratch(st, (size_t)ncell * sizeof(double4), &acc)) return s;
+  // y/z pencils are split into segments until about 2^18 lanes march per pass
+  auto nseg_for = [&](int64_t pencils, int L) {
+    int64_t s = (262144 + pencils - 1) / pencils;
+    s = std::max<int64_t>(1, std::min<int64_t>(s, L));
+    return (int)s;
+  };
+  const int segy = nseg_for((int64_t)g->nx * g->nz, g->ny), segz = nseg_for((int64_t)g->nx * g->ny, g->nz);
+  const size_t seg_elems = 3 * (size_t)std::max((int64_t)g->nx * g->nz * segy, (int64_t)g->nx * g->ny * segz);
+  void *buf;
+  if (ism_status s = scratch(st, (size_t)ncell * sizeof(double4) + seg_elems * sizeof(double), &buf)) return s;
   ColArgs a;
   a.nx = g->nx; a.ny = g->ny; a.nz = g->nz; a.dx = g->dx_cm;
-  a.n = n; a.xH2 = xH2; a.xC = xC; a.acc = (double4 *)acc;
+  a.n = n; a.xH2 = xH2; a.xC = xC;
+  a.acc = (double4 *)buf;
+  a.seg = (double *)((char *)buf + (size_t)ncell * sizeof(double4));
   a.chiPE = chi_PE; a.chiLW = chi_LW; a.chiH2 = chi_H2; a.chiC = chi_C; a.Neff = N_eff; a.xi = xi_cr;
-  a.out_f32 = prec == ISM_PREC_MIXED; a.cr_mode = p->cr_mode;
+  a.cr_mode = p->cr_mode;
   a.chi0 = p->chi0; a.Zd = p->Zd; a.xi0 = p->xi_cr0;
   a.sPE = g_host_coef.sig_d_abs[2] * p->Zd;
   a.sLW = g_host_coef.sig_d_abs[1] * p->Zd;
   a.tab = st->tab64;
+  const bool f32 = prec == ISM_PREC_MIXED;
   const int64_t rows = (int64_t)g->ny * g->nz;
-  hipLaunchKernelGGL(columns_x_kernel, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, stream, a);
+  if (f32) hipLaunchKernelGGL(columns_x_kernel<float>, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, stream, a);
+  else hipLaunchKernelGGL(columns_x_kernel<double>, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, stream, a);
   HIP_TRY(hipGetLastError());
-  const unsigned bx = (unsigned)((g->nx + 63) / 64);
-  hipLaunchKernelGGL(columns_yz_kernel<1>, dim3(bx, (unsigned)g->nz), dim3(64), 0, stream, a);
-  HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(columns_yz_kernel<2>, dim3(bx, (unsigned)g->ny), dim3(64), 0, stream, a);
-  HIP_TRY(hipGetLastError());
+  for (int ax = 1; ax <= 2; ++ax) {
+    a.nseg = ax == 1 ? segy : segz;
+    const int L = ax == 1 ? g->ny : g->nz;
+    a.seglen = (L + a.nseg - 1) / a.nseg;
+    const int64_t lanes = (int64_t)g->nx * (ax == 1 ? g->nz : g->ny) * a.nseg;
+    const dim3 grid((unsigned)((lanes + 255) / 256)), blk(256);
+    if (a.nseg > 1) {
+      if (ax == 1) hipLaunchKernelGGL(columns_segsum_kernel<1>, grid, blk, 0, stream, a);
+      else hipLaunchKernelGGL(columns_segsum_kernel<2>, grid, blk, 0, stream, a);
+      HIP_TRY(hipGetLastError());
+    }
+    if (ax == 1) {
+      if (f32) hipLaunchKernelGGL((columns_march_kernel<float, 1>), grid, blk, 0, stream, a);
+      else hipLaunchKernelGGL((columns_march_kernel<double, 1>), grid, blk, 0, stream, a);
+    } else {
+      if (f32) hipLaunchKernelGGL((columns_march_kernel<float, 2>), grid, blk, 0, stream, a);
+      else hipLaunchKernelGGL((columns_march_kernel<double, 2>), grid, blk, 0, stream, a);
+    }
+    HIP_TRY(hipGetLastError());
+  }
   return ISM_OK;
 }
 

@@ -50,7 +50,8 @@ def test_columns6_parity(ism, shape, seed, prec):
     out = ism.columns6(H.to_dev(n).view(shape), H.to_dev(xH2).view(shape), H.to_dev(xC).view(shape), dx,
                        H.ism_params_from(par), prec)
     torch.cuda.synchronize()
-    tol = 1e-12 if prec == 0 else 2e-6
+    # float outputs come from float transcendental cores (~1e-6 relative through the steep C-shielding table)
+    tol = 1e-12 if prec == 0 else 1e-5
     for k in ("chi_PE", "chi_LW", "chi_H2", "chi_C", "N_eff", "xi"):
         g = out[k].cpu().numpy().astype(np.float64)
         r = ref[k]
@@ -276,7 +277,7 @@ def test_end_to_end_128_sampled(ism, grf128, prec):
     rc = ocol.columns6_cells(s["n"], s["xH2"], None, dx, par, cells)
     for k, gk in (("chi_PE", "chi_PE"), ("chi_H2", "chi_H2"), ("N_eff", "N_eff"), ("xi", "xi")):
         g = rad[gk].view(-1)[torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.float64)
-        tol = 1e-11 if prec == 0 else 2e-6
+        tol = 1e-11 if prec == 0 else 1e-5
         assert H.rel_err(g, rc[k], 1e14 if k == "N_eff" else 1e-30).max() < tol, k
     radi = dict(chi_PE=rc["chi_PE"], chi_LW=rc["chi_LW"], chi_H2=rc["chi_H2"], chi_C=rc["chi_C"],
                 phi=np.zeros(len(idx)), xi=rc["xi"], Neff=rc["N_eff"])
