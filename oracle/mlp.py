@@ -3,10 +3,10 @@
 Network: 10 -> 128 -> 128 -> 128 -> 3, SiLU on the hidden layers, linear output;
 loss = mean over samples and outputs of (y_hat - y)^2 on standardised targets.
 Training keeps FP32 master weights and Adam moments; the products run on BF16 copies
-of the weights and of the layer inputs with wide accumulation.  The reference takes
-those BF16 quantisation points as part of its definition -- ``bf16()`` rounds to the
-nearest BF16 value (ties to even) before every product -- and accumulates exactly in
-FP64, so the only differences left to the GPU are its FP32 accumulation order and,
+of the weights, of the layer inputs and (backward) of the error signal, with wide
+accumulation.  The reference takes those BF16 quantisation points as part of its
+definition -- ``bf16()`` rounds to the nearest BF16 value (ties to even) before every
+product -- and accumulates exactly in FP64, so the only differences left to the GPU are its FP32 accumulation order and,
 rarely, a BF16 rounding that flips because an FP32 sum sits on a rounding boundary.
 
 Parameter layout (flat FP32 vector, 34,819 values):
@@ -106,9 +106,10 @@ def loss_and_grad(theta, X, Y, quant=True):
         h, z = cache[k]
         if k < len(params) - 1:
             d = d * dsilu(z)
-        grads[k] = (d.T @ h, d.sum(axis=0))
+        # the error signal is a BF16 operand of both products; the bias gradient sums it unrounded
+        grads[k] = (q(d).T @ h, d.sum(axis=0))
         if k > 0:
-            d = d @ q(W)
+            d = q(d) @ q(W)
     return L, flatten(grads)
 
 
