@@ -144,6 +144,64 @@ ism_status ism_chem_cool_step(const ism_params *p, ism_precision prec, int64_t n
                               const void *N_eff, void *xCp, void *xCO, void *xe,
                               int32_t *nsub, uint8_t *status, hipStream_t stream);
 
+/* ---------------------------------------------------------------- learned surrogate
+ * A small MLP maps a cell's (state, radiation, dt) to its post-step (x_H2, x_H+, log10 T):
+ * 10 inputs -> 128 -> 128 -> 128 -> 3 outputs, SiLU on the hidden layers.  The products
+ * run on the matrix cores with BF16 operands (weights, layer inputs and, backward, the
+ * error signal) and FP32 accumulation; the master weights and the Adam moments are FP32.
+ * The surrogate is not part of the paper's method: the plain step above is its teacher,
+ * its fallback and its judge.
+ *
+ * Parameters (flat FP32, ISM_SURR_NPARAM values, row-major W[out][in]):
+ *   W1[128x10] b1[128] W2[128x128] b2[128] W3[128x128] b3[128] W4[3x128] b4[3].
+ * Inputs are standardised inside the library, x_s = (x - mu_x) / sd_x, and outputs are
+ * returned as y = y_s sd_y + mu_y; the loss is the mean over samples and the 3 outputs of
+ * (y_s - (y_target - mu_y) / sd_y)^2.  Adam: beta1 0.9, beta2 0.999, eps 1e-8, bias
+ * corrected, one step counter per surrogate.
+ *
+ * The object owns its device buffers on the device that was current at create; every
+ * other call must be made with that device current.  Calls on one object are ordered by
+ * the stream they are given; two streams using one object concurrently race. */
+#define ISM_SURR_NIN 10
+#define ISM_SURR_NOUT 3
+#define ISM_SURR_NPARAM 34819
+/* Checkpoint layout of get/set_params (floats): theta[NPARAM], adam_m[NPARAM],
+ * adam_v[NPARAM], step, mu_x[10], sd_x[10], mu_y[3], sd_y[3]. */
+#define ISM_SURR_STATE_FLOATS (3 * ISM_SURR_NPARAM + 1 + 26)
+
+typedef struct ism_surrogate ism_surrogate;
+
+/* Allocate a surrogate: He-uniform weights (bound sqrt(6/fan_in)) drawn from a counter-based
+ * generator keyed by `seed`, zero biases, zero moments, identity standardisation.
+ * Requires ism_init on the current device. */
+ism_status ism_surrogate_create(ism_surrogate **out, uint64_t seed);
+ism_status ism_surrogate_destroy(ism_surrogate *m);
+
+/* Host arrays; sd values must be finite and > 0.  Copies synchronously. */
+ism_status ism_surrogate_set_norm(ism_surrogate *m, const float *mu_x, const float *sd_x,
+                                  const float *mu_y, const float *sd_y);
+
+/* Inference: X [B][10] raw inputs -> Y [B][3] (device FP32, caller-owned).  B >= 0. */
+ism_status ism_surrogate_forward(ism_surrogate *m, const float *X, float *Y, int64_t B,
+                                 hipStream_t stream);
+
+/* Gradient of sum_{b,o} dY[b][o] * y_s[b][o] with respect to the parameters, where y_s is
+ * the standardised output: X [B][10], dY [B][3], grad [ISM_SURR_NPARAM] (device FP32,
+ * caller-owned, overwritten).  B >= 1. */
+ism_status ism_surrogate_backward(ism_surrogate *m, const float *X, const float *dY,
+                                  float *grad, int64_t B, hipStream_t stream);
+
+/* One training step on a batch: forward, MSE loss against Y [B][3] (raw targets),
+ * backward, Adam with learning rate lr.  loss_dev (device float, nullable) receives the
+ * batch loss before the update.  B >= 1, lr finite and >= 0. */
+ism_status ism_surrogate_train_step(ism_surrogate *m, const float *X, const float *Y, int64_t B,
+                                    float lr, float *loss_dev, hipStream_t stream);
+
+/* Host checkpoint of the whole training state (layout above).  get synchronises the
+ * device; set copies synchronously and rebuilds the BF16 weight copies. */
+ism_status ism_surrogate_get_params(const ism_surrogate *m, float *flat);
+ism_status ism_surrogate_set_params(ism_surrogate *m, const float *flat);
+
 #ifdef __cplusplus
 }
 #endif

@@ -19,6 +19,7 @@
 #include "coef_load.h"
 #include "kernels_step.h"
 #include "kernels_columns.h"
+#include "kernels_mlp.h"
 
 using namespace ism;
 using ism::host::coef_to_f32;
@@ -348,6 +349,302 @@ ism_status ism_chem_cool_step(const ism_params *p, ism_precision prec, int64_t n
   }
   HIP_TRY(hipGetLastError());
   return ISM_OK;
+}
+
+
+// ====================================================================== surrogate
+}  // extern "C"
+
+struct ism_surrogate {
+  int device = 0;
+  int num_cu = 1;
+  float *params = nullptr;  // theta | adam m | adam v | grad scratch, NPARAM floats each
+  uint8_t *img = nullptr;   // forward image | backward image
+  float *norm = nullptr;    // mlp::NRM_FLOATS
+  float norm_host[26];      // mu_x sd_x mu_y sd_y
+  int64_t step = 0;
+  void *work = nullptr;
+  size_t work_bytes = 0;
+  float *theta() const { return params; }
+  float *adam_m() const { return params + mlp::NPARAM; }
+  float *adam_v() const { return params + 2 * mlp::NPARAM; }
+  uint8_t *fimg() const { return img; }
+  uint8_t *bimg() const { return img + mlp::FI_BYTES; }
+};
+
+namespace {
+
+uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+ism_status surr_check(const ism_surrogate *m) {
+  if (!m) return fail(ISM_E_ARG, "surrogate is NULL");
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != m->device) return fail(ISM_E_ARG, "surrogate belongs to another device");
+  return ISM_OK;
+}
+
+ism_status surr_upload_norm(ism_surrogate *m) {
+  float d[mlp::NRM_FLOATS] = {0.f};
+  for (int k = 0; k < mlp::NIN; ++k) {
+    d[mlp::NRM_MUX + k] = m->norm_host[k];
+    d[mlp::NRM_ISDX + k] = (float)(1.0 / (double)m->norm_host[10 + k]);
+  }
+  for (int k = 0; k < mlp::NOUT; ++k) {
+    d[mlp::NRM_MUY + k] = m->norm_host[20 + k];
+    d[mlp::NRM_SDY + k] = m->norm_host[23 + k];
+    d[mlp::NRM_ISDY + k] = (float)(1.0 / (double)m->norm_host[23 + k]);
+  }
+  HIP_TRY(hipMemcpy(m->norm, d, sizeof(d), hipMemcpyHostToDevice));
+  return ISM_OK;
+}
+
+ism_status surr_pack(ism_surrogate *m) {
+  HIP_TRY(hipMemset(m->img, 0, mlp::FI_BYTES + mlp::BI_BYTES));
+  hipLaunchKernelGGL(mlp::mlp_pack_kernel, dim3((mlp::NPARAM + 255) / 256), dim3(256), 0, nullptr, m->theta(),
+                     m->fimg(), m->bimg());
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipDeviceSynchronize());
+  return ISM_OK;
+}
+
+// Per-batch buffers of a training or backward pass.
+struct SurrWork {
+  uint16_t *h0, *h1, *h2, *h3;
+  float *z1, *z2, *z3, *d4, *part, *loss_part;
+  int64_t chunk;
+  int nchunk, grid_fwd;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int fwd_grid(const ism_surrogate *m, int64_t B) {
+  const int64_t per_block = (int64_t)mlp::FWD_WAVES * mlp::WTILE;
+  return (int)std::max<int64_t>(1, std::min<int64_t>((B + per_block - 1) / per_block, m->num_cu));
+}
+
+ism_status surr_work(ism_surrogate *m, int64_t B, SurrWork &w) {
+  w.chunk = std::max<int64_t>(64, ((B + 127) / 128 + 63) / 64 * 64);
+  w.nchunk = (int)((B + w.chunk - 1) / w.chunk);
+  w.grid_fwd = fwd_grid(m, B);
+  const size_t sz[10] = {align256((size_t)B * mlp::K1 * 2), align256((size_t)B * mlp::NH * 2),
+                         align256((size_t)B * mlp::NH * 2), align256((size_t)B * mlp::NH * 2),
+                         align256((size_t)B * mlp::NH * 4), align256((size_t)B * mlp::NH * 4),
+                         align256((size_t)B * mlp::NH * 4), align256((size_t)B * mlp::NOUT * 4),
+                         align256((size_t)w.nchunk * mlp::NPARAM * 4),
+                         align256((size_t)w.grid_fwd * mlp::FWD_WAVES * 4)};
+  size_t total = 0;
+  for (size_t x : sz) total += x;
+  if (m->work_bytes < total) {
+    if (m->work) {
+      HIP_TRY(hipDeviceSynchronize());
+      (void)hipFree(m->work);
+    }
+    m->work = nullptr;
+    m->work_bytes = 0;
+    hipError_t e = hipMalloc(&m->work, total);
+    if (e != hipSuccess) return fail(ISM_E_NOMEM, std::string("surrogate workspace: ") + hipGetErrorString(e));
+    m->work_bytes = total;
+  }
+  uint8_t *p = (uint8_t *)m->work;
+  void *ptr[10];
+  for (int i = 0; i < 10; ++i) {
+    ptr[i] = p;
+    p += sz[i];
+  }
+  w.h0 = (uint16_t *)ptr[0]; w.h1 = (uint16_t *)ptr[1]; w.h2 = (uint16_t *)ptr[2]; w.h3 = (uint16_t *)ptr[3];
+  w.z1 = (float *)ptr[4]; w.z2 = (float *)ptr[5]; w.z3 = (float *)ptr[6]; w.d4 = (float *)ptr[7];
+  w.part = (float *)ptr[8]; w.loss_part = (float *)ptr[9];
+  return ISM_OK;
+}
+
+// Forward with stored activations, backward through the layers, per-chunk weight gradients.
+void surr_fwd_bwd(ism_surrogate *m, const float *X, const float *Yt, const float *dY, int64_t B, SurrWork &w,
+                  hipStream_t stream) {
+  mlp::FwdArgs fa{};
+  fa.X = X; fa.B = B; fa.fimg = m->fimg(); fa.norm = m->norm;
+  fa.h0 = w.h0; fa.h1 = w.h1; fa.h2 = w.h2; fa.h3 = w.h3; fa.z1 = w.z1; fa.z2 = w.z2; fa.z3 = w.z3;
+  const float *d4 = dY;
+  if (Yt) {
+    fa.Yt = Yt; fa.dscale = (float)(2.0 / (3.0 * (double)B)); fa.d4 = w.d4; fa.loss_part = w.loss_part;
+    d4 = w.d4;
+    hipLaunchKernelGGL(mlp::mlp_fwd_kernel<2>, dim3(w.grid_fwd), dim3(mlp::FWD_THREADS), 0, stream, fa);
+  } else {
+    hipLaunchKernelGGL(mlp::mlp_fwd_kernel<1>, dim3(w.grid_fwd), dim3(mlp::FWD_THREADS), 0, stream, fa);
+  }
+  mlp::BwdArgs ba{B, m->bimg(), d4, w.z1, w.z2, w.z3};
+  hipLaunchKernelGGL(mlp::mlp_bwd_kernel, dim3(w.grid_fwd), dim3(mlp::FWD_THREADS), 0, stream, ba);
+  mlp::DwArgs da{B, w.chunk, w.h0, w.h1, w.h2, w.h3, w.z1, w.z2, w.z3, d4, w.part};
+  hipLaunchKernelGGL(mlp::mlp_dw_kernel, dim3(w.nchunk, 4), dim3(mlp::DW_THREADS), 0, stream, da);
+}
+
+}  // namespace
+
+extern "C" {
+
+ism_status ism_surrogate_create(ism_surrogate **out, uint64_t seed) {
+  g_err.clear();
+  if (!out) return fail(ISM_E_ARG, "out is NULL");
+  *out = nullptr;
+  DevState *st;
+  int dev = 0;
+  if (ism_status s = current_state(&st, &dev)) return s;
+  ism_surrogate *m = new ism_surrogate();
+  m->device = dev;
+  m->num_cu = std::max(st->num_cu, 1);
+  for (int k = 0; k < 26; ++k) m->norm_host[k] = (k >= 10 && k < 20) || k >= 23 ? 1.f : 0.f;
+  std::vector<float> theta(mlp::NPARAM, 0.f);
+  const int fan_in[4] = {mlp::NIN, mlp::NH, mlp::NH, mlp::NH};
+  const int woff[4] = {mlp::OFF_W1, mlp::OFF_W2, mlp::OFF_W3, mlp::OFF_W4};
+  const int wlen[4] = {mlp::NH * mlp::NIN, mlp::NH * mlp::NH, mlp::NH * mlp::NH, mlp::NOUT * mlp::NH};
+  for (int l = 0; l < 4; ++l) {
+    const double lim = std::sqrt(6.0 / fan_in[l]);
+    for (int i = 0; i < wlen[l]; ++i) {
+      const uint64_t u = splitmix64(seed * 0x100000001B3ull + (uint64_t)(woff[l] + i));
+      const double x = (double)(u >> 11) * (1.0 / 9007199254740992.0);
+      theta[woff[l] + i] = (float)(lim * (2.0 * x - 1.0));
+    }
+  }
+  hipError_t e = hipMalloc(&m->params, 4 * (size_t)mlp::NPARAM * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&m->img, mlp::FI_BYTES + mlp::BI_BYTES);
+  if (e == hipSuccess) e = hipMalloc(&m->norm, mlp::NRM_FLOATS * sizeof(float));
+  if (e == hipSuccess) e = hipMemset(m->params, 0, 4 * (size_t)mlp::NPARAM * sizeof(float));
+  if (e == hipSuccess) e = hipMemcpy(m->params, theta.data(), mlp::NPARAM * sizeof(float), hipMemcpyHostToDevice);
+  ism_status rc = e == hipSuccess ? ISM_OK : fail(ISM_E_NOMEM, std::string("surrogate: ") + hipGetErrorString(e));
+  if (rc == ISM_OK) rc = surr_upload_norm(m);
+  if (rc == ISM_OK) rc = surr_pack(m);
+  if (rc != ISM_OK) {
+    ism_surrogate_destroy(m);
+    return rc;
+  }
+  *out = m;
+  return ISM_OK;
+}
+
+ism_status ism_surrogate_destroy(ism_surrogate *m) {
+  if (!m) return ISM_OK;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(m->device);
+  (void)hipDeviceSynchronize();
+  if (m->params) (void)hipFree(m->params);
+  if (m->img) (void)hipFree(m->img);
+  if (m->norm) (void)hipFree(m->norm);
+  if (m->work) (void)hipFree(m->work);
+  (void)hipSetDevice(prev);
+  delete m;
+  return ISM_OK;
+}
+
+ism_status ism_surrogate_set_norm(ism_surrogate *m, const float *mu_x, const float *sd_x, const float *mu_y,
+                                  const float *sd_y) {
+  g_err.clear();
+  if (ism_status s = surr_check(m)) return s;
+  if (!mu_x || !sd_x || !mu_y || !sd_y) return fail(ISM_E_ARG, "a normalisation array is NULL");
+  for (int k = 0; k < mlp::NIN; ++k)
+    if (!std::isfinite(mu_x[k]) || !(sd_x[k] > 0.f) || !std::isfinite(sd_x[k]))
+      return fail(ISM_E_ARG, "mu_x must be finite and sd_x finite and > 0");
+  for (int k = 0; k < mlp::NOUT; ++k)
+    if (!std::isfinite(mu_y[k]) || !(sd_y[k] > 0.f) || !std::isfinite(sd_y[k]))
+      return fail(ISM_E_ARG, "mu_y must be finite and sd_y finite and > 0");
+  HIP_TRY(hipDeviceSynchronize());
+  std::memcpy(m->norm_host, mu_x, 10 * sizeof(float));
+  std::memcpy(m->norm_host + 10, sd_x, 10 * sizeof(float));
+  std::memcpy(m->norm_host + 20, mu_y, 3 * sizeof(float));
+  std::memcpy(m->norm_host + 23, sd_y, 3 * sizeof(float));
+  return surr_upload_norm(m);
+}
+
+ism_status ism_surrogate_forward(ism_surrogate *m, const float *X, float *Y, int64_t B, hipStream_t stream) {
+  g_err.clear();
+  if (ism_status s = surr_check(m)) return s;
+  if (B < 0) return fail(ISM_E_ARG, "B must be >= 0");
+  if (B == 0) return ISM_OK;
+  if (!X || !Y) return fail(ISM_E_ARG, "X and Y must not be NULL");
+  mlp::FwdArgs fa{};
+  fa.X = X; fa.B = B; fa.fimg = m->fimg(); fa.norm = m->norm; fa.Y = Y;
+  hipLaunchKernelGGL(mlp::mlp_fwd_kernel<0>, dim3(fwd_grid(m, B)), dim3(mlp::FWD_THREADS), 0, stream, fa);
+  HIP_TRY(hipGetLastError());
+  return ISM_OK;
+}
+
+ism_status ism_surrogate_backward(ism_surrogate *m, const float *X, const float *dY, float *grad, int64_t B,
+                                  hipStream_t stream) {
+  g_err.clear();
+  if (ism_status s = surr_check(m)) return s;
+  if (B < 1) return fail(ISM_E_ARG, "B must be >= 1");
+  if (!X || !dY || !grad) return fail(ISM_E_ARG, "X, dY and grad must not be NULL");
+  SurrWork w;
+  if (ism_status s = surr_work(m, B, w)) return s;
+  surr_fwd_bwd(m, X, nullptr, dY, B, w, stream);
+  mlp::AdamArgs aa{};
+  aa.part = w.part; aa.nchunk = w.nchunk; aa.grad = grad; aa.adam = 0;
+  hipLaunchKernelGGL(mlp::mlp_reduce_adam_kernel, dim3((mlp::NPARAM + 255) / 256), dim3(256), 0, stream, aa);
+  HIP_TRY(hipGetLastError());
+  return ISM_OK;
+}
+
+ism_status ism_surrogate_train_step(ism_surrogate *m, const float *X, const float *Y, int64_t B, float lr,
+                                    float *loss_dev, hipStream_t stream) {
+  g_err.clear();
+  if (ism_status s = surr_check(m)) return s;
+  if (B < 1) return fail(ISM_E_ARG, "B must be >= 1");
+  if (!X || !Y) return fail(ISM_E_ARG, "X and Y must not be NULL");
+  if (!std::isfinite(lr) || lr < 0.f) return fail(ISM_E_ARG, "lr must be finite and >= 0");
+  SurrWork w;
+  if (ism_status s = surr_work(m, B, w)) return s;
+  surr_fwd_bwd(m, X, Y, nullptr, B, w, stream);
+  const int64_t t = m->step + 1;
+  mlp::AdamArgs aa{};
+  aa.part = w.part; aa.nchunk = w.nchunk; aa.theta = m->theta(); aa.m = m->adam_m(); aa.v = m->adam_v();
+  aa.fimg = m->fimg(); aa.bimg = m->bimg(); aa.lr = lr; aa.b1 = 0.9f; aa.b2 = 0.999f; aa.eps = 1e-8f;
+  aa.bc1 = (float)(1.0 - std::pow(0.9, (double)t));
+  aa.bc2 = (float)(1.0 - std::pow(0.999, (double)t));
+  aa.adam = 1;
+  if (loss_dev)
+    hipLaunchKernelGGL(mlp::mlp_loss_kernel, dim3(1), dim3(256), 0, stream, w.loss_part,
+                       w.grid_fwd * mlp::FWD_WAVES, 1.0 / (3.0 * (double)B), loss_dev);
+  hipLaunchKernelGGL(mlp::mlp_reduce_adam_kernel, dim3((mlp::NPARAM + 255) / 256), dim3(256), 0, stream, aa);
+  HIP_TRY(hipGetLastError());
+  m->step = t;
+  return ISM_OK;
+}
+
+ism_status ism_surrogate_get_params(const ism_surrogate *m, float *flat) {
+  g_err.clear();
+  if (ism_status s = surr_check(m)) return s;
+  if (!flat) return fail(ISM_E_ARG, "flat is NULL");
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(flat, m->params, 3 * (size_t)mlp::NPARAM * sizeof(float), hipMemcpyDeviceToHost));
+  flat[3 * mlp::NPARAM] = (float)m->step;
+  std::memcpy(flat + 3 * mlp::NPARAM + 1, m->norm_host, sizeof(m->norm_host));
+  return ISM_OK;
+}
+
+ism_status ism_surrogate_set_params(ism_surrogate *m, const float *flat) {
+  g_err.clear();
+  if (ism_status s = surr_check(m)) return s;
+  if (!flat) return fail(ISM_E_ARG, "flat is NULL");
+  for (size_t i = 0; i < (size_t)ISM_SURR_STATE_FLOATS; ++i)
+    if (!std::isfinite(flat[i])) return fail(ISM_E_ARG, "state holds a non-finite value");
+  const float step = flat[3 * mlp::NPARAM];
+  if (step < 0.f || step != std::floor(step)) return fail(ISM_E_ARG, "step must be a whole number >= 0");
+  const float *nh = flat + 3 * mlp::NPARAM + 1;
+  for (int k = 10; k < 20; ++k)
+    if (!(nh[k] > 0.f)) return fail(ISM_E_ARG, "sd_x must be > 0");
+  for (int k = 23; k < 26; ++k)
+    if (!(nh[k] > 0.f)) return fail(ISM_E_ARG, "sd_y must be > 0");
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(m->params, flat, 3 * (size_t)mlp::NPARAM * sizeof(float), hipMemcpyHostToDevice));
+  m->step = (int64_t)step;
+  std::memcpy(m->norm_host, nh, sizeof(m->norm_host));
+  if (ism_status s = surr_upload_norm(m)) return s;
+  return surr_pack(m);
 }
 
 }  // extern "C"

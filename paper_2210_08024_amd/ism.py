@@ -82,15 +82,28 @@ def lib():
         L.ism_columns6.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Params), ctypes.c_int] + [_vp] * 10
         L.ism_rates.argtypes = [ctypes.POINTER(_Params), ctypes.c_int, _i64] + [_vp] * 13
         L.ism_chem_cool_step.argtypes = [ctypes.POINTER(_Params), ctypes.c_int, _i64, _dp] + [_vp] * 17
-        for name in ("ism_init", "ism_shutdown", "ism_columns6", "ism_rates", "ism_chem_cool_step"):
+        L.ism_surrogate_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_uint64]
+        L.ism_surrogate_destroy.argtypes = [_vp]
+        L.ism_surrogate_set_norm.argtypes = [_vp] * 5
+        L.ism_surrogate_forward.argtypes = [_vp, _vp, _vp, _i64, _vp]
+        L.ism_surrogate_backward.argtypes = [_vp, _vp, _vp, _vp, _i64, _vp]
+        L.ism_surrogate_train_step.argtypes = [_vp, _vp, _vp, _i64, ctypes.c_float, _vp, _vp]
+        L.ism_surrogate_get_params.argtypes = [_vp, _vp]
+        L.ism_surrogate_set_params.argtypes = [_vp, _vp]
+        for name in ("ism_init", "ism_shutdown", "ism_columns6", "ism_rates", "ism_chem_cool_step") + SURROGATE_SYMBOLS:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
 
 
+SURROGATE_SYMBOLS = ("ism_surrogate_create", "ism_surrogate_destroy", "ism_surrogate_set_norm",
+                     "ism_surrogate_forward", "ism_surrogate_backward", "ism_surrogate_train_step",
+                     "ism_surrogate_get_params", "ism_surrogate_set_params")
+
+
 def exported_symbols():
     return ["ism_params_default", "ism_init", "ism_shutdown", "ism_last_error", "ism_ndiag", "ism_diag_name",
-            "ism_columns6", "ism_rates", "ism_chem_cool_step"]
+            "ism_columns6", "ism_rates", "ism_chem_cool_step"] + list(SURROGATE_SYMBOLS)
 
 
 def _check(rc):
@@ -206,3 +219,86 @@ def chem_cool_step(n, T, xH2, xHp, rad, dt_s, params, prec=F64, want=("xCp", "xC
         _ptr(g("nsub"), torch.int32, N, "nsub", True), _ptr(g("status"), torch.uint8, N, "status", True),
         _stream(stream)))
     return out
+
+
+# ---------------------------------------------------------------- learned surrogate
+SURR_NIN, SURR_NOUT, SURR_NPARAM = 10, 3, 34819
+SURR_STATE_FLOATS = 3 * SURR_NPARAM + 1 + 26
+
+
+class Surrogate:
+    """Handle of an ism_surrogate (10 -> 128 -> 128 -> 128 -> 3 SiLU MLP on the matrix cores)."""
+
+    def __init__(self, seed=0, device=None):
+        dev = torch.cuda.current_device() if device is None else int(device)
+        if dev not in _inited:
+            init(dev)
+        self.device = dev
+        h = ctypes.c_void_p()
+        with torch.cuda.device(dev):
+            _check(lib().ism_surrogate_create(ctypes.byref(h), ctypes.c_uint64(seed)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ism_surrogate_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_norm(self, mu_x, sd_x, mu_y, sd_y):
+        arrs = [(ctypes.c_float * k)(*[float(v) for v in a]) for a, k in
+                ((mu_x, 10), (sd_x, 10), (mu_y, 3), (sd_y, 3))]
+        _check(lib().ism_surrogate_set_norm(self._h, *[ctypes.cast(a, _vp) for a in arrs]))
+
+    def forward(self, X, Y=None, stream=None):
+        B = X.shape[0]
+        if Y is None:
+            Y = torch.empty((B, 3), dtype=torch.float32, device=X.device)
+        _check(lib().ism_surrogate_forward(self._h, _ptr(X, torch.float32, B * 10, "X"),
+                                           _ptr(Y, torch.float32, B * 3, "Y"), B, _stream(stream)))
+        return Y
+
+    def backward(self, X, dY, grad=None, stream=None):
+        B = X.shape[0]
+        if grad is None:
+            grad = torch.empty(SURR_NPARAM, dtype=torch.float32, device=X.device)
+        _check(lib().ism_surrogate_backward(self._h, _ptr(X, torch.float32, B * 10, "X"),
+                                            _ptr(dY, torch.float32, B * 3, "dY"),
+                                            _ptr(grad, torch.float32, SURR_NPARAM, "grad"), B, _stream(stream)))
+        return grad
+
+    def train_step(self, X, Y, lr, loss=None, stream=None):
+        B = X.shape[0]
+        _check(lib().ism_surrogate_train_step(self._h, _ptr(X, torch.float32, B * 10, "X"),
+                                              _ptr(Y, torch.float32, B * 3, "Y"), B, ctypes.c_float(lr),
+                                              _ptr(loss, torch.float32, 1, "loss", allow_none=True),
+                                              _stream(stream)))
+        return loss
+
+    def get_params(self):
+        import numpy as np
+        out = np.empty(SURR_STATE_FLOATS, dtype=np.float32)
+        _check(lib().ism_surrogate_get_params(self._h, out.ctypes.data))
+        return out
+
+    def set_params(self, flat):
+        import numpy as np
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        if a.size != SURR_STATE_FLOATS:
+            raise ValueError(f"state has {a.size} floats, expected {SURR_STATE_FLOATS}")
+        _check(lib().ism_surrogate_set_params(self._h, a.ctypes.data))
+
+    @staticmethod
+    def state(theta, m=None, v=None, step=0, mu_x=None, sd_x=None, mu_y=None, sd_y=None):
+        """Assemble a checkpoint vector (layout of ism_surrogate_get/set_params)."""
+        import numpy as np
+        z = np.zeros(SURR_NPARAM)
+        parts = [theta, z if m is None else m, z if v is None else v, [step],
+                 np.zeros(10) if mu_x is None else mu_x, np.ones(10) if sd_x is None else sd_x,
+                 np.zeros(3) if mu_y is None else mu_y, np.ones(3) if sd_y is None else sd_y]
+        return np.concatenate([np.asarray(p, dtype=np.float64).ravel() for p in parts]).astype(np.float32)

@@ -96,3 +96,24 @@ def test_init_rejects_missing_or_bad_coefficient_file(tmp_path):
     bad.write_text('{"printed": {}, "standin": {}, "tables": {}}')
     assert ism.lib().ism_init(0, str(bad).encode()) == -5
     assert "missing coefficient" in ism.lib().ism_last_error().decode()
+
+
+def test_surrogate_entry_points_reject_null_handles():
+    L = ism.lib()
+    assert L.ism_surrogate_create(None, 0) == -1
+    assert L.ism_surrogate_destroy(None) == 0
+    assert L.ism_surrogate_set_norm(None, None, None, None, None) == -1
+    assert L.ism_surrogate_forward(None, None, None, 4, None) == -1
+    assert "NULL" in L.ism_last_error().decode()
+    assert L.ism_surrogate_backward(None, None, None, None, 4, None) == -1
+    assert L.ism_surrogate_train_step(None, None, None, 4, ctypes.c_float(1e-3), None, None) == -1
+    assert L.ism_surrogate_get_params(None, None) == -1
+    assert L.ism_surrogate_set_params(None, None) == -1
+
+
+def test_surrogate_sizes_match_the_reference_network():
+    from oracle import mlp
+    assert ism.SURR_NPARAM == mlp.n_params() == 34819
+    text = open(os.path.join(ROOT, "include", "ism.h")).read()
+    assert "#define ISM_SURR_NPARAM 34819" in text
+    assert ism.SURR_STATE_FLOATS == 3 * 34819 + 27
