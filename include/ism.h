@@ -22,7 +22,9 @@
  *    launch/runtime errors return ISM_E_DEVICE.  ism_last_error() gives the message
  *    (thread-local).  Per-cell numerical trouble never fails a call: it is reported
  *    in the per-cell status bits below and the call returns ISM_OK.
- *  - Thread safety: concurrent calls on different streams are safe after ism_init.
+ *  - Thread safety: after ism_init, ism_rates and ism_chem_cool_step may run concurrently on
+ *    different streams.  ism_columns6 and ism_chem_cool_step_surrogate use a per-device
+ *    scratch buffer: their calls on one device must not overlap in time.
  */
 #ifndef ISM_H
 #define ISM_H
@@ -201,6 +203,41 @@ ism_status ism_surrogate_train_step(ism_surrogate *m, const float *X, const floa
  * device; set copies synchronously and rebuilds the BF16 weight copies. */
 ism_status ism_surrogate_get_params(const ism_surrogate *m, float *flat);
 ism_status ism_surrogate_set_params(ism_surrogate *m, const float *flat);
+
+/* Training pairs for the surrogate: X [ncell][10] network inputs from the pre-step state
+ * (n, T0, xH2_0, xHp_0), radiation (chi_PE, phi_LyC (nullable = 0), xi_cr, N_eff; double for
+ * F64, float for MIXED), Z'_g and dt; Y [ncell][3] targets (x_H2, x_H+, log10 T) from the
+ * post-step state (T1, xH2_1, xHp_1), skipped when Y is NULL.  Inputs, in order:
+ * log10 n, log10 T, log10 max(chi_PE, 1e-10), log10 max(phi_LyC, 1), log10 max(xi_cr, 1e-30),
+ * log10 Z'_g, x_H2, x_H+, log10 max(N_eff, 1e17 cm^-2), log10(dt / 1 yr).  dt_s > 0. */
+ism_status ism_surrogate_pairs(const ism_params *p, ism_precision prec, int64_t ncell, double dt_s,
+                               const double *n, const double *T0, const double *xH2_0,
+                               const double *xHp_0, const void *chi_PE, const void *phi_LyC,
+                               const void *xi_cr, const void *N_eff, const double *T1,
+                               const double *xH2_1, const double *xHp_1, float *X, float *Y,
+                               hipStream_t stream);
+
+/* The source step with the surrogate in front of the plain solver (MIXED precision only:
+ * radiation and x_C+, x_CO, x_e float).  Arguments as for ism_chem_cool_step.
+ * For every cell the network predicts the post-step (x_H2, x_H+, T) from the inputs above;
+ * the prediction seeds a Newton solve for the equilibrium of (dT/dt, C_H2, C_H+) (Eqs.
+ * e:ODE1, e:HH, e:HII; Jacobian by forward differences).  The root is accepted only where
+ * the plain step's result no longer depends on its substep path: Newton converged to
+ * accept_tol (relative), every eigenvalue of the Jacobian at the root has real part below
+ * -20/dt, the root's T is within a factor e^0.1 of the prediction, and dT/dt keeps the sign
+ * of T_root - T along four temperatures from T to T_root.  Accepted cells return the root
+ * with equilibrium C/O/e there, nsub = 0, status = 0; every other cell runs the plain
+ * MIXED step and has ISM_ST_FALLBACK set.  m may be NULL: the seed is then the input state
+ * itself (the method without the network).  n_fallback_dev (device int64, nullable)
+ * receives the number of plain-step cells.  accept_tol in (0, 1e-3]; ncell < 2^31.
+ * Uses a per-device scratch buffer: calls on one device must not overlap in time. */
+ism_status ism_chem_cool_step_surrogate(ism_surrogate *m, const ism_params *p, int64_t ncell,
+                                        double dt_s, const double *n, double *T, double *xH2,
+                                        double *xHp, const void *chi_PE, const void *chi_LW,
+                                        const void *chi_H2, const void *chi_C, const void *phi_LyC,
+                                        const void *xi_cr, const void *N_eff, void *xCp, void *xCO,
+                                        void *xe, int32_t *nsub, uint8_t *status, double accept_tol,
+                                        int64_t *n_fallback_dev, hipStream_t stream);
 
 #ifdef __cplusplus
 }

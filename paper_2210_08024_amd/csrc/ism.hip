@@ -20,6 +20,7 @@
 #include "kernels_step.h"
 #include "kernels_columns.h"
 #include "kernels_mlp.h"
+#include "kernels_surr.h"
 
 using namespace ism;
 using ism::host::coef_to_f32;
@@ -44,6 +45,8 @@ struct DevState {
   size_t scratch_bytes = 0;
   int64_t *queues = nullptr;
   unsigned qnext = 0;
+  void *sscratch = nullptr;  // surrogate step: predictions + rejected list
+  size_t sscratch_bytes = 0;
   int num_cu = 0;
   int occ64 = 0, occ32 = 0;  // resident 256-thread blocks per CU of the persistent step kernels
   bool simple_step = false;   // ISM_STEP_KERNEL=simple selects the one-lane-per-cell grid
@@ -115,6 +118,20 @@ ism_status scratch(DevState *st, size_t bytes, void **out) {
     st->scratch_bytes = bytes;
   }
   *out = st->scratch;
+  return ISM_OK;
+}
+
+ism_status surr_scratch(DevState *st, size_t bytes, void **out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (st->sscratch_bytes < bytes) {
+    if (st->sscratch) (void)hipFree(st->sscratch);
+    st->sscratch = nullptr;
+    st->sscratch_bytes = 0;
+    hipError_t e = hipMalloc(&st->sscratch, bytes);
+    if (e != hipSuccess) return fail(ISM_E_NOMEM, std::string("surrogate scratch: ") + hipGetErrorString(e));
+    st->sscratch_bytes = bytes;
+  }
+  *out = st->sscratch;
   return ISM_OK;
 }
 
@@ -198,6 +215,7 @@ ism_status ism_shutdown(void) {
     if (kv.second.tab32) (void)hipFree(kv.second.tab32);
     if (kv.second.scratch) (void)hipFree(kv.second.scratch);
     if (kv.second.queues) (void)hipFree(kv.second.queues);
+    if (kv.second.sscratch) (void)hipFree(kv.second.sscratch);
   }
   g_dev.clear();
   (void)hipSetDevice(prev);
@@ -326,7 +344,8 @@ ism_status ism_chem_cool_step(const ism_params *p, ism_precision prec, int64_t n
     StepArgs<double> a{ncell, dt_s, n, T, xH2, xHp, (const double *)chi_PE, (const double *)chi_LW,
                        (const double *)chi_H2, (const double *)chi_C, (const double *)phi_LyC,
                        (const double *)xi_cr, (const double *)N_eff, (double *)xCp, (double *)xCO, (double *)xe,
-                       nsub, status, st->tab64, make_par<double>(p, g_host_coef), make_par<double>(p, g_host_coef), q};
+                       nsub, status, st->tab64, make_par<double>(p, g_host_coef), make_par<double>(p, g_host_coef), q,
+                       nullptr, nullptr, 0u};
     if (st->simple_step) {
       hipLaunchKernelGGL(step_simple_kernel<double>, dim3((unsigned)want), dim3(256), 0, stream, a);
     } else {
@@ -338,7 +357,8 @@ ism_status ism_chem_cool_step(const ism_params *p, ism_precision prec, int64_t n
     StepArgs<float> a{ncell, dt_s, n, T, xH2, xHp, (const float *)chi_PE, (const float *)chi_LW,
                       (const float *)chi_H2, (const float *)chi_C, (const float *)phi_LyC,
                       (const float *)xi_cr, (const float *)N_eff, (float *)xCp, (float *)xCO, (float *)xe,
-                      nsub, status, st->tab32, make_par<float>(p, g_host_coef), make_par<double>(p, g_host_coef), q};
+                      nsub, status, st->tab32, make_par<float>(p, g_host_coef), make_par<double>(p, g_host_coef), q,
+                      nullptr, nullptr, 0u};
     if (st->simple_step) {
       hipLaunchKernelGGL(step_simple_kernel<float>, dim3((unsigned)want), dim3(256), 0, stream, a);
     } else {
@@ -645,6 +665,99 @@ ism_status ism_surrogate_set_params(ism_surrogate *m, const float *flat) {
   std::memcpy(m->norm_host, nh, sizeof(m->norm_host));
   if (ism_status s = surr_upload_norm(m)) return s;
   return surr_pack(m);
+}
+
+ism_status ism_surrogate_pairs(const ism_params *p, ism_precision prec, int64_t ncell, double dt_s, const double *n,
+                               const double *T0, const double *xH2_0, const double *xHp_0, const void *chi_PE,
+                               const void *phi_LyC, const void *xi_cr, const void *N_eff, const double *T1,
+                               const double *xH2_1, const double *xHp_1, float *X, float *Y, hipStream_t stream) {
+  g_err.clear();
+  if (ism_status s = check_params(p)) return s;
+  if (prec != ISM_PREC_F64 && prec != ISM_PREC_MIXED) return fail(ISM_E_ARG, "invalid precision");
+  if (ncell < 0) return fail(ISM_E_ARG, "ncell must be >= 0");
+  if (!(dt_s > 0.0) || !std::isfinite(dt_s)) return fail(ISM_E_ARG, "dt_s must be finite and > 0");
+  if (ncell == 0) return ISM_OK;
+  if (!n || !T0 || !xH2_0 || !xHp_0 || !chi_PE || !xi_cr || !N_eff || !X)
+    return fail(ISM_E_ARG, "a required array is NULL");
+  if (Y && (!T1 || !xH2_1 || !xHp_1)) return fail(ISM_E_ARG, "targets need T1, xH2_1 and xHp_1");
+  DevState *st;
+  if (ism_status s = current_state(&st)) return s;
+  const float lZg = (float)std::log10(p->Zg), ldt = (float)std::log10(dt_s / 3.15576e7);
+  const dim3 grid((unsigned)((ncell + 255) / 256));
+  if (prec == ISM_PREC_F64) {
+    mlp::CellIn<double> c{n, T0, xH2_0, xHp_0, (const double *)chi_PE, (const double *)phi_LyC,
+                          (const double *)xi_cr, (const double *)N_eff, lZg, ldt};
+    hipLaunchKernelGGL(mlp::mlp_pairs_kernel<double>, grid, dim3(256), 0, stream, c, ncell, T1, xH2_1, xHp_1, X, Y);
+  } else {
+    mlp::CellIn<float> c{n, T0, xH2_0, xHp_0, (const float *)chi_PE, (const float *)phi_LyC,
+                         (const float *)xi_cr, (const float *)N_eff, lZg, ldt};
+    hipLaunchKernelGGL(mlp::mlp_pairs_kernel<float>, grid, dim3(256), 0, stream, c, ncell, T1, xH2_1, xHp_1, X, Y);
+  }
+  HIP_TRY(hipGetLastError());
+  return ISM_OK;
+}
+
+ism_status ism_chem_cool_step_surrogate(ism_surrogate *m, const ism_params *p, int64_t ncell, double dt_s,
+                                        const double *n, double *T, double *xH2, double *xHp, const void *chi_PE,
+                                        const void *chi_LW, const void *chi_H2, const void *chi_C,
+                                        const void *phi_LyC, const void *xi_cr, const void *N_eff, void *xCp,
+                                        void *xCO, void *xe, int32_t *nsub, uint8_t *status, double accept_tol,
+                                        int64_t *n_fallback_dev, hipStream_t stream) {
+  g_err.clear();
+  if (m) {
+    if (ism_status s = surr_check(m)) return s;
+  }
+  if (ism_status s = check_params(p)) return s;
+  if (ncell < 0 || ncell > (int64_t)INT32_MAX) return fail(ISM_E_ARG, "ncell must be in [0, 2^31)");
+  if (!(dt_s >= 0.0) || !std::isfinite(dt_s)) return fail(ISM_E_ARG, "dt_s must be finite and >= 0");
+  if (!(accept_tol > 0.0 && accept_tol <= 1e-3)) return fail(ISM_E_ARG, "accept_tol must be in (0, 1e-3]");
+  if (ncell == 0) {
+    if (n_fallback_dev) hipLaunchKernelGGL(queue_init_kernel, dim3(1), dim3(1), 0, stream, n_fallback_dev, (int64_t)0);
+    HIP_TRY(hipGetLastError());
+    return ISM_OK;
+  }
+  if (!n || !T || !xH2 || !xHp || !chi_PE || !chi_LW || !chi_H2 || !chi_C || !xi_cr || !N_eff)
+    return fail(ISM_E_ARG, "a required array is NULL");
+  DevState *st;
+  if (ism_status s = current_state(&st)) return s;
+  const size_t pred_bytes = m ? align256((size_t)ncell * 3 * sizeof(float)) : 0;
+  const size_t rej_bytes = align256((size_t)ncell * sizeof(int32_t));
+  void *buf;
+  if (ism_status s = surr_scratch(st, pred_bytes + rej_bytes + 256, &buf)) return s;
+  float *pred = m ? (float *)buf : nullptr;
+  int32_t *rej = (int32_t *)((uint8_t *)buf + pred_bytes);
+  unsigned long long *nrej = (unsigned long long *)((uint8_t *)buf + pred_bytes + rej_bytes);
+  hipLaunchKernelGGL(counter_reset_kernel, dim3(1), dim3(1), 0, stream, nrej);
+  if (m) {
+    mlp::FwdArgs fa{};
+    fa.cin = mlp::CellIn<float>{n, T, xH2, xHp, (const float *)chi_PE, (const float *)phi_LyC,
+                                (const float *)xi_cr, (const float *)N_eff, (float)std::log10(p->Zg),
+                                (float)std::log10(std::max(dt_s, 1e-300) / 3.15576e7)};
+    fa.B = ncell; fa.fimg = m->fimg(); fa.norm = m->norm; fa.Y = pred;
+    hipLaunchKernelGGL(mlp::mlp_fwd_kernel<3>, dim3(fwd_grid(m, ncell)), dim3(mlp::FWD_THREADS), 0, stream, fa);
+  }
+  const ParT<float> pr = make_par<float>(p, g_host_coef);
+  const ParT<double> pd = make_par<double>(p, g_host_coef);
+  AcceptArgs aa{ncell, dt_s, n, T, xH2, xHp, (const float *)chi_PE, (const float *)chi_LW, (const float *)chi_H2,
+                (const float *)chi_C, (const float *)phi_LyC, (const float *)xi_cr, (const float *)N_eff,
+                (float *)xCp, (float *)xCO, (float *)xe, nsub, status, pred, st->tab32, pr, pd, rej, nrej,
+                20.0, accept_tol, 6, 1e-3};
+  hipLaunchKernelGGL(accept_kernel, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, stream, aa);
+  int64_t *q;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    q = st->queues + (st->qnext++ % QUEUE_SLOTS);
+  }
+  StepArgs<float> sa{ncell, dt_s, n, T, xH2, xHp, (const float *)chi_PE, (const float *)chi_LW,
+                     (const float *)chi_H2, (const float *)chi_C, (const float *)phi_LyC,
+                     (const float *)xi_cr, (const float *)N_eff, (float *)xCp, (float *)xCO, (float *)xe,
+                     nsub, status, st->tab32, pr, pd, q, rej, nrej, (uint32_t)ISM_ST_FALLBACK};
+  const int64_t grid = std::min<int64_t>((ncell + 255) / 256, (int64_t)st->num_cu * std::max(st->occ32, 1));
+  hipLaunchKernelGGL(queue_init_kernel, dim3(1), dim3(1), 0, stream, q, grid * 256);
+  hipLaunchKernelGGL(step_queue_kernel<float>, dim3((unsigned)grid), dim3(256), 0, stream, sa);
+  if (n_fallback_dev) hipLaunchKernelGGL(counter_copy_kernel, dim3(1), dim3(1), 0, stream, nrej, n_fallback_dev);
+  HIP_TRY(hipGetLastError());
+  return ISM_OK;
 }
 
 }  // extern "C"

@@ -81,12 +81,41 @@ __device__ __forceinline__ int opaque_zero() {
 
 constexpr int FWD_THREADS = 512, FWD_WAVES = FWD_THREADS / 64, NT = 4, WTILE = 16 * NT;
 
+// Network inputs built from a cell's state, radiation and the step length (float logs):
+//   0 log10 n, 1 log10 T, 2 log10 max(chi_PE, 1e-10), 3 log10 max(phi_LyC, 1),
+//   4 log10 max(xi_cr, 1e-30), 5 log10 Z'_g, 6 x_H2, 7 x_H+, 8 log10 max(N_eff, 1e17),
+//   9 log10 (dt / yr).  Outputs: post-step x_H2, x_H+, log10 T.
+template <class R>
+struct CellIn {
+  const double *n, *T, *xH2, *xHp;
+  const R *chiPE, *phi, *xi, *Neff;  // phi may be null (= 0)
+  float lZg, ldt;
+};
+
+template <class R>
+__device__ __forceinline__ float cell_feature(const CellIn<R> &c, int64_t i, int k) {
+  switch (k) {
+    case 0: return log10f((float)c.n[i]);
+    case 1: return log10f((float)c.T[i]);
+    case 2: return log10f(fmaxf((float)c.chiPE[i], 1e-10f));
+    case 3: return log10f(fmaxf(c.phi ? (float)c.phi[i] : 0.f, 1.f));
+    case 4: return log10f(fmaxf((float)c.xi[i], 1e-30f));
+    case 5: return c.lZg;
+    case 6: return (float)c.xH2[i];
+    case 7: return (float)c.xHp[i];
+    case 8: return log10f(fmaxf((float)c.Neff[i], 1e17f));
+    case 9: return c.ldt;
+    default: return 0.f;
+  }
+}
+
 struct FwdArgs {
-  const float *X;  // [B][10] raw features
+  const float *X;  // [B][10] raw features (modes 0-2)
+  CellIn<float> cin;  // mode 3: features built from the cell arrays
   int64_t B;
   const uint8_t *fimg;
   const float *norm;
-  float *Y;        // mode 0: [B][3] de-standardised predictions
+  float *Y;        // modes 0, 3: [B][3] de-standardised predictions
   const float *Yt; // mode 2: [B][3] raw targets
   float dscale;    // mode 2: 2 / (3B)
   float *d4;       // mode 2: [B][3] dL/dy (standardised outputs)
@@ -125,7 +154,7 @@ __device__ __forceinline__ void fwd_hidden(const __bf16 *W, const float *b, cons
       h.z = (__bf16)(z.z * sigmoid_f(z.z));
       h.w = (__bf16)(z.w * sigmoid_f(z.w));
       hout[m][t] = h;
-      if (MODE >= 1) {
+      if (MODE == 1 || MODE == 2) {
         const int64_t n = base + 16 * t + r;
         if (n < B) {
           *(f32x4 *)(zst + n * NH + 16 * m + 4 * g) = z;
@@ -137,7 +166,8 @@ __device__ __forceinline__ void fwd_hidden(const __bf16 *W, const float *b, cons
 }
 
 // MODE 0: inference (Y).  MODE 1: store activations for a backward pass.  MODE 2: also the loss
-// against targets Yt and the output error signal d4.
+// against targets Yt and the output error signal d4.  MODE 3: inference on inputs built from
+// cell arrays (CellIn).
 template <int MODE>
 __global__ __launch_bounds__(FWD_THREADS) void mlp_fwd_kernel(FwdArgs a) {
   __shared__ __align__(16) uint8_t smem[FI_BYTES];
@@ -170,7 +200,9 @@ __global__ __launch_bounds__(FWD_THREADS) void mlp_fwd_kernel(FwdArgs a) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int k = 4 * g + j;
-        v[j] = (n < a.B && k < NIN) ? (a.X[n * NIN + k] - mux[j]) * isdx[j] : 0.f;
+        float raw = 0.f;
+        if (n < a.B && k < NIN) raw = MODE == 3 ? cell_feature(a.cin, n, k) : a.X[n * NIN + k];
+        v[j] = (n < a.B && k < NIN) ? (raw - mux[j]) * isdx[j] : 0.f;
       }
       bf16x4 h;
       h.x = (__bf16)v[0];
@@ -178,7 +210,7 @@ __global__ __launch_bounds__(FWD_THREADS) void mlp_fwd_kernel(FwdArgs a) {
       h.z = (__bf16)v[2];
       h.w = (__bf16)v[3];
       x[t] = as_i16x4(h);
-      if (MODE >= 1 && n < a.B) *(bf16x4 *)(a.h0 + n * K1 + 4 * g) = h;
+      if ((MODE == 1 || MODE == 2) && n < a.B) *(bf16x4 *)(a.h0 + n * K1 + 4 * g) = h;
     }
     bf16x4 ha[8][NT], hb[8][NT];
     // layer 1 (K = 16, one 16x16x16 product per neuron block)
@@ -195,7 +227,7 @@ __global__ __launch_bounds__(FWD_THREADS) void mlp_fwd_kernel(FwdArgs a) {
         h.z = (__bf16)(z.z * sigmoid_f(z.z));
         h.w = (__bf16)(z.w * sigmoid_f(z.w));
         ha[m][t] = h;
-        if (MODE >= 1) {
+        if (MODE == 1 || MODE == 2) {
           const int64_t n = base + 16 * t + r;
           if (n < a.B) {
             *(f32x4 *)(a.z1 + n * NH + 16 * m + 4 * g) = z;
@@ -225,7 +257,7 @@ __global__ __launch_bounds__(FWD_THREADS) void mlp_fwd_kernel(FwdArgs a) {
 #pragma unroll
           for (int j = 0; j < NOUT; ++j) {
             const float y = acc[t][j] + bias[3 * NH + j];
-            if (MODE == 0) a.Y[n * NOUT + j] = y * a.norm[NRM_SDY + j] + a.norm[NRM_MUY + j];
+            if (MODE == 0 || MODE == 3) a.Y[n * NOUT + j] = y * a.norm[NRM_SDY + j] + a.norm[NRM_MUY + j];
             if (MODE == 2) {
               const float e = y - (a.Yt[n * NOUT + j] - a.norm[NRM_MUY + j]) * a.norm[NRM_ISDY + j];
               a.d4[n * NOUT + j] = e * a.dscale;
@@ -475,6 +507,21 @@ __device__ __forceinline__ void put_param(int p, float val, uint8_t *fimg, uint8
     bw[BI_W4T / 2 + i * 16 + o] = hv;
   } else {
     fb[3 * NH + p - OFF_B4] = val;
+  }
+}
+
+// Training pairs: inputs from a cell's pre-step state, targets from its post-step state.
+template <class R>
+__global__ void mlp_pairs_kernel(CellIn<R> c, int64_t N, const double *T1, const double *xH2_1,
+                                 const double *xHp_1, float *X, float *Y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+#pragma unroll
+  for (int k = 0; k < NIN; ++k) X[i * NIN + k] = cell_feature(c, i, k);
+  if (Y) {
+    Y[i * NOUT + 0] = (float)xH2_1[i];
+    Y[i * NOUT + 1] = (float)xHp_1[i];
+    Y[i * NOUT + 2] = log10f((float)T1[i]);
   }
 }
 

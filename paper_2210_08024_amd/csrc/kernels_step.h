@@ -40,6 +40,11 @@ struct StepArgs {
   ParT<R> pr;
   ParT<double> pd;
   int64_t *queue;  // persistent variant: next unclaimed cell (device counter), else unused
+  // persistent variant only: when idx is set, work item k is cell idx[k] and the item count
+  // is *count (read on the device); st_or is or-ed into every status written
+  const int32_t *idx;
+  const unsigned long long *count;
+  uint32_t st_or;
 };
 
 // Per-lane state of one cell while it is being subcycled.
@@ -146,7 +151,7 @@ __device__ __forceinline__ void cell_end(const StepArgs<R> &a, int64_t i, const 
   if (a.xCO) a.xCO[i] = s.e.xCO;
   if (a.xe) a.xe[i] = s.e.xe;
   if (a.nsub) a.nsub[i] = s.ns;
-  if (a.status) a.status[i] = (uint8_t)s.st;
+  if (a.status) a.status[i] = (uint8_t)(s.st | a.st_or);
 }
 
 template <class R>
@@ -180,14 +185,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
   __shared__ R s_tab[TAB_STEP];
   stage_tables(a.tab, s_tab);
   const int lane = threadIdx.x & 63;
+  const int64_t nitem = a.count ? (int64_t)*a.count : a.ncell;
   int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool active = cell < a.ncell;
+  bool active = cell < nitem;
   CellState<R> s;
-  if (active) cell_begin(a, cell, s, s_tab);
+  if (active) cell_begin(a, a.idx ? (int64_t)a.idx[cell] : cell, s, s_tab);
   while (__ballot(active) != 0) {
     bool need = false;
     if (active && cell_substep(a, s, s_tab)) {
-      cell_end(a, cell, s);
+      cell_end(a, a.idx ? (int64_t)a.idx[cell] : cell, s);
       need = true;
     }
     const uint64_t m = __ballot(need);
@@ -198,8 +204,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
       base = __shfl(base, leader, 64);
       if (need) {
         cell = (int64_t)base + __popcll(m & ((1ull << lane) - 1ull));
-        active = cell < a.ncell;
-        if (active) cell_begin(a, cell, s, s_tab);
+        active = cell < nitem;
+        if (active) cell_begin(a, a.idx ? (int64_t)a.idx[cell] : cell, s, s_tab);
         else active = false;
       }
     }

@@ -1,0 +1,278 @@
+// Acceptance of learned predictions for the source step.
+//
+// The plain subcycled step is path dependent wherever a cell's relaxation times are comparable
+// to dt, so a predicted post-step state can stand in for it only where the plain result no
+// longer depends on the path: all three variables (T, x_H2, x_H+) relax much faster than dt
+// and the cell ends at the equilibrium of the coupled system.  A prediction is accepted when
+//   1. Newton from the prediction converges to a root of
+//        g = (dT/dt, C_H2, C_H+) = (H mu_H / ((1.1 + x_e - x_H2) K), C_H2, C_H+)
+//      (Jacobian by forward differences, equilibrium C/O/e re-solved at every probe),
+//   2. every eigenvalue of the Jacobian at the root has real part below -fast/dt (Routh-Hurwitz
+//      on J + (fast/dt) I), so the linearised dynamics contract by e^-fast over the step,
+//   3. the root lies within a factor e^0.1 in T of the prediction (basin of the prediction),
+//   4. T moves from T_0 toward the root: dT/dt at the input state and at three temperatures
+//      log-spaced between T_0 and the root (abundances at the root) all have the sign of
+//      T_root - T_0, so no other thermal equilibrium lies between them,
+//   5. the plain step's own end state is at the root to the output tolerance.  Near the root
+//      the plain step's last substep is one long implicit jump whose coefficients are frozen
+//      at the state it starts from, so its end state lags the root by L' (Y_prev - Y_root),
+//      L' the sensitivity of that jump to its starting state.  L' is taken by forward
+//      differences of one substep of length dt started at the root and at the root perturbed
+//      in each variable; the starting state of the last jump lies between the input state and
+//      the root, so |Y_prev - Y_root| <= |Y_0 - Y_root| componentwise, and the cell is
+//      accepted when sum_v |L'_wv| |Y_0,v - Y_root,v| <= out_tol / 2 of each output's scale
+//      (and the unperturbed jump reproduces the root).
+// Accepted cells take the root (equilibrium C/O/e at the root); the others are appended to a
+// list for the plain step.  A cheap pre-test on the chemistry diagonal rejects most
+// non-equilibrium cells after a single probe.
+#pragma once
+#include "kernels_step.h"
+
+namespace ism {
+
+struct AcceptArgs {
+  int64_t ncell;
+  double dt;
+  const double *n;
+  double *T, *xH2, *xHp;
+  const float *chiPE, *chiLW, *chiH2, *chiC, *phi, *xi, *Neff;
+  float *xCp, *xCO, *xe;
+  int32_t *nsub;
+  uint8_t *status;
+  const float *pred;  // [ncell][3] predicted x_H2, x_H+, log10 T; null = the input state itself
+  const float *tab;
+  ParT<float> pr;
+  ParT<double> pd;
+  int32_t *rej;                 // rejected cells, compacted (order unspecified)
+  unsigned long long *nrej;     // number of rejected cells (device counter, zeroed before)
+  double fast;                  // required dt * rate margin
+  double tol;                   // relative Newton convergence tolerance
+  int maxit;
+  double out_tol;               // relative tolerance the accepted outputs must meet
+};
+
+__device__ __forceinline__ bool hurwitz_shifted(const double (&J)[3][3], double s) {
+  double M[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) M[a][b] = J[a][b] + (a == b ? s : 0.0);
+  const double tr = M[0][0] + M[1][1] + M[2][2];
+  const double m2 = (M[0][0] * M[1][1] - M[0][1] * M[1][0]) + (M[0][0] * M[2][2] - M[0][2] * M[2][0]) +
+                    (M[1][1] * M[2][2] - M[1][2] * M[2][1]);
+  const double det = M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) -
+                     M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+                     M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
+  const double c2 = -tr, c1 = m2, c0 = -det;
+  return c2 > 0.0 && c0 > 0.0 && c2 * c1 > c0;
+}
+
+// Solve J d = -g by Cramer's rule; false if singular.
+__device__ __forceinline__ bool solve3(const double (&J)[3][3], const double (&g)[3], double (&d)[3]) {
+  const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+  const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+  const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+  const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+  if (!(fabs(det) > 0.0) || !isfinite(det)) return false;
+  const double inv = 1.0 / det;
+  // adjugate rows
+  const double a10 = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+  const double a11 = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+  const double a12 = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+  const double a20 = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+  const double a21 = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+  const double a22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+  d[0] = -(c00 * g[0] + a10 * g[1] + a20 * g[2]) * inv;
+  d[1] = -(c01 * g[0] + a11 * g[1] + a21 * g[2]) * inv;
+  d[2] = -(c02 * g[0] + a12 * g[1] + a22 * g[2]) * inv;
+  return isfinite(d[0]) && isfinite(d[1]) && isfinite(d[2]);
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void accept_kernel(AcceptArgs a) {
+  __shared__ float s_tab[TAB_STEP];
+  stage_tables(a.tab, s_tab);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool ok = false;
+  if (i < a.ncell) {
+    const CoefT<float> &c = coef<float>();
+    const ParT<float> &p = a.pr;
+    const double muH = a.pd.muH, dt = a.dt, delta = a.pd.fd_rel;
+    const double nd = a.n[i];
+    Rad<float> r;
+    r.chiPE = a.chiPE[i];
+    r.chiLW = a.chiLW[i];
+    r.chiH2 = a.chiH2[i];
+    r.chiC = a.chiC[i];
+    r.phi = a.phi ? a.phi[i] : 0.f;
+    r.xi = a.xi[i];
+    r.Neff = a.Neff[i];
+    const double T0 = a.T[i], x20 = a.xH2[i], xp0 = a.xHp[i];
+    const double K = nd * muH * K_B / (g_coef64.gamma - 1.0);
+    // seed, clamped to the physical range
+    double u[3];
+    if (a.pred) {
+      u[0] = exp10((double)a.pred[3 * i + 2]);
+      u[1] = (double)a.pred[3 * i + 0];
+      u[2] = (double)a.pred[3 * i + 1];
+    } else {
+      u[0] = T0;
+      u[1] = x20;
+      u[2] = xp0;
+    }
+    u[0] = fmin(fmax(u[0], a.pd.T_floor), 1e9);
+    u[1] = fmin(fmax(u[1], 0.0), 0.5);
+    u[2] = fmin(fmax(u[2], 0.0), 1.0);
+    if (2.0 * u[1] + u[2] > 1.0) {
+      const double f = 1.0 / (2.0 * u[1] + u[2]);
+      u[1] *= f;
+      u[2] *= f;
+    }
+    const double Tseed = u[0];
+    const double srate = a.fast / fmax(dt, 1e-300);
+    double J[3][3], gb[3], h[3] = {0.0, 0.0, 0.0};
+    int phase = 0, k = 0, it = 0;
+    double dir = 0.0;
+    float tdg = 0.f;
+#pragma unroll 1
+    for (;;) {
+      // probe point
+      double Tq = u[0], aq = u[1], bq = u[2];
+      if (phase == 0) {
+        if (k == 1) Tq = u[0] * (1.0 + delta);
+        else if (k == 2) aq = u[1] + h[1];
+        else if (k == 3) bq = u[2] + h[2];
+      } else if (k == 0) {
+        Tq = T0; aq = x20; bq = xp0;
+      } else {
+        Tq = T0 * exp((double)k * 0.25 * log(u[0] / T0));
+      }
+      const EqS<float> e = eq_species<float>(Tq, (float)nd, aq, bq, r, c, p, s_tab, CloseTol<float>::v, 50);
+      const Eval<float> v = evaluate<float, false, false>(Tq, nd, aq, bq, e, r, c, p, s_tab, tdg, nullptr);
+      tdg = v.Td;
+      const double gT = v.H * muH / ((1.1 + (double)e.xe - aq) * K);
+      const double g1 = v.CH2, g2 = v.CHp;
+      if (phase == 0) {
+        if (k == 0) {
+          gb[0] = gT; gb[1] = g1; gb[2] = g2;
+          // pre-test: both chemical relaxation rates must be fast on their own
+          if (dt * (2.0 * v.F + v.D) < 0.5 * a.fast || dt * (v.I + v.Rr) < 0.5 * a.fast) break;
+          h[1] = 1e-3 * fmax(u[1], 1e-6);
+          if (2.0 * (u[1] + h[1]) + u[2] > 1.0) h[1] = -h[1];
+          h[2] = 1e-3 * fmax(u[2], 1e-6);
+          if (2.0 * u[1] + u[2] + h[2] > 1.0) h[2] = -h[2];
+          k = 1;
+          continue;
+        }
+        const double step = k == 1 ? u[0] * delta : h[k - 1];
+        J[0][k - 1] = (gT - gb[0]) / step;
+        J[1][k - 1] = (g1 - gb[1]) / step;
+        J[2][k - 1] = (g2 - gb[2]) / step;
+        if (k < 3) { ++k; continue; }
+        // full Jacobian at u
+        if (it == 0 && !hurwitz_shifted(J, 0.5 * srate)) break;
+        double d[3];
+        if (!solve3(J, gb, d)) break;
+        const double un0 = u[0] + d[0], un1 = u[1] + d[1], un2 = u[2] + d[2];
+        const bool inside = un0 >= a.pd.T_floor && un0 <= 1e9 && un1 >= 0.0 && un2 >= 0.0 &&
+                            2.0 * un1 + un2 <= 1.0;
+        const bool conv = inside && fabs(d[0]) <= a.tol * un0 && fabs(d[1]) <= a.tol * fmax(un1, 1e-10) &&
+                          fabs(d[2]) <= a.tol * fmax(un2, 1e-10);
+        u[0] = fmin(fmax(un0, a.pd.T_floor), 1e9);
+        u[1] = fmin(fmax(un1, 0.0), 0.5);
+        u[2] = fmin(fmax(un2, 0.0), 1.0 - 2.0 * u[1]);
+        ++it;
+        k = 0;
+        if (conv) {
+          if (!hurwitz_shifted(J, srate)) break;
+          if (fabs(log(u[0] / Tseed)) > 0.1) break;
+          if (fabs(u[0] - T0) <= 1e-3 * T0) { ok = true; break; }
+          dir = u[0] > T0 ? 1.0 : -1.0;
+          phase = 1;
+          continue;
+        }
+        if (it >= a.maxit) break;
+        continue;
+      }
+      // phase 1: no thermal equilibrium between T_0 and the root
+      if (!(gT * dir > 0.0)) break;
+      if (k == 3) { ok = true; break; }
+      ++k;
+    }
+    if (ok) {
+      // 5. lag of the plain step's final jump: one substep of length dt from the root and
+      // from the root perturbed in T, x_H2, x_H+
+      StepArgs<float> sa{};
+      sa.dt = dt;
+      sa.pr = a.pr;
+      sa.pd = a.pd;
+      const double scale[3] = {u[0], fmax(u[1], 1e-7), fmax(u[2], 1e-7)};
+      const double hv[3] = {1e-3 * u[0], 1e-3 * fmax(u[1], 1e-8), 1e-3 * fmax(u[2], 1e-8)};
+      const double dev[3] = {fabs(T0 - u[0]), fabs(x20 - u[1]), fabs(xp0 - u[2])};
+      double base[3] = {0.0, 0.0, 0.0}, err[3] = {0.0, 0.0, 0.0};
+#pragma unroll 1
+      for (int v = -1; v < 3 && ok; ++v) {
+        double y0 = u[0], y1 = u[1], y2 = u[2];
+        if (v == 0) y0 += hv[0];
+        if (v == 1) y1 = 2.0 * (y1 + hv[1]) + y2 <= 1.0 ? y1 + hv[1] : y1 - hv[1];
+        if (v == 2) y2 = 2.0 * y1 + y2 + hv[2] <= 1.0 ? y2 + hv[2] : y2 - hv[2];
+        CellState<float> cs;
+        cs.nd = nd;
+        cs.K = K;
+        cs.r = r;
+        cs.e = eq_species<float>(y0, (float)nd, y1, y2, r, c, p, s_tab, CloseTol<float>::v, 50);
+        cs.Tmu = y0 * (1.1 + (double)cs.e.xe - y1) / muH;
+        cs.xH2 = y1;
+        cs.xHp = y2;
+        cs.t = 0.0;
+        cs.ns = 0;
+        cs.st = 0;
+        cs.tdg = tdg;
+        cell_substep(sa, cs, s_tab);
+        const double o[3] = {muH * cs.Tmu / (1.1 + (double)cs.e.xe - cs.xH2), cs.xH2, cs.xHp};
+        if (v < 0) {
+          // the root must be a fixed point of a single full-length substep
+          ok = cs.t >= dt && cs.st == 0;
+#pragma unroll
+          for (int w = 0; w < 3; ++w) {
+            base[w] = o[w];
+            ok = ok && fabs(o[w] - u[w]) <= 0.1 * a.out_tol * scale[w];
+          }
+        } else {
+          const double step = v == 0 ? hv[0] : (v == 1 ? y1 - u[1] : y2 - u[2]);
+#pragma unroll
+          for (int w = 0; w < 3; ++w) err[w] += fabs((o[w] - base[w]) / step) * dev[v];
+        }
+      }
+#pragma unroll
+      for (int w = 0; w < 3; ++w) ok = ok && err[w] <= 0.5 * a.out_tol * scale[w];
+    }
+    if (ok) {
+      const EqS<float> e = eq_species<float>(u[0], (float)nd, u[1], u[2], r, c, p, s_tab, CloseTol<float>::v, 50);
+      a.T[i] = u[0];
+      a.xH2[i] = u[1];
+      a.xHp[i] = u[2];
+      if (a.xCp) a.xCp[i] = e.xCp;
+      if (a.xCO) a.xCO[i] = e.xCO;
+      if (a.xe) a.xe[i] = e.xe;
+      if (a.nsub) a.nsub[i] = 0;
+      if (a.status) a.status[i] = 0;
+    }
+  }
+  // compact the rejected cells: one atomic per wave
+  const bool rej = i < a.ncell && !ok;
+  const uint64_t m = __ballot(rej);
+  if (m != 0) {
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(a.nrej, (unsigned long long)__popcll(m));
+    base = __shfl(base, leader, 64);
+    if (rej) a.rej[base + __popcll(m & ((1ull << lane) - 1ull))] = (int32_t)i;
+  }
+}
+
+__global__ void counter_reset_kernel(unsigned long long *c) { *c = 0ull; }
+
+__global__ void counter_copy_kernel(const unsigned long long *c, int64_t *out) { *out = (int64_t)*c; }
+
+}  // namespace ism

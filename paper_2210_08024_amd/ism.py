@@ -90,6 +90,9 @@ def lib():
         L.ism_surrogate_train_step.argtypes = [_vp, _vp, _vp, _i64, ctypes.c_float, _vp, _vp]
         L.ism_surrogate_get_params.argtypes = [_vp, _vp]
         L.ism_surrogate_set_params.argtypes = [_vp, _vp]
+        L.ism_surrogate_pairs.argtypes = [ctypes.POINTER(_Params), ctypes.c_int, _i64, _dp] + [_vp] * 14
+        L.ism_chem_cool_step_surrogate.argtypes = [_vp, ctypes.POINTER(_Params), _i64, _dp] + [_vp] * 16 + \
+            [_dp, _vp, _vp]
         for name in ("ism_init", "ism_shutdown", "ism_columns6", "ism_rates", "ism_chem_cool_step") + SURROGATE_SYMBOLS:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -98,7 +101,8 @@ def lib():
 
 SURROGATE_SYMBOLS = ("ism_surrogate_create", "ism_surrogate_destroy", "ism_surrogate_set_norm",
                      "ism_surrogate_forward", "ism_surrogate_backward", "ism_surrogate_train_step",
-                     "ism_surrogate_get_params", "ism_surrogate_set_params")
+                     "ism_surrogate_get_params", "ism_surrogate_set_params", "ism_surrogate_pairs",
+                     "ism_chem_cool_step_surrogate")
 
 
 def exported_symbols():
@@ -302,3 +306,52 @@ class Surrogate:
                  np.zeros(10) if mu_x is None else mu_x, np.ones(10) if sd_x is None else sd_x,
                  np.zeros(3) if mu_y is None else mu_y, np.ones(3) if sd_y is None else sd_y]
         return np.concatenate([np.asarray(p, dtype=np.float64).ravel() for p in parts]).astype(np.float32)
+
+
+def surrogate_pairs(n, T0, xH2_0, xHp_0, rad, dt_s, params, prec=MIXED, post=None, X=None, Y=None, stream=None):
+    """Network inputs X [N][10] (and, given post = dict(T, xH2, xHp) after the step, targets Y [N][3])."""
+    _ensure_init(n)
+    N = n.numel()
+    rd = _rdt(prec)
+    if X is None:
+        X = torch.empty((N, 10), dtype=torch.float32, device=n.device)
+    if post is not None and Y is None:
+        Y = torch.empty((N, 3), dtype=torch.float32, device=n.device)
+    p = params._c()
+    post = post or {}
+    _check(lib().ism_surrogate_pairs(
+        ctypes.byref(p), prec, N, float(dt_s), _ptr(n, torch.float64, N, "n"), _ptr(T0, torch.float64, N, "T0"),
+        _ptr(xH2_0, torch.float64, N, "xH2_0"), _ptr(xHp_0, torch.float64, N, "xHp_0"),
+        _ptr(rad["chi_PE"], rd, N, "chi_PE"), _ptr(rad.get("phi"), rd, N, "phi", allow_none=True),
+        _ptr(rad["xi"], rd, N, "xi"), _ptr(rad["N_eff"], rd, N, "N_eff"),
+        _ptr(post.get("T"), torch.float64, N, "T1", True), _ptr(post.get("xH2"), torch.float64, N, "xH2_1", True),
+        _ptr(post.get("xHp"), torch.float64, N, "xHp_1", True), _ptr(X, torch.float32, N * 10, "X"),
+        _ptr(Y, torch.float32, N * 3, "Y", True), _stream(stream)))
+    return X, Y
+
+
+def chem_cool_step_surrogate(surrogate, n, T, xH2, xHp, rad, dt_s, params, accept_tol=1e-6,
+                             want=("xCp", "xCO", "xe", "nsub", "status"), out=None, n_fallback=None, stream=None):
+    """ism_chem_cool_step_surrogate (MIXED): in-place T, xH2, xHp; surrogate None = identity seed."""
+    _ensure_init(n)
+    N = n.numel()
+    rd = torch.float32
+    if out is None:
+        out = {}
+        for k in want:
+            dt = torch.int32 if k == "nsub" else (torch.uint8 if k == "status" else rd)
+            out[k] = torch.empty(N, dtype=dt, device=n.device)
+    p = params._c()
+    g = out.get
+    h = surrogate._h if surrogate is not None else None
+    _check(lib().ism_chem_cool_step_surrogate(
+        h, ctypes.byref(p), N, float(dt_s), _ptr(n, torch.float64, N, "n"), _ptr(T, torch.float64, N, "T"),
+        _ptr(xH2, torch.float64, N, "xH2"), _ptr(xHp, torch.float64, N, "xHp"),
+        _ptr(rad["chi_PE"], rd, N, "chi_PE"), _ptr(rad["chi_LW"], rd, N, "chi_LW"),
+        _ptr(rad["chi_H2"], rd, N, "chi_H2"), _ptr(rad["chi_C"], rd, N, "chi_C"),
+        _ptr(rad.get("phi"), rd, N, "phi", allow_none=True), _ptr(rad["xi"], rd, N, "xi"),
+        _ptr(rad["N_eff"], rd, N, "N_eff"),
+        _ptr(g("xCp"), rd, N, "xCp", True), _ptr(g("xCO"), rd, N, "xCO", True), _ptr(g("xe"), rd, N, "xe", True),
+        _ptr(g("nsub"), torch.int32, N, "nsub", True), _ptr(g("status"), torch.uint8, N, "status", True),
+        float(accept_tol), _ptr(n_fallback, torch.int64, 1, "n_fallback", True), _stream(stream)))
+    return out

@@ -14,7 +14,11 @@ Recipes (all seeds derive from SeedSequence(20221014)):
   noise smoothed by a Gaussian of sigma = 2 pc in Fourier space, re-standardised,
   n = exp(1.5 g - 1.5^2 / 2) (mean 1 cm^-3); T = 3e3 / ((1.1 + x_H+ - x_H2) n)
   clipped to [10, 1e7] K; abundances Dirichlet as above.
-* ``point_sources`` 16 seeded sources for the 256^3 / 512^3 cases.
+* ``thin(N)`` i.i.d. cells in an unattenuated field (chi = 1 in every band,
+  xi_cr = 2e-16 s^-1, N_eff = 0): log10 n ~ U[0, 4], log10 T ~ U[1, 4],
+  abundances Dirichlet as above.  Optically thin gas whose three relaxation times
+  are short against long steps: the regime where the source step ends at the
+  equilibrium of the coupled system.
 
 The paper's TIGRESS snapshots are not available; these grids stand in for them.
 """
@@ -69,6 +73,18 @@ def grf_cube(N, dx_pc, salt=1):
     xHp = xHp.reshape(shape)
     T = np.clip(3.0e3 / ((1.1 + xHp - xH2) * n), 10.0, 1.0e7)
     return dict(n=n, T=T, xH2=xH2, xHp=xHp)
+
+
+def thin(N=4096, salt=2):
+    """I.i.d. optically thin cells; returns (state, radiation) with radiation arrays per cell."""
+    r = _rngs(3, salt)
+    n = 10.0 ** r[0].uniform(0.0, 4.0, N)
+    T = 10.0 ** r[1].uniform(1.0, 4.0, N)
+    xH2, xHp = dirichlet_abundances(r[2], N)
+    one = np.ones(N)
+    rad = dict(chi_PE=one, chi_LW=one.copy(), chi_H2=one.copy(), chi_C=one.copy(), phi=np.zeros(N),
+               xi=np.full(N, 2.0e-16), Neff=np.zeros(N))
+    return dict(n=n, T=T, xH2=xH2, xHp=xHp), rad
 
 
 CONFIGS = {

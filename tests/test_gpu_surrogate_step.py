@@ -1,0 +1,174 @@
+"""The source step with the surrogate in front (ism_chem_cool_step_surrogate) and the learned
+network's gain.
+
+* Cells the acceptance rules reject run the plain MIXED step: their outputs are bit-identical
+  to ism_chem_cool_step(MIXED) on the same inputs, and they carry the fallback status bit.
+* Accepted cells meet the chosen form's bar against the FP64 oracle: 1e-3 relative in T and
+  each abundance (floors 1e-7 for abundances, relative to x_C,tot for carbon species).
+* Gain: the trained network predicts the plain FP64 step's result far better than the method
+  without it (the input state carried over unchanged)."""
+import numpy as np
+import pytest
+
+from paper_2210_08024_amd import workloads
+from oracle.constants import Params as OP
+
+import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+YR = workloads.YR
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    from paper_2210_08024_amd import ism
+    torch.cuda.set_device(0)
+    ism.init(0)
+    return torch
+
+
+def _rad_dev(torch, rad, dtype):
+    return dict(chi_PE=H.to_dev(rad["chi_PE"], dtype), chi_LW=H.to_dev(rad["chi_LW"], dtype),
+                chi_H2=H.to_dev(rad["chi_H2"], dtype), chi_C=H.to_dev(rad["chi_C"], dtype),
+                phi=H.to_dev(rad["phi"], dtype), xi=H.to_dev(rad["xi"], dtype), N_eff=H.to_dev(rad["Neff"], dtype))
+
+
+def _surrogate_step(torch, sur, state, rad, dt_s, par):
+    from paper_2210_08024_amd import ism
+    d = {k: H.to_dev(state[k]) for k in ("n", "T", "xH2", "xHp")}
+    nfb = torch.zeros(1, dtype=torch.int64, device="cuda")
+    out = ism.chem_cool_step_surrogate(sur, d["n"], d["T"], d["xH2"], d["xHp"], _rad_dev(torch, rad, torch.float32),
+                                       dt_s, par, n_fallback=nfb)
+    res = {k: d[k].cpu().numpy() for k in ("T", "xH2", "xHp")}
+    res.update({k: v.cpu().numpy() for k, v in out.items()})
+    return res, int(nfb.item())
+
+
+def _settled_thin(torch, N, dt_s, salt):
+    """Thin cells after one plain FP64 step: states near their equilibrium."""
+    from paper_2210_08024_amd import ism
+    s, rad = workloads.thin(N, salt=salt)
+    d = {k: H.to_dev(s[k]) for k in ("n", "T", "xH2", "xHp")}
+    ism.chem_cool_step(d["n"], d["T"], d["xH2"], d["xHp"], _rad_dev(torch, rad, torch.float64), dt_s,
+                       ism.Params(cr_mode=0), ism.F64, want=())
+    return dict(n=s["n"], T=d["T"].cpu().numpy(), xH2=d["xH2"].cpu().numpy(), xHp=d["xHp"].cpu().numpy()), rad
+
+
+def _check_accepted(res, ref, par_o, label):
+    acc = (res["status"] & 16) == 0
+    for k in ("T", "xH2", "xHp", "xe", "xCp", "xCO"):
+        fl = H.FLOORS_MIX[k] * (par_o.xCtot if k in ("xCp", "xCO") else 1.0)
+        e = H.rel_err(res[k][acc], ref[k][acc], fl)
+        assert e.size == 0 or e.max() <= 1e-3, f"{label} {k}: accepted cell error {e.max():.2e}"
+    assert np.all(res["nsub"][acc] == 0)
+    return acc
+
+
+def test_rejected_cells_run_the_plain_mixed_step(torch_dev):
+    torch = torch_dev
+    from paper_2210_08024_amd import ism
+    st, cfg = workloads.make("tiny16")
+    par = ism.Params(cr_mode=0)
+    shape = st["n"].shape
+    n = H.to_dev(st["n"]).view(shape)
+    rad = {k: torch.empty(n.numel(), dtype=torch.float32, device="cuda") for k in
+           ("chi_PE", "chi_LW", "chi_H2", "chi_C", "N_eff", "xi")}
+    ism.columns6(n, H.to_dev(st["xH2"]).view(shape), None, cfg["dx_pc"] * workloads.PC, par, ism.MIXED,
+                 out={k: v.view(shape) for k, v in rad.items()})
+    flat = {k: v.ravel() for k, v in st.items()}
+    a = {k: H.to_dev(flat[k]) for k in ("T", "xH2", "xHp")}
+    b = {k: v.clone() for k, v in a.items()}
+    nfb = torch.zeros(1, dtype=torch.int64, device="cuda")
+    oa = ism.chem_cool_step_surrogate(None, n.view(-1), a["T"], a["xH2"], a["xHp"], rad, 1e4 * YR, par, n_fallback=nfb)
+    ob = ism.chem_cool_step(n.view(-1), b["T"], b["xH2"], b["xHp"], rad, 1e4 * YR, par, ism.MIXED)
+    fb = (oa["status"] & 16) != 0
+    assert int(fb.sum()) == nfb.item() > 0.9 * n.numel()
+    for k in ("T", "xH2", "xHp"):
+        assert torch.equal(a[k][fb], b[k][fb]), k
+    for k in ("xCp", "xCO", "xe", "nsub"):
+        assert torch.equal(oa[k][fb], ob[k][fb]), k
+    assert torch.equal(oa["status"][fb] & ~16, ob["status"][fb])
+
+
+def test_surrogate_step_empty_and_arguments(torch_dev):
+    torch = torch_dev
+    from paper_2210_08024_amd import ism
+    e = torch.empty(0, dtype=torch.float64, device="cuda")
+    f = torch.empty(0, dtype=torch.float32, device="cuda")
+    rad = dict(chi_PE=f, chi_LW=f, chi_H2=f, chi_C=f, xi=f, N_eff=f)
+    nfb = torch.full((1,), 7, dtype=torch.int64, device="cuda")
+    ism.chem_cool_step_surrogate(None, e, e.clone(), e.clone(), e.clone(), rad, 1e10, ism.Params(), n_fallback=nfb)
+    assert nfb.item() == 0
+    with pytest.raises(ism.IsmError):
+        ism.chem_cool_step_surrogate(None, e, e.clone(), e.clone(), e.clone(), rad, 1e10, ism.Params(), accept_tol=0.1)
+
+
+def test_accepted_cells_meet_the_oracle_settled_thin_gas(torch_dev):
+    """Settled optically thin gas at dt = 1e5 yr: many cells are certified, all within 1e-3."""
+    torch = torch_dev
+    from paper_2210_08024_amd import ism
+    dt = 1e5 * YR
+    st, rad = _settled_thin(torch, 4096, dt, salt=60)
+    par_o = OP(Zg=1.0, Zd=1.0, cr_mode=0)
+    ref = H.oracle_step(st, rad, dt, par_o)
+    res, nfb = _surrogate_step(torch, None, st, rad, dt, ism.Params(cr_mode=0))
+    acc = _check_accepted(res, ref, par_o, "identity seed")
+    assert acc.mean() > 0.2, acc.mean()
+    assert nfb == int((~acc).sum())
+
+
+def test_far_from_equilibrium_cells_are_not_certified(torch_dev):
+    """First step from random states: the plain step's end state depends on its substep path,
+    so nothing may be accepted unless it meets the oracle."""
+    torch = torch_dev
+    from paper_2210_08024_amd import ism
+    dt = 1e5 * YR
+    st, rad = workloads.thin(4096, salt=61)
+    par_o = OP(Zg=1.0, Zd=1.0, cr_mode=0)
+    ref = H.oracle_step(st, rad, dt, par_o)
+    res, _ = _surrogate_step(torch, None, st, rad, dt, ism.Params(cr_mode=0))
+    _check_accepted(res, ref, par_o, "first step")
+
+
+@pytest.fixture(scope="module")
+def trained(torch_dev):
+    """A surrogate trained here on pairs from the plain FP64 GPU step (small dataset)."""
+    from paper_2210_08024_amd import surrogate_train as stn
+    specs = (("tiny16", 16, (1.0,), (1e4, 1e5)), ("thin", 1 << 17, (1.0,), (1e4, 1e5, 1e6)))
+    X, Y = stn.dataset(specs, log=lambda m: None)
+    s, hist = stn.fit(X, Y, steps=1500, batch=16384, lr0=2e-3, log=lambda m: None, log_every=1500)
+    return s, hist
+
+
+def test_trained_network_gains_over_the_method_without_it(torch_dev, trained):
+    """Held-out first steps: the network's post-step prediction against the plain FP64 step's
+    result, compared with carrying the input state over unchanged."""
+    torch = torch_dev
+    from paper_2210_08024_amd import surrogate_train as stn
+    s, hist = trained
+    assert hist[-1][2] < 0.05, hist[-1]
+    for recipe, size, dt in (("thin", 8192, 1e5), ("thin", 8192, 1e6), ("tiny16", 16, 1e5)):
+        X, Y = stn.pairs_for(recipe, size, 1.0, dt, salt=7)
+        P = s.forward(X)
+        dT_net = (P[:, 2] - Y[:, 2]).abs()
+        dT_id = (X[:, 1] - Y[:, 2]).abs()
+        med_net, med_id = float(dT_net.median()), float(dT_id.median())
+        assert med_net < 0.1 * med_id, (recipe, dt, med_net, med_id)
+        dx_net = (P[:, 1] - Y[:, 1]).abs().median()
+        dx_id = (X[:, 7] - Y[:, 1]).abs().median()
+        assert float(dx_net) < 0.2 * float(dx_id), (recipe, dt, float(dx_net), float(dx_id))
+
+
+def test_trained_seed_accepted_cells_meet_the_oracle(torch_dev, trained):
+    torch = torch_dev
+    from paper_2210_08024_amd import ism
+    s, _ = trained
+    dt = 1e5 * YR
+    st, rad = _settled_thin(torch, 4096, dt, salt=62)
+    par_o = OP(Zg=1.0, Zd=1.0, cr_mode=0)
+    ref = H.oracle_step(st, rad, dt, par_o)
+    res, _ = _surrogate_step(torch, s, st, rad, dt, ism.Params(cr_mode=0))
+    acc = _check_accepted(res, ref, par_o, "trained seed")
+    assert acc.mean() > 0.1, acc.mean()
