@@ -1,13 +1,21 @@
 """Throughput of the ISM chemistry + cooling source step on one MI355X.
 
-A step is one pass of the hot path over the 128^3 lognormal-GRF workload
-(4 pc cells, Z' = 1, CR attenuation by N_eff, dt = 1e4 yr): six-ray columns, then
-the subcycled chem+cool step of every cell.  The cell state is restored from a
-device copy before each step so every step does the same work.  Prints one JSON
-line (see the fields below); `value` is cell-updates/s of the whole step with the
-inputs resident in HBM.
+A step is one pass of the hot path over the 128^3 lognormal-GRF workload (4 pc cells,
+Z' = 1, CR attenuation by N_eff, dt = 1e4 yr): six-ray columns, then the source step of
+every cell.  The cell state is restored from a device copy before each step, so every
+step does the same work.  Three forms of the step are measured in the same run:
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--path f64|mixed] [--no-cpu]
+  f64        plain method, FP64 everywhere                       (columns F64 + step F64)
+  mixed      plain method, FP32 evaluation, FP64 update/sums     (columns MIXED + step MIXED)
+  surrogate  FP32 + learned surrogate with certification and
+             fallback to the mixed step                          (columns MIXED + surrogate step)
+
+`--path` picks the form timed over K steps for `value` (cell-updates/s of the whole step,
+inputs resident in HBM); `paths` reports all three (HIP-event medians), their per-field
+error against the FP64 oracle on the CPU sample, the surrogate's fallback fraction and the
+speedups.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--path f64|mixed|surrogate] [--no-cpu]
 """
 import argparse
 import json
@@ -23,6 +31,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
+BF16_PEAK_TFLOPS = 2500.0
+MLP_FLOP_PER_CELL = 2 * (10 * 128 + 2 * 128 * 128 + 128 * 3)
+FIELDS = ("T", "xH2", "xHp", "xe", "xCp", "xCO")
 
 
 def parse():
@@ -30,10 +41,60 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--path", choices=("f64", "mixed"), default="f64")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--path", choices=("f64", "mixed", "surrogate"), default="f64")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and the error report")
     ap.add_argument("--cpu-cells", type=int, default=65536)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy a cache-cold 1 GiB buffer (the known-size kernel that scales HBM counters)")
     return ap.parse_args()
+
+
+def kernel_source_hash():
+    """SHA-256 over the HIP sources of the library: traffic counters stay valid only for this build."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2210_08024_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".h", ".hip")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, if it was taken on the
+    current sources: FETCH_SIZE x fetch factor + WRITE_SIZE x write factor (KiB -> bytes)."""
+    path = os.path.join(ROOT, "profiles", "traffic_grf128.txt")
+    if not os.path.exists(path):
+        return None
+    rows, meta = {}, {}
+    for line in open(path):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        key, _, val = line.partition("=")
+        if key in ("src_sha", "fetch_factor", "write_factor"):
+            meta[key] = val.strip()
+        else:
+            f, w = val.split()
+            rows[key.strip()] = (float(f), float(w))
+    if meta.get("src_sha") != kernel_source_hash() or kernel not in rows:
+        return None
+    f, w = rows[kernel]
+    return 1024.0 * (f * float(meta["fetch_factor"]) + w * float(meta["write_factor"]))
+
+
+def calibrate_copy():
+    import torch
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    c = torch.empty_like(a)
+    c.fill_(2.0)  # a second GiB written after a evicts it from L2 and the Infinity Cache
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration_copy_bytes": a.numel() * 4}), flush=True)
 
 
 def cpu_baseline(state, cfg, ncell_sample, par_o):
@@ -43,7 +104,7 @@ def cpu_baseline(state, cfg, ncell_sample, par_o):
     from oracle.constants import PC, YR
     rng = np.random.default_rng(7)
     shape = state["n"].shape
-    idx = rng.choice(state["n"].size, ncell_sample, replace=False)
+    idx = np.sort(rng.choice(state["n"].size, ncell_sample, replace=False))
     cells = np.stack(np.unravel_index(idx, shape), 1)
     t0 = time.perf_counter()
     rc = ocol.columns6_cells(state["n"], state["xH2"], None, cfg["dx_pc"] * PC, par_o, cells)
@@ -51,28 +112,46 @@ def cpu_baseline(state, cfg, ncell_sample, par_o):
     rad = dict(chi_PE=rc["chi_PE"], chi_LW=rc["chi_LW"], chi_H2=rc["chi_H2"], chi_C=rc["chi_C"],
                phi=np.zeros(len(idx)), xi=rc["xi"], Neff=rc["N_eff"])
     sel = lambda a: a.ravel()[idx]
-    ostep.chem_cool_step(sel(state["n"]), sel(state["T"]), sel(state["xH2"]), sel(state["xHp"]), rad,
-                         cfg["dt_yr"] * YR, par_o)
+    ref = ostep.chem_cool_step(sel(state["n"]), sel(state["T"]), sel(state["xH2"]), sel(state["xHp"]), rad,
+                               cfg["dt_yr"] * YR, par_o)
     t2 = time.perf_counter()
     try:
         threads = len(os.sched_getaffinity(0))
     except Exception:
         threads = os.cpu_count()
-    return {"value": ncell_sample / (t2 - t0), "unit": "cell-updates/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{ncell_sample} seeded random cells of the 128^3 grid: oracle six-ray columns for those cells "
-                      f"({t1 - t0:.1f} s) + oracle step ({t2 - t1:.1f} s), numpy single-threaded; host has {threads} "
-                      f"threads"}
+    base = {"value": ncell_sample / (t2 - t0), "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{ncell_sample} seeded random cells of the 128^3 grid: oracle six-ray columns for those "
+                      f"cells ({t1 - t0:.1f} s) + oracle step ({t2 - t1:.1f} s), numpy single-threaded; host has "
+                      f"{threads} threads"}
+    return base, idx, ref
+
+
+def field_errors(out, ref, idx, xCt):
+    """Per-field max / p99 relative error at the sampled cells (floors: 1e-7 for abundances, carbon
+    species relative to x_C,tot), and the fraction of sampled cells over 1e-3 in any field."""
+    rep, worst = {}, np.zeros(len(idx))
+    for k in FIELDS:
+        fl = 0.0 if k == "T" else 1e-7 * (xCt if k in ("xCp", "xCO") else 1.0)
+        a = out[k][idx].astype(np.float64)
+        b = ref[k]
+        e = np.abs(a - b) / np.maximum(np.abs(b), fl)
+        rep[k] = {"max": float(e.max()), "p99": float(np.percentile(e, 99))}
+        worst = np.maximum(worst, e)
+    rep["frac_cells_over_1e-3"] = float((worst > 1e-3).mean())
+    return rep
 
 
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported "
                                    "(the source step is per-cell independent; see the sharding notes)"}))
         sys.exit(2)
     import torch
-    from paper_2210_08024_amd import ism, workloads
+    from paper_2210_08024_amd import ism, workloads, surrogate_train
     from oracle.census import substep_census
     from oracle.constants import Params as OParams
 
@@ -82,64 +161,110 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     ism.init(0)
-    prec = ism.F64 if args.path == "f64" else ism.MIXED
-    rd = torch.float64 if prec == ism.F64 else torch.float32
     par = ism.Params(Zg=cfg["Zg"], Zd=cfg["Zg"], cr_mode=cfg["cr_mode"])
-    dx = cfg["dx_pc"] * 3.0856775814913673e18
-    dt = cfg["dt_yr"] * 3.15576e7
+    dx = cfg["dx_pc"] * workloads.PC
+    dt = cfg["dt_yr"] * workloads.YR
     init = {k: torch.from_numpy(np.ascontiguousarray(state[k]).ravel()).to(dev) for k in ("n", "T", "xH2", "xHp")}
     n = init["n"]
     T, xH2, xHp = (torch.empty_like(init[k]) for k in ("T", "xH2", "xHp"))
-    rad = {k: torch.empty(N, dtype=rd, device=dev) for k in ("chi_PE", "chi_LW", "chi_H2", "chi_C", "N_eff", "xi")}
-    outs = {"xCp": torch.empty(N, dtype=rd, device=dev), "xCO": torch.empty(N, dtype=rd, device=dev),
-            "xe": torch.empty(N, dtype=rd, device=dev), "nsub": torch.empty(N, dtype=torch.int32, device=dev),
-            "status": torch.empty(N, dtype=torch.uint8, device=dev)}
-    radv = {k: v.view(shape) for k, v in rad.items()}
-    stepr = dict(rad)
-    stepr["phi"] = None
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    sur = surrogate_train.load()
+    nfb = torch.zeros(1, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
 
-    def one_step(times=None):
+    def buffers(rd):
+        rad = {k: torch.empty(N, dtype=rd, device=dev) for k in ("chi_PE", "chi_LW", "chi_H2", "chi_C", "N_eff", "xi")}
+        outs = {"xCp": torch.empty(N, dtype=rd, device=dev), "xCO": torch.empty(N, dtype=rd, device=dev),
+                "xe": torch.empty(N, dtype=rd, device=dev), "nsub": torch.empty(N, dtype=torch.int32, device=dev),
+                "status": torch.empty(N, dtype=torch.uint8, device=dev)}
+        return rad, outs
+
+    bufs = {torch.float64: buffers(torch.float64), torch.float32: buffers(torch.float32)}
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+
+    def one_step(path, times=None):
+        prec = ism.F64 if path == "f64" else ism.MIXED
+        rad, outs = bufs[torch.float64 if path == "f64" else torch.float32]
         T.copy_(init["T"])
         xH2.copy_(init["xH2"])
         xHp.copy_(init["xHp"])
         if times is not None:
-            ev[0].record()
-        ism.columns6(n.view(shape), xH2.view(shape), None, dx, par, prec, out=radv)
+            ev[0].record(stream)
+        ism.columns6(n.view(shape), xH2.view(shape), None, dx, par, prec, out={k: v.view(shape) for k, v in rad.items()})
         if times is not None:
-            ev[1].record()
-        ism.chem_cool_step(n, T, xH2, xHp, stepr, dt, par, prec, out=outs)
+            ev[1].record(stream)
+        r = dict(rad)
+        r["phi"] = None
+        if path == "surrogate":
+            ism.chem_cool_step_surrogate(sur, n, T, xH2, xHp, r, dt, par, out=outs, n_fallback=nfb)
+        else:
+            ism.chem_cool_step(n, T, xH2, xHp, r, dt, par, prec, out=outs)
         if times is not None:
-            ev[2].record()
+            ev[2].record(stream)
             torch.cuda.synchronize()
             times["columns"].append(ev[0].elapsed_time(ev[1]) * 1e-3)
             times["step"].append(ev[1].elapsed_time(ev[2]) * 1e-3)
 
+    def measure(path, reps=5):
+        one_step(path)
+        times = {"columns": [], "step": []}
+        for _ in range(reps):
+            one_step(path, times)
+        rad, outs = bufs[torch.float64 if path == "f64" else torch.float32]
+        res = {"T": T.cpu().numpy(), "xH2": xH2.cpu().numpy(), "xHp": xHp.cpu().numpy()}
+        res.update({k: v.cpu().numpy() for k, v in outs.items()})
+        return float(np.median(times["columns"])), float(np.median(times["step"])), res
+
+    # timed region: K steps of the selected form
     for _ in range(args.warmup):
-        one_step()
+        one_step(args.path)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        one_step()
+        one_step(args.path)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    times = {"columns": [], "step": []}
-    for _ in range(max(3, min(args.steps, 5))):
-        one_step(times)
-    nsub = outs["nsub"].to(torch.int64)
-    tot_sub = int(nsub.sum().item())
-    st = outs["status"].cpu().numpy()
-    t_step = float(np.mean(times["step"]))
-    t_cols = float(np.mean(times["columns"]))
+
+    paths = {}
+    for p in ("f64", "mixed", "surrogate"):
+        tc, ts, res = measure(p)
+        nsub = res["nsub"].astype(np.int64)
+        paths[p] = {"ms_per_step": (tc + ts) * 1e3, "columns_ms": tc * 1e3, "step_ms": ts * 1e3,
+                    "cell_updates_per_s": N / (tc + ts), "step_only_cell_updates_per_s": N / ts, "_res": res,
+                    "nsub_mean": float(nsub.mean()), "nsub_p50": float(np.percentile(nsub, 50)),
+                    "nsub_p99": float(np.percentile(nsub, 99)), "nsub_max": int(nsub.max()),
+                    "status_nonzero": int(((res["status"] & 0xEF) != 0).sum())}
+        if p == "surrogate":
+            paths[p]["fallback_fraction"] = nfb.item() / N
+            paths[p]["accepted_cells"] = int(N - nfb.item())
+    for p in ("mixed", "surrogate"):
+        paths[p]["speedup_vs_f64"] = paths["f64"]["ms_per_step"] / paths[p]["ms_per_step"]
+    paths["surrogate"]["speedup_vs_mixed"] = paths["mixed"]["ms_per_step"] / paths["surrogate"]["ms_per_step"]
+
+    # inference kernel alone (network inputs built once, then timed forwards)
+    rad32, _ = bufs[torch.float32]
+    X, _ = ism.surrogate_pairs(n, init["T"], init["xH2"], init["xHp"], rad32, dt, par, ism.MIXED)
+    Y = torch.empty((N, 3), dtype=torch.float32, device=dev)
+    sur.forward(X, Y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(10):
+        sur.forward(X, Y)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_mlp = e0.elapsed_time(e1) * 1e-3 / 10
+    mlp_tf = MLP_FLOP_PER_CELL * N / t_mlp / 1e12
+
+    # dominant kernel of the selected form: the persistent step kernel
+    tot_sub = int(paths[args.path]["_res"]["nsub"].astype(np.int64).sum())
     arith, trans = substep_census(OParams())
     flops = float(tot_sub) * (arith + trans)
-    peak = FP64_PEAK_TFLOPS if prec == ism.F64 else FP32_PEAK_TFLOPS
+    peak = FP64_PEAK_TFLOPS if args.path == "f64" else FP32_PEAK_TFLOPS
+    t_step = paths[args.path]["step_ms"] * 1e-3
     achieved = flops / t_step / 1e12
     ms = wall / args.steps * 1e3
-    value = N / (wall / args.steps)
     out = {
-        "metric": "cell-updates/s per chem+cool step (columns6 + subcycled step)",
-        "value": value,
+        "metric": "cell-updates/s per chem+cool step (columns6 + source step)",
+        "value": N / (wall / args.steps),
         "unit": "cell-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -148,25 +273,33 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == ism.F64 else "f32+f64",
+        "dtype": {"f64": "f64", "mixed": "f32+f64", "surrogate": "bf16+f32+f64"}[args.path],
         "data": "synthetic",
         "config": {"workload": "grf128: 128^3 lognormal GRF (sigma_ln 1.5, 2 pc smoothing), 4 pc cells, "
                                "P/k = 3e3 K cm^-3, Z' = 1, chi0 = 1 six-ray, xi_cr0 = 2e-16 attenuated by N_eff, "
                                "dt = 1e4 yr", "cells": N, "path": args.path},
         "roofline": {"bound": "alu", "kernel": "step_queue_kernel", "achieved": achieved, "peak": peak,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": measured_traffic("step_queue_kernel<double>" if args.path == "f64"
+                                                 else "step_queue_kernel<float>"),
+                     "traffic_algorithmic": N * (133 if args.path == "f64" else 97),
                      "work": f"{tot_sub} substeps x ({arith} flops + {trans} transcendentals counted as 1) "
                              f"per launch; census of the oracle's substep"},
-        "detail": {"step_kernel_ms": t_step * 1e3, "columns_ms": t_cols * 1e3,
-                   "step_only_cell_updates_per_s": N / t_step,
-                   "nsub_mean": tot_sub / N, "nsub_max": int(nsub.max().item()),
-                   "nsub_p99": float(np.percentile(outs["nsub"].cpu().numpy(), 99)),
-                   "status_nonzero": int((st != 0).sum()),
-                   "columns_hbm_GBs_algorithmic": N * (24 + (48 if prec == ism.F64 else 24)) / t_cols / 1e9},
+        "roofline_mlp": {"bound": "mfma", "kernel": "mlp_fwd_kernel", "achieved": mlp_tf, "peak": BF16_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": mlp_tf / BF16_PEAK_TFLOPS, "ms": t_mlp * 1e3,
+                         "work": f"{MLP_FLOP_PER_CELL} FLOP/cell x {N} cells per launch"},
+        "paths": paths,
+        "detail": {"columns_hbm_GBs_algorithmic_f64": N * 72 / (paths["f64"]["columns_ms"] * 1e-3) / 1e9,
+                   "columns_hbm_GBs_algorithmic_mixed": N * 48 / (paths["mixed"]["columns_ms"] * 1e-3) / 1e9},
     }
     if not args.no_cpu:
-        from oracle.constants import Params as OP
-        out["cpu_baseline"] = cpu_baseline(state, cfg, args.cpu_cells, OP(Zg=1.0, Zd=1.0, cr_mode=1))
+        base, idx, ref = cpu_baseline(state, cfg, args.cpu_cells, OParams(Zg=1.0, Zd=1.0, cr_mode=1))
+        out["cpu_baseline"] = base
+        xCt = OParams(Zg=1.0, Zd=1.0).xCtot
+        for p in paths:
+            paths[p]["error_vs_oracle"] = field_errors(paths[p]["_res"], ref, idx, xCt)
+    for p in paths:
+        paths[p].pop("_res")
     print(json.dumps(out), flush=True)
 
 
