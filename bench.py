@@ -73,6 +73,7 @@ def measured_traffic(kernel):
         if not line or line.startswith("#"):
             continue
         key, _, val = line.partition("=")
+        key = key.strip()
         if key in ("src_sha", "fetch_factor", "write_factor"):
             meta[key] = val.strip()
         else:
