@@ -22,9 +22,10 @@
  *    launch/runtime errors return ISM_E_DEVICE.  ism_last_error() gives the message
  *    (thread-local).  Per-cell numerical trouble never fails a call: it is reported
  *    in the per-cell status bits below and the call returns ISM_OK.
- *  - Thread safety: after ism_init, ism_rates and ism_chem_cool_step may run concurrently on
- *    different streams.  ism_columns6 and ism_chem_cool_step_surrogate use a per-device
- *    scratch buffer: their calls on one device must not overlap in time.
+ *  - Thread safety: after ism_init, ism_rates, and ism_chem_cool_step with order_cells = 0,
+ *    may run concurrently on different streams.  ism_columns6, ism_chem_cool_step with
+ *    order_cells = 1 and ism_chem_cool_step_surrogate use per-device scratch buffers: their
+ *    calls on one device must not overlap in time.
  */
 #ifndef ISM_H
 #define ISM_H
@@ -80,6 +81,10 @@ typedef struct {
   int32_t kgr_const;    /* 1: k_gr = 3e-17 Z'_d (Sec. 7); 0: Eq. e:H2form                 */
   int32_t h2_rovib;     /* 1: include H2 ro-vibrational cooling                           */
   int32_t max_substeps; /* substep cap per cell (100000)                                   */
+  int32_t order_cells;  /* step calls: 1 (default) process cells grouped by temperature so
+                           that the lanes of a wave stay in one regime; 0 in index order.
+                           Results are identical either way.                              */
+  int32_t pad_;
 } ism_params;
 
 /* Fill *p with the defaults listed above (Z'_g = Z'_d = chi0 = 1, xi_cr0 = 2e-16). */

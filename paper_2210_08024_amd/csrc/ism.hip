@@ -21,6 +21,7 @@
 #include "kernels_columns.h"
 #include "kernels_mlp.h"
 #include "kernels_surr.h"
+#include "kernels_order.h"
 
 using namespace ism;
 using ism::host::coef_to_f32;
@@ -47,6 +48,8 @@ struct DevState {
   unsigned qnext = 0;
   void *sscratch = nullptr;  // surrogate step: predictions + rejected list
   size_t sscratch_bytes = 0;
+  void *oscratch = nullptr;  // cell ordering: keys, histogram, cursor, ordered list
+  size_t oscratch_bytes = 0;
   int num_cu = 0;
   int occ64 = 0, occ32 = 0;  // resident 256-thread blocks per CU of the persistent step kernels
   bool simple_step = false;   // ISM_STEP_KERNEL=simple selects the one-lane-per-cell grid
@@ -76,6 +79,7 @@ ism_status current_state(DevState **out, int *dev_out = nullptr) {
 
 ism_status check_params(const ism_params *p) {
   if (!p) return fail(ISM_E_ARG, "params is NULL");
+  if (p->order_cells != 0 && p->order_cells != 1) return fail(ISM_E_ARG, "order_cells must be 0 or 1");
   if (!(p->Zg > 0.0) || !std::isfinite(p->Zg)) return fail(ISM_E_ARG, "Zg must be finite and > 0");
   if (!(p->Zd > 0.0) || !std::isfinite(p->Zd)) return fail(ISM_E_ARG, "Zd must be finite and > 0");
   if (!(p->chi0 >= 0.0) || !std::isfinite(p->chi0)) return fail(ISM_E_ARG, "chi0 must be finite and >= 0");
@@ -135,6 +139,37 @@ ism_status surr_scratch(DevState *st, size_t bytes, void **out) {
   return ISM_OK;
 }
 
+// Order `n` items (cells, or the cells listed in `items`, `*count` of them when count is set)
+// by temperature regime; *out receives the ordered cell list (library scratch).
+ism_status order_cells(DevState *st, int64_t n, const unsigned long long *count, const int32_t *items,
+                       const double *T, const float *pred, int32_t **out, hipStream_t stream) {
+  const size_t key_b = (size_t)((n * 2 + 255) / 256 * 256), bins_b = (size_t)ORDER_BINS * 4;
+  const size_t out_b = (size_t)((n * 4 + 255) / 256 * 256);
+  const size_t bytes = key_b + 2 * bins_b + out_b;
+  uint8_t *base;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (st->oscratch_bytes < bytes) {
+      if (st->oscratch) (void)hipFree(st->oscratch);
+      st->oscratch = nullptr;
+      st->oscratch_bytes = 0;
+      hipError_t e = hipMalloc(&st->oscratch, bytes);
+      if (e != hipSuccess) return fail(ISM_E_NOMEM, std::string("order scratch: ") + hipGetErrorString(e));
+      st->oscratch_bytes = bytes;
+    }
+    base = (uint8_t *)st->oscratch;
+  }
+  OrderArgs a{n, count, items, T, pred, (uint16_t *)base, (uint32_t *)(base + key_b),
+              (uint32_t *)(base + key_b + bins_b), (int32_t *)(base + key_b + 2 * bins_b)};
+  const dim3 grid((unsigned)((n + ORDER_THREADS - 1) / ORDER_THREADS));
+  hipLaunchKernelGGL(order_zero_kernel, dim3(1), dim3(ORDER_THREADS), 0, stream, a.hist);
+  hipLaunchKernelGGL(order_key_kernel, grid, dim3(ORDER_THREADS), 0, stream, a);
+  hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(ORDER_THREADS), 0, stream, a);
+  hipLaunchKernelGGL(order_scatter_kernel, grid, dim3(ORDER_THREADS), 0, stream, a);
+  *out = a.out;
+  return ISM_OK;
+}
+
 const char *kDiagNames[NDIAG] = {
     "xCp", "xCO", "xe", "Td", "kgr", "zcrH2", "zpd", "zpiH2", "zcd", "zpiH", "zcrH", "zci", "aB",
     "agrH", "psi", "G_pe", "G_cr", "G_pi", "G_h2", "Gamma", "L_lya", "L_ci", "L_rovib", "L_cd", "L_ff", "L_rr",
@@ -150,7 +185,7 @@ void ism_params_default(ism_params *p) {
   std::memset(p, 0, sizeof(*p));
   p->Zg = 1.0; p->Zd = 1.0; p->chi0 = 1.0; p->xi_cr0 = 2.0e-16; p->dvdr_kms_pc = 1.0; p->eps_sub = 0.1;
   p->fd_rel = 1.0e-3; p->T_floor = 1.0; p->T_bb = 6.0; p->tau_opt_ratio = 1.87;
-  p->cr_mode = 0; p->kgr_const = 0; p->h2_rovib = 1; p->max_substeps = 100000;
+  p->cr_mode = 0; p->kgr_const = 0; p->h2_rovib = 1; p->max_substeps = 100000; p->order_cells = 1;
 }
 
 const char *ism_last_error(void) { return g_err.c_str(); }
@@ -216,6 +251,7 @@ ism_status ism_shutdown(void) {
     if (kv.second.scratch) (void)hipFree(kv.second.scratch);
     if (kv.second.queues) (void)hipFree(kv.second.queues);
     if (kv.second.sscratch) (void)hipFree(kv.second.sscratch);
+    if (kv.second.oscratch) (void)hipFree(kv.second.oscratch);
   }
   g_dev.clear();
   (void)hipSetDevice(prev);
@@ -340,12 +376,15 @@ ism_status ism_chem_cool_step(const ism_params *p, ism_precision prec, int64_t n
     q = st->queues + (st->qnext++ % QUEUE_SLOTS);
   }
   const int64_t want = (ncell + 255) / 256;
+  int32_t *order = nullptr;
+  if (p->order_cells && !st->simple_step && ncell <= (int64_t)INT32_MAX)
+    if (ism_status s = order_cells(st, ncell, nullptr, nullptr, T, nullptr, &order, stream)) return s;
   if (prec == ISM_PREC_F64) {
     StepArgs<double> a{ncell, dt_s, n, T, xH2, xHp, (const double *)chi_PE, (const double *)chi_LW,
                        (const double *)chi_H2, (const double *)chi_C, (const double *)phi_LyC,
                        (const double *)xi_cr, (const double *)N_eff, (double *)xCp, (double *)xCO, (double *)xe,
                        nsub, status, st->tab64, make_par<double>(p, g_host_coef), make_par<double>(p, g_host_coef), q,
-                       nullptr, nullptr, 0u};
+                       order, nullptr, 0u};
     if (st->simple_step) {
       hipLaunchKernelGGL(step_simple_kernel<double>, dim3((unsigned)want), dim3(256), 0, stream, a);
     } else {
@@ -358,7 +397,7 @@ ism_status ism_chem_cool_step(const ism_params *p, ism_precision prec, int64_t n
                       (const float *)chi_H2, (const float *)chi_C, (const float *)phi_LyC,
                       (const float *)xi_cr, (const float *)N_eff, (float *)xCp, (float *)xCO, (float *)xe,
                       nsub, status, st->tab32, make_par<float>(p, g_host_coef), make_par<double>(p, g_host_coef), q,
-                      nullptr, nullptr, 0u};
+                      order, nullptr, 0u};
     if (st->simple_step) {
       hipLaunchKernelGGL(step_simple_kernel<float>, dim3((unsigned)want), dim3(256), 0, stream, a);
     } else {
@@ -748,10 +787,13 @@ ism_status ism_chem_cool_step_surrogate(ism_surrogate *m, const ism_params *p, i
     std::lock_guard<std::mutex> lk(g_mu);
     q = st->queues + (st->qnext++ % QUEUE_SLOTS);
   }
+  int32_t *list = rej;
+  if (p->order_cells)
+    if (ism_status s = order_cells(st, ncell, nrej, rej, T, pred, &list, stream)) return s;
   StepArgs<float> sa{ncell, dt_s, n, T, xH2, xHp, (const float *)chi_PE, (const float *)chi_LW,
                      (const float *)chi_H2, (const float *)chi_C, (const float *)phi_LyC,
                      (const float *)xi_cr, (const float *)N_eff, (float *)xCp, (float *)xCO, (float *)xe,
-                     nsub, status, st->tab32, pr, pd, q, rej, nrej, (uint32_t)ISM_ST_FALLBACK};
+                     nsub, status, st->tab32, pr, pd, q, list, nrej, (uint32_t)ISM_ST_FALLBACK};
   const int64_t grid = std::min<int64_t>((ncell + 255) / 256, (int64_t)st->num_cu * std::max(st->occ32, 1));
   hipLaunchKernelGGL(queue_init_kernel, dim3(1), dim3(1), 0, stream, q, grid * 256);
   hipLaunchKernelGGL(step_queue_kernel<float>, dim3((unsigned)grid), dim3(256), 0, stream, sa);

@@ -1,0 +1,122 @@
+// Processing order for the persistent step kernels.
+//
+// A cell's result does not depend on when it is processed, but the speed of a wave does: its
+// lanes run the same instruction stream, so lanes whose cells sit in different temperature
+// regimes execute both sides of every regime branch, and lanes whose cells need different
+// numbers of substeps refill at different times.  Grouping cells with similar input
+// temperature (and, when a prediction of the end temperature is available, similar end
+// temperature) into the same waves removes most of that divergence.  The order is a
+// counting sort on a 12-bit key: a per-block LDS histogram, an exclusive scan of the 4096
+// bins, and a scatter that reserves one range per (block, bin) with a single global atomic.
+// Within a bin the order depends on atomic timing; results do not.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ism {
+
+constexpr int ORDER_BITS = 12, ORDER_BINS = 1 << ORDER_BITS, ORDER_THREADS = 1024;
+
+__device__ __forceinline__ uint32_t order_quant(float x, float lo, float hi, int bits) {
+  float u = (x - lo) / (hi - lo);
+  u = fminf(fmaxf(u, 0.f), 1.f);  // NaN maps to 0
+  return (uint32_t)(u * (float)((1 << bits) - 1) + 0.5f);
+}
+
+// Key of one cell: log10 T in [0, 8) on 12 bits, or, with a prediction, the 6-bit
+// quantisations of log10 T and of the predicted log10 T interleaved (a Morton order).
+// Bins are visited from hot to cold.
+__device__ __forceinline__ uint32_t order_key(const double *T, const float *pred, int64_t cell) {
+  const float lT = log10f((float)T[cell]);
+  uint32_t k;
+  if (pred) {
+    const uint32_t a = order_quant(lT, 0.f, 8.f, 6), b = order_quant(pred[3 * cell + 2], 0.f, 8.f, 6);
+    k = 0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) k |= (((a >> j) & 1u) << (2 * j + 1)) | (((b >> j) & 1u) << (2 * j));
+  } else {
+    k = order_quant(lT, 0.f, 8.f, ORDER_BITS);
+  }
+  return (uint32_t)(ORDER_BINS - 1) - k;
+}
+
+struct OrderArgs {
+  int64_t n;                          // items (upper bound when count is set)
+  const unsigned long long *count;    // device item count, or null (= n)
+  const int32_t *items;               // item -> cell, or null (item = cell)
+  const double *T;
+  const float *pred;                  // [cell][3] prediction, or null
+  uint16_t *key;                      // per item
+  uint32_t *hist;                     // ORDER_BINS counts
+  uint32_t *cursor;                   // ORDER_BINS running offsets
+  int32_t *out;                       // ordered cells
+};
+
+__global__ __launch_bounds__(ORDER_THREADS) void order_zero_kernel(uint32_t *hist) {
+  for (int b = threadIdx.x; b < ORDER_BINS; b += ORDER_THREADS) hist[b] = 0u;
+}
+
+__global__ __launch_bounds__(ORDER_THREADS) void order_key_kernel(OrderArgs a) {
+  __shared__ uint32_t h[ORDER_BINS];
+  for (int b = threadIdx.x; b < ORDER_BINS; b += ORDER_THREADS) h[b] = 0u;
+  __syncthreads();
+  const int64_t nitem = a.count ? (int64_t)*a.count : a.n;
+  const int64_t i = (int64_t)blockIdx.x * ORDER_THREADS + threadIdx.x;
+  if (i < nitem) {
+    const int64_t cell = a.items ? (int64_t)a.items[i] : i;
+    const uint32_t k = order_key(a.T, a.pred, cell);
+    a.key[i] = (uint16_t)k;
+    atomicAdd(&h[k], 1u);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < ORDER_BINS; b += ORDER_THREADS)
+    if (h[b]) atomicAdd(&a.hist[b], h[b]);
+}
+
+// Exclusive scan of the histogram into cursor (one block; four bins per thread).
+__global__ __launch_bounds__(ORDER_THREADS) void order_scan_kernel(OrderArgs a) {
+  __shared__ uint32_t s[ORDER_THREADS];
+  constexpr int PER = ORDER_BINS / ORDER_THREADS;
+  uint32_t v[PER], sum = 0;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    v[j] = a.hist[threadIdx.x * PER + j];
+    sum += v[j];
+  }
+  s[threadIdx.x] = sum;
+  __syncthreads();
+  for (int off = 1; off < ORDER_THREADS; off <<= 1) {
+    const uint32_t t = threadIdx.x >= (unsigned)off ? s[threadIdx.x - off] : 0u;
+    __syncthreads();
+    s[threadIdx.x] += t;
+    __syncthreads();
+  }
+  uint32_t run = s[threadIdx.x] - sum;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    a.cursor[threadIdx.x * PER + j] = run;
+    run += v[j];
+  }
+}
+
+__global__ __launch_bounds__(ORDER_THREADS) void order_scatter_kernel(OrderArgs a) {
+  __shared__ uint32_t cnt[ORDER_BINS];
+  __shared__ uint32_t base[ORDER_BINS];
+  for (int b = threadIdx.x; b < ORDER_BINS; b += ORDER_THREADS) cnt[b] = 0u;
+  __syncthreads();
+  const int64_t nitem = a.count ? (int64_t)*a.count : a.n;
+  const int64_t i = (int64_t)blockIdx.x * ORDER_THREADS + threadIdx.x;
+  uint32_t k = 0, rank = 0;
+  const bool live = i < nitem;
+  if (live) {
+    k = a.key[i];
+    rank = atomicAdd(&cnt[k], 1u);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < ORDER_BINS; b += ORDER_THREADS)
+    if (cnt[b]) base[b] = atomicAdd(&a.cursor[b], cnt[b]);
+  __syncthreads();
+  if (live) a.out[base[k] + rank] = a.items ? a.items[i] : (int32_t)i;
+}
+
+}  // namespace ism

@@ -34,7 +34,8 @@ class _Grid(ctypes.Structure):
 class _Params(ctypes.Structure):
     _fields_ = [(k, ctypes.c_double) for k in ("Zg", "Zd", "chi0", "xi_cr0", "dvdr_kms_pc", "eps_sub", "fd_rel",
                                                 "T_floor", "T_bb", "tau_opt_ratio")] + \
-               [(k, ctypes.c_int32) for k in ("cr_mode", "kgr_const", "h2_rovib", "max_substeps")]
+               [(k, ctypes.c_int32) for k in ("cr_mode", "kgr_const", "h2_rovib", "max_substeps", "order_cells",
+                                               "pad_")]
 
 
 @dataclass
@@ -54,9 +55,10 @@ class Params:
     kgr_const: int = 0
     h2_rovib: int = 1
     max_substeps: int = 100000
+    order_cells: int = 1
 
     def _c(self):
-        return _Params(**{f.name: getattr(self, f.name) for f in fields(self)})
+        return _Params(**{f.name: getattr(self, f.name) for f in fields(self)}, pad_=0)
 
 
 _lib = None

@@ -34,11 +34,12 @@ def test_params_default_matches_binding_defaults():
     ism.lib().ism_params_default(ctypes.byref(p))
     d = ism.Params()
     for f, _ in ism._Params._fields_:
-        assert getattr(p, f) == getattr(d, f), f
+        if f != "pad_":
+            assert getattr(p, f) == getattr(d, f), f
 
 
 def test_param_struct_layout():
-    assert ctypes.sizeof(ism._Params) == 10 * 8 + 4 * 4
+    assert ctypes.sizeof(ism._Params) == 10 * 8 + 6 * 4
     assert ctypes.sizeof(ism._Grid) == 24
 
 
@@ -58,7 +59,8 @@ def _bad(p=None, prec=0):
 
 @pytest.mark.parametrize("field,value,msg", [("Zg", 0.0, "Zg"), ("Zd", -1.0, "Zd"), ("eps_sub", 0.0, "eps_sub"),
                                              ("fd_rel", 0.7, "fd_rel"), ("cr_mode", 5, "cr_mode"),
-                                             ("max_substeps", 0, "max_substeps"), ("T_floor", 0.0, "T_floor")])
+                                             ("max_substeps", 0, "max_substeps"), ("T_floor", 0.0, "T_floor"),
+                                             ("order_cells", 2, "order_cells")])
 def test_invalid_params_rejected_before_launch(field, value, msg):
     p = ism.Params()
     setattr(p, field, value)

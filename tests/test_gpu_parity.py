@@ -291,3 +291,30 @@ def test_end_to_end_128_sampled(ism, grf128, prec):
     _print("128^3 sampled max/p99 rel err", rep)
     st = out["status"].cpu().numpy()
     assert np.all(st == 0), np.bincount(st)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_cell_ordering_leaves_results_unchanged(ism, grf128, prec):
+    """order_cells only changes which lane processes which cell: outputs are bitwise identical."""
+    import torch
+    _print("cell ordering prec", prec)
+    s, cfg = grf128
+    shape = s["n"].shape
+    par = Params(Zg=1.0, Zd=1.0, cr_mode=1)
+    n = H.to_dev(s["n"])
+    rad = ism.columns6(n.view(shape), H.to_dev(s["xH2"]).view(shape), None, cfg["dx_pc"] * OC.PC,
+                       H.ism_params_from(par), prec)
+    radf = {k: v.view(-1) for k, v in rad.items()}
+    radf["phi"] = None
+    res = []
+    for order in (0, 1):
+        ip = H.ism_params_from(par)
+        ip.order_cells = order
+        T, xH2, xHp = H.to_dev(s["T"]), H.to_dev(s["xH2"]), H.to_dev(s["xHp"])
+        out = ism.chem_cool_step(n, T, xH2, xHp, radf, cfg["dt_yr"] * OC.YR, ip, prec)
+        res.append((T, xH2, xHp, out))
+    (a, b) = res
+    for k in range(3):
+        assert torch.equal(a[k], b[k])
+    for k in ("xCp", "xCO", "xe", "nsub", "status"):
+        assert torch.equal(a[3][k], b[3][k]), k
