@@ -411,3 +411,79 @@ def test_columns6_symmetry():
     for k in ("chi_PE", "chi_LW", "chi_H2", "chi_C"):
         np.testing.assert_allclose(b[k][:, ::-1, ::-1], a[k], rtol=1e-12)
         np.testing.assert_allclose(c[k].transpose(2, 1, 0), a[k], rtol=1e-12)
+
+
+# ---------------------------------------------------------------- tiny-dt integration
+def _ode_solution(n, T0, x20, xp0, rad, dt, par):
+    """The ODE system the step discretises (Eqs. e:ODE1, e:HH, e:HII), integrated by scipy's
+    adaptive Runge-Kutta: d(T_mu)/dt = H / K, dx_H2/dt = C_H2, dx_H+/dt = C_H+, with the C/O/e
+    closure (Secs. 3.2-3.3) re-solved at every right-hand-side evaluation and T = mu_H T_mu /
+    (1.1 + x_e - x_H2)."""
+    from scipy.integrate import solve_ivp
+    N = n.size
+    K = n * par.muH * C.K_B / (C.GAMMA - 1.0)
+
+    def temperature(Tmu, x2, xp):
+        # T depends on x_e, which depends on T: fixed point (converges in a few sweeps)
+        T = T0.copy() if np.isscalar(Tmu) is False and Tmu.shape == T0.shape and np.allclose(Tmu, Tmu0) else None
+        T = par.muH * Tmu / (1.1 - x2) if T is None else T
+        for _ in range(60):
+            eq = micro.eq_species(T, n, x2, xp, rad["chi_PE"], rad["chi_LW"], rad["chi_C"], rad["xi"], par)
+            Tn = par.muH * Tmu / (1.1 + eq["xe"] - x2)
+            if np.all(np.abs(Tn - T) <= 1e-14 * T):
+                return Tn, eq
+            T = Tn
+        return T, eq
+
+    eq0 = micro.eq_species(T0, n, x20, xp0, rad["chi_PE"], rad["chi_LW"], rad["chi_C"], rad["xi"], par)
+    Tmu0 = T0 * (1.1 + eq0["xe"] - x20) / par.muH
+
+    def rhs(t, y):
+        Tmu, x2, xp = y[:N], y[N:2 * N], y[2 * N:]
+        T, eq = temperature(Tmu, x2, xp)
+        ev = micro.evaluate(T, n, x2, xp, eq, rad, par)
+        return np.concatenate([ev["H"] / K, ev["C_H2"], ev["C_Hp"]])
+
+    sol = solve_ivp(rhs, (0.0, dt), np.concatenate([Tmu0, x20, xp0]), method="DOP853", rtol=1e-12,
+                    atol=1e-30)
+    y = sol.y[:, -1]
+    T, _ = temperature(y[:N], y[N:2 * N], y[2 * N:])
+    return T, y[N:2 * N], y[2 * N:]
+
+
+@pytest.mark.slow
+def test_tiny_dt_step_converges_to_the_ode_at_second_order():
+    """One plain step over a tiny dt (a single substep) against an independent integration of
+    the same ODEs: the step is first order, so its local error must fall ~4x per halving of dt."""
+    rng = np.random.default_rng(4)
+    N = 6
+    n = 10.0 ** rng.uniform(-1.0, 2.5, N)
+    T0 = 10.0 ** rng.uniform(1.5, 4.0, N)
+    x20 = rng.uniform(0.01, 0.3, N)
+    xp0 = rng.uniform(0.01, 0.3, N)
+    par = Params()
+    rad = rad1(N)
+    # shortest relaxation time at the start sets the scale
+    eq = micro.eq_species(T0, n, x20, xp0, rad["chi_PE"], rad["chi_LW"], rad["chi_C"], rad["xi"], par)
+    ev = micro.evaluate(T0, n, x20, xp0, eq, rad, par)
+    K = n * par.muH * C.K_B / (C.GAMMA - 1.0)
+    Tmu0 = T0 * (1.1 + eq["xe"] - x20) / par.muH
+    tau = np.min(np.stack([K * Tmu0 / np.abs(ev["H"]), x20 / np.abs(ev["C_H2"]), xp0 / np.abs(ev["C_Hp"])]))
+    errs = []
+    for k in range(4):
+        dt = 1e-2 * tau / 2 ** k
+        out = step.chem_cool_step(n, T0, x20, xp0, rad, dt, par)
+        assert np.all(out["nsub"] == 1)
+        Te, x2e, xpe = _ode_solution(n, T0, x20, xp0, rad, dt, par)
+        # error relative to the change over the step
+        e = np.stack([np.abs(out["T"] - Te) / np.abs(Te - T0), np.abs(out["xH2"] - x2e) / np.abs(x2e - x20),
+                      np.abs(out["xHp"] - xpe) / np.abs(xpe - xp0)])
+        errs.append(e)
+    errs = np.array(errs)                      # [halving, variable, cell]
+    assert np.all(errs[0] < 0.05)              # the step follows the ODE to within a few % of the change
+    # the relative error of the change is O(dt): ~2x per halving (local error O(dt^2)); errors
+    # below 1e-5 of the change sit at the closure's iteration tolerance and are not ranked
+    ratio = errs[:-1] / errs[1:]
+    above = errs[1:] > 1e-5
+    assert above.sum() >= above.size // 3
+    assert np.all((ratio[above] > 1.7) & (ratio[above] < 2.4)), ratio
