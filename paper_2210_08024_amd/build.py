@@ -18,6 +18,9 @@ HIPCC_FLAGS = [
     # packed FP32 instructions are kept out of the generated code on purpose
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-fno-gpu-rdc", "-ffp-contract=fast", "-munsafe-fp-atomics",
+    # FP32 divide and sqrt through the hardware reciprocal (about 1 ulp): only the float
+    # parts of the mixed path, the columns and the network use FP32 division
+    "-fno-hip-fp32-correctly-rounded-divide-sqrt",
     "-Wno-unused-result",
 ]
 

@@ -1,0 +1,73 @@
+// Double-precision exp and log for the plain (FP64) path.
+//
+// The device library's exp and log handle every corner of the IEEE range and cost about 50 and
+// 110 instructions; the source step calls them some 90 and 20 times per substep and is bound by
+// instruction issue.  These versions follow the textbook constructions below, take about 20 and
+// 30 instructions, and stay within a few ulp over the arguments the step produces.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+namespace ism {
+
+// ln 2 split for Cody-Waite reduction: the head keeps 32 significant bits, so k * head is exact
+// for |k| < 2^21; head + tail = ln 2 to ~2^-86.
+constexpr double LN2_HEAD = 0x1.62e42fee00000p-1;
+constexpr double LN2_TAIL = 0x1.a39ef35793c76p-33;
+
+// e^x: x = k ln2 + r with k = rint(x / ln2), |r| <= ln2 / 2; e^r by its Taylor series to degree
+// 13 (remainder below 4e-18 relative) in Horner form; the result scaled by 2^k.  Arguments
+// outside [-746, 710] saturate (to 0 and inf); NaN propagates.
+__host__ __device__ __forceinline__ double fexp(double x) {
+  x = x < -746.0 ? -746.0 : (x > 710.0 ? 710.0 : x);
+  const double k = rint(x * 1.4426950408889634074);
+  double r = fma(-k, LN2_HEAD, x);
+  r = fma(-k, LN2_TAIL, r);
+  double p = 1.0 / 6227020800.0;            // 1/13!
+  p = fma(p, r, 1.0 / 479001600.0);         // 1/12!
+  p = fma(p, r, 1.0 / 39916800.0);
+  p = fma(p, r, 1.0 / 3628800.0);
+  p = fma(p, r, 1.0 / 362880.0);
+  p = fma(p, r, 1.0 / 40320.0);
+  p = fma(p, r, 1.0 / 5040.0);
+  p = fma(p, r, 1.0 / 720.0);
+  p = fma(p, r, 1.0 / 120.0);
+  p = fma(p, r, 1.0 / 24.0);
+  p = fma(p, r, 1.0 / 6.0);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return ldexp(p, (int)k);
+}
+
+// ln x: x = 2^e m with m in [sqrt(1/2), sqrt(2)); with f = m - 1 (exact) and s = f / (2 + f),
+// ln m = 2 atanh s = 2 (s + s^3/3 + ... + s^21/21) for |s| <= 0.1716 (remainder below 3e-19
+// relative); ln x = e ln2 + ln m.  0 gives -inf, +inf gives +inf, negative arguments and NaN
+// give NaN.
+__host__ __device__ __forceinline__ double flog(double x) {
+  int e;
+  double m = frexp(x, &e);  // m in [0.5, 1)
+  const bool lo = m < 0.70710678118654752440;
+  m = lo ? m + m : m;
+  e = lo ? e - 1 : e;
+  const double f = m - 1.0;
+  const double s = f / (2.0 + f);
+  const double z = s * s;
+  double p = 2.0 / 21.0;
+  p = fma(p, z, 2.0 / 19.0);
+  p = fma(p, z, 2.0 / 17.0);
+  p = fma(p, z, 2.0 / 15.0);
+  p = fma(p, z, 2.0 / 13.0);
+  p = fma(p, z, 2.0 / 11.0);
+  p = fma(p, z, 2.0 / 9.0);
+  p = fma(p, z, 2.0 / 7.0);
+  p = fma(p, z, 2.0 / 5.0);
+  p = fma(p, z, 2.0 / 3.0);
+  const double lm = fma(s * z, p, s + s);
+  const double de = (double)e;
+  const double r = fma(de, LN2_HEAD, fma(de, LN2_TAIL, lm));
+  const double inf = __builtin_huge_val();
+  return (x > 0.0 && x < inf) ? r : (x == 0.0 ? -inf : (x == inf ? inf : __builtin_nan("")));
+}
+
+}  // namespace ism

@@ -23,8 +23,8 @@
 //      accepted when sum_v |L'_wv| |Y_0,v - Y_root,v| <= out_tol / 2 of each output's scale
 //      (and the unperturbed jump reproduces the root).
 // Accepted cells take the root (equilibrium C/O/e at the root); the others are appended to a
-// list for the plain step.  A cheap pre-test on the chemistry diagonal rejects most
-// non-equilibrium cells after a single probe.
+// list for the plain step.  A pre-test on the chemistry diagonal, from a chemistry-only
+// probe, rejects most non-equilibrium cells before any heating/cooling evaluation.
 #pragma once
 #include "kernels_step.h"
 
@@ -129,12 +129,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
     }
     const double Tseed = u[0];
     const double srate = a.fast / fmax(dt, 1e-300);
+    // pre-test on a chemistry-only probe (no heating, cooling or dust temperature): both
+    // chemical relaxation rates must be fast on their own
+    {
+      const EqS<float> e = eq_species<float>(u[0], (float)nd, u[1], u[2], r, c, p, s_tab, CloseTol<float>::v, 50);
+      const Eval<float> v = evaluate<float, true, false>(u[0], nd, u[1], u[2], e, r, c, p, s_tab, 0.f, nullptr);
+      if (dt * (2.0 * v.F + v.D) < 0.5 * a.fast || dt * (v.I + v.Rr) < 0.5 * a.fast) u[0] = -1.0;
+    }
     double J[3][3], gb[3], h[3] = {0.0, 0.0, 0.0};
     int phase = 0, k = 0, it = 0;
     double dir = 0.0;
     float tdg = 0.f;
 #pragma unroll 1
-    for (;;) {
+    for (; u[0] > 0.0;) {
       // probe point
       double Tq = u[0], aq = u[1], bq = u[2];
       if (phase == 0) {

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include "coef.h"
+#include "fmath.h"
 
 namespace ism {
 
@@ -30,8 +31,8 @@ constexpr double LN10D = 2.3025850929940456840;
 template <class R> struct Mx;
 
 template <> struct Mx<double> {
-  static __device__ __forceinline__ double ex(double x) { return ::exp(x); }
-  static __device__ __forceinline__ double ln(double x) { return ::log(x); }
+  static __device__ __forceinline__ double ex(double x) { return fexp(x); }
+  static __device__ __forceinline__ double ln(double x) { return flog(x); }
   static __device__ __forceinline__ double sq(double x) { return ::sqrt(x); }
   static __device__ __forceinline__ double cb(double x) { return ::cbrt(x); }
 };
