@@ -122,6 +122,34 @@ ism_status ism_columns6(const ism_grid *g, const ism_params *p, ism_precision pr
                         void *chi_PE, void *chi_LW, void *chi_H2, void *chi_C,
                         void *N_eff, void *xi_cr, hipStream_t stream);
 
+/* A point source: position (cm from the grid corner, inside the grid), ionising photon rate
+ * Q [s^-1] and FUV luminosity L_FUV [erg s^-1]. */
+typedef struct {
+  double x_cm, y_cm, z_cm;
+  double Q;
+  double L_FUV;
+} ism_source;
+
+/* Point-source radiation by long characteristics: the many-ray limit of the ray tracing of
+ * Sec. 5.1 (Eq. e:Erad) at cell centres.  For every cell and source, the straight segment
+ * from the source to the cell centre gives the exact columns N_H, N_H2, N_C (sums of field x
+ * length over the cells it crosses, in double), and the source adds
+ *   chi_PE += chi_s exp(-sigma_PE N_H), chi_LW += chi_s exp(-sigma_LW N_H)   (sigma x Z'_d),
+ *   chi_H2 += that LW term x f_shld,H2(N_H2)  (Eqs. e:chi_H2, e:fshld_H2_DB),
+ *   chi_C  += that LW term x f_shld,C(N_C, N_H2),
+ *   phi_LyC += Q exp(-sigma_LyC N_H) / (4 pi r^2) inside R_St = (3Q / (4 pi alpha_B(1e4 K)))^(1/3)
+ *              (mean density 1 cm^-3), 0 beyond,
+ * with chi_s = L_FUV / (16 pi^2 r^2 J^D_FUV) (Eq. e:chi_FUV; both bands get the same
+ * normalised intensity) and r at least half a cell.  In: n, xH2 (double), xC (double or
+ * NULL = 0); in/out: the five radiation arrays (double for F64, float for MIXED) -- the
+ * contributions are added, so six-ray fields or other sources may already be there.
+ * src is a host array of nsrc <= 256 sources, copied synchronously; calls on one device
+ * must not overlap in time. */
+ism_status ism_point_sources(const ism_grid *g, const ism_params *p, ism_precision prec,
+                             int32_t nsrc, const ism_source *src, const double *n,
+                             const double *xH2, const double *xC, void *chi_PE, void *chi_LW,
+                             void *chi_H2, void *chi_C, void *phi_LyC, hipStream_t stream);
+
 /* Per-cell diagnostics of the microphysics at the given state (Secs. 3-4): every rate
  * coefficient, heating and cooling term, T_d, the equilibrium x_C+, x_CO, x_e, the
  * net volumetric rate H = n Gamma - n^2 Lambda and C_H2, C_H+ (Eqs. e:HH, e:HII,

@@ -22,6 +22,7 @@
 #include "kernels_mlp.h"
 #include "kernels_surr.h"
 #include "kernels_order.h"
+#include "kernels_sources.h"
 
 using namespace ism;
 using ism::host::coef_to_f32;
@@ -704,6 +705,49 @@ ism_status ism_surrogate_set_params(ism_surrogate *m, const float *flat) {
   std::memcpy(m->norm_host, nh, sizeof(m->norm_host));
   if (ism_status s = surr_upload_norm(m)) return s;
   return surr_pack(m);
+}
+
+ism_status ism_point_sources(const ism_grid *g, const ism_params *p, ism_precision prec, int32_t nsrc,
+                             const ism_source *src, const double *n, const double *xH2, const double *xC,
+                             void *chi_PE, void *chi_LW, void *chi_H2, void *chi_C, void *phi_LyC,
+                             hipStream_t stream) {
+  g_err.clear();
+  if (!g) return fail(ISM_E_ARG, "grid is NULL");
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1) return fail(ISM_E_ARG, "grid dimensions must be >= 1");
+  if (!(g->dx_cm > 0.0) || !std::isfinite(g->dx_cm)) return fail(ISM_E_ARG, "dx_cm must be finite and > 0");
+  if (ism_status s = check_params(p)) return s;
+  if (prec != ISM_PREC_F64 && prec != ISM_PREC_MIXED) return fail(ISM_E_ARG, "invalid precision");
+  if (nsrc < 0 || nsrc > MAX_SOURCES) return fail(ISM_E_ARG, "nsrc must be in [0, 256]");
+  if (nsrc == 0) return ISM_OK;
+  if (!src || !n || !xH2 || !chi_PE || !chi_LW || !chi_H2 || !chi_C || !phi_LyC)
+    return fail(ISM_E_ARG, "a required array is NULL");
+  DevState *st;
+  if (ism_status s = current_state(&st)) return s;
+  const double box[3] = {g->nx * g->dx_cm, g->ny * g->dx_cm, g->nz * g->dx_cm};
+  const double Rst_pref = 3.0 / (4.0 * M_PI * g_host_coef.alpha_B[0]);  // alpha_B(1e4 K), mean density 1
+  SrcDev h[MAX_SOURCES];
+  for (int s = 0; s < nsrc; ++s) {
+    const double pos[3] = {src[s].x_cm, src[s].y_cm, src[s].z_cm};
+    for (int q = 0; q < 3; ++q)
+      if (!(pos[q] >= 0.0 && pos[q] < box[q])) return fail(ISM_E_ARG, "a source lies outside the grid");
+    if (!(src[s].Q >= 0.0) || !std::isfinite(src[s].Q) || !(src[s].L_FUV >= 0.0) || !std::isfinite(src[s].L_FUV))
+      return fail(ISM_E_ARG, "source Q and L_FUV must be finite and >= 0");
+    h[s] = SrcDev{pos[0] / g->dx_cm, pos[1] / g->dx_cm, pos[2] / g->dx_cm, src[s].Q, src[s].L_FUV,
+                  std::cbrt(Rst_pref * src[s].Q)};
+  }
+  HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(g_src), h, sizeof(SrcDev) * nsrc));
+  const double Zd = p->Zd;
+  PsArgs a{g->nx, g->ny, g->nz, nsrc, g->dx_cm, n, xH2, xC, chi_PE, chi_LW, chi_H2, chi_C, phi_LyC,
+           g_host_coef.sig_d_abs[2] * Zd, g_host_coef.sig_d_abs[1] * Zd, g_host_coef.sig_d_abs[0] * Zd,
+           1.0 / (16.0 * M_PI * M_PI * g_host_coef.J_FUV), st->tab64};
+  const int64_t ncell = (int64_t)g->nx * g->ny * g->nz;
+  const dim3 grid((unsigned)((ncell + 255) / 256));
+  if (prec == ISM_PREC_F64)
+    hipLaunchKernelGGL(point_sources_kernel<double>, grid, dim3(256), 0, stream, a);
+  else
+    hipLaunchKernelGGL(point_sources_kernel<float>, grid, dim3(256), 0, stream, a);
+  HIP_TRY(hipGetLastError());
+  return ISM_OK;
 }
 
 ism_status ism_surrogate_pairs(const ism_params *p, ism_precision prec, int64_t ncell, double dt_s, const double *n,

@@ -92,6 +92,9 @@ def lib():
         L.ism_surrogate_train_step.argtypes = [_vp, _vp, _vp, _i64, ctypes.c_float, _vp, _vp]
         L.ism_surrogate_get_params.argtypes = [_vp, _vp]
         L.ism_surrogate_set_params.argtypes = [_vp, _vp]
+        L.ism_point_sources.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Params), ctypes.c_int, _i32,
+                                        ctypes.c_void_p] + [_vp] * 8 + [_vp]
+        L.ism_point_sources.restype = ctypes.c_int
         L.ism_surrogate_pairs.argtypes = [ctypes.POINTER(_Params), ctypes.c_int, _i64, _dp] + [_vp] * 14
         L.ism_chem_cool_step_surrogate.argtypes = [_vp, ctypes.POINTER(_Params), _i64, _dp] + [_vp] * 16 + \
             [_dp, _vp, _vp]
@@ -109,7 +112,7 @@ SURROGATE_SYMBOLS = ("ism_surrogate_create", "ism_surrogate_destroy", "ism_surro
 
 def exported_symbols():
     return ["ism_params_default", "ism_init", "ism_shutdown", "ism_last_error", "ism_ndiag", "ism_diag_name",
-            "ism_columns6", "ism_rates", "ism_chem_cool_step"] + list(SURROGATE_SYMBOLS)
+            "ism_columns6", "ism_rates", "ism_chem_cool_step", "ism_point_sources"] + list(SURROGATE_SYMBOLS)
 
 
 def _check(rc):
@@ -153,6 +156,32 @@ def _stream(stream):
 
 def _rdt(prec):
     return torch.float64 if prec == F64 else torch.float32
+
+
+class _Source(ctypes.Structure):
+    _fields_ = [("x_cm", ctypes.c_double), ("y_cm", ctypes.c_double), ("z_cm", ctypes.c_double),
+                ("Q", ctypes.c_double), ("L_FUV", ctypes.c_double)]
+
+
+def point_sources(n, xH2, xC, dx_cm, params, prec, sources, out, stream=None):
+    """ism_point_sources: add the sources' radiation to out's chi_PE, chi_LW, chi_H2, chi_C and phi.
+
+    n, xH2 (and xC or None): float64 device tensors shaped [nz, ny, nx]; sources: rows of
+    (x_cm, y_cm, z_cm, Q, L_FUV); out: dict of device tensors of the path's dtype."""
+    _ensure_init(n)
+    nz, ny, nx = n.shape
+    N = n.numel()
+    rd = _rdt(prec)
+    src = [tuple(float(v) for v in row) for row in sources]
+    arr = (_Source * max(len(src), 1))(*[_Source(*r) for r in src])
+    g = _Grid(nx, ny, nz, 0, float(dx_cm))
+    p = params._c()
+    _check(lib().ism_point_sources(
+        ctypes.byref(g), ctypes.byref(p), prec, len(src), ctypes.cast(arr, ctypes.c_void_p),
+        _ptr(n, torch.float64, N, "n"), _ptr(xH2, torch.float64, N, "xH2"),
+        _ptr(xC, torch.float64, N, "xC", allow_none=True),
+        *[_ptr(out[k], rd, N, k) for k in ("chi_PE", "chi_LW", "chi_H2", "chi_C", "phi")], _stream(stream)))
+    return out
 
 
 def ndiag():

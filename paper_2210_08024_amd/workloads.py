@@ -14,6 +14,10 @@ Recipes (all seeds derive from SeedSequence(20221014)):
   noise smoothed by a Gaussian of sigma = 2 pc in Fourier space, re-standardised,
   n = exp(1.5 g - 1.5^2 / 2) (mean 1 cm^-3); T = 3e3 / ((1.1 + x_H+ - x_H2) n)
   clipped to [10, 1e7] K; abundances Dirichlet as above.
+* ``point_sources(nsrc, box_cm)`` seeded uniform positions in the box, each source with
+  Q = 1.24e50 s^-1 and L_FUV = 1.36e6 L_sun (a young cluster's LyC and FUV output).
+* ``c2``: the GRF recipe at 256^3 with 2 pc cells (the same 512 pc box), 16 point sources,
+  xi_cr per cell log-uniform in [1e-17, 1e-15] s^-1, ten successive steps of 1e4 yr.
 * ``thin(N)`` i.i.d. cells in an unattenuated field (chi = 1 in every band,
   xi_cr = 2e-16 s^-1, N_eff = 0): log10 n ~ U[0, 4], log10 T ~ U[1, 4],
   abundances Dirichlet as above.  Optically thin gas whose three relaxation times
@@ -87,9 +91,25 @@ def thin(N=4096, salt=2):
     return dict(n=n, T=T, xH2=xH2, xHp=xHp), rad
 
 
+L_SUN = 3.828e33
+
+
+def point_sources(nsrc, box_cm, salt=3):
+    """Rows of (x_cm, y_cm, z_cm, Q, L_FUV) at seeded uniform positions inside the box."""
+    r = _rngs(1, salt)[0]
+    pos = r.uniform(0.0, 1.0, (nsrc, 3)) * np.asarray(box_cm, dtype=np.float64)[None, :]
+    return np.concatenate([pos, np.full((nsrc, 1), 1.24e50), np.full((nsrc, 1), 1.36e6 * L_SUN)], axis=1)
+
+
+def cr_map(shape, salt=4):
+    r = _rngs(1, salt)[0]
+    return 10.0 ** r.uniform(-17.0, -15.0, shape)
+
+
 CONFIGS = {
     "tiny16": dict(grid=16, dx_pc=2.0, Zg=1.0, dt_yr=1.0e4, cr_mode=0),
     "grf128": dict(grid=128, dx_pc=4.0, Zg=1.0, dt_yr=1.0e4, cr_mode=1),
+    "c2": dict(grid=256, dx_pc=2.0, Zg=1.0, dt_yr=1.0e4, cr_mode=2, nsrc=16, steps=10),
 }
 
 
@@ -104,4 +124,8 @@ def make(name, grid=None):
         s = {k: v.reshape(N, N, N) for k, v in s.items()}
     else:
         s = grf_cube(N, cfg["dx_pc"])
+    if name == "c2":
+        box = N * cfg["dx_pc"] * PC
+        s["xi"] = cr_map(s["n"].shape)
+        cfg["sources"] = point_sources(cfg["nsrc"], (box, box, box))
     return s, cfg
