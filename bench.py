@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--path", choices=("f64", "mixed", "surrogate"), default="f64")
+    ap.add_argument("--workload", choices=("grf128", "c2"), default="grf128",
+                    help="grf128: the metric workload; c2: 256^3 with 16 point sources, ten successive steps "
+                         "(mixed form)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and the error report")
     ap.add_argument("--cpu-cells", type=int, default=65536)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -142,11 +145,114 @@ def field_errors(out, ref, idx, xCt):
     return rep
 
 
+def bench_c2(args):
+    """256^3, 2 pc cells, 16 point sources (maps once), CR map, ten successive mixed steps of
+    1e4 yr with x_C fed back into the columns; value = cell-updates/s over the ten steps,
+    the one-time point-source maps included."""
+    import torch
+    from paper_2210_08024_amd import ism, workloads
+    from oracle.census import substep_census
+    from oracle.constants import Params as OParams
+    s, cfg = workloads.make("c2")
+    shape = s["n"].shape
+    N = s["n"].size
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ism.init(0)
+    par = ism.Params(Zg=1.0, Zd=1.0, cr_mode=2)
+    dx = cfg["dx_pc"] * workloads.PC
+    dt = cfg["dt_yr"] * workloads.YR
+    stream = torch.cuda.current_stream()
+    init = {k: torch.from_numpy(np.ascontiguousarray(s[k]).ravel()).to(dev) for k in ("n", "T", "xH2", "xHp")}
+    xi = torch.from_numpy(s["xi"].ravel()).to(dev, torch.float32)
+    n = init["n"].view(shape)
+    T, xH2, xHp = (torch.empty_like(init[k]) for k in ("T", "xH2", "xHp"))
+    f32 = lambda: torch.empty(N, dtype=torch.float32, device=dev)
+    maps = {k: f32() for k in ("chi_PE", "chi_LW", "chi_H2", "chi_C", "phi")}
+    rad = {k: f32() for k in ("chi_PE", "chi_LW", "chi_H2", "chi_C", "N_eff", "xi")}
+    outs = {"xCp": f32(), "xCO": f32(), "xe": f32(), "nsub": torch.empty(N, dtype=torch.int32, device=dev),
+            "status": torch.empty(N, dtype=torch.uint8, device=dev)}
+    xC = torch.empty(N, dtype=torch.float64, device=dev)
+    xCt = OParams(Zg=1.0).xCtot
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    times = {"maps": [], "columns": [], "step": []}
+    tot_sub = []
+
+    def run(record):
+        T.copy_(init["T"])
+        xH2.copy_(init["xH2"])
+        xHp.copy_(init["xHp"])
+        for v in maps.values():
+            v.zero_()
+        ev[0].record(stream)
+        ism.point_sources(n, xH2.view(shape), None, dx, par, ism.MIXED, cfg["sources"],
+                          {k: v.view(shape) for k, v in maps.items()})
+        ev[1].record(stream)
+        if record:
+            torch.cuda.synchronize()
+            times["maps"].append(ev[0].elapsed_time(ev[1]) * 1e-3)
+        for step in range(cfg["steps"]):
+            rad["xi"].copy_(xi)
+            ev[2].record(stream)
+            ism.columns6(n, xH2.view(shape), None if step == 0 else xC.view(shape), dx, par, ism.MIXED,
+                         out={k: v.view(shape) for k, v in rad.items()})
+            for k in ("chi_PE", "chi_LW", "chi_H2", "chi_C"):
+                rad[k].add_(maps[k])
+            r = dict(rad)
+            r["phi"] = maps["phi"]
+            ev[3].record(stream)
+            ism.chem_cool_step(init["n"], T, xH2, xHp, r, dt, par, ism.MIXED, out=outs)
+            ev[0].record(stream)
+            torch.sub(xCt, outs["xCp"].double() + outs["xCO"].double(), out=xC).clamp_(min=0.0)
+            if record:
+                torch.cuda.synchronize()
+                times["columns"].append(ev[2].elapsed_time(ev[3]) * 1e-3)
+                times["step"].append(ev[3].elapsed_time(ev[0]) * 1e-3)
+                tot_sub.append(int(outs["nsub"].to(torch.int64).sum().item()))
+
+    for _ in range(args.warmup):
+        run(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run(False)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps
+    run(True)
+    arith, trans = substep_census(OParams())
+    t_step = float(np.sum(times["step"]))
+    achieved = float(np.sum(tot_sub)) * (arith + trans) / t_step / 1e12
+    out = {
+        "metric": "cell-updates/s per chem+cool step (columns6 + source step)",
+        "value": N * cfg["steps"] / wall, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall * 1e3 / cfg["steps"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "c2: 256^3 lognormal GRF (2 pc cells, 512 pc box), 16 point sources (Q 1.24e50 s^-1, "
+                               "L_FUV 1.36e6 L_sun; maps once), chi0 = 1 six-ray, xi_cr log-uniform [1e-17, 1e-15], "
+                               "Z' = 1, ten successive steps of 1e4 yr", "cells": N, "path": "mixed",
+                   "job": "point-source maps once + ten (columns6 + step)"},
+        "roofline": {"bound": "alu", "kernel": "step_queue_kernel", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
+                     "traffic": None, "work": f"{int(np.sum(tot_sub))} substeps over ten steps x ({arith} + {trans})"},
+        "detail": {"maps_ms": times["maps"][0] * 1e3, "columns_ms_mean": float(np.mean(times["columns"])) * 1e3,
+                   "step_ms_mean": float(np.mean(times["step"])) * 1e3,
+                   "step_ms_each": [round(t * 1e3, 3) for t in times["step"]],
+                   "nsub_mean_each": [round(x / N, 3) for x in tot_sub],
+                   "status_nonzero_last": int(((outs["status"] & 0xEF) != 0).sum().item())},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
         calibrate_copy()
         return
+    if args.workload == "c2":
+        if args.gpus != 1:
+            print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
+            sys.exit(2)
+        return bench_c2(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported "
                                    "(the source step is per-cell independent; see the sharding notes)"}))

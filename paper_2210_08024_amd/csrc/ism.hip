@@ -737,15 +737,19 @@ ism_status ism_point_sources(const ism_grid *g, const ism_params *p, ism_precisi
   }
   HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(g_src), h, sizeof(SrcDev) * nsrc));
   const double Zd = p->Zd;
-  PsArgs a{g->nx, g->ny, g->nz, nsrc, g->dx_cm, n, xH2, xC, chi_PE, chi_LW, chi_H2, chi_C, phi_LyC,
+  PsArgs a{g->nx, g->ny, g->nz, nsrc, 0, 0, g->dx_cm, n, xH2, xC, chi_PE, chi_LW, chi_H2, chi_C, phi_LyC,
            g_host_coef.sig_d_abs[2] * Zd, g_host_coef.sig_d_abs[1] * Zd, g_host_coef.sig_d_abs[0] * Zd,
            1.0 / (16.0 * M_PI * M_PI * g_host_coef.J_FUV), st->tab64};
   const int64_t ncell = (int64_t)g->nx * g->ny * g->nz;
   const dim3 grid((unsigned)((ncell + 255) / 256));
-  if (prec == ISM_PREC_F64)
-    hipLaunchKernelGGL(point_sources_kernel<double>, grid, dim3(256), 0, stream, a);
-  else
-    hipLaunchKernelGGL(point_sources_kernel<float>, grid, dim3(256), 0, stream, a);
+  for (int s = 0; s < nsrc; ++s) {
+    a.s0 = s;
+    a.s1 = s + 1;
+    if (prec == ISM_PREC_F64)
+      hipLaunchKernelGGL(point_sources_kernel<double>, grid, dim3(256), 0, stream, a);
+    else
+      hipLaunchKernelGGL(point_sources_kernel<float>, grid, dim3(256), 0, stream, a);
+  }
   HIP_TRY(hipGetLastError());
   return ISM_OK;
 }

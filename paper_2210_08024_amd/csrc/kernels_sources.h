@@ -1,11 +1,12 @@
 // Point-source radiation by long characteristics: the many-ray limit of the ray tracing of
 // Sec. 5.1 (Eq. e:Erad) evaluated at cell centres.
 //
-// One lane per cell; for every source the lane walks the straight segment from the source to
-// its cell centre through the grid (voxel traversal: at each step the nearest of the three next
-// plane crossings), integrating n, n x_H2 and n x_C times the length inside each cell, in
-// double.  Neighbouring lanes walk nearly parallel segments through the same cells, so the
-// loads are served by the caches.  Each source adds
+// One lane per cell; the lane walks the straight segment from the source to its cell centre
+// through the grid (voxel traversal: at each step the nearest of the three next plane
+// crossings), integrating n, n x_H2 and n x_C times the length inside each cell, in double.
+// One launch per source: all rays of a launch converge on the same source, so neighbouring
+// lanes and concurrent waves walk through the same cells near it and the loads hit the
+// caches.  Each source adds
 //   chi_PE += chi_s exp(-sigma_PE Z'_d N_H),  chi_LW += chi_s exp(-sigma_LW Z'_d N_H),
 //   chi_H2 += (LW term) f_shld,H2(N_H2),      chi_C += (LW term) f_shld,C(N_C, N_H2),
 //   phi    += Q exp(-sigma_LyC Z'_d N_H) / (4 pi r^2)  inside the Stromgren radius,
@@ -28,6 +29,7 @@ __constant__ SrcDev g_src[MAX_SOURCES];
 
 struct PsArgs {
   int32_t nx, ny, nz, nsrc;
+  int32_t s0, s1;         // sources handled by this launch
   double dx;
   const double *n, *xH2, *xC;
   void *chiPE, *chiLW, *chiH2, *chiC, *phi;
@@ -48,7 +50,7 @@ __global__ __launch_bounds__(256) void point_sources_kernel(PsArgs a) {
   const int dims[3] = {a.nx, a.ny, a.nz};
   const int max_steps = a.nx + a.ny + a.nz + 4;
   double aPE = 0.0, aLW = 0.0, aH2 = 0.0, aC = 0.0, aphi = 0.0;
-  for (int s = 0; s < a.nsrc; ++s) {
+  for (int s = a.s0; s < a.s1; ++s) {
     const SrcDev src = g_src[s];
     const double p0[3] = {src.x, src.y, src.z};
     double d[3], tmax[3], tdel[3];
