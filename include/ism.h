@@ -122,6 +122,17 @@ ism_status ism_columns6(const ism_grid *g, const ism_params *p, ism_precision pr
                         void *chi_PE, void *chi_LW, void *chi_H2, void *chi_C,
                         void *N_eff, void *xi_cr, hipStream_t stream);
 
+/* Local shielding-length radiation (Sec. 7.1.2): a cell of density n and shielding length
+ * L_cm (per cell) sees the background through N_shld = n L:
+ *   chi_PE/LW = chi0 exp(-sigma_PE/LW Z'_d N_shld), chi_H2 = chi_LW f_shld,H2(0.5 x_H2 n L),
+ *   chi_C = chi_LW f_shld,C(0.5 x_C n L, 0.5 x_H2 n L), N_eff = N_shld,
+ *   xi_cr: cr_mode 0 xi_cr0, 1 Eq. e:cratt on N_eff, 2 left unchanged (may be NULL).
+ * In: n, xH2, L_cm (double), xC (double or NULL = 0).  Out: double (F64) or float (MIXED). */
+ism_status ism_local_shielding(const ism_params *p, ism_precision prec, int64_t ncell,
+                               const double *n, const double *xH2, const double *xC,
+                               const double *L_cm, void *chi_PE, void *chi_LW, void *chi_H2,
+                               void *chi_C, void *N_eff, void *xi_cr, hipStream_t stream);
+
 /* A point source: position (cm from the grid corner, inside the grid), ionising photon rate
  * Q [s^-1] and FUV luminosity L_FUV [erg s^-1]. */
 typedef struct {

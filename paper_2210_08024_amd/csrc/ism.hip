@@ -707,6 +707,32 @@ ism_status ism_surrogate_set_params(ism_surrogate *m, const float *flat) {
   return surr_pack(m);
 }
 
+ism_status ism_local_shielding(const ism_params *p, ism_precision prec, int64_t ncell, const double *n,
+                               const double *xH2, const double *xC, const double *L_cm, void *chi_PE, void *chi_LW,
+                               void *chi_H2, void *chi_C, void *N_eff, void *xi_cr, hipStream_t stream) {
+  g_err.clear();
+  if (ism_status s = check_params(p)) return s;
+  if (prec != ISM_PREC_F64 && prec != ISM_PREC_MIXED) return fail(ISM_E_ARG, "invalid precision");
+  if (ncell < 0) return fail(ISM_E_ARG, "ncell must be >= 0");
+  if (ncell == 0) return ISM_OK;
+  if (!n || !xH2 || !L_cm || !chi_PE || !chi_LW || !chi_H2 || !chi_C || !N_eff || (!xi_cr && p->cr_mode != 2))
+    return fail(ISM_E_ARG, "a required array is NULL");
+  DevState *st;
+  if (ism_status s = current_state(&st)) return s;
+  const double sPE = g_host_coef.sig_d_abs[2] * p->Zd, sLW = g_host_coef.sig_d_abs[1] * p->Zd;
+  const dim3 grid((unsigned)((ncell + 255) / 256));
+  if (prec == ISM_PREC_F64)
+    hipLaunchKernelGGL(local_shield_kernel<double>, grid, dim3(256), 0, stream, ncell, n, xH2, xC, L_cm,
+                       (double *)chi_PE, (double *)chi_LW, (double *)chi_H2, (double *)chi_C, (double *)N_eff,
+                       (double *)xi_cr, p->chi0, sPE, sLW, p->xi_cr0, p->cr_mode, st->tab64);
+  else
+    hipLaunchKernelGGL(local_shield_kernel<float>, grid, dim3(256), 0, stream, ncell, n, xH2, xC, L_cm,
+                       (float *)chi_PE, (float *)chi_LW, (float *)chi_H2, (float *)chi_C, (float *)N_eff,
+                       (float *)xi_cr, p->chi0, sPE, sLW, p->xi_cr0, p->cr_mode, st->tab64);
+  HIP_TRY(hipGetLastError());
+  return ISM_OK;
+}
+
 ism_status ism_point_sources(const ism_grid *g, const ism_params *p, ism_precision prec, int32_t nsrc,
                              const ism_source *src, const double *n, const double *xH2, const double *xC,
                              void *chi_PE, void *chi_LW, void *chi_H2, void *chi_C, void *phi_LyC,

@@ -256,4 +256,30 @@ __global__ __launch_bounds__(256) void columns_march_kernel(ColArgs a) {
   }
 }
 
+// Local shielding-length radiation (Sec. 7.1.2): each cell sees the background field through
+// N_shld = n L, with H2 and C self-shielding through half of its own H2 and C columns.
+template <class R>
+__global__ __launch_bounds__(256) void local_shield_kernel(int64_t ncell, const double *n, const double *xH2,
+                                                            const double *xC, const double *L, R *chiPE, R *chiLW,
+                                                            R *chiH2, R *chiC, R *Neff, R *xi, double chi0,
+                                                            double sPE, double sLW, double xi0, int cr_mode,
+                                                            const double *tab) {
+  __shared__ double s_cs[CS_NX * CS_NY];
+  load_cs(tab, s_cs);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ncell) return;
+  const double nL = n[i] * L[i];
+  const double wPE = chi0 * (double)Mx<R>::ex(-sPE * nL);
+  const double wLW = chi0 * (double)Mx<R>::ex(-sLW * nL);
+  const double NH2 = 0.5 * xH2[i] * nL;
+  const double NC = xC ? 0.5 * xC[i] * nL : 0.0;
+  chiPE[i] = (R)wPE;
+  chiLW[i] = (R)wLW;
+  chiH2[i] = (R)(wLW * f_shld_H2<R>(NH2));
+  chiC[i] = (R)(wLW * f_shld_C<R>(NC, NH2, s_cs));
+  Neff[i] = (R)nL;
+  if (cr_mode == 0) xi[i] = (R)xi0;
+  else if (cr_mode == 1) xi[i] = (R)(nL <= g_coef64.N0_cr ? xi0 : xi0 * g_coef64.N0_cr / nL);
+}
+
 }  // namespace ism

@@ -92,6 +92,8 @@ def lib():
         L.ism_surrogate_train_step.argtypes = [_vp, _vp, _vp, _i64, ctypes.c_float, _vp, _vp]
         L.ism_surrogate_get_params.argtypes = [_vp, _vp]
         L.ism_surrogate_set_params.argtypes = [_vp, _vp]
+        L.ism_local_shielding.argtypes = [ctypes.POINTER(_Params), ctypes.c_int, _i64] + [_vp] * 11
+        L.ism_local_shielding.restype = ctypes.c_int
         L.ism_point_sources.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Params), ctypes.c_int, _i32,
                                         ctypes.c_void_p] + [_vp] * 8 + [_vp]
         L.ism_point_sources.restype = ctypes.c_int
@@ -112,7 +114,8 @@ SURROGATE_SYMBOLS = ("ism_surrogate_create", "ism_surrogate_destroy", "ism_surro
 
 def exported_symbols():
     return ["ism_params_default", "ism_init", "ism_shutdown", "ism_last_error", "ism_ndiag", "ism_diag_name",
-            "ism_columns6", "ism_rates", "ism_chem_cool_step", "ism_point_sources"] + list(SURROGATE_SYMBOLS)
+            "ism_columns6", "ism_rates", "ism_chem_cool_step", "ism_point_sources",
+            "ism_local_shielding"] + list(SURROGATE_SYMBOLS)
 
 
 def _check(rc):
@@ -156,6 +159,23 @@ def _stream(stream):
 
 def _rdt(prec):
     return torch.float64 if prec == F64 else torch.float32
+
+
+def local_shielding(n, xH2, xC, L_cm, params, prec=F64, out=None, stream=None):
+    """ism_local_shielding: radiation of cells shielded by their own column n L (Sec. 7.1.2)."""
+    _ensure_init(n)
+    N = n.numel()
+    rd = _rdt(prec)
+    if out is None:
+        out = {k: torch.empty(N, dtype=rd, device=n.device) for k in ("chi_PE", "chi_LW", "chi_H2", "chi_C",
+                                                                      "N_eff", "xi")}
+    p = params._c()
+    _check(lib().ism_local_shielding(
+        ctypes.byref(p), prec, N, _ptr(n, torch.float64, N, "n"), _ptr(xH2, torch.float64, N, "xH2"),
+        _ptr(xC, torch.float64, N, "xC", allow_none=True), _ptr(L_cm, torch.float64, N, "L_cm"),
+        *[_ptr(out[k], rd, N, k) for k in ("chi_PE", "chi_LW", "chi_H2", "chi_C", "N_eff")],
+        _ptr(out.get("xi"), rd, N, "xi", allow_none=True), _stream(stream)))
+    return out
 
 
 class _Source(ctypes.Structure):

@@ -1,0 +1,55 @@
+"""The shielded one-zone equilibrium (Sec. 7.1.2) against the thresholds the paper prints for
+chi0 = 1, Z' = 1 (H2 rovibrational cooling on): molecular (x_H2 > 0.25) above n ~ 20 cm^-3,
+CO-dominated (x_CO / x_C,tot > 0.5) above n ~ 350, T_d ~ 6 K at n ~ 1e6, CR heating above PE
+heating for n > 10^3.7 where N_shld = 5e21 cm^-2.  The CO fit and coolants partly rest on
+stand-in data, so the density thresholds are checked to within a factor 2 (0.3 dex)."""
+import numpy as np
+import pytest
+
+from oracle import micro, shield
+from oracle.constants import Params
+
+pytestmark = [pytest.mark.filterwarnings("ignore::RuntimeWarning"), pytest.mark.slow]
+
+
+@pytest.fixture(scope="module")
+def curve():
+    par = Params(cr_mode=1)
+    n = 10 ** np.linspace(0.0, 6.5, 53)
+    out, rad = shield.shielded_equilibrium(n, par)
+    eq = {k: out[k] for k in ("xCp", "xCO", "xC", "xOp", "xO", "xe")}
+    ev = micro.evaluate(out["T"], n, out["xH2"], out["xHp"], eq, rad, par)
+    return n, out, ev, par
+
+
+def _crossing(logn, y, level):
+    k = np.nonzero((y[:-1] < level) & (y[1:] >= level))[0]
+    assert k.size == 1, k
+    k = k[0]
+    return logn[k] + (level - y[k]) * (logn[k + 1] - logn[k]) / (y[k + 1] - y[k])
+
+
+def test_shielding_column_at_the_cr_crossing_density():
+    n = 10 ** 3.7
+    assert n * shield.shielding_length(n) == pytest.approx(5e21, rel=0.02)
+
+
+def test_molecular_above_about_20(curve):
+    n, out, ev, par = curve
+    assert abs(_crossing(np.log10(n), out["xH2"], 0.25) - np.log10(20.0)) < 0.3
+
+
+def test_co_dominated_above_about_350(curve):
+    n, out, ev, par = curve
+    assert abs(_crossing(np.log10(n), out["xCO"] / par.xCtot, 0.5) - np.log10(350.0)) < 0.3
+
+
+def test_dust_at_the_bath_temperature_at_1e6(curve):
+    n, out, ev, par = curve
+    i = np.argmin(np.abs(np.log10(n) - 6.0))
+    assert ev["Td"][i] == pytest.approx(6.0, abs=0.5)
+
+
+def test_cr_heating_overtakes_pe_heating_near_10_3p7(curve):
+    n, out, ev, par = curve
+    assert abs(_crossing(np.log10(n), np.log10(ev["G_cr"] / ev["G_pe"]), 0.0) - 3.7) < 0.3
