@@ -122,6 +122,16 @@ ism_status ism_columns6(const ism_grid *g, const ism_params *p, ism_precision pr
                         void *chi_PE, void *chi_LW, void *chi_H2, void *chi_C,
                         void *N_eff, void *xi_cr, hipStream_t stream);
 
+/* A beam of surface intensity chi0 (params) entering every x row through the x = 0 face
+ * along +x: the plane-parallel slab of Sec. 7.2.  Per cell the same terms as one six-ray
+ * direction of ism_columns6 with weight chi0 instead of chi0/6: dust attenuation to the entry
+ * face times the cell average, H2 and C shielding at mid-cell.  N_eff and xi_cr as in
+ * ism_columns6.  Arguments and layout as ism_columns6 (no scratch). */
+ism_status ism_columns_beam(const ism_grid *g, const ism_params *p, ism_precision prec,
+                            const double *n, const double *xH2, const double *xC,
+                            void *chi_PE, void *chi_LW, void *chi_H2, void *chi_C,
+                            void *N_eff, void *xi_cr, hipStream_t stream);
+
 /* Local shielding-length radiation (Sec. 7.1.2): a cell of density n and shielding length
  * L_cm (per cell) sees the background through N_shld = n L:
  *   chi_PE/LW = chi0 exp(-sigma_PE/LW Z'_d N_shld), chi_H2 = chi_LW f_shld,H2(0.5 x_H2 n L),

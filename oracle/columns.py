@@ -105,6 +105,30 @@ def columns6(n, xH2, xC, dx, par, xi_in=None):
     return dict(chi_PE=chiPE, chi_LW=chiLW, chi_H2=chiH2, chi_C=chiC, N_eff=Neff, xi=xi)
 
 
+def columns_beam(n, xH2, xC, dx, par):
+    """Radiation of a beam of surface intensity chi0 entering through the x = 0 face along +x
+    (the plane-parallel slab of Sec. 7.2): the +x ray of columns6 with weight chi0 instead of
+    chi0 / 6.  Same cell average and mid-cell shielding columns; N_eff and xi as in columns6."""
+    n = np.asarray(n, dtype=np.float64)
+    xH2 = np.asarray(xH2, dtype=np.float64)
+    xC = np.zeros_like(n) if xC is None else np.asarray(xC, dtype=np.float64)
+    Zd, chi0 = par.Zd, par.chi0
+    sPE, sLW = C.SIG_D_PE * Zd, C.SIG_D_LW * Zd
+    qH, qH2, qC = n * dx, n * xH2 * dx, n * xC * dx
+    NH = upstream_columns(qH, 2, True)
+    NH2m = upstream_columns(qH2, 2, True) + 0.5 * qH2
+    NCm = upstream_columns(qC, 2, True) + 0.5 * qC
+    chiPE = chi0 * np.exp(-sPE * NH) * g_slab(sPE * qH)
+    chiLW = chi0 * np.exp(-sLW * NH) * g_slab(sLW * qH)
+    Neff = -np.log(chiPE / chi0) / (C.SIG_D_NEFF * Zd) if chi0 > 0.0 else np.zeros_like(n)
+    if par.cr_mode == 0:
+        xi = np.full_like(n, par.xi_cr0)
+    else:
+        xi = cr_attenuation(Neff, par.xi_cr0)
+    return dict(chi_PE=chiPE, chi_LW=chiLW, chi_H2=chiLW * f_shld_H2(NH2m), chi_C=chiLW * f_shld_C(NCm, NH2m),
+                N_eff=Neff, xi=xi)
+
+
 def cr_attenuation(Neff, xi0):
     """Eq. e:cratt: xi0 for N_eff <= N0, xi0 (N_eff / N0)^-1 beyond."""
     return np.where(Neff <= C.N0_CR, xi0, xi0 * C.N0_CR / np.maximum(Neff, C.N0_CR))

@@ -707,6 +707,37 @@ ism_status ism_surrogate_set_params(ism_surrogate *m, const float *flat) {
   return surr_pack(m);
 }
 
+ism_status ism_columns_beam(const ism_grid *g, const ism_params *p, ism_precision prec, const double *n,
+                            const double *xH2, const double *xC, void *chi_PE, void *chi_LW, void *chi_H2,
+                            void *chi_C, void *N_eff, void *xi_cr, hipStream_t stream) {
+  g_err.clear();
+  if (!g) return fail(ISM_E_ARG, "grid is NULL");
+  if (ism_status s = check_params(p)) return s;
+  if (prec != ISM_PREC_F64 && prec != ISM_PREC_MIXED) return fail(ISM_E_ARG, "invalid precision");
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1) return fail(ISM_E_ARG, "grid dimensions must be >= 1");
+  if (!(g->dx_cm > 0.0) || !std::isfinite(g->dx_cm)) return fail(ISM_E_ARG, "dx_cm must be finite and > 0");
+  if (!n || !xH2 || !chi_PE || !chi_LW || !chi_H2 || !chi_C || !N_eff)
+    return fail(ISM_E_ARG, "n, xH2 and all chi/N_eff outputs must be non-NULL");
+  if (p->cr_mode != 2 && !xi_cr) return fail(ISM_E_ARG, "xi_cr output is NULL (cr_mode 0/1 writes it)");
+  DevState *st;
+  if (ism_status s = current_state(&st)) return s;
+  ColArgs a{};
+  a.nx = g->nx; a.ny = g->ny; a.nz = g->nz; a.dx = g->dx_cm;
+  a.n = n; a.xH2 = xH2; a.xC = xC;
+  a.chiPE = chi_PE; a.chiLW = chi_LW; a.chiH2 = chi_H2; a.chiC = chi_C; a.Neff = N_eff; a.xi = xi_cr;
+  a.cr_mode = p->cr_mode;
+  a.chi0 = p->chi0; a.Zd = p->Zd; a.xi0 = p->xi_cr0;
+  a.sPE = g_host_coef.sig_d_abs[2] * p->Zd;
+  a.sLW = g_host_coef.sig_d_abs[1] * p->Zd;
+  a.tab = st->tab64;
+  const int64_t rows = (int64_t)g->ny * g->nz;
+  const dim3 grid((unsigned)((rows + 3) / 4));
+  if (prec == ISM_PREC_MIXED) hipLaunchKernelGGL(columns_beam_kernel<float>, grid, dim3(256), 0, stream, a);
+  else hipLaunchKernelGGL(columns_beam_kernel<double>, grid, dim3(256), 0, stream, a);
+  HIP_TRY(hipGetLastError());
+  return ISM_OK;
+}
+
 ism_status ism_local_shielding(const ism_params *p, ism_precision prec, int64_t ncell, const double *n,
                                const double *xH2, const double *xC, const double *L_cm, void *chi_PE, void *chi_LW,
                                void *chi_H2, void *chi_C, void *N_eff, void *xi_cr, hipStream_t stream) {

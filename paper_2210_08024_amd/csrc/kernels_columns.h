@@ -256,6 +256,50 @@ __global__ __launch_bounds__(256) void columns_march_kernel(ColArgs a) {
   }
 }
 
+// A beam of surface intensity chi0 entering through the x = 0 face along +x (plane-parallel
+// slab): the +x ray of the six-ray pass with weight chi0, finalised in the same kernel.
+template <class R>
+__global__ __launch_bounds__(256) void columns_beam_kernel(ColArgs a) {
+  __shared__ double s_cs[CS_NX * CS_NY];
+  load_cs(a.tab, s_cs);
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (row >= (int64_t)a.ny * a.nz) return;
+  const int64_t base = row * a.nx;
+  const int nch = (a.nx + 63) >> 6;
+  double cH = 0.0, cH2 = 0.0, cC = 0.0;
+  for (int ch = 0; ch < nch; ++ch) {
+    const int i = (ch << 6) + lane;
+    const bool ok = i < a.nx;
+    double qH = 0.0, qH2 = 0.0, qC = 0.0;
+    if (ok) cell_q(a, base + i, qH, qH2, qC);
+    double tH, tH2, tC;
+    const double eH = wave_excl(qH, lane, tH) + cH;
+    const double eH2 = wave_excl(qH2, lane, tH2) + cH2;
+    const double eC = wave_excl(qC, lane, tC) + cC;
+    cH += tH;
+    cH2 += tH2;
+    cC += tC;
+    if (ok) {
+      const double4 t = ray_term<R>(a, eH, eH2, eC, qH, qH2, qC, s_cs);
+      const int64_t idx = base + i;
+      const double cPE = a.chi0 * t.x;
+      const double Neff = a.chi0 > 0.0 ? -::log(cPE / a.chi0) / (g_coef64.sig_d_Neff * a.Zd) : 0.0;
+      double xi = a.xi0;
+      if (a.cr_mode == 1) {
+        const double N0 = g_coef64.N0_cr;
+        xi = Neff <= N0 ? a.xi0 : a.xi0 * N0 / (Neff > N0 ? Neff : N0);
+      }
+      store_out<R>(a.chiPE, idx, cPE);
+      store_out<R>(a.chiLW, idx, a.chi0 * t.y);
+      store_out<R>(a.chiH2, idx, a.chi0 * t.z);
+      store_out<R>(a.chiC, idx, a.chi0 * t.w);
+      store_out<R>(a.Neff, idx, Neff);
+      if (a.cr_mode != 2) store_out<R>(a.xi, idx, xi);
+    }
+  }
+}
+
 // Local shielding-length radiation (Sec. 7.1.2): each cell sees the background field through
 // N_shld = n L, with H2 and C self-shielding through half of its own H2 and C columns.
 template <class R>

@@ -92,6 +92,8 @@ def lib():
         L.ism_surrogate_train_step.argtypes = [_vp, _vp, _vp, _i64, ctypes.c_float, _vp, _vp]
         L.ism_surrogate_get_params.argtypes = [_vp, _vp]
         L.ism_surrogate_set_params.argtypes = [_vp, _vp]
+        L.ism_columns_beam.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Params), ctypes.c_int] + [_vp] * 10
+        L.ism_columns_beam.restype = ctypes.c_int
         L.ism_local_shielding.argtypes = [ctypes.POINTER(_Params), ctypes.c_int, _i64] + [_vp] * 11
         L.ism_local_shielding.restype = ctypes.c_int
         L.ism_point_sources.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Params), ctypes.c_int, _i32,
@@ -115,7 +117,7 @@ SURROGATE_SYMBOLS = ("ism_surrogate_create", "ism_surrogate_destroy", "ism_surro
 def exported_symbols():
     return ["ism_params_default", "ism_init", "ism_shutdown", "ism_last_error", "ism_ndiag", "ism_diag_name",
             "ism_columns6", "ism_rates", "ism_chem_cool_step", "ism_point_sources",
-            "ism_local_shielding"] + list(SURROGATE_SYMBOLS)
+            "ism_local_shielding", "ism_columns_beam"] + list(SURROGATE_SYMBOLS)
 
 
 def _check(rc):
@@ -159,6 +161,24 @@ def _stream(stream):
 
 def _rdt(prec):
     return torch.float64 if prec == F64 else torch.float32
+
+
+def columns_beam(n, xH2, xC, dx_cm, params, prec=F64, out=None, stream=None):
+    """ism_columns_beam on an [nz, ny, nx] grid: a beam entering through x = 0 along +x."""
+    _ensure_init(n)
+    nz, ny, nx = n.shape
+    N = n.numel()
+    rd = _rdt(prec)
+    if out is None:
+        out = {k: torch.empty_like(n, dtype=rd) for k in ("chi_PE", "chi_LW", "chi_H2", "chi_C", "N_eff", "xi")}
+    g = _Grid(nx, ny, nz, 0, float(dx_cm))
+    p = params._c()
+    _check(lib().ism_columns_beam(ctypes.byref(g), ctypes.byref(p), prec, _ptr(n, torch.float64, N, "n"),
+                                  _ptr(xH2, torch.float64, N, "xH2"),
+                                  _ptr(xC, torch.float64, N, "xC", allow_none=True),
+                                  *[_ptr(out[k], rd, N, k) for k in ("chi_PE", "chi_LW", "chi_H2", "chi_C", "N_eff")],
+                                  _ptr(out.get("xi"), rd, N, "xi", allow_none=True), _stream(stream)))
+    return out
 
 
 def local_shielding(n, xH2, xC, L_cm, params, prec=F64, out=None, stream=None):
