@@ -171,6 +171,46 @@ ism_status ism_point_sources(const ism_grid *g, const ism_params *p, ism_precisi
                              const double *xH2, const double *xC, void *chi_PE, void *chi_LW,
                              void *chi_H2, void *chi_C, void *phi_LyC, hipStream_t stream);
 
+/* Options of the adaptive ray tracing (Sec. 5.1): packets start at HEALPix level level0
+ * (12 4^level0 per source), split into four down to max_level (<= 13) while fewer than
+ * rays_per_cell rays of a level would cross a cell, and stop once the optical depth from the
+ * source exceeds tau_max in every band.  The paper's values: 4, (unbounded), 4, 30. */
+typedef struct {
+  int32_t level0;
+  int32_t max_level;
+  double rays_per_cell;
+  double tau_max;
+} ism_art_options;
+
+/* Point-source radiation by adaptive ray tracing (Sec. 5.1, Eqs. e:Erad, e:Erad_H2, e:chi_H2).
+ * Each source emits photon packets along the HEALPix directions (Gorski et al. 2005, nested
+ * numbering); a packet crossing a cell over ds deposits, per band, L_in (1 - exp(-alpha ds)) /
+ * alpha with L_in = L exp(-tau) / N_ray(level), tau from the source to the entry face:
+ *   PE, LW: alpha = n sigma_d Z'_d, L = L_FUV, deposit / (4 pi dV J^D_FUV) added to chi_PE,
+ *           chi_LW; the LW deposit times f_shld,H2(N_H2) to chi_H2 and times f_shld,C(N_C, N_H2)
+ *           to chi_C, columns to the middle of the segment;
+ *   LyC:    alpha = n (x_HI sigma_pi,H + x_H2 sigma_pi,H2 + Z'_d sigma_d,LyC),
+ *           x_HI = max(0, 1 - 2 x_H2 - x_H+), L = Q, deposit / dV added to phi_LyC (photons
+ *           cm^-2 s^-1).
+ * A packet is split into its four children (same distance r, own directions, same columns)
+ * before entering a cell where N_ray dx^2 / (4 pi r^2) < rays_per_cell, dropped where every
+ * band's tau > tau_max, and lost through the grid faces (all open).
+ * In: n, xH2, xHp (double, [nz][ny][nx]), xC (double or NULL = 0); src: host array of
+ * nsrc <= 256 sources inside the grid; opt: NULL for the defaults {4, 13, 4.0, 30.0}.
+ * In/out: the five radiation arrays (double for F64, float for MIXED): contributions are
+ * added (atomically, so the last bits vary between runs).  budget: NULL, or a device array of
+ * nsrc x 6 doubles that receives per source the luminosity lost through the faces (PE, LW in
+ * erg s^-1, LyC in photons s^-1) and then the luminosity dropped at tau > tau_max.
+ * The call returns when the work is done: it reads the number of packets of each level back
+ * to the host.  The packet lists are library memory on the current device (48 bytes a packet;
+ * a level may hold up to 4x the previous one) and the sources sit in constant memory, so
+ * calls on one device must not overlap in time.  ISM_E_NOMEM when a list cannot grow. */
+ism_status ism_ray_trace(const ism_grid *g, const ism_params *p, ism_precision prec, int32_t nsrc,
+                         const ism_source *src, const ism_art_options *opt, const double *n,
+                         const double *xH2, const double *xHp, const double *xC, void *chi_PE,
+                         void *chi_LW, void *chi_H2, void *chi_C, void *phi_LyC, double *budget,
+                         hipStream_t stream);
+
 /* Per-cell diagnostics of the microphysics at the given state (Secs. 3-4): every rate
  * coefficient, heating and cooling term, T_d, the equilibrium x_C+, x_CO, x_e, the
  * net volumetric rate H = n Gamma - n^2 Lambda and C_H2, C_H+ (Eqs. e:HH, e:HII,

@@ -18,7 +18,9 @@ packet enters a cell at distance r it is
   and carry the parent's columns, if N_ray(l) dx^2 / (4 pi r^2) < Phi_c (rays per cell per
   source; default 4),
 
-and it is lost through the domain boundary (all six faces open).
+and it is lost through the domain boundary (all six faces open).  A piece that would start
+within 1e-10 cells of the boundary is not entered: where a plane crossing meets the domain
+exit (up to rounding) the packet leaves rather than splitting on the boundary.
 
 Bands and opacities (Sec. 5.1): PE and LW by dust only, alpha = n sigma_d Z'_d; LyC by H, H2
 and dust, alpha = n (x_HI sigma_pi,H + x_H2 sigma_pi,H2 + Z'_d sigma_d,LyC), x_HI = 1 - 2 x_H2
@@ -79,7 +81,11 @@ def healpix_dirs(level, pix=None):
     xf = (np.floor(xs / (2 * q)) + 0.5) * 2 * q
     phi = np.where(eq, xs, xf + (xs - xf) / sig)
     s = np.sqrt(np.maximum(1.0 - z * z, 0.0))
-    return np.stack([s * np.cos(phi), s * np.sin(phi), z], 1)
+    u = np.stack([s * np.cos(phi), s * np.sin(phi), z], 1)
+    # components that vanish exactly (directions in a coordinate plane) are zero, not the
+    # 1e-17 left by cos(pi/2); the smallest true component at level 13 is about 1e-9
+    u[np.abs(u) < 1e-12] = 0.0
+    return u
 
 
 def _g(y):
@@ -115,6 +121,9 @@ class _Grid:
         self.dims = np.array([nx, ny, nz])
 
 
+EXIT_TOL = 1e-10  # cells
+
+
 def _walk(G, s, lev, pix, state, rays_per_cell, tau_max, max_level):
     """One packet from its start to where it ends or splits.
 
@@ -130,7 +139,7 @@ def _walk(G, s, lev, pix, state, rays_per_cell, tau_max, max_level):
         rb = np.where(u != 0, (bound - s) / np.where(u != 0, u, 1.0), np.inf)
     r_exit = float(np.min(rb))
     p0 = s + r0 * u
-    if np.any(p0 < 0.0) or np.any(p0 >= box) or r_exit <= r0:
+    if np.any(p0 < 0.0) or np.any(p0 >= box) or r0 >= r_exit - EXIT_TOL * dx:
         return "exit", None, state
     cuts = [r0, r_exit]
     for a in range(3):
@@ -142,6 +151,10 @@ def _walk(G, s, lev, pix, state, rays_per_cell, tau_max, max_level):
         cuts.extend(rm[(rm > r0) & (rm < r_exit)].tolist())
     cuts = np.unique(np.array(cuts))
     ra, rbnd = cuts[:-1], cuts[1:]
+    # a piece that would start within EXIT_TOL cells of the exit is not entered: the packet
+    # has left (a plane crossing that meets the exit up to rounding is not a cell entry)
+    keep = ra < r_exit - EXIT_TOL * dx
+    ra, rbnd = ra[keep], rbnd[keep]
     mid = s[None, :] + (0.5 * (ra + rbnd))[:, None] * u[None, :]
     ijk = np.clip(np.floor(mid / dx).astype(np.int64), 0, G.dims - 1)
     cell = ijk[:, 0] + G.nx * (ijk[:, 1] + G.ny * ijk[:, 2])

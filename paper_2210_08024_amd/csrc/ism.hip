@@ -23,6 +23,7 @@
 #include "kernels_surr.h"
 #include "kernels_order.h"
 #include "kernels_sources.h"
+#include "kernels_art.h"
 
 using namespace ism;
 using ism::host::coef_to_f32;
@@ -51,6 +52,10 @@ struct DevState {
   size_t sscratch_bytes = 0;
   void *oscratch = nullptr;  // cell ordering: keys, histogram, cursor, ordered list
   size_t oscratch_bytes = 0;
+  ArtRay *art_list[2] = {nullptr, nullptr};  // ray tracing: packet lists of two levels
+  int64_t art_cap[2] = {0, 0};
+  unsigned long long *art_count = nullptr;     // children appended by a level launch
+  unsigned long long *art_count_host = nullptr;
   int num_cu = 0;
   int occ64 = 0, occ32 = 0;  // resident 256-thread blocks per CU of the persistent step kernels
   bool simple_step = false;   // ISM_STEP_KERNEL=simple selects the one-lane-per-cell grid
@@ -253,6 +258,10 @@ ism_status ism_shutdown(void) {
     if (kv.second.queues) (void)hipFree(kv.second.queues);
     if (kv.second.sscratch) (void)hipFree(kv.second.sscratch);
     if (kv.second.oscratch) (void)hipFree(kv.second.oscratch);
+    for (int b = 0; b < 2; ++b)
+      if (kv.second.art_list[b]) (void)hipFree(kv.second.art_list[b]);
+    if (kv.second.art_count) (void)hipFree(kv.second.art_count);
+    if (kv.second.art_count_host) (void)hipHostFree(kv.second.art_count_host);
   }
   g_dev.clear();
   (void)hipSetDevice(prev);
@@ -808,6 +817,116 @@ ism_status ism_point_sources(const ism_grid *g, const ism_params *p, ism_precisi
       hipLaunchKernelGGL(point_sources_kernel<float>, grid, dim3(256), 0, stream, a);
   }
   HIP_TRY(hipGetLastError());
+  return ISM_OK;
+}
+
+// Packet list b with room for at least `rays` packets (grows, never shrinks).
+ism_status art_list(DevState *st, int b, int64_t rays) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!st->art_count) {
+    hipError_t e = hipMalloc(&st->art_count, sizeof(unsigned long long));
+    if (e != hipSuccess) return fail(ISM_E_NOMEM, std::string("ray counter: ") + hipGetErrorString(e));
+    e = hipHostMalloc(&st->art_count_host, sizeof(unsigned long long));
+    if (e != hipSuccess) return fail(ISM_E_NOMEM, std::string("ray counter (host): ") + hipGetErrorString(e));
+  }
+  if (st->art_cap[b] < rays) {
+    if (st->art_list[b]) (void)hipFree(st->art_list[b]);
+    st->art_list[b] = nullptr;
+    st->art_cap[b] = 0;
+    const int64_t want = std::max<int64_t>(rays, 1 << 16);
+    hipError_t e = hipMalloc(&st->art_list[b], sizeof(ArtRay) * (size_t)want);
+    if (e != hipSuccess)
+      return fail(ISM_E_NOMEM, "ray list of " + std::to_string(want) + " packets: " + hipGetErrorString(e));
+    st->art_cap[b] = want;
+  }
+  return ISM_OK;
+}
+
+ism_status ism_ray_trace(const ism_grid *g, const ism_params *p, ism_precision prec, int32_t nsrc,
+                         const ism_source *src, const ism_art_options *opt, const double *n, const double *xH2,
+                         const double *xHp, const double *xC, void *chi_PE, void *chi_LW, void *chi_H2,
+                         void *chi_C, void *phi_LyC, double *budget, hipStream_t stream) {
+  g_err.clear();
+  if (!g) return fail(ISM_E_ARG, "grid is NULL");
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1) return fail(ISM_E_ARG, "grid dimensions must be >= 1");
+  if ((int64_t)g->nx + g->ny + g->nz > (int64_t)INT32_MAX / 2) return fail(ISM_E_ARG, "grid too large");
+  if (!(g->dx_cm > 0.0) || !std::isfinite(g->dx_cm)) return fail(ISM_E_ARG, "dx_cm must be finite and > 0");
+  if (ism_status s = check_params(p)) return s;
+  if (prec != ISM_PREC_F64 && prec != ISM_PREC_MIXED) return fail(ISM_E_ARG, "invalid precision");
+  if (nsrc < 0 || nsrc > MAX_SOURCES) return fail(ISM_E_ARG, "nsrc must be in [0, 256]");
+  ism_art_options o{4, 13, 4.0, 30.0};
+  if (opt) o = *opt;
+  if (o.level0 < 0 || o.level0 > o.max_level || o.max_level > ART_MAX_LEVEL)
+    return fail(ISM_E_ARG, "need 0 <= level0 <= max_level <= 13");
+  if (!(o.rays_per_cell > 0.0) || !std::isfinite(o.rays_per_cell))
+    return fail(ISM_E_ARG, "rays_per_cell must be finite and > 0");
+  if (!(o.tau_max > 0.0)) return fail(ISM_E_ARG, "tau_max must be > 0");
+  if (nsrc == 0) return ISM_OK;
+  if (!src || !n || !xH2 || !xHp || !chi_PE || !chi_LW || !chi_H2 || !chi_C || !phi_LyC)
+    return fail(ISM_E_ARG, "a required array is NULL");
+  DevState *st;
+  if (ism_status s = current_state(&st)) return s;
+  const double box[3] = {g->nx * g->dx_cm, g->ny * g->dx_cm, g->nz * g->dx_cm};
+  SrcDev h[MAX_SOURCES];
+  for (int s = 0; s < nsrc; ++s) {
+    const double pos[3] = {src[s].x_cm, src[s].y_cm, src[s].z_cm};
+    for (int q = 0; q < 3; ++q)
+      if (!(pos[q] >= 0.0 && pos[q] < box[q])) return fail(ISM_E_ARG, "a source lies outside the grid");
+    if (!(src[s].Q >= 0.0) || !std::isfinite(src[s].Q) || !(src[s].L_FUV >= 0.0) || !std::isfinite(src[s].L_FUV))
+      return fail(ISM_E_ARG, "source Q and L_FUV must be finite and >= 0");
+    h[s] = SrcDev{pos[0] / g->dx_cm, pos[1] / g->dx_cm, pos[2] / g->dx_cm, src[s].Q, src[s].L_FUV, 0.0};
+  }
+  HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(g_src), h, sizeof(SrcDev) * nsrc));
+  const double Zd = p->Zd;
+  const double dV = g->dx_cm * g->dx_cm * g->dx_cm;
+  ArtArgs a{};
+  a.nx = g->nx; a.ny = g->ny; a.nz = g->nz; a.nsrc = nsrc;
+  a.max_level = o.max_level;
+  a.dx = g->dx_cm;
+  a.tau_max = o.tau_max;
+  a.n = n; a.xH2 = xH2; a.xHp = xHp; a.xC = xC;
+  a.chiPE = chi_PE; a.chiLW = chi_LW; a.chiH2 = chi_H2; a.chiC = chi_C; a.phi = phi_LyC;
+  a.sPE = g_host_coef.sig_d_abs[2] * Zd;
+  a.sLW = g_host_coef.sig_d_abs[1] * Zd;
+  a.sdLyC = g_host_coef.sig_d_abs[0] * Zd;
+  a.spiH = g_host_coef.sig_pi_H;
+  a.spiH2 = g_host_coef.sig_pi_H2;
+  a.fuv_norm = 1.0 / (4.0 * M_PI * dV * g_host_coef.J_FUV);
+  a.phi_norm = 1.0 / dV;
+  a.budget = budget;
+  a.tab = st->tab64;
+  if (budget)
+    hipLaunchKernelGGL(art_zero_kernel, dim3((unsigned)((6 * nsrc + 255) / 256)), dim3(256), 0, stream, budget,
+                       (int64_t)6 * nsrc, (unsigned long long *)nullptr);
+  const size_t lds = budget ? sizeof(double) * 6 * (size_t)nsrc : 0;
+  int64_t nin = (int64_t)nsrc * (12ll << (2 * o.level0));
+  int cur = 0;
+  for (int level = o.level0; nin > 0 && level <= o.max_level; ++level) {
+    const int nxt = cur ^ 1;
+    if (level < o.max_level)
+      if (ism_status s = art_list(st, nxt, 4 * nin)) return s;
+    if (!st->art_count)
+      if (ism_status s = art_list(st, nxt, 0)) return s;
+    a.level = level;
+    a.nin = nin;
+    a.in = level == o.level0 ? nullptr : st->art_list[cur];
+    a.out = st->art_list[nxt];
+    a.nout = st->art_count;
+    a.R2split = (12.0 * std::ldexp(1.0, 2 * level)) / (4.0 * M_PI * o.rays_per_cell);
+    hipLaunchKernelGGL(art_zero_kernel, dim3(1), dim3(64), 0, stream, (double *)nullptr, (int64_t)0,
+                       st->art_count);
+    const dim3 grid((unsigned)((nin + 255) / 256));
+    if (prec == ISM_PREC_F64)
+      hipLaunchKernelGGL(art_level_kernel<double>, grid, dim3(256), lds, stream, a);
+    else
+      hipLaunchKernelGGL(art_level_kernel<float>, grid, dim3(256), lds, stream, a);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(st->art_count_host, st->art_count, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                           stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    nin = level < o.max_level ? (int64_t)*st->art_count_host : 0;
+    cur = nxt;
+  }
   return ISM_OK;
 }
 

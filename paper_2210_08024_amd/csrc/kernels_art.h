@@ -1,0 +1,297 @@
+// Adaptive ray tracing of point sources (Sec. 5.1, Eqs. e:Erad, e:Erad_H2, e:chi_H2).
+//
+// Packets start at each source along the HEALPix directions of level l0 (12 4^l0 of them) and
+// walk the grid cell by cell.  In a cell crossed over ds, band j (PE, LW: dust; LyC: H, H2 and
+// dust) deposits L_in,j (1 - exp(-alpha_j ds)) / alpha_j, with L_in,j = L_j exp(-tau_j) /
+// N_ray(l) and tau_j from the source to the entry face; the LW deposit is also weighted by
+// f_shld,H2 and f_shld,C of the columns to the middle of the segment.  Before entering a cell
+// at distance r a packet is dropped when every tau_j exceeds tau_max, and split into its four
+// nested children (same r, own directions, the parent's columns) when fewer than Phi_c rays
+// of its level cross a cell there: N_ray(l) dx^2 / (4 pi r^2) < Phi_c.
+//
+// The tracing is level-synchronous: one launch per HEALPix level, one lane per packet.  The
+// first launch makes its packets from the lane index; every launch appends the children of
+// its split packets to the next level's list (one atomic per wave; the four children of a
+// parent are adjacent, so neighbouring lanes of the next launch walk neighbouring rays).
+// Deposits are atomic adds into the output fields, so the summation order, and the last bits
+// of the result, vary between runs.  Distances inside the kernel are in cell units.
+#pragma once
+#include "kernels_sources.h"
+
+namespace ism {
+
+constexpr int ART_MAX_LEVEL = 13;  // 12 4^13 pixels still fit a 32-bit index
+constexpr double EXIT_TOL = 1e-10;  // cells
+
+struct ArtRay {  // 48 bytes
+  uint32_t pix;
+  uint16_t src;
+  uint16_t pad;
+  double r;                    // start distance from the source, cell units
+  double NH, NH2, NC, tauLyC;  // columns (cm^-2) and LyC optical depth from the source
+};
+
+struct ArtArgs {
+  int32_t nx, ny, nz, nsrc;
+  int32_t level, max_level;
+  int64_t nin;                  // packets in this launch
+  const ArtRay *in;             // null: the launch makes nsrc x 12 4^level packets at r = 0
+  ArtRay *out;                  // children (capacity 4 nin when level < max_level)
+  unsigned long long *nout;
+  double dx;                    // cm
+  double R2split;               // split when r^2 > R2split (cell units)
+  double tau_max;
+  const double *n, *xH2, *xHp, *xC;
+  void *chiPE, *chiLW, *chiH2, *chiC, *phi;
+  double sPE, sLW, sdLyC, spiH, spiH2;  // dust cross sections x Z'_d; photoionisation
+  double fuv_norm;              // 1 / (4 pi dV J^D_FUV)
+  double phi_norm;              // 1 / dV
+  double *budget;               // [nsrc][6]: escaped PE, LW, LyC, dropped PE, LW, LyC; or null
+  const double *tab;
+};
+
+// Gather every other bit (bits 0, 2, 4, ...) of a 32-bit word into the low half.
+__device__ __forceinline__ uint32_t even_bits(uint32_t x) {
+  x &= 0x55555555u;
+  x = (x | (x >> 1)) & 0x33333333u;
+  x = (x | (x >> 2)) & 0x0F0F0F0Fu;
+  x = (x | (x >> 4)) & 0x00FF00FFu;
+  x = (x | (x >> 8)) & 0x0000FFFFu;
+  return x;
+}
+
+// Centre of HEALPix pixel p (nested numbering) at a level (Gorski et al. 2005): the base pixel
+// and the in-face coordinates give the ring index (counted from the north pole) and the
+// position in the ring; polar rings hold 4 nr pixels at z = +-(1 - nr^2 / (3 nside^2)), the
+// equatorial belt's rings 4 nside pixels at z = 2 (2 nside - ring) / (3 nside), every other
+// belt ring shifted by half a pixel.
+__device__ __forceinline__ void healpix_dir(int level, uint32_t p, double u[3]) {
+  const int64_t ns = 1ll << level;
+  const uint32_t f = p >> (2 * level);
+  const uint32_t ipf = p & (uint32_t)(ns * ns - 1);
+  const int64_t ix = even_bits(ipf), iy = even_bits(ipf >> 1);
+  const int64_t ring_base = (int64_t)(f >> 2) + 2;                     // 2, 3, 4 by row of faces
+  const int64_t col_base = f < 4 ? 2 * f + 1 : (f < 8 ? 2 * (f - 4) : 2 * (f - 8) + 1);
+  const int64_t jr = ring_base * ns - ix - iy - 1;
+  int64_t nr, shift;
+  double z, sth;
+  const double inv3n2 = 1.0 / (3.0 * (double)(ns * ns));
+  if (jr < ns) {
+    nr = jr;
+    shift = 0;
+    const double t = (double)(nr * nr) * inv3n2;  // 1 - z
+    z = 1.0 - t;
+    sth = sqrt(t * (2.0 - t));
+  } else if (jr > 3 * ns) {
+    nr = 4 * ns - jr;
+    shift = 0;
+    const double t = (double)(nr * nr) * inv3n2;
+    z = t - 1.0;
+    sth = sqrt(t * (2.0 - t));
+  } else {
+    nr = ns;
+    shift = (jr - ns) & 1;
+    z = (double)(2 * ns - jr) * 2.0 / (3.0 * (double)ns);
+    sth = sqrt((1.0 - z) * (1.0 + z));
+  }
+  int64_t jp = (col_base * nr + ix - iy + 1 + shift) / 2;
+  if (jp > 4 * ns) jp -= 4 * ns;
+  if (jp < 1) jp += 4 * ns;
+  // phi / pi, so that directions in a coordinate plane (phi a multiple of pi/2) get exactly
+  // zero components
+  const double phi_pi = ((double)jp - 0.5 * (double)(shift + 1)) / (double)(2 * nr);
+  double sp, cp;
+  sincospi(phi_pi, &sp, &cp);
+  u[0] = sth * cp;
+  u[1] = sth * sp;
+  u[2] = z;
+}
+
+__device__ __forceinline__ double expm1_neg(double y, double) { return ::expm1(-y); }
+__device__ __forceinline__ double expm1_neg(double y, float) { return (double)::expm1f((float)-y); }
+
+// (1 - exp(-y)) / y for y >= 0 and exp(-y): from one expm1 while exp(-y) is near 1 (where
+// 1 - exp(-y) would cancel), from one exp beyond (where 1 + expm1(-y) would).
+template <class R>
+__device__ __forceinline__ void absorb(double y, double &g, double &e) {
+  if (y < 1e-8) {
+    g = 1.0 - 0.5 * y;
+    e = 1.0 - y;
+  } else if (y < 0.5) {
+    const double m = expm1_neg(y, R(0));
+    g = -m / y;
+    e = 1.0 + m;
+  } else {
+    e = (double)Mx<R>::ex(-y);
+    g = (1.0 - e) / y;
+  }
+}
+
+template <class R>
+__device__ __forceinline__ void deposit_add(void *p, int64_t i, double v) {
+  atomicAdd((R *)p + i, (R)v);
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void art_level_kernel(ArtArgs a) {
+  __shared__ double s_cs[CS_NX * CS_NY];
+  extern __shared__ double s_budget[];  // [nsrc][6] when a.budget is set
+  load_cs(a.tab, s_cs);
+  if (a.budget) {
+    for (int k = threadIdx.x; k < 6 * a.nsrc; k += blockDim.x) s_budget[k] = 0.0;
+    __syncthreads();
+  }
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = id < a.nin;
+  const int level = a.level;
+  const double nray = 12.0 * (double)(1ll << (2 * level));
+  bool split = false;
+  ArtRay ray;
+  if (live) {
+    if (a.in) {
+      ray = a.in[id];
+    } else {
+      const int64_t np0 = 12ll << (2 * level);
+      ray.src = (uint16_t)(id / np0);
+      ray.pix = (uint32_t)(id % np0);
+      ray.pad = 0;
+      ray.r = ray.NH = ray.NH2 = ray.NC = ray.tauLyC = 0.0;
+    }
+    const SrcDev S = g_src[ray.src];
+    const double s[3] = {S.x, S.y, S.z};
+    double u[3];
+    healpix_dir(level, ray.pix, u);
+    const int dims[3] = {a.nx, a.ny, a.nz};
+    int c[3], step[3];
+    double tmax[3], inv[3];
+    bool inside = true;
+    double r = ray.r;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const double pq = s[q] + r * u[q];
+      c[q] = (int)floor(pq);
+      inside = inside && pq >= 0.0 && c[q] < dims[q];
+      if (u[q] > 0.0) {
+        step[q] = 1;
+        inv[q] = 1.0 / u[q];
+        tmax[q] = ((double)(c[q] + 1) - s[q]) * inv[q];
+      } else if (u[q] < 0.0) {
+        step[q] = -1;
+        inv[q] = 1.0 / u[q];
+        tmax[q] = ((double)c[q] - s[q]) * inv[q];
+      } else {
+        step[q] = 0;
+        inv[q] = 0.0;
+        tmax[q] = 1e300;
+      }
+    }
+    // distance to the domain exit; a packet whose next piece would start within EXIT_TOL
+    // cells of it has left (a plane crossing that coincides with the exit, up to rounding,
+    // must not count as a cell entry)
+    double r_exit = 1e300;
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      if (step[q] != 0) r_exit = fmin(r_exit, ((step[q] > 0 ? (double)dims[q] : 0.0) - s[q]) * inv[q]);
+    const double Lfuv = S.L / nray, Lq = S.Q / nray;
+    double NH = ray.NH, NH2 = ray.NH2, NC = ray.NC, tL = ray.tauLyC;
+    double ePE = (double)Mx<R>::ex(-a.sPE * NH), eLW = (double)Mx<R>::ex(-a.sLW * NH);
+    double eL = (double)Mx<R>::ex(-tL);
+    bool dropped = false;
+    const int max_steps = a.nx + a.ny + a.nz + 3;
+    for (int it = 0; inside && it < max_steps; ++it) {
+      const int q = tmax[0] <= tmax[1] ? (tmax[0] <= tmax[2] ? 0 : 2) : (tmax[1] <= tmax[2] ? 1 : 2);
+      const double rn = tmax[q];
+      if (rn > r) {
+        // a piece of positive length starts here: the checks at its entry face
+        if (r >= r_exit - EXIT_TOL) {
+          inside = false;
+          break;
+        }
+        if (fmin(fmin(a.sPE * NH, a.sLW * NH), tL) > a.tau_max) {
+          dropped = true;
+          break;
+        }
+        if (level < a.max_level && r * r > a.R2split) {
+          split = true;
+          break;
+        }
+        const double ds = (rn - r) * a.dx;
+        const int64_t vi = (int64_t)c[0] + (int64_t)a.nx * ((int64_t)c[1] + (int64_t)a.ny * c[2]);
+        const double nn = a.n[vi], x2 = a.xH2[vi], xp = a.xHp[vi];
+        const double xc = a.xC ? a.xC[vi] : 0.0;
+        const double xHI = fmax(1.0 - 2.0 * x2 - xp, 0.0);
+        const double aL = nn * (xHI * a.spiH + x2 * a.spiH2 + a.sdLyC);
+        double gPE, gLW, gL, fPE, fLW, fL;
+        absorb<R>(a.sPE * nn * ds, gPE, fPE);
+        absorb<R>(a.sLW * nn * ds, gLW, fLW);
+        absorb<R>(aL * ds, gL, fL);
+        const double mH2 = NH2 + 0.5 * nn * x2 * ds, mC = NC + 0.5 * nn * xc * ds;
+        const double wPE = Lfuv * ePE * ds * gPE * a.fuv_norm;
+        const double wLW = Lfuv * eLW * ds * gLW * a.fuv_norm;
+        deposit_add<R>(a.chiPE, vi, wPE);
+        deposit_add<R>(a.chiLW, vi, wLW);
+        deposit_add<R>(a.chiH2, vi, wLW * f_shld_H2<R>(mH2));
+        deposit_add<R>(a.chiC, vi, wLW * f_shld_C<R>(mC, mH2, s_cs));
+        deposit_add<R>(a.phi, vi, Lq * eL * ds * gL * a.phi_norm);
+        NH += nn * ds;
+        NH2 += nn * x2 * ds;
+        NC += nn * xc * ds;
+        tL += aL * ds;
+        ePE *= fPE;
+        eLW *= fLW;
+        eL *= fL;
+        r = rn;
+      }
+      c[q] += step[q];
+      if (c[q] < 0 || c[q] >= dims[q]) {
+        inside = false;
+        break;
+      }
+      tmax[q] = ((double)(step[q] > 0 ? c[q] + 1 : c[q]) - s[q]) * inv[q];
+    }
+    if (a.budget && !split) {
+      // the packet ends here: lost through the boundary or dropped at tau > tau_max
+      const int o = 6 * ray.src + (dropped ? 3 : 0);
+      const double tPE = a.sPE * NH, tLW = a.sLW * NH;
+      atomicAdd(&s_budget[o + 0], S.L * exp(-tPE) / nray);
+      atomicAdd(&s_budget[o + 1], S.L * exp(-tLW) / nray);
+      atomicAdd(&s_budget[o + 2], S.Q * exp(-tL) / nray);
+    }
+    ray.r = r;
+    ray.NH = NH;
+    ray.NH2 = NH2;
+    ray.NC = NC;
+    ray.tauLyC = tL;
+  }
+  // children of the split packets: one reservation per wave
+  const uint64_t mask = __ballot(split);
+  if (mask) {
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(a.nout, 4ull * (unsigned long long)__popcll(mask));
+    base = __shfl(base, leader);
+    if (split) {
+      const unsigned long long k = base + 4ull * __popcll(mask & ((1ull << lane) - 1ull));
+#pragma unroll
+      for (int ch = 0; ch < 4; ++ch) {
+        ArtRay cr = ray;
+        cr.pix = 4u * ray.pix + (uint32_t)ch;
+        a.out[k + ch] = cr;
+      }
+    }
+  }
+  if (a.budget) {
+    __syncthreads();
+    for (int k = threadIdx.x; k < 6 * a.nsrc; k += blockDim.x)
+      if (s_budget[k] != 0.0) atomicAdd(&a.budget[k], s_budget[k]);
+  }
+}
+
+__global__ void art_zero_kernel(double *p, int64_t n, unsigned long long *cnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+  if (i == 0 && cnt) *cnt = 0ull;
+}
+
+}  // namespace ism

@@ -99,6 +99,9 @@ def lib():
         L.ism_point_sources.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Params), ctypes.c_int, _i32,
                                         ctypes.c_void_p] + [_vp] * 8 + [_vp]
         L.ism_point_sources.restype = ctypes.c_int
+        L.ism_ray_trace.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Params), ctypes.c_int, _i32,
+                                    ctypes.c_void_p, ctypes.c_void_p] + [_vp] * 10 + [_vp]
+        L.ism_ray_trace.restype = ctypes.c_int
         L.ism_surrogate_pairs.argtypes = [ctypes.POINTER(_Params), ctypes.c_int, _i64, _dp] + [_vp] * 14
         L.ism_chem_cool_step_surrogate.argtypes = [_vp, ctypes.POINTER(_Params), _i64, _dp] + [_vp] * 16 + \
             [_dp, _vp, _vp]
@@ -117,7 +120,7 @@ SURROGATE_SYMBOLS = ("ism_surrogate_create", "ism_surrogate_destroy", "ism_surro
 def exported_symbols():
     return ["ism_params_default", "ism_init", "ism_shutdown", "ism_last_error", "ism_ndiag", "ism_diag_name",
             "ism_columns6", "ism_rates", "ism_chem_cool_step", "ism_point_sources",
-            "ism_local_shielding", "ism_columns_beam"] + list(SURROGATE_SYMBOLS)
+            "ism_ray_trace", "ism_local_shielding", "ism_columns_beam"] + list(SURROGATE_SYMBOLS)
 
 
 def _check(rc):
@@ -221,6 +224,42 @@ def point_sources(n, xH2, xC, dx_cm, params, prec, sources, out, stream=None):
         _ptr(n, torch.float64, N, "n"), _ptr(xH2, torch.float64, N, "xH2"),
         _ptr(xC, torch.float64, N, "xC", allow_none=True),
         *[_ptr(out[k], rd, N, k) for k in ("chi_PE", "chi_LW", "chi_H2", "chi_C", "phi")], _stream(stream)))
+    return out
+
+
+class _ArtOptions(ctypes.Structure):
+    _fields_ = [("level0", ctypes.c_int32), ("max_level", ctypes.c_int32), ("rays_per_cell", ctypes.c_double),
+                ("tau_max", ctypes.c_double)]
+
+
+def ray_trace(n, xH2, xHp, xC, dx_cm, params, prec, sources, out, level0=4, max_level=13, rays_per_cell=4.0,
+              tau_max=30.0, budget=False, stream=None):
+    """ism_ray_trace: add the sources' radiation, by adaptive ray tracing, to out's chi_PE,
+    chi_LW, chi_H2, chi_C and phi.
+
+    n, xH2, xHp (and xC or None): float64 device tensors shaped [nz, ny, nx]; sources: rows of
+    (x_cm, y_cm, z_cm, Q, L_FUV); out: dict of device tensors of the path's dtype.  With
+    budget=True, out["budget"] receives the [nsrc, 6] escaped / dropped luminosities."""
+    _ensure_init(n)
+    nz, ny, nx = n.shape
+    N = n.numel()
+    rd = _rdt(prec)
+    src = [tuple(float(v) for v in row) for row in sources]
+    arr = (_Source * max(len(src), 1))(*[_Source(*r) for r in src])
+    opt = _ArtOptions(int(level0), int(max_level), float(rays_per_cell), float(tau_max))
+    g = _Grid(nx, ny, nz, 0, float(dx_cm))
+    p = params._c()
+    bud = None
+    if budget:
+        bud = torch.zeros((max(len(src), 1), 6), dtype=torch.float64, device=n.device)
+        out["budget"] = bud
+    _check(lib().ism_ray_trace(
+        ctypes.byref(g), ctypes.byref(p), prec, len(src), ctypes.cast(arr, ctypes.c_void_p),
+        ctypes.cast(ctypes.pointer(opt), ctypes.c_void_p),
+        _ptr(n, torch.float64, N, "n"), _ptr(xH2, torch.float64, N, "xH2"), _ptr(xHp, torch.float64, N, "xHp"),
+        _ptr(xC, torch.float64, N, "xC", allow_none=True),
+        *[_ptr(out[k], rd, N, k) for k in ("chi_PE", "chi_LW", "chi_H2", "chi_C", "phi")],
+        None if bud is None else ctypes.c_void_p(bud.data_ptr()), _stream(stream)))
     return out
 
 

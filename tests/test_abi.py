@@ -119,3 +119,29 @@ def test_surrogate_sizes_match_the_reference_network():
     text = open(os.path.join(ROOT, "include", "ism.h")).read()
     assert "#define ISM_SURR_NPARAM 34819" in text
     assert ism.SURR_STATE_FLOATS == 3 * 34819 + 27
+
+
+def test_ray_trace_rejects_bad_options_before_launch():
+    g = ism._Grid(8, 8, 8, 0, 3.0e18)
+    cp = ism.Params()._c()
+    src = (ism._Source * 1)(ism._Source(1e18, 1e18, 1e18, 1e49, 1e38))
+    L = ism.lib()
+
+    def call(opt, nsrc=1, arrays=None):
+        o = None if opt is None else ctypes.cast(ctypes.pointer(ism._ArtOptions(*opt)), ctypes.c_void_p)
+        rc = L.ism_ray_trace(ctypes.byref(g), ctypes.byref(cp), 0, nsrc, ctypes.cast(src, ctypes.c_void_p), o,
+                             *(arrays or [None] * 10), None)
+        return rc, L.ism_last_error().decode()
+
+    assert ctypes.sizeof(ism._ArtOptions) == 24
+    for opt, msg in (((5, 4, 4.0, 30.0), "level0"), ((0, 14, 4.0, 30.0), "max_level"),
+                     ((-1, 4, 4.0, 30.0), "level0"), ((4, 13, 0.0, 30.0), "rays_per_cell"),
+                     ((4, 13, float("inf"), 30.0), "rays_per_cell"), ((4, 13, 4.0, 0.0), "tau_max")):
+        rc, err = call(opt)
+        assert rc == -1 and msg in err, (opt, err)
+    rc, err = call(None, nsrc=257)
+    assert rc == -1 and "nsrc" in err
+    rc, err = call(None)
+    assert rc == -1 and "NULL" in err
+    # no sources: a no-op that succeeds without touching the device
+    assert call(None, nsrc=0)[0] == 0
