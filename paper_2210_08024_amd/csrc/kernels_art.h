@@ -127,26 +127,63 @@ __device__ __forceinline__ void absorb(double y, double &g, double &e) {
   }
 }
 
+// Deposits of one step of a wave's packets.  Neighbouring lanes walk neighbouring directions,
+// so several of them often add into the same cell in the same step; global atomics to one
+// address serialise in the L2, so the lanes first pick one leader per distinct cell (a loop
+// over the distinct cells of the step, uniform over the wave), add their five values into the
+// leader's slot in LDS, and the leaders alone update the fields.
 template <class R>
-__device__ __forceinline__ void deposit_add(void *p, int64_t i, double v) {
-  atomicAdd((R *)p + i, (R)v);
+__device__ __forceinline__ void wave_deposit(const ArtArgs &a, R *slot, bool dep, int64_t vi, const double v[5]) {
+  const int lane = threadIdx.x & 63;
+  uint64_t pend = __ballot(dep);
+  if (!pend) return;
+  int leader = -1;
+  while (pend) {
+    const int first = __ffsll((unsigned long long)pend) - 1;
+    const int64_t key = __shfl(vi, first);
+    const bool same = dep && leader < 0 && vi == key;
+    const uint64_t m = __ballot(same);
+    if (same) leader = first;
+    pend &= ~m;
+  }
+  R *mine = slot + 5 * lane;
+  if (dep && leader == lane)
+#pragma unroll
+    for (int k = 0; k < 5; ++k) mine[k] = R(0);
+  __builtin_amdgcn_wave_barrier();
+  if (dep) {
+    R *dst = slot + 5 * leader;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) atomicAdd(dst + k, (R)v[k]);
+  }
+  __builtin_amdgcn_wave_barrier();
+  if (dep && leader == lane) {
+    R *f[5] = {(R *)a.chiPE, (R *)a.chiLW, (R *)a.chiH2, (R *)a.chiC, (R *)a.phi};
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const R t = mine[k];
+      if (t != R(0)) atomicAdd(f[k] + vi, t);
+    }
+  }
 }
 
 template <class R>
 __global__ __launch_bounds__(256) void art_level_kernel(ArtArgs a) {
   __shared__ double s_cs[CS_NX * CS_NY];
+  __shared__ R s_slot[256 * 5];         // per lane: its cell's five sums while it leads
   extern __shared__ double s_budget[];  // [nsrc][6] when a.budget is set
   load_cs(a.tab, s_cs);
   if (a.budget) {
     for (int k = threadIdx.x; k < 6 * a.nsrc; k += blockDim.x) s_budget[k] = 0.0;
     __syncthreads();
   }
+  R *slot = s_slot + 5 * 64 * (threadIdx.x >> 6);
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = id < a.nin;
   const int level = a.level;
   const double nray = 12.0 * (double)(1ll << (2 * level));
-  bool split = false;
-  ArtRay ray;
+  const int dims[3] = {a.nx, a.ny, a.nz};
+  ArtRay ray{};
   if (live) {
     if (a.in) {
       ray = a.in[id];
@@ -154,115 +191,122 @@ __global__ __launch_bounds__(256) void art_level_kernel(ArtArgs a) {
       const int64_t np0 = 12ll << (2 * level);
       ray.src = (uint16_t)(id / np0);
       ray.pix = (uint32_t)(id % np0);
-      ray.pad = 0;
-      ray.r = ray.NH = ray.NH2 = ray.NC = ray.tauLyC = 0.0;
     }
-    const SrcDev S = g_src[ray.src];
-    const double s[3] = {S.x, S.y, S.z};
-    double u[3];
-    healpix_dir(level, ray.pix, u);
-    const int dims[3] = {a.nx, a.ny, a.nz};
-    int c[3], step[3];
-    double tmax[3], inv[3];
-    bool inside = true;
-    double r = ray.r;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const double pq = s[q] + r * u[q];
-      c[q] = (int)floor(pq);
-      inside = inside && pq >= 0.0 && c[q] < dims[q];
-      if (u[q] > 0.0) {
-        step[q] = 1;
-        inv[q] = 1.0 / u[q];
-        tmax[q] = ((double)(c[q] + 1) - s[q]) * inv[q];
-      } else if (u[q] < 0.0) {
-        step[q] = -1;
-        inv[q] = 1.0 / u[q];
-        tmax[q] = ((double)c[q] - s[q]) * inv[q];
-      } else {
-        step[q] = 0;
-        inv[q] = 0.0;
-        tmax[q] = 1e300;
-      }
-    }
-    // distance to the domain exit; a packet whose next piece would start within EXIT_TOL
-    // cells of it has left (a plane crossing that coincides with the exit, up to rounding,
-    // must not count as a cell entry)
-    double r_exit = 1e300;
-#pragma unroll
-    for (int q = 0; q < 3; ++q)
-      if (step[q] != 0) r_exit = fmin(r_exit, ((step[q] > 0 ? (double)dims[q] : 0.0) - s[q]) * inv[q]);
-    const double Lfuv = S.L / nray, Lq = S.Q / nray;
-    double NH = ray.NH, NH2 = ray.NH2, NC = ray.NC, tL = ray.tauLyC;
-    double ePE = (double)Mx<R>::ex(-a.sPE * NH), eLW = (double)Mx<R>::ex(-a.sLW * NH);
-    double eL = (double)Mx<R>::ex(-tL);
-    bool dropped = false;
-    const int max_steps = a.nx + a.ny + a.nz + 3;
-    for (int it = 0; inside && it < max_steps; ++it) {
-      const int q = tmax[0] <= tmax[1] ? (tmax[0] <= tmax[2] ? 0 : 2) : (tmax[1] <= tmax[2] ? 1 : 2);
-      const double rn = tmax[q];
-      if (rn > r) {
-        // a piece of positive length starts here: the checks at its entry face
-        if (r >= r_exit - EXIT_TOL) {
-          inside = false;
-          break;
-        }
-        if (fmin(fmin(a.sPE * NH, a.sLW * NH), tL) > a.tau_max) {
-          dropped = true;
-          break;
-        }
-        if (level < a.max_level && r * r > a.R2split) {
-          split = true;
-          break;
-        }
-        const double ds = (rn - r) * a.dx;
-        const int64_t vi = (int64_t)c[0] + (int64_t)a.nx * ((int64_t)c[1] + (int64_t)a.ny * c[2]);
-        const double nn = a.n[vi], x2 = a.xH2[vi], xp = a.xHp[vi];
-        const double xc = a.xC ? a.xC[vi] : 0.0;
-        const double xHI = fmax(1.0 - 2.0 * x2 - xp, 0.0);
-        const double aL = nn * (xHI * a.spiH + x2 * a.spiH2 + a.sdLyC);
-        double gPE, gLW, gL, fPE, fLW, fL;
-        absorb<R>(a.sPE * nn * ds, gPE, fPE);
-        absorb<R>(a.sLW * nn * ds, gLW, fLW);
-        absorb<R>(aL * ds, gL, fL);
-        const double mH2 = NH2 + 0.5 * nn * x2 * ds, mC = NC + 0.5 * nn * xc * ds;
-        const double wPE = Lfuv * ePE * ds * gPE * a.fuv_norm;
-        const double wLW = Lfuv * eLW * ds * gLW * a.fuv_norm;
-        deposit_add<R>(a.chiPE, vi, wPE);
-        deposit_add<R>(a.chiLW, vi, wLW);
-        deposit_add<R>(a.chiH2, vi, wLW * f_shld_H2<R>(mH2));
-        deposit_add<R>(a.chiC, vi, wLW * f_shld_C<R>(mC, mH2, s_cs));
-        deposit_add<R>(a.phi, vi, Lq * eL * ds * gL * a.phi_norm);
-        NH += nn * ds;
-        NH2 += nn * x2 * ds;
-        NC += nn * xc * ds;
-        tL += aL * ds;
-        ePE *= fPE;
-        eLW *= fLW;
-        eL *= fL;
-        r = rn;
-      }
-      c[q] += step[q];
-      if (c[q] < 0 || c[q] >= dims[q]) {
-        inside = false;
-        break;
-      }
-      tmax[q] = ((double)(step[q] > 0 ? c[q] + 1 : c[q]) - s[q]) * inv[q];
-    }
-    if (a.budget && !split) {
-      // the packet ends here: lost through the boundary or dropped at tau > tau_max
-      const int o = 6 * ray.src + (dropped ? 3 : 0);
-      const double tPE = a.sPE * NH, tLW = a.sLW * NH;
-      atomicAdd(&s_budget[o + 0], S.L * exp(-tPE) / nray);
-      atomicAdd(&s_budget[o + 1], S.L * exp(-tLW) / nray);
-      atomicAdd(&s_budget[o + 2], S.Q * exp(-tL) / nray);
-    }
-    ray.r = r;
-    ray.NH = NH;
-    ray.NH2 = NH2;
-    ray.NC = NC;
-    ray.tauLyC = tL;
   }
+  const SrcDev S = g_src[live ? ray.src : 0];
+  const double s[3] = {S.x, S.y, S.z};
+  double u[3];
+  healpix_dir(level, live ? ray.pix : 0u, u);
+  int c[3], step[3];
+  double tmax[3], inv[3];
+  bool inside = live;
+  double r = ray.r;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const double pq = s[q] + r * u[q];
+    c[q] = (int)floor(pq);
+    inside = inside && pq >= 0.0 && c[q] < dims[q];
+    if (u[q] > 0.0) {
+      step[q] = 1;
+      inv[q] = 1.0 / u[q];
+      tmax[q] = ((double)(c[q] + 1) - s[q]) * inv[q];
+    } else if (u[q] < 0.0) {
+      step[q] = -1;
+      inv[q] = 1.0 / u[q];
+      tmax[q] = ((double)c[q] - s[q]) * inv[q];
+    } else {
+      step[q] = 0;
+      inv[q] = 0.0;
+      tmax[q] = 1e300;
+    }
+  }
+  // distance to the domain exit; a packet whose next piece would start within EXIT_TOL cells
+  // of it has left (a plane crossing that coincides with the exit, up to rounding, must not
+  // count as a cell entry)
+  double r_exit = 1e300;
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+    if (step[q] != 0) r_exit = fmin(r_exit, ((step[q] > 0 ? (double)dims[q] : 0.0) - s[q]) * inv[q]);
+  const double Lfuv = S.L / nray, Lq = S.Q / nray;
+  double NH = ray.NH, NH2 = ray.NH2, NC = ray.NC, tL = ray.tauLyC;
+  double ePE = (double)Mx<R>::ex(-a.sPE * NH), eLW = (double)Mx<R>::ex(-a.sLW * NH);
+  double eL = (double)Mx<R>::ex(-tL);
+  bool split = false, dropped = false, active = inside;
+  const int max_steps = a.nx + a.ny + a.nz + 3;
+  int it = 0;
+  // one cell per trip, uniform over the wave so that its deposits can be combined
+  while (__ballot(active)) {
+    bool dep = false;
+    int64_t vi = 0;
+    double v[5];
+    if (active) {
+      if (++it > max_steps) {
+        active = false;
+      } else {
+        const int q = tmax[0] <= tmax[1] ? (tmax[0] <= tmax[2] ? 0 : 2) : (tmax[1] <= tmax[2] ? 1 : 2);
+        const double rn = tmax[q];
+        if (rn > r) {
+          // a piece of positive length starts here: the checks at its entry face
+          if (r >= r_exit - EXIT_TOL) {
+            active = false;
+          } else if (fmin(fmin(a.sPE * NH, a.sLW * NH), tL) > a.tau_max) {
+            active = false;
+            dropped = true;
+          } else if (level < a.max_level && r * r > a.R2split) {
+            active = false;
+            split = true;
+          } else {
+            const double ds = (rn - r) * a.dx;
+            vi = (int64_t)c[0] + (int64_t)a.nx * ((int64_t)c[1] + (int64_t)a.ny * c[2]);
+            const double nn = a.n[vi], x2 = a.xH2[vi], xp = a.xHp[vi];
+            const double xc = a.xC ? a.xC[vi] : 0.0;
+            const double xHI = fmax(1.0 - 2.0 * x2 - xp, 0.0);
+            const double aL = nn * (xHI * a.spiH + x2 * a.spiH2 + a.sdLyC);
+            double gPE, gLW, gL, fPE, fLW, fL;
+            absorb<R>(a.sPE * nn * ds, gPE, fPE);
+            absorb<R>(a.sLW * nn * ds, gLW, fLW);
+            absorb<R>(aL * ds, gL, fL);
+            const double mH2 = NH2 + 0.5 * nn * x2 * ds, mC = NC + 0.5 * nn * xc * ds;
+            const double wLW = Lfuv * eLW * ds * gLW * a.fuv_norm;
+            v[0] = Lfuv * ePE * ds * gPE * a.fuv_norm;
+            v[1] = wLW;
+            v[2] = wLW * f_shld_H2<R>(mH2);
+            v[3] = wLW * f_shld_C<R>(mC, mH2, s_cs);
+            v[4] = Lq * eL * ds * gL * a.phi_norm;
+            dep = true;
+            NH += nn * ds;
+            NH2 += nn * x2 * ds;
+            NC += nn * xc * ds;
+            tL += aL * ds;
+            ePE *= fPE;
+            eLW *= fLW;
+            eL *= fL;
+            r = rn;
+          }
+        }
+        if (active) {
+          c[q] += step[q];
+          if (c[q] < 0 || c[q] >= dims[q])
+            active = false;
+          else
+            tmax[q] = ((double)(step[q] > 0 ? c[q] + 1 : c[q]) - s[q]) * inv[q];
+        }
+      }
+    }
+    wave_deposit<R>(a, slot, dep, vi, v);
+  }
+  if (live && a.budget && !split) {
+    // the packet ends here: lost through the boundary or dropped at tau > tau_max
+    const int o = 6 * ray.src + (dropped ? 3 : 0);
+    atomicAdd(&s_budget[o + 0], S.L * exp(-a.sPE * NH) / nray);
+    atomicAdd(&s_budget[o + 1], S.L * exp(-a.sLW * NH) / nray);
+    atomicAdd(&s_budget[o + 2], S.Q * exp(-tL) / nray);
+  }
+  ray.r = r;
+  ray.NH = NH;
+  ray.NH2 = NH2;
+  ray.NC = NC;
+  ray.tauLyC = tL;
   // children of the split packets: one reservation per wave
   const uint64_t mask = __ballot(split);
   if (mask) {
