@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--workload", choices=("grf128", "c2"), default="grf128",
                     help="grf128: the metric workload; c2: 256^3 with 16 point sources, ten successive steps "
                          "(mixed form)")
+    ap.add_argument("--maps", choices=("lc", "art"), default="lc",
+                    help="c2 point-source maps: lc straight-line 1/r^2 exp(-tau) with the Stromgren cap (the "
+                         "configuration's recipe), art adaptive ray tracing (Sec. 5.1)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and the error report")
     ap.add_argument("--cpu-cells", type=int, default=65536)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -146,9 +149,10 @@ def field_errors(out, ref, idx, xCt):
 
 
 def bench_c2(args):
-    """256^3, 2 pc cells, 16 point sources (maps once by adaptive ray tracing), CR map, ten
-    successive mixed steps of 1e4 yr with x_C fed back into the columns; value = cell-updates/s
-    over the ten steps, the one-time point-source maps included."""
+    """256^3, 2 pc cells, 16 point sources (maps once: straight-line 1/r^2 exp(-tau) maps, or
+    with --maps art the adaptive ray tracing of Sec. 5.1), CR map, ten successive mixed steps of
+    1e4 yr with x_C fed back into the columns; value = cell-updates/s over the ten steps, the
+    one-time point-source maps included."""
     import torch
     from paper_2210_08024_amd import ism, workloads
     from oracle.census import substep_census
@@ -185,8 +189,12 @@ def bench_c2(args):
         for v in maps.values():
             v.zero_()
         ev[0].record(stream)
-        ism.ray_trace(n, xH2.view(shape), xHp.view(shape), None, dx, par, ism.MIXED, cfg["sources"],
-                      {k: v.view(shape) for k, v in maps.items()})
+        if args.maps == "art":
+            ism.ray_trace(n, xH2.view(shape), xHp.view(shape), None, dx, par, ism.MIXED, cfg["sources"],
+                          {k: v.view(shape) for k, v in maps.items()})
+        else:
+            ism.point_sources(n, xH2.view(shape), None, dx, par, ism.MIXED, cfg["sources"],
+                              {k: v.view(shape) for k, v in maps.items()})
         ev[1].record(stream)
         if record:
             torch.cuda.synchronize()
@@ -219,14 +227,20 @@ def bench_c2(args):
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / args.steps
     run(True)
-    # for reference, outside the timed job: the same maps by long characteristics
-    lc = {k: torch.zeros_like(v) for k, v in maps.items()}
+    # for reference, outside the timed job: the other way of making the maps
+    other = {k: torch.zeros_like(v) for k, v in maps.items()}
     ev[0].record(stream)
-    ism.point_sources(n, init["xH2"].view(shape), None, dx, par, ism.MIXED, cfg["sources"],
-                      {k: v.view(shape) for k, v in lc.items()})
+    if args.maps == "art":
+        ism.point_sources(n, init["xH2"].view(shape), None, dx, par, ism.MIXED, cfg["sources"],
+                          {k: v.view(shape) for k, v in other.items()})
+    else:
+        ism.ray_trace(n, init["xH2"].view(shape), init["xHp"].view(shape), None, dx, par, ism.MIXED,
+                      cfg["sources"], {k: v.view(shape) for k, v in other.items()})
     ev[1].record(stream)
     torch.cuda.synchronize()
-    lc_ms = ev[0].elapsed_time(ev[1])
+    other_ms = ev[0].elapsed_time(ev[1])
+    how = ("adaptive ray tracing (Sec. 5.1)" if args.maps == "art" else
+           "straight-line 1/r^2 exp(-tau) maps with the Stromgren cap")
     arith, trans = substep_census(OParams())
     t_step = float(np.sum(times["step"]))
     achieved = float(np.sum(tot_sub)) * (arith + trans) / t_step / 1e12
@@ -236,13 +250,14 @@ def bench_c2(args):
         "warmup": args.warmup, "ms_per_step": wall * 1e3 / cfg["steps"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": "c2: 256^3 lognormal GRF (2 pc cells, 512 pc box), 16 point sources (Q 1.24e50 s^-1, "
-                               "L_FUV 1.36e6 L_sun; adaptive ray tracing once), chi0 = 1 six-ray, xi_cr log-uniform [1e-17, 1e-15], "
+                               "L_FUV 1.36e6 L_sun; maps once by " + how + "), chi0 = 1 six-ray, xi_cr log-uniform [1e-17, 1e-15], "
                                "Z' = 1, ten successive steps of 1e4 yr", "cells": N, "path": "mixed",
-                   "job": "point-source maps by adaptive ray tracing once + ten (columns6 + step)"},
+                   "maps": args.maps, "job": "point-source maps once + ten (columns6 + step)"},
         "roofline": {"bound": "alu", "kernel": "step_queue_kernel", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
                      "traffic": None, "work": f"{int(np.sum(tot_sub))} substeps over ten steps x ({arith} + {trans})"},
-        "detail": {"maps_ms": times["maps"][0] * 1e3, "maps_long_characteristics_ms": lc_ms, "columns_ms_mean": float(np.mean(times["columns"])) * 1e3,
+        "detail": {"maps_ms": times["maps"][0] * 1e3,
+                   ("maps_long_characteristics_ms" if args.maps == "art" else "maps_ray_tracing_ms"): other_ms, "columns_ms_mean": float(np.mean(times["columns"])) * 1e3,
                    "step_ms_mean": float(np.mean(times["step"])) * 1e3,
                    "step_ms_each": [round(t * 1e3, 3) for t in times["step"]],
                    "nsub_mean_each": [round(x / N, 3) for x in tot_sub],

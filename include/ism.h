@@ -195,8 +195,9 @@ typedef struct {
  * A packet is split into its four children (same distance r, own directions, same columns)
  * before entering a cell where N_ray dx^2 / (4 pi r^2) < rays_per_cell, dropped where every
  * band's tau > tau_max, and lost through the grid faces (all open).
- * In: n, xH2, xHp (double, [nz][ny][nx]), xC (double or NULL = 0); src: host array of
- * nsrc <= 256 sources inside the grid; opt: NULL for the defaults {4, 13, 4.0, 30.0}.
+ * In: n, xH2, xHp (double, [nz][ny][nx], at most 2^31 - 1 cells), xC (double or NULL = 0);
+ * src: host array of nsrc <= 256 sources inside the grid; opt: NULL for the defaults
+ * {4, 13, 4.0, 30.0}.
  * In/out: the five radiation arrays (double for F64, float for MIXED): contributions are
  * added (atomically, so the last bits vary between runs).  budget: NULL, or a device array of
  * nsrc x 6 doubles that receives per source the luminosity lost through the faces (PE, LW in

@@ -849,7 +849,8 @@ ism_status ism_ray_trace(const ism_grid *g, const ism_params *p, ism_precision p
   g_err.clear();
   if (!g) return fail(ISM_E_ARG, "grid is NULL");
   if (g->nx < 1 || g->ny < 1 || g->nz < 1) return fail(ISM_E_ARG, "grid dimensions must be >= 1");
-  if ((int64_t)g->nx + g->ny + g->nz > (int64_t)INT32_MAX / 2) return fail(ISM_E_ARG, "grid too large");
+  if ((int64_t)g->nx * g->ny * g->nz > (int64_t)INT32_MAX)
+    return fail(ISM_E_ARG, "grid too large for the ray tracer (at most 2^31 - 1 cells)");
   if (!(g->dx_cm > 0.0) || !std::isfinite(g->dx_cm)) return fail(ISM_E_ARG, "dx_cm must be finite and > 0");
   if (ism_status s = check_params(p)) return s;
   if (prec != ISM_PREC_F64 && prec != ISM_PREC_MIXED) return fail(ISM_E_ARG, "invalid precision");

@@ -132,19 +132,22 @@ __device__ __forceinline__ void absorb(double y, double &g, double &e) {
 // address serialise in the L2, so the lanes first pick one leader per distinct cell (a loop
 // over the distinct cells of the step, uniform over the wave), add their five values into the
 // leader's slot in LDS, and the leaders alone update the fields.
+// Cell indices are below 2^31 (checked on the host), so a key is one 32-bit word, read from
+// the first pending lane with a scalar readlane.
 template <class R>
-__device__ __forceinline__ void wave_deposit(const ArtArgs &a, R *slot, bool dep, int64_t vi, const double v[5]) {
+__device__ __forceinline__ void wave_deposit(const ArtArgs &a, R *slot, bool dep, int32_t vi, const double v[5]) {
   const int lane = threadIdx.x & 63;
   uint64_t pend = __ballot(dep);
   if (!pend) return;
-  int leader = -1;
+  int leader = 0;
   while (pend) {
-    const int first = __ffsll((unsigned long long)pend) - 1;
-    const int64_t key = __shfl(vi, first);
-    const bool same = dep && leader < 0 && vi == key;
-    const uint64_t m = __ballot(same);
+    // the first pending lane's cell; every lane of that cell takes it as leader (lanes of
+    // earlier cells hold other keys, lanes without a deposit are not pending)
+    const int first = __builtin_ctzll(pend);
+    const int32_t key = __builtin_amdgcn_readlane(vi, first);
+    const bool same = vi == key;
     if (same) leader = first;
-    pend &= ~m;
+    pend &= ~__ballot(same);
   }
   R *mine = slot + 5 * lane;
   if (dep && leader == lane)
@@ -159,11 +162,12 @@ __device__ __forceinline__ void wave_deposit(const ArtArgs &a, R *slot, bool dep
   __builtin_amdgcn_wave_barrier();
   if (dep && leader == lane) {
     R *f[5] = {(R *)a.chiPE, (R *)a.chiLW, (R *)a.chiH2, (R *)a.chiC, (R *)a.phi};
+    R t[5];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      const R t = mine[k];
-      if (t != R(0)) atomicAdd(f[k] + vi, t);
-    }
+    for (int k = 0; k < 5; ++k) t[k] = mine[k];
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+      if (t[k] != R(0)) atomicAdd(f[k] + vi, t[k]);
   }
 }
 
@@ -237,7 +241,7 @@ __global__ __launch_bounds__(256) void art_level_kernel(ArtArgs a) {
   // one cell per trip, uniform over the wave so that its deposits can be combined
   while (__ballot(active)) {
     bool dep = false;
-    int64_t vi = 0;
+    int32_t vi = 0;
     double v[5];
     if (active) {
       if (++it > max_steps) {
@@ -257,7 +261,7 @@ __global__ __launch_bounds__(256) void art_level_kernel(ArtArgs a) {
             split = true;
           } else {
             const double ds = (rn - r) * a.dx;
-            vi = (int64_t)c[0] + (int64_t)a.nx * ((int64_t)c[1] + (int64_t)a.ny * c[2]);
+            vi = c[0] + a.nx * (c[1] + a.ny * c[2]);
             const double nn = a.n[vi], x2 = a.xH2[vi], xp = a.xHp[vi];
             const double xc = a.xC ? a.xC[vi] : 0.0;
             const double xHI = fmax(1.0 - 2.0 * x2 - xp, 0.0);
