@@ -42,9 +42,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--path", choices=("f64", "mixed", "surrogate"), default="f64")
-    ap.add_argument("--workload", choices=("grf128", "c2"), default="grf128",
+    ap.add_argument("--workload", choices=("grf128", "c2", "c4"), default="grf128",
                     help="grf128: the metric workload; c2: 256^3 with 16 point sources, ten successive steps "
-                         "(mixed form)")
+                         "(mixed form); c4: 512^3 with 16 point sources, one step on each path")
+    ap.add_argument("--c4-stride", type=int, default=8,
+                    help="c4: error report on every s-th cell along each axis (8: a 64^3 subsample)")
     ap.add_argument("--maps", choices=("lc", "art"), default="lc",
                     help="c2 point-source maps: lc straight-line 1/r^2 exp(-tau) with the Stromgren cap (the "
                          "configuration's recipe), art adaptive ray tracing (Sec. 5.1)")
@@ -266,16 +268,185 @@ def bench_c2(args):
     print(json.dumps(out), flush=True)
 
 
+def _oracle_chunk(job):
+    """One chunk of the oracle step (a worker of the C4 error report)."""
+    from oracle import step as ostep
+    n, T, xH2, xHp, rad, dt, par = job
+    return ostep.chem_cool_step(n, T, xH2, xHp, rad, dt, par)
+
+
+def bench_c4(args):
+    """512^3, 2 pc cells, 16 point sources, CR map, one step of 1e4 yr on each path (plain F64,
+    plain mixed, FP32 + surrogate with the plain step as fallback).  The point-source maps are
+    computed once from the initial state (in double; the mixed paths take them rounded to
+    float) and are not part of the timed step.  value = cell-updates/s of the surrogate path
+    (columns6 + step).  Errors: every path against the FP64 oracle step on the stride-s
+    subsample (s = 8: 64^3 cells), fed the GPU's FP64 radiation at those cells; the oracle runs
+    in a pool of worker processes forked before the GPU is touched."""
+    import multiprocessing as mp
+    try:
+        ncores = len(os.sched_getaffinity(0))
+    except Exception:
+        ncores = os.cpu_count() or 1
+    procs = max(1, min(16, ncores))
+    pool = mp.get_context("fork").Pool(procs)
+    import torch
+    from paper_2210_08024_amd import ism, workloads, surrogate_train
+    from oracle.census import substep_census
+    from oracle.constants import Params as OParams
+    t_gen = time.perf_counter()
+    s, cfg = workloads.make("c4")
+    t_gen = time.perf_counter() - t_gen
+    shape = s["n"].shape
+    N = s["n"].size
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ism.init(0)
+    par = ism.Params(Zg=1.0, Zd=1.0, cr_mode=2)
+    par_o = OParams(Zg=1.0, Zd=1.0, cr_mode=2)
+    dx = cfg["dx_pc"] * workloads.PC
+    dt = cfg["dt_yr"] * workloads.YR
+    stream = torch.cuda.current_stream()
+    init = {k: torch.from_numpy(np.ascontiguousarray(s[k]).ravel()).to(dev) for k in ("n", "T", "xH2", "xHp")}
+    xi64 = torch.from_numpy(s["xi"].ravel()).to(dev)
+    n = init["n"]
+    T, xH2, xHp = (torch.empty_like(init[k]) for k in ("T", "xH2", "xHp"))
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    # point-source maps once, in double
+    maps64 = {k: torch.zeros(N, dtype=torch.float64, device=dev) for k in ("chi_PE", "chi_LW", "chi_H2", "chi_C", "phi")}
+    ev[0].record(stream)
+    if args.maps == "art":
+        ism.ray_trace(n.view(shape), init["xH2"].view(shape), init["xHp"].view(shape), None, dx, par, ism.F64,
+                      cfg["sources"], {k: v.view(shape) for k, v in maps64.items()})
+    else:
+        ism.point_sources(n.view(shape), init["xH2"].view(shape), None, dx, par, ism.F64, cfg["sources"],
+                          {k: v.view(shape) for k, v in maps64.items()})
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    maps_ms = ev[0].elapsed_time(ev[1])
+    maps32 = {k: v.float() for k, v in maps64.items()}
+    sur = surrogate_train.load()
+    nfb = torch.zeros(1, dtype=torch.int64, device=dev)
+
+    def buffers(rd):
+        rad = {k: torch.empty(N, dtype=rd, device=dev) for k in ("chi_PE", "chi_LW", "chi_H2", "chi_C", "N_eff", "xi")}
+        outs = {"xCp": torch.empty(N, dtype=rd, device=dev), "xCO": torch.empty(N, dtype=rd, device=dev),
+                "xe": torch.empty(N, dtype=rd, device=dev), "nsub": torch.empty(N, dtype=torch.int32, device=dev),
+                "status": torch.empty(N, dtype=torch.uint8, device=dev)}
+        return rad, outs
+
+    bufs = {torch.float64: buffers(torch.float64), torch.float32: buffers(torch.float32)}
+
+    def one_step(path, times=None):
+        f64 = path == "f64"
+        prec = ism.F64 if f64 else ism.MIXED
+        rad, outs = bufs[torch.float64 if f64 else torch.float32]
+        maps = maps64 if f64 else maps32
+        T.copy_(init["T"])
+        xH2.copy_(init["xH2"])
+        xHp.copy_(init["xHp"])
+        rad["xi"].copy_(xi64)
+        ev[0].record(stream)
+        ism.columns6(n.view(shape), xH2.view(shape), None, dx, par, prec, out={k: v.view(shape) for k, v in rad.items()})
+        for k in ("chi_PE", "chi_LW", "chi_H2", "chi_C"):
+            rad[k].add_(maps[k])
+        r = dict(rad)
+        r["phi"] = maps["phi"]
+        ev[1].record(stream)
+        if path == "surrogate":
+            ism.chem_cool_step_surrogate(sur, n, T, xH2, xHp, r, dt, par, out=outs, n_fallback=nfb)
+        else:
+            ism.chem_cool_step(n, T, xH2, xHp, r, dt, par, prec, out=outs)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        if times is not None:
+            times["columns"].append(ev[0].elapsed_time(ev[1]) * 1e-3)
+            times["step"].append(ev[1].elapsed_time(ev[2]) * 1e-3)
+
+    # the subsample: every s-th cell along each axis
+    st = args.c4_stride
+    kk, jj, ii = np.meshgrid(np.arange(0, shape[0], st), np.arange(0, shape[1], st), np.arange(0, shape[2], st),
+                             indexing="ij")
+    idx = (ii + shape[2] * (jj + shape[1] * kk)).ravel()
+    tid = torch.from_numpy(idx).to(dev)
+    paths, rad_sample = {}, None
+    for p in ("f64", "mixed", "surrogate"):
+        for _ in range(args.warmup):
+            one_step(p)
+        times = {"columns": [], "step": []}
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            one_step(p, times)
+        wall = (time.perf_counter() - t0) / args.steps
+        rad, outs = bufs[torch.float64 if p == "f64" else torch.float32]
+        if p == "f64":
+            rad_sample = {k: rad[k][tid].double().cpu().numpy() for k in ("chi_PE", "chi_LW", "chi_H2", "chi_C", "xi")}
+            rad_sample["Neff"] = rad["N_eff"][tid].double().cpu().numpy()
+            rad_sample["phi"] = maps64["phi"][tid].cpu().numpy()
+        res = {"T": T[tid].cpu().numpy(), "xH2": xH2[tid].cpu().numpy(), "xHp": xHp[tid].cpu().numpy()}
+        res.update({k: outs[k][tid].double().cpu().numpy() for k in ("xCp", "xCO", "xe")})
+        nsub = outs["nsub"].to(torch.int64)
+        tc, ts = float(np.median(times["columns"])), float(np.median(times["step"]))
+        paths[p] = {"ms_per_step": (tc + ts) * 1e3, "columns_ms": tc * 1e3, "step_ms": ts * 1e3, "wall_ms": wall * 1e3,
+                    "cell_updates_per_s": N / (tc + ts), "nsub_mean": float(nsub.double().mean()),
+                    "substeps": int(nsub.sum()),
+                    "status_nonzero": int(((outs["status"] & 0xEF) != 0).sum()), "_res": res}
+        if p == "surrogate":
+            paths[p]["fallback_fraction"] = nfb.item() / N
+    for p in ("mixed", "surrogate"):
+        paths[p]["speedup_vs_f64"] = paths["f64"]["ms_per_step"] / paths[p]["ms_per_step"]
+    paths["surrogate"]["speedup_vs_mixed"] = paths["mixed"]["ms_per_step"] / paths["surrogate"]["ms_per_step"]
+    # the FP64 oracle on the subsample, fed the GPU's FP64 radiation there
+    sel = lambda a: np.ascontiguousarray(a.ravel()[idx])
+    st0 = {k: sel(s[k]) for k in ("n", "T", "xH2", "xHp")}
+    chunk = 4096
+    jobs = [tuple(st0[k][a:a + chunk] for k in ("n", "T", "xH2", "xHp")) +
+            ({k: v[a:a + chunk] for k, v in rad_sample.items()}, dt, par_o) for a in range(0, len(idx), chunk)]
+    t0 = time.perf_counter()
+    parts = pool.map(_oracle_chunk, jobs)
+    t_or = time.perf_counter() - t0
+    pool.close()
+    ref = {k: np.concatenate([q[k] for q in parts]) for k in FIELDS}
+    xCt = par_o.xCtot
+    ar = np.arange(len(idx))
+    for p in paths:
+        paths[p]["error_vs_oracle"] = field_errors(paths[p].pop("_res"), ref, ar, xCt)
+    arith, trans = substep_census(par_o)
+    sp = paths["surrogate"]
+    achieved = sp["substeps"] * (arith + trans) / (sp["step_ms"] * 1e-3) / 1e12
+    how = ("adaptive ray tracing (Sec. 5.1)" if args.maps == "art" else
+           "straight-line 1/r^2 exp(-tau) maps with the Stromgren cap")
+    out = {
+        "metric": "cell-updates/s per chem+cool step (columns6 + source step)",
+        "value": sp["cell_updates_per_s"], "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": sp["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16+f32+f64", "data": "synthetic",
+        "config": {"workload": "c4: 512^3 lognormal GRF (2 pc cells, 1024 pc box), 16 point sources (Q 1.24e50 s^-1, "
+                               "L_FUV 1.36e6 L_sun; maps once by " + how + "), chi0 = 1 six-ray, xi_cr log-uniform "
+                               "[1e-17, 1e-15], Z' = 1, one step of 1e4 yr", "cells": N, "path": "surrogate",
+                   "maps": args.maps},
+        "roofline": {"bound": "alu", "kernel": "step_queue_kernel", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "work": f"{sp['substeps']} substeps x ({arith} + {trans}) on the surrogate path's fallback"},
+        "cpu_baseline": {"value": len(idx) / t_or, "unit": "cell-updates/s", "cores": procs, "kind": "oracle",
+                         "sample": f"the stride-{st} subsample ({len(idx)} cells): oracle step from the GPU's FP64 "
+                                   f"radiation, {procs} worker processes, {t_or:.1f} s"},
+        "paths": paths,
+        "detail": {"maps_ms": maps_ms, "generate_s": t_gen, "subsample_cells": int(len(idx))},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
         calibrate_copy()
         return
-    if args.workload == "c2":
+    if args.workload in ("c2", "c4"):
         if args.gpus != 1:
             print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
             sys.exit(2)
-        return bench_c2(args)
+        return bench_c2(args) if args.workload == "c2" else bench_c4(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported "
                                    "(the source step is per-cell independent; see the sharding notes)"}))
