@@ -69,6 +69,7 @@ __device__ __forceinline__ void cell_begin(const StepArgs<R> &a, int64_t i, Cell
   s.r.phi = a.phi ? a.phi[i] : R(0);
   s.r.xi = a.xi[i];
   s.r.Neff = a.Neff[i];
+  fixed_terms(s.r, s.nd, c, a.pr);
   const double T0 = a.T[i];
   s.xH2 = a.xH2[i];
   s.xHp = a.xHp[i];
@@ -241,6 +242,7 @@ __global__ __launch_bounds__(128) void rates_kernel(RatesArgs<R> a) {
   r.xi = a.xi[i];
   r.Neff = a.Neff[i];
   const double nd = a.n[i];
+  fixed_terms(r, nd, c, a.pr);
   const double T = a.T[i];
   const double xH2 = a.xH2[i], xHp = a.xHp[i];
   EqS<R> e = eq_species<R>(T, R(nd), xH2, xHp, r, c, a.pr, s_tab, CloseTol<R>::v, 50);

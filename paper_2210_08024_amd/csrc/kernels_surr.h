@@ -106,6 +106,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
     r.phi = a.phi ? a.phi[i] : 0.f;
     r.xi = a.xi[i];
     r.Neff = a.Neff[i];
+    fixed_terms(r, nd, c, p);
     const double T0 = a.T[i], x20 = a.xH2[i], xp0 = a.xHp[i];
     const double K = nd * muH * K_B / (g_coef64.gamma - 1.0);
     // seed, clamped to the physical range

@@ -98,6 +98,10 @@ __device__ __forceinline__ double co_lookup(const R *tab, double lT, double lN, 
 template <class R>
 struct Rad {
   R chiPE, chiLW, chiH2, chiC, phi, xi, Neff;
+  // terms fixed by the cell's density and radiation for the whole step (fixed_terms)
+  R G;      // dust heating per Z'_d
+  R qH2;    // heat per CR ionisation of H2, erg
+  R ncrit;  // critical density of the CO fit
 };
 
 template <class R>
@@ -198,13 +202,8 @@ __device__ EqS<R> eq_species(double T, R n, double xH2_d, double xHp_d, const Ra
   }
   e.xCp = y;
   e.xe = xe;
-  const R xi16 = rmax(r.xi / R(1e-16), R(1e-10));
-  const double lxi = Mx<R>::ln((double)xi16);
-  // n_CO,crit = (4e3 Z'_d xi16^-2)^(chi^1/3) (50 xi16 / Z'_d^1.4)
-  const R ncrit = Mx<R>::ex((double)Mx<R>::cb(r.chiLW) * (cd.ln_co0 + (double)p.lnZd - 2.0 * lxi)) *
-                  (c.co_fit[1] * xi16 / Mx<R>::ex(cd.co_fit[2] * (double)p.lnZd));
   const R frac = rmax(y / xCt, xHp);
-  const R qq = ncrit / n;
+  const R qq = r.ncrit / n;
   e.xCO = xCt * R(2) * xH2 * (R(1) - frac) / (R(1) + qq * qq);
   e.xC = xCt - y - e.xCO;
   e.xO = R((double)xOt * (1.0 - xHp_d)) - e.xCO;  // x_O,tot - x_O+ formed in double (x_H+ -> 1)
@@ -225,6 +224,29 @@ __device__ __forceinline__ R dust_heating_per_Zd(const Rad<R> &r, const CoefT<R>
   const R opt = fourpi * (c.sig_d_abs[2] * c.J_PE + c.sig_d_abs[1] * c.J_LW) * p.chi0 *
                 Mx<R>::ex(-(double)tau / (double)p.tau_ratio);
   return uv + opt;
+}
+
+// The terms of one cell that depend only on its density and radiation, so are the same in
+// every evaluation of the step: the dust heating G, the CR heating per H2 ionisation (piecewise
+// linear in log10 n) and the CO critical density n_CO,crit = (4e3 Z'_d xi16^-2)^(chi^1/3)
+// (50 xi16 / Z'_d^1.4) of Eq. e:CO_fit with chi_CO = chi_LW.
+template <class R>
+__device__ __forceinline__ void fixed_terms(Rad<R> &r, double n_d, const CoefT<R> &c, const ParT<R> &p) {
+  const CoefT<double> &cd = coef64();
+  r.G = dust_heating_per_Zd(r, c, p);
+  const double *qq = cd.q_cr_H2;  // values qq[0..3] at log10 n = qq[4..7], linear between, flat outside
+  const double ln = Mx<R>::ln(n_d) / LN10D;
+  double val;
+  if (ln <= qq[4]) val = qq[0];
+  else if (ln >= qq[7]) val = qq[3];
+  else if (ln < qq[5]) val = (qq[1] - qq[0]) / (qq[5] - qq[4]) * (ln - qq[4]) + qq[0];
+  else if (ln < qq[6]) val = (qq[2] - qq[1]) / (qq[6] - qq[5]) * (ln - qq[5]) + qq[1];
+  else val = (qq[3] - qq[2]) / (qq[7] - qq[6]) * (ln - qq[6]) + qq[2];
+  r.qH2 = R(val) * R(EV);
+  const R xi16 = rmax(r.xi / R(1e-16), R(1e-10));
+  const double lxi = Mx<R>::ln((double)xi16);
+  r.ncrit = Mx<R>::ex((double)Mx<R>::cb(r.chiLW) * (cd.ln_co0 + (double)p.lnZd - 2.0 * lxi)) *
+            (c.co_fit[1] * xi16 / Mx<R>::ex(cd.co_fit[2] * (double)p.lnZd));
 }
 
 template <class R> struct RootTol;
@@ -354,18 +376,7 @@ __device__ Eval<R> evaluate(double T, double n_d, double xH2_d, double xHp_d, co
                 (R(1) + c.pe_C[2] * Mx<R>::ex(cd.pe_C[5] * lnpsi) * (R(1) + c.pe_C[3] * Mx<R>::ex(cd.pe_C[6] * lnpsi)));
   const R g_pe = c.pe_pref * G0 * eps * Zd;
   const R qH = (c.q_cr_H[0] + c.q_cr_H[1] * Mx<R>::sq(xe / (xe + c.q_cr_H[2]))) * ev;
-  R qH2;
-  {
-    const double *qq = cd.q_cr_H2;  // values qq[0..3] at log10 n = qq[4..7], linear between, flat outside
-    const double ln = Mx<R>::ln(n_d) / LN10D;
-    double val;
-    if (ln <= qq[4]) val = qq[0];
-    else if (ln >= qq[7]) val = qq[3];
-    else if (ln < qq[5]) val = (qq[1] - qq[0]) / (qq[5] - qq[4]) * (ln - qq[4]) + qq[0];
-    else if (ln < qq[6]) val = (qq[2] - qq[1]) / (qq[6] - qq[5]) * (ln - qq[5]) + qq[1];
-    else val = (qq[3] - qq[2]) / (qq[7] - qq[6]) * (ln - qq[6]) + qq[2];
-    qH2 = R(val) * ev;
-  }
+  const R qH2 = r.qH2;
   const R g_cr = r.xi * (xH * qH + R(2) * xH2 * qH2);
   const R g_pi = xH * (c.q_pi_H_eV * ev) * zpiH + xH2 * (c.q_pi_H2_eV * ev) * zpiH2;
   const R kHH = c.k_H2_H[0] * sqrtT * Mx<R>::ex(-cd.k_H2_H[1] * q.invT);
@@ -446,7 +457,7 @@ __device__ Eval<R> evaluate(double T, double n_d, double xH2_d, double xHp_d, co
                               : (expo > 0.0 ? R(0) : (expo < 0.0 ? R(INFINITY) : R(1)));
     l_neb = Zg * xe * xHp * c.neb[0] * ef / (Mx<R>::sq(T4) * (R(1) + c.neb[2] * dens));
   }
-  const R G = dust_heating_per_Zd(r, c, p);
+  const R G = r.G;
   bool bad;
   const R Td = dust_T(Tr, sqrtT, n, G, td_guess, c, p, bad);
   v.Td = Td;
