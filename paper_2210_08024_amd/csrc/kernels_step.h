@@ -53,7 +53,7 @@ struct CellState {
   double nd, K, Tmu, xH2, xHp, t;
   Rad<R> r;
   EqS<R> e;
-  R tdg;
+  double tdg;
   int32_t ns;
   uint32_t st;
 };
@@ -80,7 +80,7 @@ __device__ __forceinline__ void cell_begin(const StepArgs<R> &a, int64_t i, Cell
   s.t = 0.0;
   s.ns = 0;
   s.st = 0;
-  s.tdg = R(0);
+  s.tdg = 0.0;
 }
 
 // One substep of Sec. 6.1 for the lane's cell; returns true when the cell is finished.

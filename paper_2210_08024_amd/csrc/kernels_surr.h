@@ -140,7 +140,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
     double J[3][3], gb[3], h[3] = {0.0, 0.0, 0.0};
     int phase = 0, k = 0, it = 0;
     double dir = 0.0;
-    float tdg = 0.f;
+    double tdg = 0.0;
 #pragma unroll 1
     for (; u[0] > 0.0;) {
       // probe point

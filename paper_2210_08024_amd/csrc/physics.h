@@ -112,8 +112,8 @@ struct EqS {
 // Everything the update needs from one evaluation; Gamma/Lambda/H in double.
 template <class R>
 struct Eval {
-  R F, D, I, Rr, CH2, CHp, Td;
-  double Gamma, Lambda, H;
+  R F, D, I, Rr;
+  double CH2, CHp, Td, Gamma, Lambda, H;
   bool td_bad;
 };
 
@@ -122,11 +122,13 @@ struct Tq {
   double T, lnT, invT, lnT4;
 };
 
+// ln T in double on both paths: it feeds polynomial fits in log T whose terms cancel (the
+// nebular and rovibrational cooling), which would magnify the float log's absolute error.
 template <class R>
 __device__ __forceinline__ Tq make_tq(double T) {
   Tq q;
   q.T = T;
-  q.lnT = Mx<R>::ln(T);
+  q.lnT = flog(T);
   q.invT = 1.0 / T;
   q.lnT4 = q.lnT - LN1E4;
   return q;
@@ -254,18 +256,24 @@ template <> struct RootTol<double> { static constexpr double v = 1e-14; static c
 template <> struct RootTol<float> { static constexpr float v = 2e-7f; static constexpr int it = 40; };
 
 template <class R>
-__device__ R dust_T(R T, R sqrtT, R n, R G, R guess, const CoefT<R> &c, const ParT<R> &p, bool &bad) {
+__device__ R dust_T(R T, R sqrtT, R n, R G, R guess, R Tbb, const CoefT<R> &c, bool &bad) {
   const R A = c.sigma_IR10 / R(100) * R(C_LIGHT) * c.a_rad;
   const R B = n * c.alpha_gd * sqrtT;
-  const R Tbb2 = p.T_bb * p.T_bb, Tbb4 = Tbb2 * Tbb2;
+  const R Tbb2 = Tbb * Tbb, Tbb4 = Tbb2 * Tbb2;
   const R rhs = G + B * T;
-  R lo = rmin(p.T_bb, T), hi = R(1e4);
+  R lo = rmin(Tbb, T), hi = R(1e4);
   const R h2 = hi * hi;
   if (A * h2 * (h2 * h2 - Tbb4) + B * hi - rhs < R(0)) { bad = true; return hi; }
   bad = false;
   R x = guess;
-  if (!(x > lo && x < hi)) {  // cold start: radiative-equilibrium estimate (rhs / A)^(1/6)
+  if (!(x > lo && x < hi)) {
+    // cold start from the smaller of two one-term estimates: radiation alone, (rhs / A)^(1/6),
+    // and gas-dust coupling alone, rhs / B.  The second bounds the root from above (g >= 0
+    // there once it exceeds T_bb); where coupling dominates (dense gas) the first lies far
+    // above the root, and Newton on the degree-6 polynomial would walk down from it by only
+    // about a sixth per iteration.
     x = Mx<R>::ex(Mx<R>::ln((double)(rhs / A)) / 6.0);
+    if (B > R(0)) x = rmin(x, rhs / B);
     if (!(x > lo && x < hi)) x = R(0.5) * (lo + hi);
   }
   for (int it = 0; it < RootTol<R>::it; ++it) {
@@ -273,7 +281,15 @@ __device__ R dust_T(R T, R sqrtT, R n, R G, R guess, const CoefT<R> &c, const Pa
     const R g = A * x2 * (x2 * x2 - Tbb4) + B * x - rhs;
     if (g >= R(0)) hi = x; else lo = x;
     const R dg = A * (R(6) * x2 * x2 * x - R(2) * Tbb4 * x) + B;
-    R xn = x - g / dg;
+    const R step = g / dg;
+    R xn = x - step;
+    // converged: tested before the bracket safeguard, which would otherwise take a root hit
+    // exactly (g = 0 makes x the new upper end, so the step lands on it) for a Newton step
+    // leaving the bracket and fall back to bisection
+    if (fabs(step) <= RootTol<R>::v * x) {
+      x = xn;
+      break;
+    }
     if (!(xn > lo && xn < hi)) xn = R(0.5) * (lo + hi);
     const R dx = fabs(xn - x);
     x = xn;
@@ -322,7 +338,7 @@ enum Diag {
 // every term into diag[NDIAG].
 template <class R, bool CHEM_ONLY, bool DIAG>
 __device__ Eval<R> evaluate(double T, double n_d, double xH2_d, double xHp_d, const EqS<R> &e, const Rad<R> &r,
-                            const CoefT<R> &c, const ParT<R> &p, const R *tab, R td_guess, R *diag) {
+                            const CoefT<R> &c, const ParT<R> &p, const R *tab, double td_guess, R *diag) {
   const CoefT<double> &cd = coef64();
   Eval<R> v;
   const Tq q = make_tq<R>(T);
@@ -357,16 +373,18 @@ __device__ Eval<R> evaluate(double T, double n_d, double xH2_d, double xHp_d, co
   v.D = c.cr_destr * zcrH2 + zpd + zpiH2 + zcd;
   v.I = zpiH + zcrH + zci;
   v.Rr = aB * n * xe + agrH * n;
-  v.CH2 = v.F * xH - v.D * xH2;
-  v.CHp = v.I * xH - v.Rr * xHp;
-  v.Td = R(0);
+  // net rates in double from the rate coefficients: near balance the two terms cancel, and
+  // the substep size follows 1 / |C|
+  v.CH2 = (double)v.F * (xHd > 0.0 ? xHd : 0.0) - (double)v.D * xH2_d;
+  v.CHp = (double)v.I * (xHd > 0.0 ? xHd : 0.0) - (double)v.Rr * xHp_d;
+  v.Td = 0.0;
   v.td_bad = false;
   v.Gamma = v.Lambda = v.H = 0.0;
   if (DIAG) {
     diag[DG_XCP] = e.xCp; diag[DG_XCO] = e.xCO; diag[DG_XE] = e.xe; diag[DG_KGR] = kgr; diag[DG_ZCRH2] = zcrH2;
     diag[DG_ZPD] = zpd; diag[DG_ZPIH2] = zpiH2; diag[DG_ZCD] = zcd; diag[DG_ZPIH] = zpiH; diag[DG_ZCRH] = zcrH;
-    diag[DG_ZCI] = zci; diag[DG_AB] = aB; diag[DG_AGRH] = agrH; diag[DG_PSI] = psi; diag[DG_CH2] = v.CH2;
-    diag[DG_CHP] = v.CHp;
+    diag[DG_ZCI] = zci; diag[DG_AB] = aB; diag[DG_AGRH] = agrH; diag[DG_PSI] = psi; diag[DG_CH2] = R(v.CH2);
+    diag[DG_CHP] = R(v.CHp);
   }
   if (CHEM_ONLY) return v;
   const R ev = R(EV);
@@ -457,12 +475,14 @@ __device__ Eval<R> evaluate(double T, double n_d, double xH2_d, double xHp_d, co
                               : (expo > 0.0 ? R(0) : (expo < 0.0 ? R(INFINITY) : R(1)));
     l_neb = Zg * xe * xHp * c.neb[0] * ef / (Mx<R>::sq(T4) * (R(1) + c.neb[2] * dens));
   }
-  const R G = r.G;
+  // dust temperature in double on both paths: where gas and dust are coupled T_d -> T, and the
+  // gas-dust term goes as T - T_d
   bool bad;
-  const R Td = dust_T(Tr, sqrtT, n, G, td_guess, c, p, bad);
+  const double sqrtTd = Mx<double>::sq(T);
+  const double Td = dust_T<double>(T, sqrtTd, n_d, (double)r.G, td_guess, (double)p.T_bb, cd, bad);
   v.Td = Td;
   v.td_bad = bad;
-  const R l_gd = c.alpha_gd * sqrtT * (Tr - Td) * Zd;
+  const R l_gd = R(cd.alpha_gd * sqrtTd * (T - Td) * (double)Zd);
   const R S = R(1) / (R(1) + Mx<R>::ex(-cd.sigmoid[0] * (T - 0.5 * (cd.sigmoid[1] + cd.sigmoid[2])) /
                                          (cd.sigmoid[2] - cd.sigmoid[1])));
   const double lgT = q.lnT / LN10D;
