@@ -69,9 +69,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary, if it was taken on the
-    current sources: FETCH_SIZE x fetch factor + WRITE_SIZE x write factor (KiB -> bytes)."""
+def measured_counters(kernel):
+    """Counters per launch of `kernel` from the committed summary, if it was taken on the current
+    sources: HBM bytes (FETCH_SIZE x fetch factor + WRITE_SIZE x write factor, KiB -> bytes),
+    VALU wave instructions and lane utilisation.  None when absent or stale."""
     path = os.path.join(ROOT, "profiles", "traffic_grf128.txt")
     if not os.path.exists(path):
         return None
@@ -85,12 +86,19 @@ def measured_traffic(kernel):
         if key in ("src_sha", "fetch_factor", "write_factor"):
             meta[key] = val.strip()
         else:
-            f, w = val.split()
-            rows[key.strip()] = (float(f), float(w))
+            rows[key] = [float(v) for v in val.split()]
     if meta.get("src_sha") != kernel_source_hash() or kernel not in rows:
         return None
-    f, w = rows[kernel]
-    return 1024.0 * (f * float(meta["fetch_factor"]) + w * float(meta["write_factor"]))
+    v = rows[kernel]
+    out = {"bytes": 1024.0 * (v[0] * float(meta["fetch_factor"]) + v[1] * float(meta["write_factor"]))}
+    if len(v) >= 4:
+        out["valu_insts"], out["lane_util"] = v[2], v[3]
+    return out
+
+
+def measured_traffic(kernel):
+    c = measured_counters(kernel)
+    return None if c is None else c["bytes"]
 
 
 def calibrate_copy():
@@ -437,6 +445,24 @@ def bench_c4(args):
     print(json.dumps(out), flush=True)
 
 
+# VALU issue slots: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4 cycles at 2.4 GHz
+# (full-rate FP32 and FP64 FMA; transcendental and FP64 helper instructions take longer, so this
+# is an upper bound on the instructions a kernel can issue).
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
+
+
+def issue_roofline(kernel, t_launch):
+    """VALU wave instructions per second of the kernel (counters from the committed summary over
+    the measured launch time) against the chip's issue rate; None when the counters are stale."""
+    c = measured_counters(kernel)
+    if c is None or "valu_insts" not in c:
+        return None
+    rate = c["valu_insts"] / t_launch
+    return {"bound": "alu-issue", "kernel": kernel, "achieved": rate, "peak": VALU_ISSUE_PEAK,
+            "unit": "wave64 VALU instructions/s", "frac": rate / VALU_ISSUE_PEAK, "lane_util": c["lane_util"],
+            "counters": "SQ_INSTS_VALU per launch from profiles/traffic_grf128.txt"}
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -586,6 +612,8 @@ def main():
                      "traffic_algorithmic": N * (133 if args.path == "f64" else 97),
                      "work": f"{tot_sub} substeps x ({arith} flops + {trans} transcendentals counted as 1) "
                              f"per launch; census of the oracle's substep"},
+        "roofline_issue": issue_roofline(
+            "step_queue_kernel<double>" if args.path == "f64" else "step_queue_kernel<float>", t_step),
         "roofline_mlp": {"bound": "mfma", "kernel": "mlp_fwd_kernel", "achieved": mlp_tf, "peak": BF16_PEAK_TFLOPS,
                          "unit": "TFLOP/s", "frac": mlp_tf / BF16_PEAK_TFLOPS, "ms": t_mlp * 1e3,
                          "work": f"{MLP_FLOP_PER_CELL} FLOP/cell x {N} cells per launch"},
