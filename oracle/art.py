@@ -28,6 +28,13 @@ and dust, alpha = n (x_HI sigma_pi,H + x_H2 sigma_pi,H2 + Z'_d sigma_d,LyC), x_H
 the same unattenuated intensity (the point-source recipe of the long-characteristics module);
 LyC packets carry Q photons s^-1 and give the photon flux phi = sum dQ / alpha_LyC / dV.
 
+With flux=True the trace also returns the flux vector of each band, the same sums with every
+deposit times the packet's direction n (Eq. e:Frad): F_j = sum dL_j n / alpha_j / dV.  PE and
+LW are given as band energy fluxes (erg cm^-2 s^-1): a packet's FUV luminosity is shared
+between them as J^D_PE : J^D_LW, the shares of the Draine field, so that F_PE + F_LW is the
+FUV flux; LyC as a photon flux (photons cm^-2 s^-1).  radiation_force turns them into the
+force per volume on the gas-dust mixture (Sec. 5.4) with the grain-destruction switch.
+
 The HEALPix pixel centres are taken from the continuous inverse HEALPix projection
 (Calabretta & Roukema 2007) evaluated at the centre of each base-pixel sub-square, not from
 the ring-index formulas.
@@ -194,19 +201,33 @@ def _deposits(G, segs, lev, Lband):
 
 
 FIELDS = ("chi_PE", "chi_LW", "chi_H2", "chi_C", "phi")
+# flux components, in the order of the 'flux' output: band-major, then x, y, z
+FLUX = ("F_PE_x", "F_PE_y", "F_PE_z", "F_LW_x", "F_LW_y", "F_LW_z", "F_LyC_x", "F_LyC_y", "F_LyC_z")
+
+
+def _flux_deposits(w, u):
+    """Flux additions [9, pieces] of one packet with direction u from its chi_PE, chi_LW and
+    phi additions w (Eq. e:Frad): chi deposits carry 1 / (4 pi J^D_FUV), so 4 pi J^D_PE and
+    4 pi J^D_LW turn them into the bands' energy fluxes; phi is already a photon flux."""
+    wPE, wLW, _, _, wLyC = w
+    out = []
+    for wb, k in ((wPE, 4.0 * np.pi * C.J_PE), (wLW, 4.0 * np.pi * C.J_LW), (wLyC, 1.0)):
+        out.extend(k * wb * u[a] for a in range(3))
+    return out
 
 
 def ray_trace(n, xH2, xHp, xC, dx, sources, par, level0=4, rays_per_cell=4.0, tau_max=30.0,
-              max_level=13):
+              max_level=13, flux=False):
     """Radiation of the point sources on the grid.
 
     n, xH2, xHp, xC: arrays [nz, ny, nx] (xC may be None = 0).  sources: [m, 5] of
     (x, y, z, Q, L_FUV) in cm, s^-1, erg s^-1.  Returns dict chi_PE, chi_LW, chi_H2, chi_C, phi
     (arrays shaped like n) and budget [m, 6]: luminosity lost through the boundary in PE, LW,
     LyC, then luminosity dropped at tau > tau_max in the same bands (erg s^-1, erg s^-1,
-    photons s^-1)."""
+    photons s^-1); with flux=True also 'flux' [9, nz, ny, nx] in the order of FLUX."""
     G = _Grid(n, xH2, xHp, xC, dx, par)
-    acc = {k: np.zeros(int(np.prod(G.shape))) for k in FIELDS}
+    keys = FIELDS + (FLUX if flux else ())
+    acc = {k: np.zeros(int(np.prod(G.shape))) for k in keys}
     srcs = np.atleast_2d(np.asarray(sources, dtype=np.float64))
     budget = np.zeros((len(srcs), 6))
     for si, (sx, sy, sz, Q, L) in enumerate(srcs):
@@ -218,7 +239,9 @@ def ray_trace(n, xH2, xHp, xC, dx, sources, par, level0=4, rays_per_cell=4.0, ta
             reason, segs, end = _walk(G, s, lev, pix, state, rays_per_cell, tau_max, max_level)
             if segs is not None:
                 c, w = _deposits(G, segs, lev, Lband)
-                for k, v in zip(FIELDS, w):
+                if flux:
+                    w = tuple(w) + tuple(_flux_deposits(w, healpix_dirs(lev, pix)[0]))
+                for k, v in zip(keys, w):
                     np.add.at(acc[k], c, v)
             if reason == "split":
                 stack.extend((lev + 1, 4 * pix + ch, end) for ch in range(4))
@@ -227,7 +250,9 @@ def ray_trace(n, xH2, xHp, xC, dx, sources, par, level0=4, rays_per_cell=4.0, ta
                 att = np.exp(-np.array([G.sPE * NH, G.sLW * NH, tL]))
                 o = 0 if reason == "exit" else 3
                 budget[si, o:o + 3] += Lband * att / (12.0 * 4.0 ** lev)
-    out = {k: v.reshape(G.shape) for k, v in acc.items()}
+    out = {k: acc[k].reshape(G.shape) for k in FIELDS}
+    if flux:
+        out["flux"] = np.stack([acc[k].reshape(G.shape) for k in FLUX])
     out["budget"] = budget
     return out
 
@@ -239,8 +264,9 @@ DESC_RADIUS = 2.0
 
 
 def ray_trace_cells(n, xH2, xHp, xC, dx, sources, par, cells, level0=4, rays_per_cell=4.0,
-                    tau_max=30.0, max_level=13):
-    """ray_trace at selected cells only: dict of arrays [len(cells)].
+                    tau_max=30.0, max_level=13, flux=False):
+    """ray_trace at selected cells only: dict of arrays [len(cells)] (and 'flux' [9, len(cells)]
+    with flux=True).
 
     Packet trees of different level-l0 pixels are independent, so a cell's value is the sum
     over the packets whose lines cross it.  For each cell and source the candidates are the
@@ -252,7 +278,8 @@ def ray_trace_cells(n, xH2, xHp, xC, dx, sources, par, cells, level0=4, rays_per
     cell are kept.  cells: int array [k, 3] of (k, j, i)."""
     G = _Grid(n, xH2, xHp, xC, dx, par)
     cells = np.atleast_2d(np.asarray(cells, dtype=np.int64))
-    out = {k: np.zeros(len(cells)) for k in FIELDS}
+    keys = FIELDS + (FLUX if flux else ())
+    out = {k: np.zeros(len(cells)) for k in keys}
     srcs = np.atleast_2d(np.asarray(sources, dtype=np.float64))
     rho = 0.5 * np.sqrt(3.0)  # circumscribed radius of a cell, cell units
     R = [np.sqrt(12.0 * 4.0 ** l / (4.0 * np.pi * rays_per_cell)) for l in range(max_level + 2)]
@@ -298,12 +325,16 @@ def ray_trace_cells(n, xH2, xHp, xC, dx, sources, par, cells, level0=4, rays_per
                             c, dep = _deposits(G, w[1], lev, Lband)
                             m = c == target
                             if m.any():
-                                for key, val in zip(FIELDS, dep):
+                                if flux:
+                                    dep = tuple(dep) + tuple(_flux_deposits(dep, healpix_dirs(lev, int(p))[0]))
+                                for key, val in zip(keys, dep):
                                     out[key][ci] += float(np.sum(val[m]))
                 if lev >= max_level or R[lev] > d + rho:
                     break
                 pix = (4 * pix[:, None] + np.arange(4)[None, :]).ravel()
                 lev += 1
+    if flux:
+        out["flux"] = np.stack([out.pop(k) for k in FLUX])
     return out
 
 
@@ -319,3 +350,54 @@ def absorbed(out, n, xH2, xHp, dx, par):
     return np.array([np.sum(C.SIG_D_PE * Zd * n * out["chi_PE"]) * k,
                      np.sum(C.SIG_D_LW * Zd * n * out["chi_LW"]) * k,
                      np.sum(aLyC * out["phi"]) * dV])
+
+
+# Grain destruction (appendix on grain destruction): grains are taken as destroyed, and the
+# radiation force on them omitted, where T exceeds 1e6 K (thermal sputtering) or where the
+# radiation pressure exceeds 50 times the gas pressure (non-thermal sputtering: the terminal
+# drift then lies on the branch s ~ sqrt(P_rad / P) >~ sqrt(50)); P_rad = |F| / c with F the
+# total flux of the traced bands and P = 2 n k_B T.
+T_DESTROY = 1.0e6
+PRAD_RATIO_MAX = 50.0
+
+
+def radiation_force(n, T, xH2, xHp, flux, par, T_destroy=T_DESTROY, prad_ratio_max=PRAD_RATIO_MAX,
+                    dt=0.0, mom=None, etot=None):
+    """Radiation force per volume on the gas-dust mixture (Sec. 5.4): the sum over bands of
+    alpha_j F_j / c, alpha_j the band's opacity (PE, LW: dust; LyC: dust, H and H2; the same
+    opacities as the trace), with the LyC photon flux carrying h nu_LyC per photon.  Where the
+    grains are destroyed the dust part of every band is dropped and only the photoionisation
+    part of LyC remains.
+
+    n, T, xH2, xHp: arrays of any shape; flux: [9, *shape] as ray_trace returns it.  Returns
+    dict f [3, *shape] (dyn cm^-3) and dust_off (bool).  With mom ([3, *shape] momentum
+    density, g cm^-2 s^-1) the source-term update of Sec. 5.4 is also made on copies: mom + f dt
+    and, with etot (total energy density, erg cm^-3), etot plus the change of rho v^2 / 2 at
+    fixed rho = mu_H m_H n; returned as 'mom' and 'etot'."""
+    n = np.asarray(n, dtype=np.float64)
+    T = np.asarray(T, dtype=np.float64)
+    xH2 = np.asarray(xH2, dtype=np.float64)
+    xHp = np.asarray(xHp, dtype=np.float64)
+    F = np.asarray(flux, dtype=np.float64).reshape((3, 3) + n.shape)
+    F_PE, F_LW, F_LyC = F[0], F[1], C.HNU_LYC * F[2]  # energy fluxes
+    Ftot = F_PE + F_LW + F_LyC
+    prad = np.sqrt(np.sum(Ftot * Ftot, 0)) / C.C_LIGHT
+    P = 2.0 * n * C.K_B * T
+    off = (T > T_destroy) | (prad > prad_ratio_max * P)
+    keep = np.where(off, 0.0, 1.0)
+    Zd = par.Zd
+    xHI = np.maximum(1.0 - 2.0 * xH2 - xHp, 0.0)
+    a_gas = n * (xHI * C.SIGMA_PI_H + xH2 * C.SIGMA_PI_H2)
+    f = (keep * n * Zd * (C.SIG_D_PE * F_PE + C.SIG_D_LW * F_LW + C.SIG_D_LYC * F_LyC)
+         + a_gas * F_LyC) / C.C_LIGHT
+    out = {"f": f, "dust_off": off}
+    if mom is not None:
+        p0 = np.asarray(mom, dtype=np.float64)
+        p1 = p0 + f * dt
+        out["mom"] = p1
+        if etot is not None:
+            rho = par.muH * C.M_H * n
+            with np.errstate(divide="ignore", invalid="ignore"):
+                dk = np.where(rho > 0.0, (np.sum(p1 * p1, 0) - np.sum(p0 * p0, 0)) / (2.0 * rho), 0.0)
+            out["etot"] = np.asarray(etot, dtype=np.float64) + dk
+    return out

@@ -15,6 +15,7 @@ import numpy as np
 K_B = 1.380649e-16          # erg / K
 EV = 1.602176634e-12        # erg
 C_LIGHT = 2.99792458e10     # cm / s
+M_H = 1.67262192369e-24 + 9.1093837015e-28  # g: hydrogen atom, proton + electron
 PC = 3.0856775814913673e18  # cm
 YR = 3.15576e7              # s (Julian year)
 

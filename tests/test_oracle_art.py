@@ -197,3 +197,163 @@ def test_cells_mode_matches_the_full_trace():
         for k in art.FIELDS:
             ref = full[k][cells[:, 0], cells[:, 1], cells[:, 2]]
             np.testing.assert_allclose(got[k], ref, rtol=1e-12, atol=0)
+
+
+# ---- flux (Eq. e:Frad) and radiation force (Sec. 5.4) ---------------------------------
+
+def _energy_fluxes(out):
+    """c E_j per band in the flux's units: 4 pi J^D_j chi_j for PE and LW, phi for LyC."""
+    return (4 * np.pi * C.J_PE * out["chi_PE"], 4 * np.pi * C.J_LW * out["chi_LW"], out["phi"])
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(level0=1, tau_max=3.0, max_level=4)])
+def test_flux_bounded_by_the_energy_density(kw):
+    """|F_j| <= c E_j in every cell (a sum of unit vectors times the deposits), with equality
+    where one packet alone deposits."""
+    par = Params()
+    n, xH2, xHp, xC = _medium((10, 11, 12), 1)
+    out = art.ray_trace(n, xH2, xHp, xC, DX, SRC, par, flux=True, **kw)
+    F = out["flux"]
+    for b, cE in enumerate(_energy_fluxes(out)):
+        mag = np.sqrt(np.sum(F[3 * b:3 * b + 3] ** 2, 0))
+        assert np.all(mag <= cE * (1 + 1e-12)), b
+        assert mag.max() > 0
+
+
+def _cone(shape, s):
+    """Per cell: distance d from s to the centre (cm), unit vector to the centre, and cos of
+    the half-angle of the cell's circumscribed sphere seen from s (0 where s is inside it)."""
+    kk, jj, ii = np.indices(shape)
+    v = np.stack([(ii + 0.5) * DX - s[0], (jj + 0.5) * DX - s[1], (kk + 0.5) * DX - s[2]])
+    d = np.sqrt(np.sum(v * v, 0))
+    rho = 0.5 * np.sqrt(3) * DX
+    cosmax = np.where(d > rho, np.sqrt(np.maximum(1 - (rho / np.maximum(d, rho)) ** 2, 0)), 0.0)
+    return d, v / np.maximum(d, 1e-300), cosmax
+
+
+def test_flux_points_away_from_the_source():
+    """Packets travel on straight lines from the source, so every packet crossing a cell is
+    within the cone of the cell's circumscribed sphere: F_j . r_hat >= cos(theta_max) c E_j
+    in every cell (exact; a wrong sign or a swapped component fails it)."""
+    par = Params()
+    shape = (12, 13, 14)
+    n, xH2, xHp, xC = _medium(shape, 5, dense=False)
+    s = np.array([6.3, 5.2, 7.9]) * DX
+    out = art.ray_trace(n, xH2, xHp, xC, DX, [[*s, 1e49, 1e5 * sources.L_SUN]], par, flux=True)
+    d, rhat, cosmax = _cone(shape, s)
+    F = out["flux"]
+    m = cosmax > 0.5
+    assert m.sum() > 1000
+    for b, cE in enumerate(_energy_fluxes(out)):
+        along = np.sum(F[3 * b:3 * b + 3] * rhat, 0)
+        assert np.all(along[m] >= cosmax[m] * cE[m] * (1 - 1e-12)), b
+        assert np.all(along[m] > 0)
+
+
+def test_flux_mirror_antisymmetry():
+    """A source at a cell centre in a medium symmetric under x -> -x about it: F_x changes sign
+    under the mirror, F_y and F_z do not (the HEALPix directions are mirror-symmetric)."""
+    par = Params()
+    shape = (9, 10, 11)
+    n, xH2, xHp, xC = _medium(shape, 6, dense=False)
+    n, xH2, xHp, xC = (0.5 * (a + a[:, :, ::-1]) for a in (n, xH2, xHp, xC))
+    s = np.array([5.5, 4.7, 4.2]) * DX
+    out = art.ray_trace(n, xH2, xHp, xC, DX, [[*s, 1e49, 1e5 * sources.L_SUN]], par, flux=True)
+    F = out["flux"]
+    for b in range(3):
+        sc = np.abs(F[3 * b:3 * b + 3]).max()
+        np.testing.assert_allclose(F[3 * b], -F[3 * b][:, :, ::-1], rtol=0, atol=1e-10 * sc)
+        for a in (1, 2):
+            np.testing.assert_allclose(F[3 * b + a], F[3 * b + a][:, :, ::-1], rtol=0, atol=1e-10 * sc)
+
+
+def test_force_matches_the_absorbed_luminosity():
+    """Every packet's absorbed luminosity dL_j brings the momentum dL_j n / c, so in each cell
+    f . r_hat c dV lies between cos(theta_max) and 1 times the cell's absorbed luminosity
+    alpha_j c E_j dV summed over bands (with h nu_LyC per LyC photon)."""
+    par = Params()
+    shape = (12, 13, 14)
+    n, xH2, xHp, xC = _medium(shape, 7, dense=False)
+    s = np.array([6.3, 5.2, 7.9]) * DX
+    out = art.ray_trace(n, xH2, xHp, xC, DX, [[*s, 1e49, 1e5 * sources.L_SUN]], par, flux=True)
+    T = np.full(shape, 50.0)
+    fr = art.radiation_force(n, T, xH2, xHp, out["flux"], par, prad_ratio_max=np.inf)
+    assert not fr["dust_off"].any()
+    xHI = 1 - 2 * xH2 - xHp
+    aLyC = n * (xHI * C.SIGMA_PI_H + xH2 * C.SIGMA_PI_H2 + par.Zd * C.SIG_D_LYC)
+    cE = _energy_fluxes(out)
+    absorbed = (C.SIG_D_PE * par.Zd * n * cE[0] + C.SIG_D_LW * par.Zd * n * cE[1]
+                + aLyC * C.HNU_LYC * cE[2]) * DX ** 3
+    d, rhat, cosmax = _cone(shape, s)
+    along = np.sum(fr["f"] * rhat, 0) * C.C_LIGHT * DX ** 3
+    m = cosmax > 0.5
+    assert np.all(along[m] >= cosmax[m] * absorbed[m] * (1 - 1e-12))
+    assert np.all(along[m] <= absorbed[m] * (1 + 1e-12))
+
+
+def test_force_grain_destruction_switch():
+    """Dust force off above 1e6 K and where P_rad = |F| / c exceeds 50 times 2 n k_B T; the
+    photoionisation part of LyC stays; with no neutral hydrogen and the grains destroyed the
+    force vanishes."""
+    par = Params()
+    n = np.array([1.0, 1.0, 1.0, 1.0, 10.0, 10.0, 10.0])
+    T = np.array([1e4, 1.01e6, 1e4, 1e4, 100.0, 100.0, 2e6])
+    xH2 = np.zeros(7)
+    xHp = np.array([0.5, 0.5, 0.5, 0.5, 1.0, 1.0, 1.0])
+    F = np.zeros((9, 7))
+    F[0] = [1e-3, 1e-3, 0, 0, 0, 0, 0]          # PE energy flux along x
+    P = 2 * n * C.K_B * T
+    # cells 2 and 3: a LyC photon flux along -y whose pressure is 50 P times (1 -+ 1e-6)
+    F[7, 2] = -50 * P[2] * C.C_LIGHT / C.HNU_LYC * (1 - 1e-6)
+    F[7, 3] = -50 * P[3] * C.C_LIGHT / C.HNU_LYC * (1 + 1e-6)
+    F[6, 4] = 1e6                                  # weak LyC in an ionised cell
+    F[6, 5] = 50 * P[5] * C.C_LIGHT / C.HNU_LYC * 2  # strong LyC in an ionised cell
+    F[6, 6] = 1e6
+    fr = art.radiation_force(n, T, xH2, xHp, F, par)
+    off = fr["dust_off"]
+    assert off.tolist() == [False, True, False, True, False, True, True]
+    f = fr["f"]
+    assert f[0, 0] > 0 and f[0, 1] == 0.0
+    # below the threshold the dust and the gas push; above it only the neutral hydrogen
+    gas = n[2] * 0.5 * C.SIGMA_PI_H
+    dust = n[2] * par.Zd * C.SIG_D_LYC
+    np.testing.assert_allclose(f[1, 2] / F[7, 2], (gas + dust) * C.HNU_LYC / C.C_LIGHT, rtol=1e-14)
+    np.testing.assert_allclose(f[1, 3] / F[7, 3], gas * C.HNU_LYC / C.C_LIGHT, rtol=1e-14)
+    assert f[0, 4] > 0 and np.all(f[:, 5] == 0) and np.all(f[:, 6] == 0)
+
+
+def test_force_momentum_update():
+    """The source-term update of Sec. 5.4: from rest the energy gains the kinetic energy of the
+    acquired momentum, (f dt)^2 / (2 rho); a force that reverses the momentum (f dt = -2 p)
+    leaves the energy as it was; n = 0 is left alone."""
+    par = Params(Zg=1.0)
+    n = np.array([2.0, 3.0, 0.0])
+    z = np.zeros(3)
+    F = np.zeros((9, 3))
+    F[0] = [1e-2, 1e-2, 1e-2]
+    F[4] = [3e-3, -2e-3, 0.0]
+    dt = 1e11
+    f = art.radiation_force(n, np.full(3, 100.0), z, z, F, par, prad_ratio_max=np.inf)["f"]
+    rho = 1.4 * C.M_H * n
+    mom0 = np.zeros((3, 3))
+    mom0[:, 1] = -0.5 * f[:, 1] * dt
+    e0 = np.array([3e-22, 2e-10, 3e-10])
+    out = art.radiation_force(n, np.full(3, 100.0), z, z, F, par, prad_ratio_max=np.inf,
+                              dt=dt, mom=mom0, etot=e0)
+    np.testing.assert_allclose(out["mom"], mom0 + f * dt, rtol=1e-15)
+    np.testing.assert_allclose(out["etot"][0] - e0[0], np.sum((f[:, 0] * dt) ** 2) / (2 * rho[0]), rtol=1e-12)
+    np.testing.assert_allclose(out["etot"][1], e0[1], rtol=1e-12)
+    assert np.all(f[:, 2] == 0) and out["etot"][2] == e0[2]
+
+
+def test_cells_mode_flux_matches_the_full_trace():
+    par = Params()
+    shape = (10, 11, 12)
+    n, xH2, xHp, xC = _medium(shape, 2)
+    rng = np.random.default_rng(8)
+    cells = np.stack(np.unravel_index(rng.choice(n.size, 20, replace=False), shape), 1)
+    full = art.ray_trace(n, xH2, xHp, xC, DX, SRC, par, flux=True)
+    got = art.ray_trace_cells(n, xH2, xHp, xC, DX, SRC, par, cells, flux=True)
+    ref = full["flux"][:, cells[:, 0], cells[:, 1], cells[:, 2]]
+    sc = np.abs(full["flux"]).max(axis=(1, 2, 3))[:, None]
+    np.testing.assert_allclose(got["flux"], ref, rtol=1e-12, atol=1e-14 * sc.max())
