@@ -249,6 +249,9 @@ def bench_c2(args):
     ev[1].record(stream)
     torch.cuda.synchronize()
     other_ms = ev[0].elapsed_time(ev[1])
+    force = None
+    if args.maps == "art":
+        force = bench_radiation_force(ism, par, n, init, shape, dx, cfg["sources"], stream, ev)
     how = ("adaptive ray tracing (Sec. 5.1)" if args.maps == "art" else
            "straight-line 1/r^2 exp(-tau) maps with the Stromgren cap")
     arith, trans = substep_census(OParams())
@@ -273,7 +276,45 @@ def bench_c2(args):
                    "nsub_mean_each": [round(x / N, 3) for x in tot_sub],
                    "status_nonzero_last": int(((outs["status"] & 0xEF) != 0).sum().item())},
     }
+    if force is not None:
+        out["radiation_force"] = force
     print(json.dumps(out), flush=True)
+
+
+# Algorithmic bytes per cell of radiation_force_kernel on the mixed path: reads the 9 float
+# flux components and n, T, x_H2, x_H+ (double), writes 3 float force components and the
+# grain-destruction byte.
+FORCE_BYTES_MIXED = 9 * 4 + 4 * 8 + 3 * 4 + 1
+
+
+def bench_radiation_force(ism, par, n, init, shape, dx, sources, stream, ev, reps=20):
+    """Outside the timed job: the ray trace with the flux estimator (Eq. e:Frad) on the initial
+    state, and the radiation force with the grain-destruction switch (Sec. 5.4) from it."""
+    import torch
+    N = n.numel()
+    fx = {k: torch.zeros(shape, dtype=torch.float32, device="cuda") for k in ("chi_PE", "chi_LW", "chi_H2", "chi_C", "phi")}
+    fx["flux"] = torch.zeros((9,) + tuple(shape), dtype=torch.float32, device="cuda")
+    xH2, xHp, T = init["xH2"].view(shape), init["xHp"].view(shape), init["T"].view(shape)
+    ev[0].record(stream)
+    ism.ray_trace(n, xH2, xHp, None, dx, par, ism.MIXED, sources, fx)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    trace_ms = ev[0].elapsed_time(ev[1])
+    f_rad = torch.empty((3,) + tuple(shape), dtype=torch.float32, device="cuda")
+    off = torch.empty(tuple(shape), dtype=torch.uint8, device="cuda")
+    ism.radiation_force(n, T, xH2, xHp, fx["flux"], par, ism.MIXED, f_rad=f_rad, dust_off=off)
+    ev[2].record(stream)
+    for _ in range(reps):
+        ism.radiation_force(n, T, xH2, xHp, fx["flux"], par, ism.MIXED, f_rad=f_rad, dust_off=off)
+    ev[3].record(stream)
+    torch.cuda.synchronize()
+    force_ms = ev[2].elapsed_time(ev[3]) / reps
+    gbs = N * FORCE_BYTES_MIXED / (force_ms * 1e-3) / 1e9
+    return {"ray_trace_with_flux_ms": trace_ms, "radiation_force_ms": force_ms,
+            "dust_off_fraction": float(off.double().mean().item()),
+            "roofline": {"bound": "hbm", "kernel": "radiation_force_kernel", "achieved": gbs, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                         "work": f"{FORCE_BYTES_MIXED} B/cell x {N} cells per launch"}}
 
 
 def _oracle_chunk(job):

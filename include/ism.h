@@ -199,7 +199,12 @@ typedef struct {
  * src: host array of nsrc <= 256 sources inside the grid; opt: NULL for the defaults
  * {4, 13, 4.0, 30.0}.
  * In/out: the five radiation arrays (double for F64, float for MIXED): contributions are
- * added (atomically, so the last bits vary between runs).  budget: NULL, or a device array of
+ * added (atomically, so the last bits vary between runs).  flux: NULL, or 9 arrays of ncell
+ * (the path's precision; band-major PE, LW, LyC, then x, y, z; component k of cell i at
+ * flux + k * ncell + i) to which the flux vectors of Eq. e:Frad, F_j = sum dL_j n / alpha_j /
+ * dV with n the packet's direction, are added: PE and LW as band energy fluxes in
+ * erg cm^-2 s^-1 (a packet's L_FUV shared as J^D_PE : J^D_LW, the Draine field's shares), LyC
+ * as a photon flux in photons cm^-2 s^-1.  budget: NULL, or a device array of
  * nsrc x 6 doubles that receives per source the luminosity lost through the faces (PE, LW in
  * erg s^-1, LyC in photons s^-1) and then the luminosity dropped at tau > tau_max.
  * The call returns when the work is done: it reads the number of packets of each level back
@@ -209,8 +214,34 @@ typedef struct {
 ism_status ism_ray_trace(const ism_grid *g, const ism_params *p, ism_precision prec, int32_t nsrc,
                          const ism_source *src, const ism_art_options *opt, const double *n,
                          const double *xH2, const double *xHp, const double *xC, void *chi_PE,
-                         void *chi_LW, void *chi_H2, void *chi_C, void *phi_LyC, double *budget,
-                         hipStream_t stream);
+                         void *chi_LW, void *chi_H2, void *chi_C, void *phi_LyC, void *flux,
+                         double *budget, hipStream_t stream);
+
+typedef struct {
+  double T_destroy_K;     /* grains destroyed above this gas temperature (1e6) */
+  double prad_ratio_max;  /* ... or where |F| / c exceeds this multiple of 2 n k_B T (50) */
+} ism_force_options;
+
+/* Radiation force per volume on the gas-dust mixture (Sec. 5.4): f = sum_j alpha_j F_j / c
+ * over the traced bands with the opacities of ism_ray_trace (PE, LW: dust; LyC: dust, H and
+ * H2), h nu_LyC per LyC photon.  Grain destruction (appendix on grain destruction): where
+ * T > T_destroy_K or P_rad = |F_PE + F_LW + h nu F_LyC| / c > prad_ratio_max x 2 n k_B T
+ * the dust part of every band is dropped and only LyC photoionisation of H and H2 pushes.
+ * In: n, T, xH2, xHp (double, ncell each), flux (9 x ncell, the layout and precision that
+ * ism_ray_trace writes); opt: NULL for {1e6, 50} (an infinite value turns a test off).
+ * Out: f_rad (3 x ncell, the path's precision, dyn cm^-3: x, y, z at f_rad + q * ncell + i);
+ * dust_off: NULL or ncell bytes, 1 where the grains count as destroyed.
+ * Source-term update (optional): mom, NULL or 3 x ncell doubles of momentum density
+ * (g cm^-2 s^-1, in/out), receives f dt_s; etot, NULL or ncell doubles of total energy
+ * density (erg cm^-3, in/out, needs mom), receives the change of rho v^2 / 2 at
+ * rho = mu_H m_H n (cells with n = 0 unchanged).  Arithmetic in double on both paths.
+ * ISM_E_ARG for NULL required arrays, ncell outside [0, 2^32 - 256), NaN or non-positive
+ * thresholds, dt_s negative or not finite, etot without mom. */
+ism_status ism_radiation_force(const ism_params *p, ism_precision prec, int64_t ncell,
+                               const double *n, const double *T, const double *xH2,
+                               const double *xHp, const void *flux, const ism_force_options *opt,
+                               void *f_rad, uint8_t *dust_off, double dt_s, double *mom,
+                               double *etot, hipStream_t stream);
 
 /* Per-cell diagnostics of the microphysics at the given state (Secs. 3-4): every rate
  * coefficient, heating and cooling term, T_d, the equilibrium x_C+, x_CO, x_e, the

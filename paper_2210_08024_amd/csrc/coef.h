@@ -15,6 +15,7 @@ namespace ism {
 constexpr double K_B = 1.380649e-16;
 constexpr double EV = 1.602176634e-12;
 constexpr double C_LIGHT = 2.99792458e10;
+constexpr double M_H = 1.67262192369e-24 + 9.1093837015e-28;  // g: hydrogen atom, proton + electron
 constexpr double PC_CM = 3.0856775814913673e18;
 constexpr double LN10 = 2.302585092994045684;
 

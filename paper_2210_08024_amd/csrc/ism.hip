@@ -845,7 +845,7 @@ ism_status art_list(DevState *st, int b, int64_t rays) {
 ism_status ism_ray_trace(const ism_grid *g, const ism_params *p, ism_precision prec, int32_t nsrc,
                          const ism_source *src, const ism_art_options *opt, const double *n, const double *xH2,
                          const double *xHp, const double *xC, void *chi_PE, void *chi_LW, void *chi_H2,
-                         void *chi_C, void *phi_LyC, double *budget, hipStream_t stream) {
+                         void *chi_C, void *phi_LyC, void *flux, double *budget, hipStream_t stream) {
   g_err.clear();
   if (!g) return fail(ISM_E_ARG, "grid is NULL");
   if (g->nx < 1 || g->ny < 1 || g->nz < 1) return fail(ISM_E_ARG, "grid dimensions must be >= 1");
@@ -896,6 +896,10 @@ ism_status ism_ray_trace(const ism_grid *g, const ism_params *p, ism_precision p
   a.phi_norm = 1.0 / dV;
   a.budget = budget;
   a.tab = st->tab64;
+  a.flux = flux;
+  a.ncell = (int64_t)g->nx * g->ny * g->nz;
+  a.kPE = 4.0 * M_PI * g_host_coef.J_PE;
+  a.kLW = 4.0 * M_PI * g_host_coef.J_LW;
   if (budget)
     hipLaunchKernelGGL(art_zero_kernel, dim3((unsigned)((6 * nsrc + 255) / 256)), dim3(256), 0, stream, budget,
                        (int64_t)6 * nsrc, (unsigned long long *)nullptr);
@@ -917,10 +921,17 @@ ism_status ism_ray_trace(const ism_grid *g, const ism_params *p, ism_precision p
     hipLaunchKernelGGL(art_zero_kernel, dim3(1), dim3(64), 0, stream, (double *)nullptr, (int64_t)0,
                        st->art_count);
     const dim3 grid((unsigned)((nin + 255) / 256));
-    if (prec == ISM_PREC_F64)
-      hipLaunchKernelGGL(art_level_kernel<double>, grid, dim3(256), lds, stream, a);
-    else
-      hipLaunchKernelGGL(art_level_kernel<float>, grid, dim3(256), lds, stream, a);
+    if (prec == ISM_PREC_F64) {
+      if (flux)
+        hipLaunchKernelGGL((art_level_kernel<double, true>), grid, dim3(256), lds, stream, a);
+      else
+        hipLaunchKernelGGL((art_level_kernel<double, false>), grid, dim3(256), lds, stream, a);
+    } else {
+      if (flux)
+        hipLaunchKernelGGL((art_level_kernel<float, true>), grid, dim3(256), lds, stream, a);
+      else
+        hipLaunchKernelGGL((art_level_kernel<float, false>), grid, dim3(256), lds, stream, a);
+    }
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(st->art_count_host, st->art_count, sizeof(unsigned long long), hipMemcpyDeviceToHost,
                            stream));
@@ -928,6 +939,51 @@ ism_status ism_ray_trace(const ism_grid *g, const ism_params *p, ism_precision p
     nin = level < o.max_level ? (int64_t)*st->art_count_host : 0;
     cur = nxt;
   }
+  return ISM_OK;
+}
+
+ism_status ism_radiation_force(const ism_params *p, ism_precision prec, int64_t ncell, const double *n,
+                               const double *T, const double *xH2, const double *xHp, const void *flux,
+                               const ism_force_options *opt, void *f_rad, uint8_t *dust_off, double dt_s,
+                               double *mom, double *etot, hipStream_t stream) {
+  g_err.clear();
+  if (ism_status s = check_params(p)) return s;
+  if (prec != ISM_PREC_F64 && prec != ISM_PREC_MIXED) return fail(ISM_E_ARG, "invalid precision");
+  if (ncell < 0) return fail(ISM_E_ARG, "ncell must be >= 0");
+  ism_force_options o{1.0e6, 50.0};
+  if (opt) o = *opt;
+  if (!(o.T_destroy_K > 0.0)) return fail(ISM_E_ARG, "T_destroy_K must be > 0");
+  if (!(o.prad_ratio_max > 0.0)) return fail(ISM_E_ARG, "prad_ratio_max must be > 0");
+  if (!(dt_s >= 0.0) || !std::isfinite(dt_s)) return fail(ISM_E_ARG, "dt_s must be finite and >= 0");
+  if (etot && !mom) return fail(ISM_E_ARG, "etot needs mom");
+  if (ncell > (int64_t)0xFFFFFF00ll) return fail(ISM_E_ARG, "ncell must be below 2^32 - 256");
+  if (ncell == 0) return ISM_OK;
+  if (!n || !T || !xH2 || !xHp || !flux || !f_rad) return fail(ISM_E_ARG, "a required array is NULL");
+  DevState *st;
+  if (ism_status s = current_state(&st)) return s;
+  const double Zd = p->Zd;
+  ForceArgs a{};
+  a.ncell = ncell;
+  a.n = n; a.T = T; a.xH2 = xH2; a.xHp = xHp;
+  a.flux = flux; a.f = f_rad; a.dust_off = dust_off; a.mom = mom; a.etot = etot;
+  a.dt = dt_s;
+  a.T_destroy = o.T_destroy_K;
+  a.prad_ratio_max = o.prad_ratio_max;
+  a.sPE = g_host_coef.sig_d_abs[2] * Zd;
+  a.sLW = g_host_coef.sig_d_abs[1] * Zd;
+  a.sdLyC = g_host_coef.sig_d_abs[0] * Zd;
+  a.spiH = g_host_coef.sig_pi_H;
+  a.spiH2 = g_host_coef.sig_pi_H2;
+  a.hnu = g_host_coef.hnu_LyC_eV * EV;
+  a.inv_c = 1.0 / C_LIGHT;
+  a.two_kB = 2.0 * K_B;
+  a.rho_per_n = (g_host_coef.muH0 - g_host_coef.muH_slope * (p->Zg - 1.0)) * M_H;
+  const dim3 grid((unsigned)((ncell + 255) / 256));
+  if (prec == ISM_PREC_F64)
+    hipLaunchKernelGGL(radiation_force_kernel<double>, grid, dim3(256), 0, stream, a);
+  else
+    hipLaunchKernelGGL(radiation_force_kernel<float>, grid, dim3(256), 0, stream, a);
+  HIP_TRY(hipGetLastError());
   return ISM_OK;
 }
 

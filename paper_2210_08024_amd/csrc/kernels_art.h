@@ -15,6 +15,12 @@
 // parent are adjacent, so neighbouring lanes of the next launch walk neighbouring rays).
 // Deposits are atomic adds into the output fields, so the summation order, and the last bits
 // of the result, vary between runs.  Distances inside the kernel are in cell units.
+//
+// With a flux output the packets also deposit their chi_PE, chi_LW and phi additions times
+// their direction (Eq. e:Frad): nine more sums per cell, band-major (PE, LW, LyC) then x, y, z.
+// PE and LW become band energy fluxes (the packet's FUV luminosity shared as J^D_PE : J^D_LW,
+// the Draine field's shares), LyC a photon flux.  radiation_force_kernel turns them into the
+// force per volume on the gas-dust mixture (Sec. 5.4) with the grain-destruction switch.
 #pragma once
 #include "kernels_sources.h"
 
@@ -48,6 +54,9 @@ struct ArtArgs {
   double phi_norm;              // 1 / dV
   double *budget;               // [nsrc][6]: escaped PE, LW, LyC, dropped PE, LW, LyC; or null
   const double *tab;
+  void *flux;                   // null, or 9 arrays of ncell (band-major, then x, y, z)
+  int64_t ncell;
+  double kPE, kLW;              // 4 pi J^D_PE, 4 pi J^D_LW: chi additions to energy fluxes
 };
 
 // Gather every other bit (bits 0, 2, 4, ...) of a 32-bit word into the low half.
@@ -130,12 +139,12 @@ __device__ __forceinline__ void absorb(double y, double &g, double &e) {
 // Deposits of one step of a wave's packets.  Neighbouring lanes walk neighbouring directions,
 // so several of them often add into the same cell in the same step; global atomics to one
 // address serialise in the L2, so the lanes first pick one leader per distinct cell (a loop
-// over the distinct cells of the step, uniform over the wave), add their five values into the
-// leader's slot in LDS, and the leaders alone update the fields.
+// over the distinct cells of the step, uniform over the wave), add their NV values into the
+// leader's slot in LDS, and the leaders alone update the fields f[0 .. NV-1] at the cell.
 // Cell indices are below 2^31 (checked on the host), so a key is one 32-bit word, read from
 // the first pending lane with a scalar readlane.
-template <class R>
-__device__ __forceinline__ void wave_deposit(const ArtArgs &a, R *slot, bool dep, int32_t vi, const double v[5]) {
+template <class R, int NV>
+__device__ __forceinline__ void wave_deposit(R *const f[NV], R *slot, bool dep, int32_t vi, const double v[NV]) {
   const int lane = threadIdx.x & 63;
   uint64_t pend = __ballot(dep);
   if (!pend) return;
@@ -149,39 +158,49 @@ __device__ __forceinline__ void wave_deposit(const ArtArgs &a, R *slot, bool dep
     if (same) leader = first;
     pend &= ~__ballot(same);
   }
-  R *mine = slot + 5 * lane;
+  R *mine = slot + NV * lane;
   if (dep && leader == lane)
 #pragma unroll
-    for (int k = 0; k < 5; ++k) mine[k] = R(0);
+    for (int k = 0; k < NV; ++k) mine[k] = R(0);
   __builtin_amdgcn_wave_barrier();
   if (dep) {
-    R *dst = slot + 5 * leader;
+    R *dst = slot + NV * leader;
 #pragma unroll
-    for (int k = 0; k < 5; ++k) atomicAdd(dst + k, (R)v[k]);
+    for (int k = 0; k < NV; ++k) atomicAdd(dst + k, (R)v[k]);
   }
   __builtin_amdgcn_wave_barrier();
   if (dep && leader == lane) {
-    R *f[5] = {(R *)a.chiPE, (R *)a.chiLW, (R *)a.chiH2, (R *)a.chiC, (R *)a.phi};
-    R t[5];
+    R t[NV];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) t[k] = mine[k];
+    for (int k = 0; k < NV; ++k) t[k] = mine[k];
 #pragma unroll
-    for (int k = 0; k < 5; ++k)
+    for (int k = 0; k < NV; ++k)
       if (t[k] != R(0)) atomicAdd(f[k] + vi, t[k]);
   }
 }
 
-template <class R>
+template <class R, bool FLUX>
 __global__ __launch_bounds__(256) void art_level_kernel(ArtArgs a) {
+  constexpr int NV = FLUX ? 14 : 5;
   __shared__ double s_cs[CS_NX * CS_NY];
-  __shared__ R s_slot[256 * 5];         // per lane: its cell's five sums while it leads
+  __shared__ R s_slot[256 * NV];        // per lane: its cell's NV sums while it leads
   extern __shared__ double s_budget[];  // [nsrc][6] when a.budget is set
   load_cs(a.tab, s_cs);
   if (a.budget) {
     for (int k = threadIdx.x; k < 6 * a.nsrc; k += blockDim.x) s_budget[k] = 0.0;
     __syncthreads();
   }
-  R *slot = s_slot + 5 * 64 * (threadIdx.x >> 6);
+  R *slot = s_slot + NV * 64 * (threadIdx.x >> 6);
+  R *fields[NV];
+  fields[0] = (R *)a.chiPE;
+  fields[1] = (R *)a.chiLW;
+  fields[2] = (R *)a.chiH2;
+  fields[3] = (R *)a.chiC;
+  fields[4] = (R *)a.phi;
+  if constexpr (FLUX) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) fields[5 + k] = (R *)a.flux + (int64_t)k * a.ncell;
+  }
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = id < a.nin;
   const int level = a.level;
@@ -242,7 +261,7 @@ __global__ __launch_bounds__(256) void art_level_kernel(ArtArgs a) {
   while (__ballot(active)) {
     bool dep = false;
     int32_t vi = 0;
-    double v[5];
+    double v[NV];
     if (active) {
       if (++it > max_steps) {
         active = false;
@@ -277,6 +296,14 @@ __global__ __launch_bounds__(256) void art_level_kernel(ArtArgs a) {
             v[2] = wLW * f_shld_H2<R>(mH2);
             v[3] = wLW * f_shld_C<R>(mC, mH2, s_cs);
             v[4] = Lq * eL * ds * gL * a.phi_norm;
+            if constexpr (FLUX) {
+#pragma unroll
+              for (int q2 = 0; q2 < 3; ++q2) {
+                v[5 + q2] = a.kPE * v[0] * u[q2];
+                v[8 + q2] = a.kLW * v[1] * u[q2];
+                v[11 + q2] = v[4] * u[q2];
+              }
+            }
             dep = true;
             NH += nn * ds;
             NH2 += nn * x2 * ds;
@@ -297,7 +324,7 @@ __global__ __launch_bounds__(256) void art_level_kernel(ArtArgs a) {
         }
       }
     }
-    wave_deposit<R>(a, slot, dep, vi, v);
+    wave_deposit<R, NV>(fields, slot, dep, vi, v);
   }
   if (live && a.budget && !split) {
     // the packet ends here: lost through the boundary or dropped at tau > tau_max
@@ -333,6 +360,77 @@ __global__ __launch_bounds__(256) void art_level_kernel(ArtArgs a) {
     __syncthreads();
     for (int k = threadIdx.x; k < 6 * a.nsrc; k += blockDim.x)
       if (s_budget[k] != 0.0) atomicAdd(&a.budget[k], s_budget[k]);
+  }
+}
+
+// Radiation force per volume on the gas-dust mixture (Sec. 5.4): sum over bands of
+// alpha_j F_j / c with the trace's opacities (PE, LW: dust; LyC: dust, H and H2) and h nu_LyC
+// per LyC photon.  Grains count as destroyed (appendix on grain destruction) where T exceeds
+// T_destroy or P_rad = |F| / c exceeds prad_ratio_max times P = 2 n k_B T, F the total flux of
+// the three bands; there the dust part is dropped and only LyC photoionisation pushes.  With
+// mom the momentum density takes f dt, and with etot the total energy the change of
+// rho v^2 / 2 at rho = mu_H m_H n.  All arithmetic in double; one thread per cell.
+struct ForceArgs {
+  int64_t ncell;
+  const double *n, *T, *xH2, *xHp;
+  const void *flux;   // 9 x ncell, the path's precision
+  void *f;            // 3 x ncell, the path's precision
+  uint8_t *dust_off;  // or null
+  double *mom, *etot; // or null
+  double dt;
+  double T_destroy, prad_ratio_max;
+  double sPE, sLW, sdLyC, spiH, spiH2;  // dust cross sections x Z'_d; photoionisation
+  double hnu, inv_c, two_kB, rho_per_n;
+};
+
+template <class R>
+__global__ __launch_bounds__(256) void radiation_force_kernel(ForceArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.ncell) return;
+  const R *F = (const R *)a.flux;
+  const int64_t N = a.ncell;
+  double Fb[3][3];
+#pragma unroll
+  for (int b = 0; b < 3; ++b)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) Fb[b][q] = (double)F[(3 * b + q) * N + i];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) Fb[2][q] *= a.hnu;
+  const double nn = a.n[i], T = a.T[i], x2 = a.xH2[i], xp = a.xHp[i];
+  double F2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const double t = Fb[0][q] + Fb[1][q] + Fb[2][q];
+    F2 += t * t;
+  }
+  const double prad = sqrt(F2) * a.inv_c;
+  const bool off = T > a.T_destroy || prad > a.prad_ratio_max * (a.two_kB * nn * T);
+  const double keep = off ? 0.0 : 1.0;
+  const double xHI = fmax(1.0 - 2.0 * x2 - xp, 0.0);
+  const double agas = nn * (xHI * a.spiH + x2 * a.spiH2);
+  double f[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+    f[q] = (keep * nn * (a.sPE * Fb[0][q] + a.sLW * Fb[1][q] + a.sdLyC * Fb[2][q]) + agas * Fb[2][q]) * a.inv_c;
+  R *fo = (R *)a.f;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) fo[q * N + i] = (R)f[q];
+  if (a.dust_off) a.dust_off[i] = off ? 1 : 0;
+  if (a.mom) {
+    double p0[3], p1[3], d2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      p0[q] = a.mom[q * N + i];
+      p1[q] = p0[q] + f[q] * a.dt;
+      a.mom[q * N + i] = p1[q];
+    }
+    if (a.etot) {
+      const double rho = a.rho_per_n * nn;
+      if (rho > 0.0) {
+        d2 = (p1[0] * p1[0] + p1[1] * p1[1] + p1[2] * p1[2]) - (p0[0] * p0[0] + p0[1] * p0[1] + p0[2] * p0[2]);
+        a.etot[i] += d2 / (2.0 * rho);
+      }
+    }
   }
 }
 

@@ -100,8 +100,11 @@ def lib():
                                         ctypes.c_void_p] + [_vp] * 8 + [_vp]
         L.ism_point_sources.restype = ctypes.c_int
         L.ism_ray_trace.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Params), ctypes.c_int, _i32,
-                                    ctypes.c_void_p, ctypes.c_void_p] + [_vp] * 10 + [_vp]
+                                    ctypes.c_void_p, ctypes.c_void_p] + [_vp] * 11 + [_vp]
         L.ism_ray_trace.restype = ctypes.c_int
+        L.ism_radiation_force.argtypes = [ctypes.POINTER(_Params), ctypes.c_int, _i64] + [_vp] * 8 + \
+            [_dp, _vp, _vp, _vp]
+        L.ism_radiation_force.restype = ctypes.c_int
         L.ism_surrogate_pairs.argtypes = [ctypes.POINTER(_Params), ctypes.c_int, _i64, _dp] + [_vp] * 14
         L.ism_chem_cool_step_surrogate.argtypes = [_vp, ctypes.POINTER(_Params), _i64, _dp] + [_vp] * 16 + \
             [_dp, _vp, _vp]
@@ -120,7 +123,8 @@ SURROGATE_SYMBOLS = ("ism_surrogate_create", "ism_surrogate_destroy", "ism_surro
 def exported_symbols():
     return ["ism_params_default", "ism_init", "ism_shutdown", "ism_last_error", "ism_ndiag", "ism_diag_name",
             "ism_columns6", "ism_rates", "ism_chem_cool_step", "ism_point_sources",
-            "ism_ray_trace", "ism_local_shielding", "ism_columns_beam"] + list(SURROGATE_SYMBOLS)
+            "ism_ray_trace", "ism_radiation_force", "ism_local_shielding", "ism_columns_beam"] + \
+        list(SURROGATE_SYMBOLS)
 
 
 def _check(rc):
@@ -227,6 +231,10 @@ def point_sources(n, xH2, xC, dx_cm, params, prec, sources, out, stream=None):
     return out
 
 
+class _ForceOptions(ctypes.Structure):
+    _fields_ = [("T_destroy_K", ctypes.c_double), ("prad_ratio_max", ctypes.c_double)]
+
+
 class _ArtOptions(ctypes.Structure):
     _fields_ = [("level0", ctypes.c_int32), ("max_level", ctypes.c_int32), ("rays_per_cell", ctypes.c_double),
                 ("tau_max", ctypes.c_double)]
@@ -235,7 +243,8 @@ class _ArtOptions(ctypes.Structure):
 def ray_trace(n, xH2, xHp, xC, dx_cm, params, prec, sources, out, level0=4, max_level=13, rays_per_cell=4.0,
               tau_max=30.0, budget=False, stream=None):
     """ism_ray_trace: add the sources' radiation, by adaptive ray tracing, to out's chi_PE,
-    chi_LW, chi_H2, chi_C and phi.
+    chi_LW, chi_H2, chi_C and phi (and to out["flux"], [9, nz, ny, nx] of the path's dtype,
+    when out holds one).
 
     n, xH2, xHp (and xC or None): float64 device tensors shaped [nz, ny, nx]; sources: rows of
     (x_cm, y_cm, z_cm, Q, L_FUV); out: dict of device tensors of the path's dtype.  With
@@ -259,8 +268,34 @@ def ray_trace(n, xH2, xHp, xC, dx_cm, params, prec, sources, out, level0=4, max_
         _ptr(n, torch.float64, N, "n"), _ptr(xH2, torch.float64, N, "xH2"), _ptr(xHp, torch.float64, N, "xHp"),
         _ptr(xC, torch.float64, N, "xC", allow_none=True),
         *[_ptr(out[k], rd, N, k) for k in ("chi_PE", "chi_LW", "chi_H2", "chi_C", "phi")],
+        _ptr(out.get("flux"), rd, 9 * N, "flux", allow_none=True),
         None if bud is None else ctypes.c_void_p(bud.data_ptr()), _stream(stream)))
     return out
+
+
+def radiation_force(n, T, xH2, xHp, flux, params, prec, f_rad=None, dust_off=None, dt_s=0.0, mom=None, etot=None,
+                    T_destroy=1.0e6, prad_ratio_max=50.0, stream=None):
+    """ism_radiation_force: the force per volume of the traced radiation on the gas-dust mixture,
+    with the grain-destruction switch, and optionally the momentum / energy source update.
+
+    n, T, xH2, xHp: float64 device tensors of N cells; flux: [9, ...] of the path's dtype as
+    ray_trace writes it.  Returns f_rad ([3, ...] of the path's dtype; allocated when None);
+    dust_off (uint8, N) and mom ([3, ...] float64) / etot (float64) are updated in place."""
+    _ensure_init(n)
+    N = n.numel()
+    rd = _rdt(prec)
+    if f_rad is None:
+        f_rad = torch.empty((3,) + tuple(n.shape), dtype=rd, device=n.device)
+    opt = _ForceOptions(float(T_destroy), float(prad_ratio_max))
+    p = params._c()
+    _check(lib().ism_radiation_force(
+        ctypes.byref(p), prec, N, _ptr(n, torch.float64, N, "n"), _ptr(T, torch.float64, N, "T"),
+        _ptr(xH2, torch.float64, N, "xH2"), _ptr(xHp, torch.float64, N, "xHp"), _ptr(flux, rd, 9 * N, "flux"),
+        ctypes.cast(ctypes.pointer(opt), ctypes.c_void_p), _ptr(f_rad, rd, 3 * N, "f_rad"),
+        _ptr(dust_off, torch.uint8, N, "dust_off", allow_none=True), float(dt_s),
+        _ptr(mom, torch.float64, 3 * N, "mom", allow_none=True), _ptr(etot, torch.float64, N, "etot", allow_none=True),
+        _stream(stream)))
+    return f_rad
 
 
 def ndiag():

@@ -130,7 +130,7 @@ def test_ray_trace_rejects_bad_options_before_launch():
     def call(opt, nsrc=1, arrays=None):
         o = None if opt is None else ctypes.cast(ctypes.pointer(ism._ArtOptions(*opt)), ctypes.c_void_p)
         rc = L.ism_ray_trace(ctypes.byref(g), ctypes.byref(cp), 0, nsrc, ctypes.cast(src, ctypes.c_void_p), o,
-                             *(arrays or [None] * 10), None)
+                             *(arrays or [None] * 11), None)
         return rc, L.ism_last_error().decode()
 
     assert ctypes.sizeof(ism._ArtOptions) == 24
@@ -145,3 +145,28 @@ def test_ray_trace_rejects_bad_options_before_launch():
     assert rc == -1 and "NULL" in err
     # no sources: a no-op that succeeds without touching the device
     assert call(None, nsrc=0)[0] == 0
+
+
+def test_radiation_force_rejects_bad_arguments_before_launch():
+    cp = ism.Params()._c()
+    L = ism.lib()
+    fake = ctypes.c_void_p(4096)  # never dereferenced: every case fails in the host checks
+
+    def call(opt, ncell=8, arrays=None, dt=0.0, mom=None, etot=None):
+        o = None if opt is None else ctypes.cast(ctypes.pointer(ism._ForceOptions(*opt)), ctypes.c_void_p)
+        arr = arrays if arrays is not None else [fake] * 5
+        rc = L.ism_radiation_force(ctypes.byref(cp), 0, ncell, *arr[:5], o, fake, None, dt, mom, etot, None)
+        return rc, L.ism_last_error().decode()
+
+    assert ctypes.sizeof(ism._ForceOptions) == 16
+    for opt, msg in (((0.0, 50.0), "T_destroy"), ((float("nan"), 50.0), "T_destroy"),
+                     ((1e6, -1.0), "prad_ratio_max"), ((1e6, float("nan")), "prad_ratio_max")):
+        rc, err = call(opt)
+        assert rc == -1 and msg in err, (opt, err)
+    assert "dt_s" in call(None, dt=-1.0)[1]
+    assert "dt_s" in call(None, dt=float("inf"))[1]
+    assert "etot needs mom" in call(None, etot=fake)[1]
+    assert "ncell" in call(None, ncell=-1)[1]
+    assert "ncell" in call(None, ncell=1 << 33)[1]
+    assert "NULL" in call(None, arrays=[fake, None, fake, fake, fake])[1]
+    assert call(None, ncell=0)[0] == 0

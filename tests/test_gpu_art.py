@@ -8,7 +8,18 @@ source at a cell centre or corner, a direction at 45 degrees) leaves a piece of 
 (1e-16 of a cell) on one side of the edge or the other depending on the last bit of its
 direction, worth about 1e-16 of the field's maximum, which matters only in cells that no ray
 really crosses.  The escaped / dropped budgets are accumulated in double
-in both paths: 1e-9."""
+in both paths: 1e-9.
+
+Flux vectors (Eq. e:Frad) are compared as vectors, |F_gpu - F_oracle| against the same bars
+relative to max(|F|, 1e-2 c E, 1e-6 of the band's largest c E), c E = 4 pi J^D chi (phi for
+LyC) in the cell: where rays cross a cell in opposite directions (a source's own cell) the
+flux cancels far below c E, while the rounding of its sum scales with c E.  The radiation
+force (ism_radiation_force) computes in double on both paths from its inputs: on shared
+synthetic inputs 1e-12 (F64) and the float rounding of its output, 1e-6 (MIXED, whose flux
+input is float; the oracle gets the same float-rounded flux so that both take the
+grain-destruction decision on the same numbers); end to end it inherits the flux bars, and
+cells whose pressure ratio lies within the flux tolerance of the threshold are left out of
+the comparison of the switch."""
 import numpy as np
 import pytest
 
@@ -122,6 +133,121 @@ def test_ray_trace_edge_cases(ism):
             ism.ray_trace(dev(n), dev(xH2), dev(xHp), None, DX, ip, 0, args, out, **kw)
 
 
+def _cE(out):
+    """c E per band from a result dict (device tensors or oracle arrays), as float64 numpy."""
+    g = lambda k: np.asarray(out[k].cpu().numpy() if hasattr(out[k], "cpu") else out[k], dtype=np.float64)
+    return np.stack([4 * np.pi * OC.J_PE * g("chi_PE"), 4 * np.pi * OC.J_LW * g("chi_LW"), g("phi")])
+
+
+def _compare_flux(got_flux, ref_flux, cE_ref, prec, label):
+    tol = 1e-9 if prec == 0 else 1e-4
+    G = np.asarray(got_flux, dtype=np.float64).reshape(3, 3, -1)
+    Rf = np.asarray(ref_flux, dtype=np.float64).reshape(3, 3, -1)
+    cE = cE_ref.reshape(3, -1)
+    for b in range(3):
+        d = np.sqrt(np.sum((G[b] - Rf[b]) ** 2, 0))
+        mag = np.sqrt(np.sum(Rf[b] ** 2, 0))
+        den = np.maximum(np.maximum(mag, 1e-2 * cE[b]), 1e-6 * cE[b].max() + 1e-300)
+        err = d / den
+        assert err.max() < tol, (label, "band", b, err.max())
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("kw", [dict(), dict(level0=1, tau_max=3.0, max_level=4)], ids=["default", "deep-split"])
+def test_ray_trace_flux_matches_oracle_full_grid(ism, prec, kw):
+    import torch
+    par = Params(Zd=1.3)
+    shape = (10, 11, 12)
+    n, xH2, xHp, xC = _medium(shape, 1)
+    print(f"ray_trace flux full grid prec={prec} {kw}", flush=True)
+    ref = art.ray_trace(n, xH2, xHp, xC, DX, SRC, par, flux=True, **kw)
+    rd = torch.float64 if prec == 0 else torch.float32
+    out = _zeros(torch, shape, rd)
+    out["flux"] = torch.zeros((9,) + shape, dtype=rd, device="cuda")
+    dev = lambda a: H.to_dev(a).view(shape)
+    ism.ray_trace(dev(n), dev(xH2), dev(xHp), dev(xC), DX, H.ism_params_from(par), prec, SRC, out, budget=True, **kw)
+    _compare(out, ref, prec, f"flux run prec {prec} {kw}")
+    _compare_flux(out["flux"].cpu().numpy(), ref["flux"], _cE(ref), prec, f"flux prec {prec} {kw}")
+    # the radiation force of the traced field, end to end, with a temperature field that
+    # puts some cells above 1e6 K
+    rng = np.random.default_rng(9)
+    T = 10 ** rng.uniform(1, 7, shape)
+    fo = art.radiation_force(n, T, xH2, xHp, ref["flux"], par)
+    dust_off = torch.zeros(shape, dtype=torch.uint8, device="cuda")
+    f = ism.radiation_force(dev(n), dev(T), dev(xH2), dev(xHp), out["flux"], H.ism_params_from(par), prec,
+                            dust_off=dust_off)
+    F = ref["flux"].reshape(3, 3, -1)
+    Ftot = F[0] + F[1] + OC.HNU_LYC * F[2]
+    ratio = np.sqrt(np.sum(Ftot ** 2, 0)) / OC.C_LIGHT / (2 * n.ravel() * OC.K_B * T.ravel())
+    tol = 1e-9 if prec == 0 else 1e-4
+    clear = np.abs(ratio / art.PRAD_RATIO_MAX - 1) > 10 * tol
+    assert 0 < fo["dust_off"].sum() < n.size
+    np.testing.assert_array_equal(dust_off.cpu().numpy().ravel()[clear], fo["dust_off"].ravel()[clear])
+    # the force is the flux weighted by opacities: its error bar is the flux's, scaled by the
+    # largest opacity-weighted c E in the cell
+    xHI = 1 - 2 * xH2 - xHp
+    aL = n * (xHI * OC.SIGMA_PI_H + xH2 * OC.SIGMA_PI_H2 + par.Zd * OC.SIG_D_LYC)
+    cE = _cE(ref)
+    wE = (OC.SIG_D_PE * par.Zd * n * cE[0] + OC.SIG_D_LW * par.Zd * n * cE[1]
+          + aL * OC.HNU_LYC * cE[2]).ravel() / OC.C_LIGHT
+    g = f.cpu().numpy().astype(np.float64).reshape(3, -1)[:, clear]
+    r = fo["f"].reshape(3, -1)[:, clear]
+    d = np.sqrt(np.sum((g - r) ** 2, 0))
+    den = np.maximum(np.maximum(np.sqrt(np.sum(r ** 2, 0)), 1e-2 * wE[clear]), 1e-6 * wE.max() + 1e-300)
+    assert (d / den).max() < tol, (d / den).max()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_radiation_force_matches_oracle_on_synthetic_flux(ism, prec):
+    """The force kernel alone on seeded synthetic inputs shared by both sides: fluxes whose
+    pressure ratio spans the destruction threshold, temperatures across 1e6 K, the momentum
+    and energy update, and the degenerate cells n = 0, flux = 0 and full ionisation."""
+    import torch
+    rng = np.random.default_rng(31 + prec)
+    N = 4099
+    n = 10 ** rng.uniform(-3, 4, N)
+    T = 10 ** rng.uniform(1, 7.5, N)
+    xH2 = 0.5 * rng.uniform(0, 1, N)
+    xHp = rng.uniform(0, 1, N) * (1 - 2 * xH2)
+    n[:5] = 0.0
+    xH2[5:10], xHp[5:10] = 0.0, 1.0
+    dirs = rng.normal(size=(3, 3, N))
+    P = 2 * n * OC.K_B * T
+    mag = 50 * np.maximum(P, 1e-20) * OC.C_LIGHT * 10 ** rng.uniform(-2, 1, (3, N))
+    mag[2] /= OC.HNU_LYC
+    flux = dirs * (mag / np.sqrt(np.sum(dirs ** 2, 1)))[:, None, :]
+    flux[:, :, 10:15] = 0.0
+    flux = flux.reshape(9, N)
+    if prec == 1:
+        flux = flux.astype(np.float32).astype(np.float64)
+    mom = rng.normal(size=(3, N)) * 1e-20
+    etot = 10 ** rng.uniform(-14, -8, N)
+    dt = 3.15576e11
+    par = Params(Zd=0.7, Zg=0.5)
+    ref = art.radiation_force(n, T, xH2, xHp, flux, par, dt=dt, mom=mom, etot=etot)
+    rd = torch.float64 if prec == 0 else torch.float32
+    dev = H.to_dev
+    dust_off = torch.zeros(N, dtype=torch.uint8, device="cuda")
+    mom_d = torch.from_numpy(mom.copy()).cuda()
+    etot_d = torch.from_numpy(etot.copy()).cuda()
+    fl = torch.from_numpy(flux).to(rd).cuda()
+    print(f"radiation_force synthetic prec={prec}", flush=True)
+    f = ism.radiation_force(dev(n), dev(T), dev(xH2), dev(xHp), fl, H.ism_params_from(par), prec,
+                            dust_off=dust_off, dt_s=dt, mom=mom_d, etot=etot_d)
+    off = ref["dust_off"]
+    assert 0.1 < off.mean() < 0.9
+    np.testing.assert_array_equal(dust_off.cpu().numpy().astype(bool), off)
+    tol = 1e-12 if prec == 0 else 1e-6
+    g = f.cpu().numpy().astype(np.float64)
+    d = np.sqrt(np.sum((g - ref["f"]) ** 2, 0))
+    mag_r = np.sqrt(np.sum(ref["f"] ** 2, 0))
+    assert np.all(d <= tol * mag_r + 1e-300), (d / np.maximum(mag_r, 1e-300)).max()
+    assert np.all(g[:, :5] == 0) and np.all(g[:, 10:15] == 0)
+    # the update is made from the output force on the GPU and from the oracle's on the CPU
+    np.testing.assert_allclose(mom_d.cpu().numpy(), ref["mom"], rtol=tol, atol=1e-300)
+    np.testing.assert_allclose(etot_d.cpu().numpy(), ref["etot"], rtol=1e-12 if prec == 0 else 1e-5, atol=0)
+
+
 @pytest.fixture(scope="module")
 def c2():
     from paper_2210_08024_amd import workloads
@@ -143,7 +269,8 @@ def test_ray_trace_c2_sampled_and_conservation(ism, c2, prec):
     xH2, xHp = H.to_dev(s["xH2"]).view(shape), H.to_dev(s["xHp"]).view(shape)
     rd = torch.float64 if prec == 0 else torch.float32
     out = _zeros(torch, shape, rd)
-    print(f"ray_trace c2 prec={prec}", flush=True)
+    out["flux"] = torch.zeros((9,) + shape, dtype=rd, device="cuda")
+    print(f"ray_trace c2 prec={prec} (with flux)", flush=True)
     ism.ray_trace(n, xH2, xHp, None, dx, H.ism_params_from(par), prec, cfg["sources"], out, budget=True)
     torch.cuda.synchronize()
     # conservation (reductions on the device in float64)
@@ -167,6 +294,8 @@ def test_ray_trace_c2_sampled_and_conservation(ism, c2, prec):
     idx = rng.choice(N, 16, replace=False)
     own = [(int(z // dx), int(y // dx), int(x // dx)) for x, y, z in src[:6, :3]]
     cells = np.concatenate([np.stack(np.unravel_index(idx, shape), 1), np.array(own)])
-    ref = art.ray_trace_cells(s["n"], s["xH2"], s["xHp"], None, dx, src, par, cells)
+    ref = art.ray_trace_cells(s["n"], s["xH2"], s["xHp"], None, dx, src, par, cells, flux=True)
     got = {k: out[k][cells[:, 0], cells[:, 1], cells[:, 2]] for k in KEYS}
     _compare(got, ref, prec, f"c2 prec {prec}")
+    gf = out["flux"][:, cells[:, 0], cells[:, 1], cells[:, 2]].cpu().numpy()
+    _compare_flux(gf, ref["flux"], _cE(ref), prec, f"c2 flux prec {prec}")
