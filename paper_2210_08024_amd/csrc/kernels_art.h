@@ -136,43 +136,99 @@ __device__ __forceinline__ void absorb(double y, double &g, double &e) {
   }
 }
 
+// Per-lane LDS stride of the combine, in elements of R: a multiple of 16 bytes such that the
+// eight lanes served by one pass of a 128-bit LDS access fall in distinct banks.
+template <class R, int NV> struct SlotStride;
+template <> struct SlotStride<float, 5> { static constexpr int v = 12; };
+template <> struct SlotStride<float, 14> { static constexpr int v = 20; };
+template <> struct SlotStride<double, 5> { static constexpr int v = 6; };
+template <> struct SlotStride<double, 14> { static constexpr int v = 14; };
+template <class R> struct Vec16;
+template <> struct Vec16<float> { using T = float4; static constexpr int n = 4; };
+template <> struct Vec16<double> { using T = double2; static constexpr int n = 2; };
+
+// Lanes of one wave exchange values through LDS below.  The LDS executes a wave's
+// instructions in order, so only the compiler has to be kept from moving or forwarding memory
+// accesses across an exchange point: an empty asm statement that clobbers memory.
+__device__ __forceinline__ void lane_exchange() {
+  __builtin_amdgcn_wave_barrier();
+  __asm__ __volatile__("" ::: "memory");
+}
+
+// Entries per wave of the leader table (a power of two); hash of a cell index into it.
+constexpr int ART_HTAB = 256;
+__device__ __forceinline__ uint32_t cell_hash(int32_t vi) { return ((uint32_t)vi * 2654435761u) >> 24; }
+
 // Deposits of one step of a wave's packets.  Neighbouring lanes walk neighbouring directions,
 // so several of them often add into the same cell in the same step; global atomics to one
-// address serialise in the L2, so the lanes first pick one leader per distinct cell (a loop
-// over the distinct cells of the step, uniform over the wave), add their NV values into the
-// leader's slot in LDS, and the leaders alone update the fields f[0 .. NV-1] at the cell.
-// Cell indices are below 2^31 (checked on the host), so a key is one 32-bit word, read from
-// the first pending lane with a scalar readlane.
+// address serialise, so the lanes of a cell first agree on one leader: each depositing lane
+// writes its lane number at its cell's hash in the wave's table, and the number left there
+// leads every lane of that cell; cells that lost their entry to another cell pick leaders in
+// a loop over their distinct cells.  Where no two lanes share a cell each lane deposits its
+// own values; otherwise each leader stores its NV values in its LDS slot, the other lanes of
+// its cell add theirs there, and the leaders alone update the fields f[0 .. NV-1] at the cell.
+// Cell indices are below 2^31 (checked on the host), so a key is one 32-bit word.
 template <class R, int NV>
-__device__ __forceinline__ void wave_deposit(R *const f[NV], R *slot, bool dep, int32_t vi, const double v[NV]) {
+__device__ __forceinline__ void wave_deposit(R *const f[NV], R *slot, int *htab, bool dep, int32_t vi,
+                                             const double v[NV]) {
   const int lane = threadIdx.x & 63;
-  uint64_t pend = __ballot(dep);
-  if (!pend) return;
-  int leader = 0;
+  if (!__ballot(dep)) return;
+  const uint32_t h = cell_hash(vi);
+  if (dep) htab[h] = lane;
+  lane_exchange();
+  int leader = dep ? htab[h] : lane;
+  lane_exchange();
+  const int32_t wkey = __shfl(vi, leader);
+  uint64_t pend = __ballot(dep && wkey != vi);
   while (pend) {
-    // the first pending lane's cell; every lane of that cell takes it as leader (lanes of
-    // earlier cells hold other keys, lanes without a deposit are not pending)
     const int first = __builtin_ctzll(pend);
     const int32_t key = __builtin_amdgcn_readlane(vi, first);
-    const bool same = vi == key;
+    const bool same = dep && vi == key;
     if (same) leader = first;
     pend &= ~__ballot(same);
   }
-  R *mine = slot + NV * lane;
-  if (dep && leader == lane)
+  R t[NV];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) mine[k] = R(0);
-  __builtin_amdgcn_wave_barrier();
-  if (dep) {
-    R *dst = slot + NV * leader;
+  for (int k = 0; k < NV; ++k) t[k] = (R)v[k];
+  const bool lead = dep && leader == lane;
+  const bool follow = dep && leader != lane;
+  if (__ballot(follow)) {
+    using V = typename Vec16<R>::T;
+    constexpr int W = Vec16<R>::n, NW = (NV + W - 1) / W, S = SlotStride<R, NV>::v;
+    static_assert(S >= NW * W && (S * sizeof(R)) % 16 == 0, "slot stride");
+    V *mine = reinterpret_cast<V *>(slot + S * lane);
+    if (lead) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) atomicAdd(dst + k, (R)v[k]);
+      for (int w = 0; w < NW; ++w) {
+        R q[W];
+#pragma unroll
+        for (int e = 0; e < W; ++e) q[e] = W * w + e < NV ? t[W * w + e] : R(0);
+        V x;
+        __builtin_memcpy(&x, q, sizeof(V));
+        mine[w] = x;
+      }
+    }
+    lane_exchange();
+    if (follow) {
+      R *dst = slot + S * leader;
+#pragma unroll
+      for (int k = 0; k < NV; ++k) atomicAdd(dst + k, t[k]);
+    }
+    lane_exchange();
+    if (lead) {
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        const V x = mine[w];
+        R q[W];
+        __builtin_memcpy(q, &x, sizeof(V));
+#pragma unroll
+        for (int e = 0; e < W; ++e)
+          if (W * w + e < NV) t[W * w + e] = q[e];
+      }
+    }
+    lane_exchange();
   }
-  __builtin_amdgcn_wave_barrier();
-  if (dep && leader == lane) {
-    R t[NV];
-#pragma unroll
-    for (int k = 0; k < NV; ++k) t[k] = mine[k];
+  if (lead) {
 #pragma unroll
     for (int k = 0; k < NV; ++k)
       if (t[k] != R(0)) atomicAdd(f[k] + vi, t[k]);
@@ -182,15 +238,18 @@ __device__ __forceinline__ void wave_deposit(R *const f[NV], R *slot, bool dep, 
 template <class R, bool FLUX>
 __global__ __launch_bounds__(256) void art_level_kernel(ArtArgs a) {
   constexpr int NV = FLUX ? 14 : 5;
+  constexpr int SS = SlotStride<R, NV>::v;
   __shared__ double s_cs[CS_NX * CS_NY];
-  __shared__ R s_slot[256 * NV];        // per lane: its cell's NV sums while it leads
+  __shared__ __align__(16) R s_slot[256 * SS];  // per lane: its cell's NV sums while it leads
+  __shared__ int s_htab[4 * ART_HTAB];          // per wave: the leader table
   extern __shared__ double s_budget[];  // [nsrc][6] when a.budget is set
   load_cs(a.tab, s_cs);
   if (a.budget) {
     for (int k = threadIdx.x; k < 6 * a.nsrc; k += blockDim.x) s_budget[k] = 0.0;
     __syncthreads();
   }
-  R *slot = s_slot + NV * 64 * (threadIdx.x >> 6);
+  R *slot = s_slot + SS * 64 * (threadIdx.x >> 6);
+  int *htab = s_htab + ART_HTAB * (threadIdx.x >> 6);
   R *fields[NV];
   fields[0] = (R *)a.chiPE;
   fields[1] = (R *)a.chiLW;
@@ -324,7 +383,7 @@ __global__ __launch_bounds__(256) void art_level_kernel(ArtArgs a) {
         }
       }
     }
-    wave_deposit<R, NV>(fields, slot, dep, vi, v);
+    wave_deposit<R, NV>(fields, slot, htab, dep, vi, v);
   }
   if (live && a.budget && !split) {
     // the packet ends here: lost through the boundary or dropped at tau > tau_max
