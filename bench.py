@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--maps", choices=("lc", "art"), default="lc",
                     help="c2 point-source maps: lc straight-line 1/r^2 exp(-tau) with the Stromgren cap (the "
                          "configuration's recipe), art adaptive ray tracing (Sec. 5.1)")
+    ap.add_argument("--c2-order", choices=("previous", "temperature"), default="previous",
+                    help="c2 processing order of steps 2-10: by the previous step's substep counts (order_cells 2) "
+                         "or by temperature (order_cells 1); the first step is always by temperature")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and the error report")
     ap.add_argument("--cpu-cells", type=int, default=65536)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -174,6 +177,8 @@ def bench_c2(args):
     torch.cuda.set_device(dev)
     ism.init(0)
     par = ism.Params(Zg=1.0, Zd=1.0, cr_mode=2)
+    # steps after the first: cells grouped by the previous step's substep counts (in outs["nsub"])
+    par_next = ism.Params(Zg=1.0, Zd=1.0, cr_mode=2, order_cells=2 if args.c2_order == "previous" else 1)
     dx = cfg["dx_pc"] * workloads.PC
     dt = cfg["dt_yr"] * workloads.YR
     stream = torch.cuda.current_stream()
@@ -219,7 +224,7 @@ def bench_c2(args):
             r = dict(rad)
             r["phi"] = maps["phi"]
             ev[3].record(stream)
-            ism.chem_cool_step(init["n"], T, xH2, xHp, r, dt, par, ism.MIXED, out=outs)
+            ism.chem_cool_step(init["n"], T, xH2, xHp, r, dt, par if step == 0 else par_next, ism.MIXED, out=outs)
             ev[0].record(stream)
             torch.sub(xCt, outs["xCp"].double() + outs["xCO"].double(), out=xC).clamp_(min=0.0)
             if record:
@@ -265,7 +270,9 @@ def bench_c2(args):
         "config": {"workload": "c2: 256^3 lognormal GRF (2 pc cells, 512 pc box), 16 point sources (Q 1.24e50 s^-1, "
                                "L_FUV 1.36e6 L_sun; maps once by " + how + "), chi0 = 1 six-ray, xi_cr log-uniform [1e-17, 1e-15], "
                                "Z' = 1, ten successive steps of 1e4 yr", "cells": N, "path": "mixed",
-                   "maps": args.maps, "job": "point-source maps once + ten (columns6 + step)"},
+                   "maps": args.maps, "job": "point-source maps once + ten (columns6 + step)",
+                   "order": "steps 2-10 by the previous step's substep counts" if args.c2_order == "previous"
+                   else "by temperature"},
         "roofline": {"bound": "alu", "kernel": "step_queue_kernel", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
                      "traffic": None, "work": f"{int(np.sum(tot_sub))} substeps over ten steps x ({arith} + {trans})"},

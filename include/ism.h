@@ -82,8 +82,12 @@ typedef struct {
   int32_t h2_rovib;     /* 1: include H2 ro-vibrational cooling                           */
   int32_t max_substeps; /* substep cap per cell (100000)                                   */
   int32_t order_cells;  /* step calls: 1 (default) process cells grouped by temperature so
-                           that the lanes of a wave stay in one regime; 0 in index order.
-                           Results are identical either way.                              */
+                           that the lanes of a wave stay in one regime; 0 in index order;
+                           2 (ism_chem_cool_step with an nsub array) grouped by the
+                           substep counts nsub holds on entry, e.g. the previous step's
+                           of the same cells, longest first (as 1 without nsub; the
+                           surrogate step treats 2 as 1).  Results are identical in
+                           every mode.                                                    */
   int32_t pad_;
 } ism_params;
 

@@ -85,7 +85,7 @@ ism_status current_state(DevState **out, int *dev_out = nullptr) {
 
 ism_status check_params(const ism_params *p) {
   if (!p) return fail(ISM_E_ARG, "params is NULL");
-  if (p->order_cells != 0 && p->order_cells != 1) return fail(ISM_E_ARG, "order_cells must be 0 or 1");
+  if (p->order_cells < 0 || p->order_cells > 2) return fail(ISM_E_ARG, "order_cells must be 0, 1 or 2");
   if (!(p->Zg > 0.0) || !std::isfinite(p->Zg)) return fail(ISM_E_ARG, "Zg must be finite and > 0");
   if (!(p->Zd > 0.0) || !std::isfinite(p->Zd)) return fail(ISM_E_ARG, "Zd must be finite and > 0");
   if (!(p->chi0 >= 0.0) || !std::isfinite(p->chi0)) return fail(ISM_E_ARG, "chi0 must be finite and >= 0");
@@ -148,7 +148,8 @@ ism_status surr_scratch(DevState *st, size_t bytes, void **out) {
 // Order `n` items (cells, or the cells listed in `items`, `*count` of them when count is set)
 // by temperature regime; *out receives the ordered cell list (library scratch).
 ism_status order_cells(DevState *st, int64_t n, const unsigned long long *count, const int32_t *items,
-                       const double *T, const float *pred, int32_t **out, hipStream_t stream) {
+                       const double *T, const float *pred, const int32_t *nsub, int32_t **out,
+                       hipStream_t stream) {
   const size_t key_b = (size_t)((n * 2 + 255) / 256 * 256), bins_b = (size_t)ORDER_BINS * 4;
   const size_t out_b = (size_t)((n * 4 + 255) / 256 * 256);
   const size_t bytes = key_b + 2 * bins_b + out_b;
@@ -165,7 +166,7 @@ ism_status order_cells(DevState *st, int64_t n, const unsigned long long *count,
     }
     base = (uint8_t *)st->oscratch;
   }
-  OrderArgs a{n, count, items, T, pred, (uint16_t *)base, (uint32_t *)(base + key_b),
+  OrderArgs a{n, count, items, T, pred, nsub, (uint16_t *)base, (uint32_t *)(base + key_b),
               (uint32_t *)(base + key_b + bins_b), (int32_t *)(base + key_b + 2 * bins_b)};
   const dim3 grid((unsigned)((n + ORDER_THREADS - 1) / ORDER_THREADS));
   hipLaunchKernelGGL(order_zero_kernel, dim3(1), dim3(ORDER_THREADS), 0, stream, a.hist);
@@ -388,7 +389,9 @@ ism_status ism_chem_cool_step(const ism_params *p, ism_precision prec, int64_t n
   const int64_t want = (ncell + 255) / 256;
   int32_t *order = nullptr;
   if (p->order_cells && !st->simple_step && ncell <= (int64_t)INT32_MAX)
-    if (ism_status s = order_cells(st, ncell, nullptr, nullptr, T, nullptr, &order, stream)) return s;
+    if (ism_status s = order_cells(st, ncell, nullptr, nullptr, T, nullptr, p->order_cells == 2 ? nsub : nullptr,
+                                   &order, stream))
+      return s;
   if (prec == ISM_PREC_F64) {
     StepArgs<double> a{ncell, dt_s, n, T, xH2, xHp, (const double *)chi_PE, (const double *)chi_LW,
                        (const double *)chi_H2, (const double *)chi_C, (const double *)phi_LyC,
@@ -1070,7 +1073,7 @@ ism_status ism_chem_cool_step_surrogate(ism_surrogate *m, const ism_params *p, i
   }
   int32_t *list = rej;
   if (p->order_cells)
-    if (ism_status s = order_cells(st, ncell, nrej, rej, T, pred, &list, stream)) return s;
+    if (ism_status s = order_cells(st, ncell, nrej, rej, T, pred, nullptr, &list, stream)) return s;
   StepArgs<float> sa{ncell, dt_s, n, T, xH2, xHp, (const float *)chi_PE, (const float *)chi_LW,
                      (const float *)chi_H2, (const float *)chi_C, (const float *)phi_LyC,
                      (const float *)xi_cr, (const float *)N_eff, (float *)xCp, (float *)xCO, (float *)xe,

@@ -60,7 +60,7 @@ def _bad(p=None, prec=0):
 @pytest.mark.parametrize("field,value,msg", [("Zg", 0.0, "Zg"), ("Zd", -1.0, "Zd"), ("eps_sub", 0.0, "eps_sub"),
                                              ("fd_rel", 0.7, "fd_rel"), ("cr_mode", 5, "cr_mode"),
                                              ("max_substeps", 0, "max_substeps"), ("T_floor", 0.0, "T_floor"),
-                                             ("order_cells", 2, "order_cells")])
+                                             ("order_cells", 3, "order_cells"), ("order_cells", -1, "order_cells")])
 def test_invalid_params_rejected_before_launch(field, value, msg):
     p = ism.Params()
     setattr(p, field, value)

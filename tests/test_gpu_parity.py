@@ -295,7 +295,8 @@ def test_end_to_end_128_sampled(ism, grf128, prec):
 
 @pytest.mark.parametrize("prec", [0, 1])
 def test_cell_ordering_leaves_results_unchanged(ism, grf128, prec):
-    """order_cells only changes which lane processes which cell: outputs are bitwise identical."""
+    """order_cells only changes which lane processes which cell: outputs are bitwise identical in
+    index order, temperature order and the order of substep counts held in nsub on entry."""
     import torch
     _print("cell ordering prec", prec)
     s, cfg = grf128
@@ -307,14 +308,20 @@ def test_cell_ordering_leaves_results_unchanged(ism, grf128, prec):
     radf = {k: v.view(-1) for k, v in rad.items()}
     radf["phi"] = None
     res = []
-    for order in (0, 1):
+    for order in (0, 1, 2):
         ip = H.ism_params_from(par)
         ip.order_cells = order
         T, xH2, xHp = H.to_dev(s["T"]), H.to_dev(s["xH2"]), H.to_dev(s["xHp"])
-        out = ism.chem_cool_step(n, T, xH2, xHp, radf, cfg["dt_yr"] * OC.YR, ip, prec)
+        out = None
+        if order == 2:
+            # keyed on the counts the nsub array holds on entry: those of the run above
+            out = {k: torch.empty_like(v) for k, v in res[1][3].items()}
+            out["nsub"].copy_(res[1][3]["nsub"])
+        out = ism.chem_cool_step(n, T, xH2, xHp, radf, cfg["dt_yr"] * OC.YR, ip, prec, out=out)
         res.append((T, xH2, xHp, out))
-    (a, b) = res
-    for k in range(3):
-        assert torch.equal(a[k], b[k])
-    for k in ("xCp", "xCO", "xe", "nsub", "status"):
-        assert torch.equal(a[3][k], b[3][k]), k
+    a = res[0]
+    for b in res[1:]:
+        for k in range(3):
+            assert torch.equal(a[k], b[k])
+        for k in ("xCp", "xCO", "xe", "nsub", "status"):
+            assert torch.equal(a[3][k], b[3][k]), k
