@@ -257,9 +257,9 @@ def c2():
 @pytest.mark.parametrize("prec", [1, 0])
 def test_ray_trace_c2_sampled_and_conservation(ism, c2, prec):
     """256^3 at 2 pc with 16 sources: sampled cells against the per-cell oracle (every packet
-    whose line crosses the cell, walked from its source), and photon conservation over the
-    whole grid: sum of alpha J 4 pi dV plus the lost and dropped budgets is the sources'
-    total in every band."""
+    whose line crosses the cell, walked from its source) -- fields, flux and the radiation
+    force from the flux --, and photon conservation over the whole grid: sum of
+    alpha J 4 pi dV plus the lost and dropped budgets is the sources' total in every band."""
     import torch
     s, cfg = c2
     shape = s["n"].shape
@@ -299,3 +299,26 @@ def test_ray_trace_c2_sampled_and_conservation(ism, c2, prec):
     _compare(got, ref, prec, f"c2 prec {prec}")
     gf = out["flux"][:, cells[:, 0], cells[:, 1], cells[:, 2]].cpu().numpy()
     _compare_flux(gf, ref["flux"], _cE(ref), prec, f"c2 flux prec {prec}")
+    # the radiation force over the whole grid at the configuration's temperatures, sampled
+    T = H.to_dev(s["T"]).view(shape)
+    off = torch.zeros(shape, dtype=torch.uint8, device="cuda")
+    f = ism.radiation_force(n, T, xH2, xHp, out["flux"], H.ism_params_from(par), prec, dust_off=off)
+    c0, c1, c2_ = cells[:, 0], cells[:, 1], cells[:, 2]
+    sub = lambda a: np.asarray(a)[c0, c1, c2_]
+    fo = art.radiation_force(sub(s["n"]), sub(s["T"]), sub(s["xH2"]), sub(s["xHp"]), ref["flux"], par)
+    F = ref["flux"].reshape(3, 3, -1)
+    Ftot = F[0] + F[1] + OC.HNU_LYC * F[2]
+    ratio = np.sqrt(np.sum(Ftot ** 2, 0)) / OC.C_LIGHT / (2 * sub(s["n"]) * OC.K_B * sub(s["T"]))
+    tol = 1e-9 if prec == 0 else 1e-4
+    clear = np.abs(ratio / art.PRAD_RATIO_MAX - 1) > 10 * tol
+    np.testing.assert_array_equal(off[c0, c1, c2_].cpu().numpy()[clear].astype(bool), fo["dust_off"][clear])
+    g = f[:, c0, c1, c2_].cpu().numpy().astype(np.float64)[:, clear]
+    r = fo["f"][:, clear]
+    xHI = 1 - 2 * sub(s["xH2"]) - sub(s["xHp"])
+    aL = sub(s["n"]) * (xHI * OC.SIGMA_PI_H + sub(s["xH2"]) * OC.SIGMA_PI_H2 + par.Zd * OC.SIG_D_LYC)
+    cE = _cE(ref)
+    wE = (OC.SIG_D_PE * par.Zd * sub(s["n"]) * cE[0] + OC.SIG_D_LW * par.Zd * sub(s["n"]) * cE[1]
+          + aL * OC.HNU_LYC * cE[2]) / OC.C_LIGHT
+    d = np.sqrt(np.sum((g - r) ** 2, 0))
+    den = np.maximum(np.maximum(np.sqrt(np.sum(r ** 2, 0)), 1e-2 * wE[clear]), 1e-300)
+    assert (d / den).max() < tol, (d / den).max()
