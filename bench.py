@@ -146,6 +146,47 @@ def cpu_baseline(state, cfg, ncell_sample, par_o):
     return base, idx, ref
 
 
+# The grid the oracle's worker processes read: set before they are forked, so each inherits it.
+_CPU_SHARED = {}
+
+
+def _cpu_chunk(idx):
+    """One chunk of the parallel oracle baseline: the oracle six-ray columns at the listed cells of
+    the shared 128^3 grid, then the oracle step of those cells.  Returns the cell count."""
+    from oracle import columns as ocol
+    from oracle import step as ostep
+    from oracle.constants import PC, YR
+    from oracle.constants import Params as OParams
+    state, cfg = _CPU_SHARED["grid"]
+    par_o = OParams(Zg=1.0, Zd=1.0, cr_mode=1)
+    cells = np.stack(np.unravel_index(idx, state["n"].shape), 1)
+    rc = ocol.columns6_cells(state["n"], state["xH2"], None, cfg["dx_pc"] * PC, par_o, cells)
+    rad = dict(chi_PE=rc["chi_PE"], chi_LW=rc["chi_LW"], chi_H2=rc["chi_H2"], chi_C=rc["chi_C"],
+               phi=np.zeros(len(idx)), xi=rc["xi"], Neff=rc["N_eff"])
+    sel = lambda a: a.ravel()[idx]
+    ostep.chem_cool_step(sel(state["n"]), sel(state["T"]), sel(state["xH2"]), sel(state["xHp"]), rad,
+                         cfg["dt_yr"] * YR, par_o)
+    return len(idx)
+
+
+def cpu_parallel(pool, procs, idx, chunk=4096):
+    """The same oracle sample in chunks of `chunk` cells over the pool of worker processes."""
+    t0 = time.perf_counter()
+    done = sum(pool.map(_cpu_chunk, [idx[i:i + chunk] for i in range(0, len(idx), chunk)]))
+    t = time.perf_counter() - t0
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": done / t, "unit": "cell-updates/s", "cores": procs, "kind": "oracle",
+            "sample": f"the same {done} cells in chunks of {chunk} over {procs} worker processes "
+                      f"({t:.1f} s); CPU {model}"}
+
+
 def field_errors(out, ref, idx, xCt):
     """Per-field max / p99 relative error at the sampled cells (floors: 1e-7 for abundances, carbon
     species relative to x_C,tot), and the fraction of sampled cells over 1e-3 in any field."""
@@ -525,12 +566,24 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported "
                                    "(the source step is per-cell independent; see the sharding notes)"}))
         sys.exit(2)
+    pool, procs = None, 0
+    if not args.no_cpu:
+        # the oracle's worker processes are forked before torch is imported and the GPU touched;
+        # they inherit the grid
+        import multiprocessing as mp
+        from paper_2210_08024_amd import workloads as wl
+        _CPU_SHARED["grid"] = wl.make("grf128")
+        try:
+            procs = max(1, min(16, len(os.sched_getaffinity(0))))
+        except Exception:
+            procs = max(1, min(16, os.cpu_count() or 1))
+        pool = mp.get_context("fork").Pool(procs)
     import torch
     from paper_2210_08024_amd import ism, workloads, surrogate_train
     from oracle.census import substep_census
     from oracle.constants import Params as OParams
 
-    state, cfg = workloads.make("grf128")
+    state, cfg = _CPU_SHARED["grid"] if "grid" in _CPU_SHARED else workloads.make("grf128")
     shape = state["n"].shape
     N = state["n"].size
     dev = torch.device("cuda:0")
@@ -671,6 +724,9 @@ def main():
     }
     if not args.no_cpu:
         base, idx, ref = cpu_baseline(state, cfg, args.cpu_cells, OParams(Zg=1.0, Zd=1.0, cr_mode=1))
+        base["parallel"] = cpu_parallel(pool, procs, idx)
+        pool.close()
+        pool.join()
         out["cpu_baseline"] = base
         xCt = OParams(Zg=1.0, Zd=1.0).xCtot
         for p in paths:
