@@ -187,6 +187,30 @@ def cpu_parallel(pool, procs, idx, chunk=4096):
                       f"({t:.1f} s); CPU {model}"}
 
 
+def conservation(res, xCt, xOt):
+    """Element budgets of a step's output.  x_H, x_C and x_O are formed from the closure
+    relations (x_H = 1 - 2 x_H2 - x_H+, x_C = x_C,tot - x_C+ - x_CO, x_O = x_O,tot - x_CO - x_O+
+    with x_O+ = x_O,tot x_H+), so each sum holds exactly; what can fail is the remainder going
+    negative.  Reported: the largest excess of each sum over its total (0 = conserved with every
+    species >= 0) and the smallest abundance."""
+    xH2, xHp = res["xH2"].astype(np.float64), res["xHp"].astype(np.float64)
+    xCp, xCO = res["xCp"].astype(np.float64), res["xCO"].astype(np.float64)
+    return {"H_excess_max": float(np.max(np.maximum(2.0 * xH2 + xHp - 1.0, 0.0))),
+            "C_excess_max": float(np.max(np.maximum((xCp + xCO) / xCt - 1.0, 0.0))),
+            "O_excess_max": float(np.max(np.maximum(xCO / xOt + xHp - 1.0, 0.0))),
+            "min_abundance": float(min(xH2.min(), xHp.min(), xCp.min(), xCO.min()))}
+
+
+def device_conservation(xH2, xHp, xCp, xCO, par_o):
+    """conservation() over whole device arrays, with reductions on the device."""
+    cp, co = xCp.double(), xCO.double()
+    xCt, xOt = par_o.xCtot, par_o.xOtot
+    return {"H_excess_max": float((2.0 * xH2 + xHp - 1.0).clamp_min(0.0).max()),
+            "C_excess_max": float(((cp + co) / xCt - 1.0).clamp_min(0.0).max()),
+            "O_excess_max": float((co / xOt + xHp - 1.0).clamp_min(0.0).max()),
+            "min_abundance": float(min(xH2.min(), xHp.min(), cp.min(), co.min()))}
+
+
 def field_errors(out, ref, idx, xCt):
     """Per-field max / p99 relative error at the sampled cells (floors: 1e-7 for abundances, carbon
     species relative to x_C,tot), and the fraction of sampled cells over 1e-3 in any field."""
@@ -322,7 +346,8 @@ def bench_c2(args):
                    "step_ms_mean": float(np.mean(times["step"])) * 1e3,
                    "step_ms_each": [round(t * 1e3, 3) for t in times["step"]],
                    "nsub_mean_each": [round(x / N, 3) for x in tot_sub],
-                   "status_nonzero_last": int(((outs["status"] & 0xEF) != 0).sum().item())},
+                   "status_nonzero_last": int(((outs["status"] & 0xEF) != 0).sum().item()),
+                   "conservation_last": device_conservation(xH2, xHp, outs["xCp"], outs["xCO"], OParams(Zg=1.0))},
     }
     if force is not None:
         out["radiation_force"] = force
@@ -488,6 +513,7 @@ def bench_c4(args):
                     "cell_updates_per_s": N / (tc + ts), "nsub_mean": float(nsub.double().mean()),
                     "substeps": int(nsub.sum()),
                     "status_nonzero": int(((outs["status"] & 0xEF) != 0).sum()), "_res": res}
+        paths[p]["conservation"] = device_conservation(xH2, xHp, outs["xCp"], outs["xCO"], OParams(Zg=1.0))
         if p == "surrogate":
             paths[p]["fallback_fraction"] = nfb.item() / N
     for p in ("mixed", "surrogate"):
@@ -658,6 +684,7 @@ def main():
         nsub = res["nsub"].astype(np.int64)
         paths[p] = {"ms_per_step": (tc + ts) * 1e3, "columns_ms": tc * 1e3, "step_ms": ts * 1e3,
                     "cell_updates_per_s": N / (tc + ts), "step_only_cell_updates_per_s": N / ts, "_res": res,
+                    "conservation": conservation(res, OParams(Zg=cfg["Zg"]).xCtot, OParams(Zg=cfg["Zg"]).xOtot),
                     "nsub_mean": float(nsub.mean()), "nsub_p50": float(np.percentile(nsub, 50)),
                     "nsub_p99": float(np.percentile(nsub, 99)), "nsub_max": int(nsub.max()),
                     "status_nonzero": int(((res["status"] & 0xEF) != 0).sum())}

@@ -202,9 +202,13 @@ __device__ EqS<R> eq_species(double T, R n, double xH2_d, double xHp_d, const Ra
       if (conv) break;
     }
   }
+  // y <= x_C,tot and frac <= 1 hold exactly; in float the quotient can land one ulp above, which
+  // would leave x_C and x_CO at -ulp
+  y = y < xCt ? y : xCt;
   e.xCp = y;
   e.xe = xe;
-  const R frac = rmax(y / xCt, xHp);
+  const R fr = rmax(y / xCt, xHp);
+  const R frac = fr < R(1) ? fr : R(1);
   const R qq = r.ncrit / n;
   e.xCO = xCt * R(2) * xH2 * (R(1) - frac) / (R(1) + qq * qq);
   e.xC = xCt - y - e.xCO;
