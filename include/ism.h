@@ -22,10 +22,11 @@
  *    launch/runtime errors return ISM_E_DEVICE.  ism_last_error() gives the message
  *    (thread-local).  Per-cell numerical trouble never fails a call: it is reported
  *    in the per-cell status bits below and the call returns ISM_OK.
- *  - Thread safety: after ism_init, ism_rates, and ism_chem_cool_step with order_cells = 0,
- *    may run concurrently on different streams.  ism_columns6, ism_chem_cool_step with
- *    order_cells = 1 and ism_chem_cool_step_surrogate use per-device scratch buffers: their
- *    calls on one device must not overlap in time.
+ *  - Thread safety: after ism_init, ism_rates, ism_radiation_force and ism_chem_cool_step
+ *    with order_cells = 0 may run concurrently on different streams.  ism_columns6,
+ *    ism_chem_cool_step with order_cells = 1 or 2, ism_chem_cool_step_surrogate and
+ *    ism_ray_trace use per-device scratch buffers (and the ray tracer the sources in constant
+ *    memory): their calls on one device must not overlap in time.
  */
 #ifndef ISM_H
 #define ISM_H
