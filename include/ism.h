@@ -240,7 +240,7 @@ typedef struct {
  * (g cm^-2 s^-1, in/out), receives f dt_s; etot, NULL or ncell doubles of total energy
  * density (erg cm^-3, in/out, needs mom), receives the change of rho v^2 / 2 at
  * rho = mu_H m_H n (cells with n = 0 unchanged).  Arithmetic in double on both paths.
- * ISM_E_ARG for NULL required arrays, ncell outside [0, 2^32 - 256), NaN or non-positive
+ * ISM_E_ARG for NULL required arrays, ncell outside [0, 2^32 - 256], NaN or non-positive
  * thresholds, dt_s negative or not finite, etot without mom. */
 ism_status ism_radiation_force(const ism_params *p, ism_precision prec, int64_t ncell,
                                const double *n, const double *T, const double *xH2,

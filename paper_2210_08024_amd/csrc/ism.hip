@@ -959,7 +959,7 @@ ism_status ism_radiation_force(const ism_params *p, ism_precision prec, int64_t 
   if (!(o.prad_ratio_max > 0.0)) return fail(ISM_E_ARG, "prad_ratio_max must be > 0");
   if (!(dt_s >= 0.0) || !std::isfinite(dt_s)) return fail(ISM_E_ARG, "dt_s must be finite and >= 0");
   if (etot && !mom) return fail(ISM_E_ARG, "etot needs mom");
-  if (ncell > (int64_t)0xFFFFFF00ll) return fail(ISM_E_ARG, "ncell must be below 2^32 - 256");
+  if (ncell > (int64_t)0xFFFFFF00ll) return fail(ISM_E_ARG, "ncell must be in [0, 2^32 - 256]");
   if (ncell == 0) return ISM_OK;
   if (!n || !T || !xH2 || !xHp || !flux || !f_rad) return fail(ISM_E_ARG, "a required array is NULL");
   DevState *st;
