@@ -496,8 +496,9 @@ struct SurrWork {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 int fwd_grid(const ism_surrogate *m, int64_t B) {
-  const int64_t per_block = (int64_t)mlp::FWD_WAVES * mlp::WTILE;
-  return (int)std::max<int64_t>(1, std::min<int64_t>((B + per_block - 1) / per_block, m->num_cu));
+  // tiles go to the waves of all blocks in turn (wave-major), so a batch of at least one tile
+  // per CU spreads over every CU
+  return (int)std::max<int64_t>(1, std::min<int64_t>((B + mlp::WTILE - 1) / mlp::WTILE, m->num_cu));
 }
 
 ism_status surr_work(ism_surrogate *m, int64_t B, SurrWork &w) {
@@ -656,7 +657,7 @@ ism_status ism_surrogate_backward(ism_surrogate *m, const float *X, const float 
   surr_fwd_bwd(m, X, nullptr, dY, B, w, stream);
   mlp::AdamArgs aa{};
   aa.part = w.part; aa.nchunk = w.nchunk; aa.grad = grad; aa.adam = 0;
-  hipLaunchKernelGGL(mlp::mlp_reduce_adam_kernel, dim3((mlp::NPARAM + 255) / 256), dim3(256), 0, stream, aa);
+  hipLaunchKernelGGL(mlp::mlp_reduce_adam_kernel, dim3((mlp::NPARAM + mlp::RA_PARAMS - 1) / mlp::RA_PARAMS), dim3(256), 0, stream, aa);
   HIP_TRY(hipGetLastError());
   return ISM_OK;
 }
@@ -681,7 +682,7 @@ ism_status ism_surrogate_train_step(ism_surrogate *m, const float *X, const floa
   if (loss_dev)
     hipLaunchKernelGGL(mlp::mlp_loss_kernel, dim3(1), dim3(256), 0, stream, w.loss_part,
                        w.grid_fwd * mlp::FWD_WAVES, 1.0 / (3.0 * (double)B), loss_dev);
-  hipLaunchKernelGGL(mlp::mlp_reduce_adam_kernel, dim3((mlp::NPARAM + 255) / 256), dim3(256), 0, stream, aa);
+  hipLaunchKernelGGL(mlp::mlp_reduce_adam_kernel, dim3((mlp::NPARAM + mlp::RA_PARAMS - 1) / mlp::RA_PARAMS), dim3(256), 0, stream, aa);
   HIP_TRY(hipGetLastError());
   m->step = t;
   return ISM_OK;

@@ -185,7 +185,7 @@ __global__ __launch_bounds__(FWD_THREADS) void mlp_fwd_kernel(FwdArgs a) {
   }
   float lossacc = 0.f;
   const int64_t stride = (int64_t)gridDim.x * FWD_WAVES * WTILE;
-  for (int64_t base = ((int64_t)blockIdx.x * FWD_WAVES + wave) * WTILE; base < a.B; base += stride) {
+  for (int64_t base = ((int64_t)wave * gridDim.x + blockIdx.x) * WTILE; base < a.B; base += stride) {
     const uint8_t *sm = smem + opaque_zero();
     const __bf16 *W1 = (const __bf16 *)(sm + FI_W1);
     const __bf16 *W2 = (const __bf16 *)(sm + FI_W2);
@@ -330,7 +330,7 @@ __global__ __launch_bounds__(FWD_THREADS) void mlp_bwd_kernel(BwdArgs a) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = lane & 15, g = lane >> 4;
   const int64_t stride = (int64_t)gridDim.x * FWD_WAVES * WTILE;
-  for (int64_t base = ((int64_t)blockIdx.x * FWD_WAVES + wave) * WTILE; base < a.B; base += stride) {
+  for (int64_t base = ((int64_t)wave * gridDim.x + blockIdx.x) * WTILE; base < a.B; base += stride) {
     const uint8_t *sm = smem + opaque_zero();
     const __bf16 *W4t = (const __bf16 *)(sm + BI_W4T);
     const __bf16 *W3t = (const __bf16 *)(sm + BI_W3T);
@@ -382,6 +382,37 @@ template <int ROWS, int WSRC, typename T>
 __device__ __forceinline__ void dw_stage(__bf16 *dst, const T *src, int64_t s0, int64_t s1, float (&bsum)[ROWS / 8]) {
   const int p = threadIdx.x & 31, q = threadIdx.x >> 5;
   const int64_t na = s0 + 2 * p, nb = na + 1;
+  constexpr int PER = ROWS / 8;
+  typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+  constexpr bool VEC = WSRC == ROWS && PER % (16 / (int)sizeof(T)) == 0;
+  if constexpr (VEC) {
+    // the thread's PER features of a sample are contiguous (16-byte aligned): 16-byte loads
+    constexpr int EPV = 16 / (int)sizeof(T), NV = PER / EPV;
+    T ra[PER], rb[PER];
+    const uint4 *pa = reinterpret_cast<const uint4 *>(src + na * WSRC + q * PER);
+    const uint4 *pb = reinterpret_cast<const uint4 *>(src + nb * WSRC + q * PER);
+#pragma unroll
+    for (int w = 0; w < NV; ++w) {
+      const uint4 xa = na < s1 ? pa[w] : make_uint4(0u, 0u, 0u, 0u);
+      const uint4 xb = nb < s1 ? pb[w] : make_uint4(0u, 0u, 0u, 0u);
+      __builtin_memcpy(ra + EPV * w, &xa, 16);
+      __builtin_memcpy(rb + EPV * w, &xb, 16);
+    }
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      bf16x2 v;
+      if constexpr (sizeof(T) == 4) {
+        bsum[e] += (float)ra[e] + (float)rb[e];
+        v.x = (__bf16)(float)ra[e];
+        v.y = (__bf16)(float)rb[e];
+      } else {
+        v.x = __builtin_bit_cast(__bf16, (uint16_t)ra[e]);
+        v.y = __builtin_bit_cast(__bf16, (uint16_t)rb[e]);
+      }
+      *(bf16x2 *)(dst + (q * PER + e) * DW_LROW + 2 * p) = v;
+    }
+    return;
+  }
 #pragma unroll
   for (int e = 0; e < ROWS / 8; ++e) {
     const int f = q * (ROWS / 8) + e;
@@ -398,7 +429,6 @@ __device__ __forceinline__ void dw_stage(__bf16 *dst, const T *src, int64_t s0, 
         if (nb < s1) bb = __builtin_bit_cast(__bf16, (uint16_t)src[nb * WSRC + f]);
       }
     }
-    typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
     bf16x2 v;
     v.x = ba;
     v.y = bb;
@@ -540,13 +570,22 @@ struct AdamArgs {
   int adam;
 };
 
-// Sum the per-chunk partial gradients in chunk order; then either store the gradient or take
-// one Adam step on the FP32 master parameter and refresh its BF16 image entries.
-__global__ void mlp_reduce_adam_kernel(AdamArgs a) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= NPARAM) return;
-  float gsum = 0.f;
-  for (int c = 0; c < a.nchunk; ++c) gsum += a.part[(int64_t)c * NPARAM + p];
+// Sum the per-chunk partial gradients: four threads per parameter each take every fourth
+// chunk, and the four sums are added in a fixed order (the result is the same on every run);
+// then either store the gradient or take one Adam step on the FP32 master parameter and
+// refresh its BF16 image entries.  Blocks of 256 threads cover 64 parameters.
+constexpr int RA_PARAMS = 64;
+__global__ __launch_bounds__(256) void mlp_reduce_adam_kernel(AdamArgs a) {
+  __shared__ float s[256];
+  const int t = threadIdx.x, j = t & (RA_PARAMS - 1), q = t / RA_PARAMS;
+  const int p = blockIdx.x * RA_PARAMS + j;
+  float part = 0.f;
+  if (p < NPARAM)
+    for (int c = q; c < a.nchunk; c += 4) part += a.part[(int64_t)c * NPARAM + p];
+  s[t] = part;
+  __syncthreads();
+  if (q != 0 || p >= NPARAM) return;
+  const float gsum = (s[j] + s[j + RA_PARAMS]) + (s[j + 2 * RA_PARAMS] + s[j + 3 * RA_PARAMS]);
   if (!a.adam) {
     a.grad[p] = gsum;
     return;
