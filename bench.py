@@ -42,9 +42,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--path", choices=("f64", "mixed", "surrogate"), default="f64")
-    ap.add_argument("--workload", choices=("grf128", "c2", "c4"), default="grf128",
+    ap.add_argument("--workload", choices=("grf128", "c2", "c4", "train"), default="grf128",
                     help="grf128: the metric workload; c2: 256^3 with 16 point sources, ten successive steps "
-                         "(mixed form); c4: 512^3 with 16 point sources, one step on each path")
+                         "(mixed form); c4: 512^3 with 16 point sources, one step on each path; train: surrogate "
+                         "training, one Adam step of batch 65,536 per step (use --steps of a few hundred)")
     ap.add_argument("--c4-stride", type=int, default=8,
                     help="c4: error report on every s-th cell along each axis (8: a 64^3 subsample)")
     ap.add_argument("--maps", choices=("lc", "art"), default="lc",
@@ -390,6 +391,72 @@ def bench_radiation_force(ism, par, n, init, shape, dx, sources, stream, ev, rep
                          "work": f"{FORCE_BYTES_MIXED} B/cell x {N} cells per launch"}}
 
 
+# Per training sample: forward 2 (10 x 128 + 2 x 128 x 128 + 128 x 3) FLOP, backward (error
+# signal and weight gradients) twice that.
+TRAIN_FLOP_PER_SAMPLE = 3 * 68864
+# HBM bytes per training sample as the kernels move them: the forward stores the FP32
+# pre-activations (3 x 128) and BF16 layer inputs (16 + 3 x 128) and reads X, Y (13 floats); the
+# backward reads the pre-activations and writes the error signals over them (2 x 3 x 128 FP32);
+# the weight gradients read the error signals (3 x 128 FP32 + 3) and the layer inputs again.
+TRAIN_BYTES_PER_SAMPLE = (3 * 128 * 4 + (16 + 3 * 128) * 2 + 13 * 4) + 2 * 3 * 128 * 4 + \
+    (3 * 128 * 4 + 3 * 4 + (16 + 3 * 128) * 2)
+
+
+def bench_train(args):
+    """Surrogate training: K timed Adam steps (forward with stored activations, backward, per-chunk
+    weight gradients, ordered reduction, Adam on FP32 masters) of batch 65,536 on seeded standard
+    normal pairs of the network's shapes (10 inputs, 3 outputs; the checkpoint itself is trained
+    by surrogate_train.py on pairs from the plain FP64 step).  HIP events on the launch stream."""
+    import torch
+    from paper_2210_08024_amd import ism
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    ism.init(0)
+    B = 65536
+    g = torch.Generator(device="cuda").manual_seed(11)
+    X = torch.randn((16 * B, 10), device="cuda", generator=g)
+    Y = torch.randn((16 * B, 3), device="cuda", generator=g)
+    sur = ism.Surrogate(seed=0)
+    sur.set_norm([0.0] * 10, [1.0] * 10, [0.0] * 3, [1.0] * 3)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step(k):
+        b = k % 16
+        sur.train_step(X[b * B:(b + 1) * B], Y[b * B:(b + 1) * B], 1e-3, loss)
+
+    for k in range(args.warmup):
+        step(k)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for k in range(args.steps):
+        step(k)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    t = ev[0].elapsed_time(ev[1]) * 1e-3
+    tf = TRAIN_FLOP_PER_SAMPLE * B * args.steps / t / 1e12
+    gbs = TRAIN_BYTES_PER_SAMPLE * B * args.steps / t / 1e9
+    out = {"metric": "surrogate training samples/s", "value": B * args.steps / t, "unit": "samples/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": t * 1e3 / max(args.steps, 1),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f32",
+           "data": "synthetic",
+           "config": {"workload": "train: 10 -> 128 -> 128 -> 128 -> 3 SiLU network, batch 65,536, Adam; seeded "
+                                  "standard normal pairs", "wall_ms_per_step": wall * 1e3 / max(args.steps, 1),
+                      "final_loss": float(loss.item())},
+           "roofline": {"bound": "mfma", "kernel": "training step (5 kernels)", "achieved": tf,
+                        "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": tf / BF16_PEAK_TFLOPS, "traffic": None,
+                        "work": f"{TRAIN_FLOP_PER_SAMPLE} FLOP/sample x {B} samples per step"},
+           "roofline_hbm": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": gbs / HBM_PEAK_GBS,
+                            "work": f"{TRAIN_BYTES_PER_SAMPLE} B/sample of stored activations moved per step"}}
+    print(json.dumps(out), flush=True)
+
+
 def _oracle_chunk(job):
     """One chunk of the oracle step (a worker of the C4 error report)."""
     from oracle import step as ostep
@@ -583,6 +650,8 @@ def main():
     if args.calibrate_copy:
         calibrate_copy()
         return
+    if args.workload == "train":
+        return bench_train(args)
     if args.workload in ("c2", "c4"):
         if args.gpus != 1:
             print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
