@@ -106,9 +106,13 @@ def test_ray_trace_edge_cases(ism):
                     [4.5 * DX, 1.5 * DX, 0.5 * DX, 1e49, 0.0]])                  # no FUV
     for kw in (dict(), dict(level0=0), dict(level0=0, max_level=0), dict(rays_per_cell=16.0, tau_max=0.5)):
         print(f"ray_trace edge case {kw}", flush=True)
-        ref = art.ray_trace(n, xH2, xHp, None, DX, src, par, **kw)
-        out = _run(ism, torch, n, xH2, xHp, None, src, par, 0, **kw)
+        ref = art.ray_trace(n, xH2, xHp, None, DX, src, par, flux=True, **kw)
+        out = _zeros(torch, shape, torch.float64)
+        out["flux"] = torch.zeros((9,) + shape, dtype=torch.float64, device="cuda")
+        dv = lambda a: H.to_dev(a).view(shape)
+        ism.ray_trace(dv(n), dv(xH2), dv(xHp), None, DX, H.ism_params_from(par), 0, src, out, budget=True, **kw)
         _compare(out, ref, 0, f"edge {kw}")
+        _compare_flux(out["flux"].cpu().numpy(), ref["flux"], _cE(ref), 0, f"edge flux {kw}")
         np.testing.assert_allclose(out["budget"].cpu().numpy(), ref["budget"], rtol=1e-9, atol=1e-300)
     # contributions add to what is there; no sources is a no-op
     ref = art.ray_trace(n, xH2, xHp, xC, DX, src, par)
@@ -120,9 +124,10 @@ def test_ray_trace_edge_cases(ism):
     ism.ray_trace(dev(n), dev(xH2), dev(xHp), dev(xC), DX, ip, 0, src, out)
     for k in KEYS:
         np.testing.assert_allclose(out[k].cpu().numpy(), 1.0 + ref[k], rtol=1e-9)
+    out["flux"] = torch.ones((9,) + shape, dtype=torch.float64, device="cuda")
     before = {k: v.clone() for k, v in out.items()}
     ism.ray_trace(dev(n), dev(xH2), dev(xHp), dev(xC), DX, ip, 0, [], out)
-    for k in KEYS:
+    for k in KEYS + ("flux",):
         assert torch.equal(before[k], out[k])
     # invalid arguments are rejected before any launch
     bad = src.copy()
