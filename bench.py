@@ -118,6 +118,24 @@ def calibrate_copy():
     print(json.dumps({"calibration_copy_bytes": a.numel() * 4}), flush=True)
 
 
+def copy_bandwidth(reps=3):
+    """Achievable HBM bandwidth: best of `reps` timed device copies of 1 GiB (read + write), GB/s."""
+    import torch
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    best = float("inf")
+    for _ in range(reps + 1):
+        ev[0].record()
+        b.copy_(a)
+        ev[1].record()
+        torch.cuda.synchronize()
+        best = min(best, ev[0].elapsed_time(ev[1]) * 1e-3)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * (1 << 30) / best / 1e9
+
+
 def cpu_baseline(state, cfg, ncell_sample, par_o):
     """The CPU oracle on a seeded sample of the same workload (columns for the sampled cells + the step)."""
     from oracle import columns as ocol
@@ -384,11 +402,13 @@ def bench_radiation_force(ism, par, n, init, shape, dx, sources, stream, ev, rep
     torch.cuda.synchronize()
     force_ms = ev[2].elapsed_time(ev[3]) / reps
     gbs = N * FORCE_BYTES_MIXED / (force_ms * 1e-3) / 1e9
+    copy = copy_bandwidth()
     return {"ray_trace_with_flux_ms": trace_ms, "radiation_force_ms": force_ms,
             "dust_off_fraction": float(off.double().mean().item()),
             "roofline": {"bound": "hbm", "kernel": "radiation_force_kernel", "achieved": gbs, "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None,
-                         "work": f"{FORCE_BYTES_MIXED} B/cell x {N} cells per launch"}}
+                         "work": f"{FORCE_BYTES_MIXED} B/cell x {N} cells per launch",
+                         "copy_GBs_measured": copy, "frac_of_copy": gbs / copy}}
 
 
 # Per training sample: forward 2 (10 x 128 + 2 x 128 x 128 + 128 x 3) FLOP, backward (error
@@ -815,7 +835,8 @@ def main():
                          "unit": "TFLOP/s", "frac": mlp_tf / BF16_PEAK_TFLOPS, "ms": t_mlp * 1e3,
                          "work": f"{MLP_FLOP_PER_CELL} FLOP/cell x {N} cells per launch"},
         "paths": paths,
-        "detail": {"columns_hbm_GBs_algorithmic_f64": N * 72 / (paths["f64"]["columns_ms"] * 1e-3) / 1e9,
+        "detail": {"hbm_copy_GBs_measured": copy_bandwidth(),
+                   "columns_hbm_GBs_algorithmic_f64": N * 72 / (paths["f64"]["columns_ms"] * 1e-3) / 1e9,
                    "columns_hbm_GBs_algorithmic_mixed": N * 48 / (paths["mixed"]["columns_ms"] * 1e-3) / 1e9},
     }
     if not args.no_cpu:
