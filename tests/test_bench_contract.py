@@ -1,0 +1,19 @@
+"""bench.py's contract on a host without a GPU: more than one GPU is refused with a message and
+exit status 2 for every workload, before anything touches a device."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.mark.parametrize("workload", ["grf128", "c2", "c4", "train"])
+def test_more_than_one_gpu_is_refused(workload):
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2", "--workload", workload,
+                        "--no-cpu"], capture_output=True, text=True, timeout=300, cwd=ROOT)
+    assert r.returncode == 2, (r.returncode, r.stderr[-500:])
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in msg["error"]
