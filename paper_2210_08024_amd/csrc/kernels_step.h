@@ -178,9 +178,14 @@ __global__ __launch_bounds__(256) void step_simple_kernel(StepArgs<R> a) {
 // Persistent variant: a grid sized to the chip; every lane keeps one cell in flight and,
 // when its cell finishes, claims the next unclaimed cell from a device counter (one
 // atomic per wave per refill, ranks by popcount), so lanes stay busy however uneven the
-// substep counts are.  Every lane leaves once the counter passes ncell and its cell is
-// done; *a.queue must hold the number of lanes in the grid at launch.
+// substep counts are.  A finished lane waits until REFILL_BATCH lanes of its wave are done
+// (or no lane is still working): the whole wave runs the refill (loads, fixed terms, entry
+// closure) whenever any lane takes it, so taking it for a dozen lanes at once beats taking it
+// for one or two lanes in nearly every pass.  Every lane leaves once the counter passes ncell
+// and its cell is done; *a.queue must hold the number of lanes in the grid at launch.
 // Two waves per SIMD: measured fastest for both precisions (more waves spill to scratch).
+constexpr int REFILL_BATCH = 12;
+
 template <class R>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void step_queue_kernel(StepArgs<R> a) {
   __shared__ R s_tab[TAB_STEP];
@@ -191,23 +196,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
   bool active = cell < nitem;
   CellState<R> s;
   if (active) cell_begin(a, a.idx ? (int64_t)a.idx[cell] : cell, s, s_tab);
-  while (__ballot(active) != 0) {
-    bool need = false;
+  bool idle = false;  // cell finished, waiting for the wave's next refill
+  while (__ballot(active || idle) != 0) {
     if (active && cell_substep(a, s, s_tab)) {
       cell_end(a, a.idx ? (int64_t)a.idx[cell] : cell, s);
-      need = true;
+      active = false;
+      idle = true;
     }
-    const uint64_t m = __ballot(need);
-    if (m != 0) {
+    const uint64_t m = __ballot(idle);
+    if (m != 0 && (__popcll(m) >= REFILL_BATCH || __ballot(active) == 0)) {
       const int leader = __ffsll((unsigned long long)m) - 1;
       unsigned long long base = 0;
       if (lane == leader) base = atomicAdd((unsigned long long *)a.queue, (unsigned long long)__popcll(m));
       base = __shfl(base, leader, 64);
-      if (need) {
+      if (idle) {
+        idle = false;
         cell = (int64_t)base + __popcll(m & ((1ull << lane) - 1ull));
         active = cell < nitem;
         if (active) cell_begin(a, a.idx ? (int64_t)a.idx[cell] : cell, s, s_tab);
-        else active = false;
       }
     }
   }
