@@ -73,3 +73,37 @@ def test_slab_steady_state_on_the_gpu(ism, prec):
         H.check_fields(g, ref, 1e-9, H.FLOORS_F64, par.xCtot, label="slab F64")
     Nt = slab.transition_column(n, g["xH2"], dx)
     assert Nt == pytest.approx(slab.transition_column(n, xH2_ref, dx), rel=1e-9 if prec == 0 else 1e-3)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_slab_with_cosmic_rays_on_the_gpu(ism, prec):
+    """The transition with CR ionisation attenuated by Eq. e:cratt (n = 100, chi0 = 1,
+    xi_cr,0 = 2e-16, 192 cells of 0.02 pc, 100 rounds of 1e6 yr): FP64 matches the oracle's
+    profile to 1e-9 and the mixed form gives the transition column to 1e-3."""
+    import torch
+    n, chi0, xi0, dx, nx = 100.0, 1.0, 2e-16, 0.02 * OC.PC, 192
+    par = Params(chi0=chi0, xi_cr0=xi0, kgr_const=1, cr_mode=1)
+    ip = H.ism_params_from(par)
+    print(f"CR slab prec={prec}", flush=True)
+    xH2_ref, ref = slab.slab_steady(n, chi0, nx, dx, dt_yr=1e6, steps=100, par=par)
+    shape = (1, 1, nx)
+    nd = torch.full(shape, n, dtype=torch.float64, device="cuda")
+    T = torch.full((nx,), 100.0, dtype=torch.float64, device="cuda")
+    xH2 = torch.full((nx,), 1e-6, dtype=torch.float64, device="cuda")
+    xHp = torch.full((nx,), 1e-4, dtype=torch.float64, device="cuda")
+    xC = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    for _ in range(100):
+        rad = ism.columns_beam(nd, xH2.view(shape), xC, dx, ip, prec)
+        r = {k: v.view(-1) for k, v in rad.items()}
+        r["phi"] = None
+        out = ism.chem_cool_step(nd.view(-1), T, xH2, xHp, r, 1e6 * OC.YR, ip, prec)
+        xC = (par.xCtot - out["xCp"].double() - out["xCO"].double()).clamp_min(0.0).view(shape)
+    g = dict(T=T.cpu().numpy(), xH2=xH2.cpu().numpy(), xHp=xHp.cpu().numpy(),
+             xe=out["xe"].cpu().numpy().astype(np.float64), xCp=out["xCp"].cpu().numpy().astype(np.float64),
+             xCO=out["xCO"].cpu().numpy().astype(np.float64))
+    if prec == 0:
+        H.check_fields(g, ref, 1e-9, H.FLOORS_F64, par.xCtot, label="CR slab F64")
+    Nt = slab.transition_column(n, g["xH2"], dx)
+    Nt_ref = slab.transition_column(n, xH2_ref, dx)
+    assert Nt_ref > slab.transition_column(n, slab.slab_steady(n, chi0, nx, dx, dt_yr=1e6, steps=100)[0], dx)
+    assert Nt == pytest.approx(Nt_ref, rel=1e-9 if prec == 0 else 1e-3)
