@@ -16,6 +16,11 @@ error against the FP64 oracle on the CPU sample, the surrogate's fallback fracti
 speedups.  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--path f64|mixed|surrogate] [--no-cpu]
+
+Other workloads (`--workload`): c2, the 256^3 grid with 16 point sources and ten successive
+mixed steps (`--maps lc|art`: straight-line maps or the adaptive ray trace, which also
+measures the flux trace and the radiation force); c4, the 512^3 grid, one step on each form
+with the error against the oracle on a subsample; train, the surrogate's Adam steps.
 """
 import argparse
 import json
