@@ -17,9 +17,9 @@ speedups.  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--path f64|mixed|surrogate] [--no-cpu]
 
-Other workloads (`--workload`): c2, the 256^3 grid with 16 point sources and ten successive
+Other workloads (`--workload`): pts256, the 256^3 grid with 16 point sources and ten successive
 mixed steps (`--maps lc|art`: straight-line maps or the adaptive ray trace, which also
-measures the flux trace and the radiation force); c4, the 512^3 grid, one step on each form
+measures the flux trace and the radiation force); pts512, the 512^3 grid, one step on each form
 with the error against the oracle on a subsample; train, the surrogate's Adam steps.
 """
 import argparse
@@ -47,17 +47,17 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--path", choices=("f64", "mixed", "surrogate"), default="f64")
-    ap.add_argument("--workload", choices=("grf128", "c2", "c4", "train"), default="grf128",
-                    help="grf128: the metric workload; c2: 256^3 with 16 point sources, ten successive steps "
-                         "(mixed form); c4: 512^3 with 16 point sources, one step on each path; train: surrogate "
+    ap.add_argument("--workload", choices=("grf128", "pts256", "pts512", "train"), default="grf128",
+                    help="grf128: the metric workload; pts256: 256^3 with 16 point sources, ten successive steps "
+                         "(mixed form); pts512: 512^3 with 16 point sources, one step on each path; train: surrogate "
                          "training, one Adam step of batch 65,536 per step (use --steps of a few hundred)")
-    ap.add_argument("--c4-stride", type=int, default=8,
-                    help="c4: error report on every s-th cell along each axis (8: a 64^3 subsample)")
+    ap.add_argument("--pts512-stride", type=int, default=8,
+                    help="pts512: error report on every s-th cell along each axis (8: a 64^3 subsample)")
     ap.add_argument("--maps", choices=("lc", "art"), default="lc",
-                    help="c2 point-source maps: lc straight-line 1/r^2 exp(-tau) with the Stromgren cap (the "
+                    help="pts256 point-source maps: lc straight-line 1/r^2 exp(-tau) with the Stromgren cap (the "
                          "configuration's recipe), art adaptive ray tracing (Sec. 5.1)")
-    ap.add_argument("--c2-order", choices=("previous", "temperature"), default="previous",
-                    help="c2 processing order of steps 2-10: by the previous step's substep counts (order_cells 2) "
+    ap.add_argument("--pts256-order", choices=("previous", "temperature"), default="previous",
+                    help="pts256 processing order of steps 2-10: by the previous step's substep counts (order_cells 2) "
                          "or by temperature (order_cells 1); the first step is always by temperature")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and the error report")
     ap.add_argument("--cpu-cells", type=int, default=65536)
@@ -250,7 +250,7 @@ def field_errors(out, ref, idx, xCt):
     return rep
 
 
-def bench_c2(args):
+def bench_pts256(args):
     """256^3, 2 pc cells, 16 point sources (maps once: straight-line 1/r^2 exp(-tau) maps, or
     with --maps art the adaptive ray tracing of Sec. 5.1), CR map, ten successive mixed steps of
     1e4 yr with x_C fed back into the columns; value = cell-updates/s over the ten steps, the
@@ -259,7 +259,7 @@ def bench_c2(args):
     from paper_2210_08024_amd import ism, workloads
     from oracle.census import substep_census
     from oracle.constants import Params as OParams
-    s, cfg = workloads.make("c2")
+    s, cfg = workloads.make("pts256")
     shape = s["n"].shape
     N = s["n"].size
     dev = torch.device("cuda:0")
@@ -267,7 +267,7 @@ def bench_c2(args):
     ism.init(0)
     par = ism.Params(Zg=1.0, Zd=1.0, cr_mode=2)
     # steps after the first: cells grouped by the previous step's substep counts (in outs["nsub"])
-    par_next = ism.Params(Zg=1.0, Zd=1.0, cr_mode=2, order_cells=2 if args.c2_order == "previous" else 1)
+    par_next = ism.Params(Zg=1.0, Zd=1.0, cr_mode=2, order_cells=2 if args.pts256_order == "previous" else 1)
     dx = cfg["dx_pc"] * workloads.PC
     dt = cfg["dt_yr"] * workloads.YR
     stream = torch.cuda.current_stream()
@@ -356,11 +356,11 @@ def bench_c2(args):
         "value": N * cfg["steps"] / wall, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": wall * 1e3 / cfg["steps"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": "c2: 256^3 lognormal GRF (2 pc cells, 512 pc box), 16 point sources (Q 1.24e50 s^-1, "
+        "config": {"workload": "pts256: 256^3 lognormal GRF (2 pc cells, 512 pc box), 16 point sources (Q 1.24e50 s^-1, "
                                "L_FUV 1.36e6 L_sun; maps once by " + how + "), chi0 = 1 six-ray, xi_cr log-uniform [1e-17, 1e-15], "
                                "Z' = 1, ten successive steps of 1e4 yr", "cells": N, "path": "mixed",
                    "maps": args.maps, "job": "point-source maps once + ten (columns6 + step)",
-                   "order": "steps 2-10 by the previous step's substep counts" if args.c2_order == "previous"
+                   "order": "steps 2-10 by the previous step's substep counts" if args.pts256_order == "previous"
                    else "by temperature"},
         "roofline": {"bound": "alu", "kernel": "step_queue_kernel", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
@@ -489,7 +489,7 @@ def _oracle_chunk(job):
     return ostep.chem_cool_step(n, T, xH2, xHp, rad, dt, par)
 
 
-def bench_c4(args):
+def bench_pts512(args):
     """512^3, 2 pc cells, 16 point sources, CR map, one step of 1e4 yr on each path (plain F64,
     plain mixed, FP32 + surrogate with the plain step as fallback).  The point-source maps are
     computed once from the initial state (in double; the mixed paths take them rounded to
@@ -509,7 +509,7 @@ def bench_c4(args):
     from oracle.census import substep_census
     from oracle.constants import Params as OParams
     t_gen = time.perf_counter()
-    s, cfg = workloads.make("c4")
+    s, cfg = workloads.make("pts512")
     t_gen = time.perf_counter() - t_gen
     shape = s["n"].shape
     N = s["n"].size
@@ -578,7 +578,7 @@ def bench_c4(args):
             times["step"].append(ev[1].elapsed_time(ev[2]) * 1e-3)
 
     # the subsample: every s-th cell along each axis
-    st = args.c4_stride
+    st = args.pts512_stride
     kk, jj, ii = np.meshgrid(np.arange(0, shape[0], st), np.arange(0, shape[1], st), np.arange(0, shape[2], st),
                              indexing="ij")
     idx = (ii + shape[2] * (jj + shape[1] * kk)).ravel()
@@ -636,7 +636,7 @@ def bench_c4(args):
         "value": sp["cell_updates_per_s"], "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": sp["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "bf16+f32+f64", "data": "synthetic",
-        "config": {"workload": "c4: 512^3 lognormal GRF (2 pc cells, 1024 pc box), 16 point sources (Q 1.24e50 s^-1, "
+        "config": {"workload": "pts512: 512^3 lognormal GRF (2 pc cells, 1024 pc box), 16 point sources (Q 1.24e50 s^-1, "
                                "L_FUV 1.36e6 L_sun; maps once by " + how + "), chi0 = 1 six-ray, xi_cr log-uniform "
                                "[1e-17, 1e-15], Z' = 1, one step of 1e4 yr", "cells": N, "path": "surrogate",
                    "maps": args.maps},
@@ -677,11 +677,11 @@ def main():
         return
     if args.workload == "train":
         return bench_train(args)
-    if args.workload in ("c2", "c4"):
+    if args.workload in ("pts256", "pts512"):
         if args.gpus != 1:
             print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
             sys.exit(2)
-        return bench_c2(args) if args.workload == "c2" else bench_c4(args)
+        return bench_pts256(args) if args.workload == "pts256" else bench_pts512(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported "
                                    "(the source step is per-cell independent; see the sharding notes)"}))

@@ -16,9 +16,9 @@ Recipes (all seeds derive from SeedSequence(20221014)):
   clipped to [10, 1e7] K; abundances Dirichlet as above.
 * ``point_sources(nsrc, box_cm)`` seeded uniform positions in the box, each source with
   Q = 1.24e50 s^-1 and L_FUV = 1.36e6 L_sun (a young cluster's LyC and FUV output).
-* ``c2``: the GRF recipe at 256^3 with 2 pc cells (the same 512 pc box), 16 point sources,
+* ``pts256``: the GRF recipe at 256^3 with 2 pc cells (the same 512 pc box), 16 point sources,
   xi_cr per cell log-uniform in [1e-17, 1e-15] s^-1, ten successive steps of 1e4 yr.
-* ``c4``: the ``c2`` recipe at 512^3 with 2 pc cells (a 1024 pc box), 16 point sources, one
+* ``pts512``: the ``pts256`` recipe at 512^3 with 2 pc cells (a 1024 pc box), 16 point sources, one
   step of 1e4 yr.
 * ``thin(N)`` i.i.d. cells in an unattenuated field (chi = 1 in every band,
   xi_cr = 2e-16 s^-1, N_eff = 0): log10 n ~ U[0, 4], log10 T ~ U[1, 4],
@@ -111,8 +111,8 @@ def cr_map(shape, salt=4):
 CONFIGS = {
     "tiny16": dict(grid=16, dx_pc=2.0, Zg=1.0, dt_yr=1.0e4, cr_mode=0),
     "grf128": dict(grid=128, dx_pc=4.0, Zg=1.0, dt_yr=1.0e4, cr_mode=1),
-    "c2": dict(grid=256, dx_pc=2.0, Zg=1.0, dt_yr=1.0e4, cr_mode=2, nsrc=16, steps=10),
-    "c4": dict(grid=512, dx_pc=2.0, Zg=1.0, dt_yr=1.0e4, cr_mode=2, nsrc=16, steps=1),
+    "pts256": dict(grid=256, dx_pc=2.0, Zg=1.0, dt_yr=1.0e4, cr_mode=2, nsrc=16, steps=10),
+    "pts512": dict(grid=512, dx_pc=2.0, Zg=1.0, dt_yr=1.0e4, cr_mode=2, nsrc=16, steps=1),
 }
 
 
@@ -127,7 +127,7 @@ def make(name, grid=None):
         s = {k: v.reshape(N, N, N) for k, v in s.items()}
     else:
         s = grf_cube(N, cfg["dx_pc"])
-    if name in ("c2", "c4"):
+    if name in ("pts256", "pts512"):
         box = N * cfg["dx_pc"] * PC
         s["xi"] = cr_map(s["n"].shape)
         cfg["sources"] = point_sources(cfg["nsrc"], (box, box, box))

@@ -10,7 +10,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-@pytest.mark.parametrize("workload", ["grf128", "c2", "c4", "train"])
+@pytest.mark.parametrize("workload", ["grf128", "pts256", "pts512", "train"])
 def test_more_than_one_gpu_is_refused(workload):
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2", "--workload", workload,
                         "--no-cpu"], capture_output=True, text=True, timeout=300, cwd=ROOT)

@@ -254,19 +254,19 @@ def test_radiation_force_matches_oracle_on_synthetic_flux(ism, prec):
 
 
 @pytest.fixture(scope="module")
-def c2():
+def pts256():
     from paper_2210_08024_amd import workloads
-    return workloads.make("c2")
+    return workloads.make("pts256")
 
 
 @pytest.mark.parametrize("prec", [1, 0])
-def test_ray_trace_c2_sampled_and_conservation(ism, c2, prec):
+def test_ray_trace_c2_sampled_and_conservation(ism, pts256, prec):
     """256^3 at 2 pc with 16 sources: sampled cells against the per-cell oracle (every packet
     whose line crosses the cell, walked from its source) -- fields, flux and the radiation
     force from the flux --, and photon conservation over the whole grid: sum of
     alpha J 4 pi dV plus the lost and dropped budgets is the sources' total in every band."""
     import torch
-    s, cfg = c2
+    s, cfg = pts256
     shape = s["n"].shape
     dx = cfg["dx_pc"] * OC.PC
     par = Params()
@@ -275,7 +275,7 @@ def test_ray_trace_c2_sampled_and_conservation(ism, c2, prec):
     rd = torch.float64 if prec == 0 else torch.float32
     out = _zeros(torch, shape, rd)
     out["flux"] = torch.zeros((9,) + shape, dtype=rd, device="cuda")
-    print(f"ray_trace c2 prec={prec} (with flux)", flush=True)
+    print(f"ray_trace pts256 prec={prec} (with flux)", flush=True)
     ism.ray_trace(n, xH2, xHp, None, dx, H.ism_params_from(par), prec, cfg["sources"], out, budget=True)
     torch.cuda.synchronize()
     # conservation (reductions on the device in float64)
@@ -301,9 +301,9 @@ def test_ray_trace_c2_sampled_and_conservation(ism, c2, prec):
     cells = np.concatenate([np.stack(np.unravel_index(idx, shape), 1), np.array(own)])
     ref = art.ray_trace_cells(s["n"], s["xH2"], s["xHp"], None, dx, src, par, cells, flux=True)
     got = {k: out[k][cells[:, 0], cells[:, 1], cells[:, 2]] for k in KEYS}
-    _compare(got, ref, prec, f"c2 prec {prec}")
+    _compare(got, ref, prec, f"pts256 prec {prec}")
     gf = out["flux"][:, cells[:, 0], cells[:, 1], cells[:, 2]].cpu().numpy()
-    _compare_flux(gf, ref["flux"], _cE(ref), prec, f"c2 flux prec {prec}")
+    _compare_flux(gf, ref["flux"], _cE(ref), prec, f"pts256 flux prec {prec}")
     # the radiation force over the whole grid at the configuration's temperatures, sampled
     T = H.to_dev(s["T"]).view(shape)
     off = torch.zeros(shape, dtype=torch.uint8, device="cuda")

@@ -39,8 +39,8 @@ def _rel(a, b, k, xCt):
 def test_c4_full_size_all_paths(ism):
     import torch
     from paper_2210_08024_amd import surrogate_train, workloads
-    print("c4: generating the 512^3 inputs", flush=True)
-    s, cfg = workloads.make("c4")
+    print("pts512: generating the 512^3 inputs", flush=True)
+    s, cfg = workloads.make("pts512")
     shape = s["n"].shape
     N = s["n"].size
     dx = cfg["dx_pc"] * OC.PC
@@ -51,7 +51,7 @@ def test_c4_full_size_all_paths(ism):
     n = dev(s["n"])
     T0, xH2_0, xHp_0 = dev(s["T"]), dev(s["xH2"]), dev(s["xHp"])
     xi = dev(s["xi"])
-    print("c4: point-source maps (F64)", flush=True)
+    print("pts512: point-source maps (F64)", flush=True)
     maps = {k: torch.zeros(N, dtype=torch.float64, device="cuda") for k in ("chi_PE", "chi_LW", "chi_H2", "chi_C", "phi")}
     ism.point_sources(n.view(shape), xH2_0.view(shape), None, dx, par, 0, cfg["sources"],
                       {k: v.view(shape) for k, v in maps.items()})
@@ -74,7 +74,7 @@ def test_c4_full_size_all_paths(ism):
     nfb = torch.zeros(1, dtype=torch.int64, device="cuda")
     got, rad_sample = {}, None
     for path in ("f64", "mixed", "surrogate"):
-        print(f"c4: path {path}", flush=True)
+        print(f"pts512: path {path}", flush=True)
         f64 = path == "f64"
         rd = torch.float64 if f64 else torch.float32
         rad = {k: torch.empty(N, dtype=rd, device="cuda") for k in RAD}
@@ -108,7 +108,7 @@ def test_c4_full_size_all_paths(ism):
         got[path] = g
         del rad, r, out
         torch.cuda.empty_cache()
-    print(f"c4: oracle on {len(idx)} cells", flush=True)
+    print(f"pts512: oracle on {len(idx)} cells", flush=True)
     ref = H.oracle_step(s, rad_sample, dt, par_o, idx=idx)
     sens = np.zeros(len(idx))
     for sign in (1.0, -1.0):
@@ -118,7 +118,7 @@ def test_c4_full_size_all_paths(ism):
         alt = H.oracle_step(sp, rad_sample, dt, par_o, idx=idx)
         for k in FIELDS:
             sens = np.maximum(sens, _rel(alt[k], ref[k], k, par_o.xCtot))
-    H.check_fields(got["f64"], ref, 1e-9, H.FLOORS_F64, par_o.xCtot, label="c4 F64")
+    H.check_fields(got["f64"], ref, 1e-9, H.FLOORS_F64, par_o.xCtot, label="pts512 F64")
     for path in ("mixed", "surrogate"):
         worst = np.zeros(len(idx))
         for k in FIELDS:

@@ -84,20 +84,20 @@ def test_point_sources_add_to_existing_fields_and_edge_cases(ism):
 
 
 @pytest.fixture(scope="module")
-def c2():
+def pts256():
     from paper_2210_08024_amd import workloads
-    return workloads.make("c2")
+    return workloads.make("pts256")
 
 
 @pytest.mark.parametrize("maps_kind", ["art", "lc"])
-def test_c2_ten_steps_sampled(ism, c2, maps_kind):
+def test_c2_ten_steps_sampled(ism, pts256, maps_kind):
     """256^3, 2 pc, 16 sources, CR map: six-ray columns every step, source maps once (from the
     initial state; adaptive ray tracing as in the benchmark, or long characteristics), ten
     mixed steps of 1e4 yr with x_C fed back.  Sampled cells: the maps against the oracle, and
     the first and last steps against the oracle step from the GPU's state and radiation of
     that step (1e-3 in T and abundances, floors as elsewhere)."""
     import torch
-    s, cfg = c2
+    s, cfg = pts256
     shape = s["n"].shape
     N = s["n"].size
     dx = cfg["dx_pc"] * OC.PC
@@ -112,7 +112,7 @@ def test_c2_ten_steps_sampled(ism, c2, maps_kind):
     idx = np.sort(rng.choice(N, 48, replace=False))
     tid = torch.from_numpy(idx).cuda()
     cells = np.stack(np.unravel_index(idx, shape), 1)
-    print(f"c2 ten steps, maps by {maps_kind}", flush=True)
+    print(f"pts256 ten steps, maps by {maps_kind}", flush=True)
     if maps_kind == "art":
         ism.ray_trace(n, xH2.view(shape), xHp.view(shape), None, dx, par, 1, cfg["sources"], maps)
         ref_maps = art.ray_trace_cells(s["n"], s["xH2"], s["xHp"], None, dx, cfg["sources"], par_o, cells)
@@ -147,7 +147,7 @@ def test_c2_ten_steps_sampled(ism, c2, maps_kind):
             g = dict(T=T[tid].cpu().numpy(), xH2=xH2[tid].cpu().numpy(), xHp=xHp[tid].cpu().numpy())
             for k in ("xCp", "xCO", "xe"):
                 g[k] = out[k][tid].cpu().numpy().astype(np.float64)
-            rep = H.check_fields(g, ref, 1e-3, H.FLOORS_MIX, xCt, label=f"c2 step {step}")
-            print(f"c2 step {step}: {rep}", flush=True)
+            rep = H.check_fields(g, ref, 1e-3, H.FLOORS_MIX, xCt, label=f"pts256 step {step}")
+            print(f"pts256 step {step}: {rep}", flush=True)
         xC = (xCt - out["xCp"].double() - out["xCO"].double()).clamp_min(0.0).view(shape)
     assert int((out["status"] & 0xEF).sum().item()) == 0
