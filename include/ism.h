@@ -267,7 +267,9 @@ ism_status ism_rates(const ism_params *p, ism_precision prec, int64_t ncell,
  * coefficients at the new temperature; equilibrium C/O/e closure (Secs. 3.2-3.3).
  * In/out: T, xH2, xHp (double).  In: n (double) and radiation (precision as above;
  * phi_LyC may be NULL = 0).  Optional outputs (NULL to skip): xCp, xCO, xe, nsub
- * (int32 substeps taken), status (uint8 bits above).  F64 evaluates everything in
+ * (int32 substeps taken; with order_cells = 2 its entry values are also read, as the
+ * ordering key, so it must then hold initialised counts), status (uint8 bits above).
+ * F64 evaluates everything in
  * double; MIXED evaluates rates, heating, cooling and the closure in float and keeps
  * the net H, the T update and the abundance update in double. */
 ism_status ism_chem_cool_step(const ism_params *p, ism_precision prec, int64_t ncell, double dt_s,

@@ -346,7 +346,9 @@ def rates(n, T, xH2, xHp, rad, params, prec=F64, out=None, stream=None):
 
 def chem_cool_step(n, T, xH2, xHp, rad, dt_s, params, prec=F64, want=("xCp", "xCO", "xe", "nsub", "status"),
                    out=None, stream=None):
-    """In-place step of T, xH2, xHp (float64 device tensors).  Returns dict of the requested extra outputs."""
+    """In-place step of T, xH2, xHp (float64 device tensors).  Returns dict of the requested extra outputs.
+    With params.order_cells == 2 the entry values of out["nsub"] are the ordering key; a binding-allocated
+    nsub then starts at zero."""
     _ensure_init(n)
     N = n.numel()
     rd = _rdt(prec)
@@ -354,7 +356,8 @@ def chem_cool_step(n, T, xH2, xHp, rad, dt_s, params, prec=F64, want=("xCp", "xC
         out = {}
         for k in want:
             dt = torch.int32 if k == "nsub" else (torch.uint8 if k == "status" else rd)
-            out[k] = torch.empty(N, dtype=dt, device=n.device)
+            alloc = torch.zeros if (k == "nsub" and params.order_cells == 2) else torch.empty
+            out[k] = alloc(N, dtype=dt, device=n.device)
     p = params._c()
     g = out.get
     _check(lib().ism_chem_cool_step(
