@@ -250,16 +250,6 @@ __global__ __launch_bounds__(256) void art_level_kernel(ArtArgs a) {
   }
   R *slot = s_slot + SS * 64 * (threadIdx.x >> 6);
   int *htab = s_htab + ART_HTAB * (threadIdx.x >> 6);
-  R *fields[NV];
-  fields[0] = (R *)a.chiPE;
-  fields[1] = (R *)a.chiLW;
-  fields[2] = (R *)a.chiH2;
-  fields[3] = (R *)a.chiC;
-  fields[4] = (R *)a.phi;
-  if constexpr (FLUX) {
-#pragma unroll
-    for (int k = 0; k < 9; ++k) fields[5 + k] = (R *)a.flux + (int64_t)k * a.ncell;
-  }
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = id < a.nin;
   const int level = a.level;
@@ -318,6 +308,8 @@ __global__ __launch_bounds__(256) void art_level_kernel(ArtArgs a) {
   int it = 0;
   // one cell per trip, uniform over the wave so that its deposits can be combined
   while (__ballot(active)) {
+    // arguments re-read per trip (see kernel_args): none of them is held across the walk
+    const ArtArgs &A = kernel_args<ArtArgs>();
     bool dep = false;
     int32_t vi = 0;
     double v[NV];
@@ -331,35 +323,35 @@ __global__ __launch_bounds__(256) void art_level_kernel(ArtArgs a) {
           // a piece of positive length starts here: the checks at its entry face
           if (r >= r_exit - EXIT_TOL) {
             active = false;
-          } else if (fmin(fmin(a.sPE * NH, a.sLW * NH), tL) > a.tau_max) {
+          } else if (fmin(fmin(A.sPE * NH, A.sLW * NH), tL) > A.tau_max) {
             active = false;
             dropped = true;
-          } else if (level < a.max_level && r * r > a.R2split) {
+          } else if (level < A.max_level && r * r > A.R2split) {
             active = false;
             split = true;
           } else {
-            const double ds = (rn - r) * a.dx;
-            vi = c[0] + a.nx * (c[1] + a.ny * c[2]);
-            const double nn = a.n[vi], x2 = a.xH2[vi], xp = a.xHp[vi];
-            const double xc = a.xC ? a.xC[vi] : 0.0;
+            const double ds = (rn - r) * A.dx;
+            vi = c[0] + A.nx * (c[1] + A.ny * c[2]);
+            const double nn = A.n[vi], x2 = A.xH2[vi], xp = A.xHp[vi];
+            const double xc = A.xC ? A.xC[vi] : 0.0;
             const double xHI = fmax(1.0 - 2.0 * x2 - xp, 0.0);
-            const double aL = nn * (xHI * a.spiH + x2 * a.spiH2 + a.sdLyC);
+            const double aL = nn * (xHI * A.spiH + x2 * A.spiH2 + A.sdLyC);
             double gPE, gLW, gL, fPE, fLW, fL;
-            absorb<R>(a.sPE * nn * ds, gPE, fPE);
-            absorb<R>(a.sLW * nn * ds, gLW, fLW);
+            absorb<R>(A.sPE * nn * ds, gPE, fPE);
+            absorb<R>(A.sLW * nn * ds, gLW, fLW);
             absorb<R>(aL * ds, gL, fL);
             const double mH2 = NH2 + 0.5 * nn * x2 * ds, mC = NC + 0.5 * nn * xc * ds;
-            const double wLW = Lfuv * eLW * ds * gLW * a.fuv_norm;
-            v[0] = Lfuv * ePE * ds * gPE * a.fuv_norm;
+            const double wLW = Lfuv * eLW * ds * gLW * A.fuv_norm;
+            v[0] = Lfuv * ePE * ds * gPE * A.fuv_norm;
             v[1] = wLW;
             v[2] = wLW * f_shld_H2<R>(mH2);
             v[3] = wLW * f_shld_C<R>(mC, mH2, s_cs);
-            v[4] = Lq * eL * ds * gL * a.phi_norm;
+            v[4] = Lq * eL * ds * gL * A.phi_norm;
             if constexpr (FLUX) {
 #pragma unroll
               for (int q2 = 0; q2 < 3; ++q2) {
-                v[5 + q2] = a.kPE * v[0] * u[q2];
-                v[8 + q2] = a.kLW * v[1] * u[q2];
+                v[5 + q2] = A.kPE * v[0] * u[q2];
+                v[8 + q2] = A.kLW * v[1] * u[q2];
                 v[11 + q2] = v[4] * u[q2];
               }
             }
@@ -382,6 +374,16 @@ __global__ __launch_bounds__(256) void art_level_kernel(ArtArgs a) {
             tmax[q] = ((double)(step[q] > 0 ? c[q] + 1 : c[q]) - s[q]) * inv[q];
         }
       }
+    }
+    R *fields[NV];
+    fields[0] = (R *)A.chiPE;
+    fields[1] = (R *)A.chiLW;
+    fields[2] = (R *)A.chiH2;
+    fields[3] = (R *)A.chiC;
+    fields[4] = (R *)A.phi;
+    if constexpr (FLUX) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) fields[5 + k] = (R *)A.flux + (int64_t)k * A.ncell;
     }
     wave_deposit<R, NV>(fields, slot, htab, dep, vi, v);
   }

@@ -19,8 +19,13 @@ __device__ __forceinline__ const CoefT<double> &coef64() {
 }
 
 template <class R> __device__ __forceinline__ const CoefT<R> &coef();
-template <> __device__ __forceinline__ const CoefT<double> &coef<double>() { return g_coef64; }
-template <> __device__ __forceinline__ const CoefT<float> &coef<float>() { return g_coef32; }
+template <> __device__ __forceinline__ const CoefT<double> &coef<double>() { return coef64(); }
+template <> __device__ __forceinline__ const CoefT<float> &coef<float>() {
+  const __attribute__((address_space(4))) CoefT<float> *p =
+      (const __attribute__((address_space(4))) CoefT<float> *)&g_coef32;
+  asm volatile("" : "+s"(p));
+  return *(const CoefT<float> *)p;
+}
 
 template <class R> struct CloseTol;
 template <> struct CloseTol<double> { static constexpr double v = 1e-12; };
@@ -187,24 +192,30 @@ __global__ __launch_bounds__(256) void step_simple_kernel(StepArgs<R> a) {
 constexpr int REFILL_BATCH = 12;
 
 template <class R>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void step_queue_kernel(StepArgs<R> a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void step_queue_kernel(StepArgs<R>) {
+  using A = StepArgs<R>;
   __shared__ R s_tab[TAB_STEP];
-  stage_tables(a.tab, s_tab);
+  stage_tables(kernel_args<A>().tab, s_tab);
   const int lane = threadIdx.x & 63;
-  const int64_t nitem = a.count ? (int64_t)*a.count : a.ncell;
+  const int64_t nitem = kernel_args<A>().count ? (int64_t)*kernel_args<A>().count : kernel_args<A>().ncell;
   int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool active = cell < nitem;
   CellState<R> s;
-  if (active) cell_begin(a, a.idx ? (int64_t)a.idx[cell] : cell, s, s_tab);
+  if (active) {
+    const A &a = kernel_args<A>();
+    cell_begin(a, a.idx ? (int64_t)a.idx[cell] : cell, s, s_tab);
+  }
   bool idle = false;  // cell finished, waiting for the wave's next refill
   while (__ballot(active || idle) != 0) {
-    if (active && cell_substep(a, s, s_tab)) {
+    if (active && cell_substep(kernel_args<A>(), s, s_tab)) {
+      const A &a = kernel_args<A>();
       cell_end(a, a.idx ? (int64_t)a.idx[cell] : cell, s);
       active = false;
       idle = true;
     }
     const uint64_t m = __ballot(idle);
     if (m != 0 && (__popcll(m) >= REFILL_BATCH || __ballot(active) == 0)) {
+      const A &a = kernel_args<A>();
       const int leader = __ffsll((unsigned long long)m) - 1;
       unsigned long long base = 0;
       if (lane == leader) base = atomicAdd((unsigned long long *)a.queue, (unsigned long long)__popcll(m));

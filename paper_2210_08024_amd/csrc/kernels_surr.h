@@ -143,6 +143,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
     double tdg = 0.0;
 #pragma unroll 1
     for (; u[0] > 0.0;) {
+      // arguments and coefficients laundered per iteration (kept out of scalar registers across the loop)
+      const AcceptArgs &A = kernel_args<AcceptArgs>();
+      const CoefT<float> &C = coef<float>();
+      const ParT<float> &P = A.pr;
       // probe point
       double Tq = u[0], aq = u[1], bq = u[2];
       if (phase == 0) {
@@ -154,8 +158,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
       } else {
         Tq = T0 * exp((double)k * 0.25 * log(u[0] / T0));
       }
-      const EqS<float> e = eq_species<float>(Tq, (float)nd, aq, bq, r, c, p, s_tab, CloseTol<float>::v, 50);
-      const Eval<float> v = evaluate<float, false, false>(Tq, nd, aq, bq, e, r, c, p, s_tab, tdg, nullptr);
+      const EqS<float> e = eq_species<float>(Tq, (float)nd, aq, bq, r, C, P, s_tab, CloseTol<float>::v, 50);
+      const Eval<float> v = evaluate<float, false, false>(Tq, nd, aq, bq, e, r, C, P, s_tab, tdg, nullptr);
       tdg = v.Td;
       const double gT = v.H * muH / ((1.1 + (double)e.xe - aq) * K);
       const double g1 = v.CH2, g2 = v.CHp;
@@ -163,7 +167,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
         if (k == 0) {
           gb[0] = gT; gb[1] = g1; gb[2] = g2;
           // pre-test: both chemical relaxation rates must be fast on their own
-          if (dt * (2.0 * v.F + v.D) < 0.5 * a.fast || dt * (v.I + v.Rr) < 0.5 * a.fast) break;
+          if (dt * (2.0 * v.F + v.D) < 0.5 * A.fast || dt * (v.I + v.Rr) < 0.5 * A.fast) break;
           h[1] = 1e-3 * fmax(u[1], 1e-6);
           if (2.0 * (u[1] + h[1]) + u[2] > 1.0) h[1] = -h[1];
           h[2] = 1e-3 * fmax(u[2], 1e-6);
@@ -181,11 +185,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
         double d[3];
         if (!solve3(J, gb, d)) break;
         const double un0 = u[0] + d[0], un1 = u[1] + d[1], un2 = u[2] + d[2];
-        const bool inside = un0 >= a.pd.T_floor && un0 <= 1e9 && un1 >= 0.0 && un2 >= 0.0 &&
+        const bool inside = un0 >= A.pd.T_floor && un0 <= 1e9 && un1 >= 0.0 && un2 >= 0.0 &&
                             2.0 * un1 + un2 <= 1.0;
-        const bool conv = inside && fabs(d[0]) <= a.tol * un0 && fabs(d[1]) <= a.tol * fmax(un1, 1e-10) &&
-                          fabs(d[2]) <= a.tol * fmax(un2, 1e-10);
-        u[0] = fmin(fmax(un0, a.pd.T_floor), 1e9);
+        const bool conv = inside && fabs(d[0]) <= A.tol * un0 && fabs(d[1]) <= A.tol * fmax(un1, 1e-10) &&
+                          fabs(d[2]) <= A.tol * fmax(un2, 1e-10);
+        u[0] = fmin(fmax(un0, A.pd.T_floor), 1e9);
         u[1] = fmin(fmax(un1, 0.0), 0.5);
         u[2] = fmin(fmax(un2, 0.0), 1.0 - 2.0 * u[1]);
         ++it;
@@ -198,7 +202,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
           phase = 1;
           continue;
         }
-        if (it >= a.maxit) break;
+        if (it >= A.maxit) break;
         continue;
       }
       // phase 1: no thermal equilibrium between T_0 and the root

@@ -59,6 +59,18 @@ template <> struct Mx<float> {
 template <class R> __device__ __forceinline__ R rmax(R a, R b) { return a > b ? a : b; }
 template <class R> __device__ __forceinline__ R rmin(R a, R b) { return a < b ? a : b; }
 
+// The kernel's own argument block (at the start of the kernarg segment) through a pointer
+// laundered by an empty asm: loads through it are not hoisted above the call.  A kernel that
+// takes it afresh inside its loop keeps two scalar registers live across the loop instead of
+// every field it reads, which would spill into vector-register lanes and cost a lane read per use.
+template <class A>
+__device__ __forceinline__ const A &kernel_args() {
+  const __attribute__((address_space(4))) A *p =
+      (const __attribute__((address_space(4))) A *)__builtin_amdgcn_kernarg_segment_ptr();
+  asm volatile("" : "+s"(p));
+  return *(const A *)p;
+}
+
 // ---------------------------------------------------------------- tables
 // Clamp x to the grid [x0, x0 + (n-1) dx]; lower node index and fraction (in double).
 __device__ __forceinline__ void axis_pos(double x, double x0, double dx, int n, int &i, double &f) {
