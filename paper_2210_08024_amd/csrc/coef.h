@@ -51,6 +51,12 @@ struct CoefT {
   R rovib_lte[11], rovib_low[7], cp_levels[4], cp_h2_over_h, c_levels[8], c_coll[5], o_levels[8], o_coll[5];
   // ---- derived on the host after loading (logs of constants used inside exponents) ----
   R ln_arrdr_T0, ln_xMH_T0, fs_slope_C, fs_slope_O, ln_lya_T, ln_co0;
+  // ---- quotients of constants, formed once on the host so the kernels multiply ----
+  R c_rat[4], o_rat[4];  // C and O atoms: g1/g0, g2/g0, g2/g1, A10/n_crit,H
+  R cp_rat[2];           // C+: A10/n_crit,H, g1/g0
+  R dust_A;              // sigma_IR(10 K)/100 c a_rad
+  R inv_J_FUV, inv_kci_T, sigmoid_iw;
+  R cie_idx, co_idx, co_idy, cs_idx, cs_idy;  // 1 / table spacing
   // ---- table axes ----
   R cie_x0, cie_dx;
   R co_x0, co_dx, co_y0, co_dy;

@@ -119,6 +119,25 @@ inline bool load_coefficients(const char *path, CoefT<double> &c, std::vector<do
   c.fs_slope_O = std::log(c.o_ncrit_H[0] / c.o_ncrit_H[1]) / std::log(500.0);
   c.ln_lya_T = std::log(c.lya[2]);
   c.ln_co0 = std::log(c.co_fit[0]);
+  const double *lvs[2] = {c.c_levels, c.o_levels}, *ncs[2] = {c.c_ncrit_H, c.o_ncrit_H};
+  double *rats[2] = {c.c_rat, c.o_rat};
+  for (int k = 0; k < 2; ++k) {
+    rats[k][0] = lvs[k][1] / lvs[k][0];
+    rats[k][1] = lvs[k][2] / lvs[k][0];
+    rats[k][2] = lvs[k][2] / lvs[k][1];
+    rats[k][3] = lvs[k][5] / ncs[k][0];
+  }
+  c.cp_rat[0] = c.cp_levels[3] / c.cp_ncrit_H[0];
+  c.cp_rat[1] = c.cp_levels[1] / c.cp_levels[0];
+  c.dust_A = c.sigma_IR10 / 100.0 * C_LIGHT * c.a_rad;
+  c.inv_J_FUV = 1.0 / c.J_FUV;
+  c.inv_kci_T = 1.0 / c.k_ci_H[2];
+  c.sigmoid_iw = 1.0 / (c.sigmoid[2] - c.sigmoid[1]);
+  c.cie_idx = 1.0 / c.cie_dx;
+  c.co_idx = 1.0 / c.co_dx;
+  c.co_idy = 1.0 / c.co_dy;
+  c.cs_idx = 1.0 / c.cs_dx;
+  c.cs_idy = 1.0 / c.cs_dy;
   // log10 cooling columns are kept relative to 1e-24 erg cm^3 s^-1 on the device (see coef.h)
   for (int i = 0; i < CIE_N; ++i)
     for (int k = 0; k < 2; ++k) tab[TAB_CIE + i * CIE_NC + k] += TAB_LOG_OFFSET;

@@ -53,12 +53,12 @@ __device__ __forceinline__ double f_shld_H2(double N) {
 template <class R>
 __device__ __forceinline__ double f_shld_C(double NC, double NH2, const double *cs) {
   const CoefT<double> &c = g_coef64;
-  const double lc = NC > 1e-300 ? Mx<R>::ln(NC) / LN10D : -300.0;
-  const double lh = NH2 > 1e-300 ? Mx<R>::ln(NH2) / LN10D : -300.0;
+  const double lc = NC > 1e-300 ? Mx<R>::ln(NC) * INV_LN10D : -300.0;
+  const double lh = NH2 > 1e-300 ? Mx<R>::ln(NH2) * INV_LN10D : -300.0;
   int i, j;
   double f, g;
-  axis_pos(lc, c.cs_x0, c.cs_dx, CS_NX, i, f);
-  axis_pos(lh, c.cs_y0, c.cs_dy, CS_NY, j, g);
+  axis_pos(lc, c.cs_x0, c.cs_dx, c.cs_idx, CS_NX, i, f);
+  axis_pos(lh, c.cs_y0, c.cs_dy, c.cs_idy, CS_NY, j, g);
   const double v00 = cs[i * CS_NY + j], v01 = cs[i * CS_NY + j + 1];
   const double v10 = cs[(i + 1) * CS_NY + j], v11 = cs[(i + 1) * CS_NY + j + 1];
   return (double)Mx<R>::ex(LN10D * ((v00 * (1.0 - g) + v01 * g) * (1.0 - f) + (v10 * (1.0 - g) + v11 * g) * f));

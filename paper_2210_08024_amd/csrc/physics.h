@@ -26,6 +26,7 @@ constexpr double LN100 = 4.6051701859880913680;
 constexpr double LN1E3 = 6.9077552789821370520;
 constexpr double LN1E4 = 9.2103403719761827361;
 constexpr double LN10D = 2.3025850929940456840;
+constexpr double INV_LN10D = 0.43429448190325182765;  // 1 / ln 10
 
 // ---------------------------------------------------------------- math policies
 template <class R> struct Mx;
@@ -73,10 +74,11 @@ __device__ __forceinline__ const A &kernel_args() {
 
 // ---------------------------------------------------------------- tables
 // Clamp x to the grid [x0, x0 + (n-1) dx]; lower node index and fraction (in double).
-__device__ __forceinline__ void axis_pos(double x, double x0, double dx, int n, int &i, double &f) {
+// idx = 1 / dx.
+__device__ __forceinline__ void axis_pos(double x, double x0, double dx, double idx, int n, int &i, double &f) {
   const double hi = x0 + (double)(n - 1) * dx;
   const double xc = x < x0 ? x0 : (x > hi ? hi : x);
-  const double u = (xc - x0) / dx;
+  const double u = (xc - x0) * idx;
   int k = (int)floor(u);
   k = k > 0 ? k : 0;  // also maps a NaN argument to node 0
   i = k < n - 2 ? k : n - 2;
@@ -88,7 +90,7 @@ __device__ __forceinline__ double cie_lookup(const R *tab, double lgT, int col) 
   const CoefT<double> &c = coef64();
   int i;
   double f;
-  axis_pos(lgT, c.cie_x0, c.cie_dx, CIE_N, i, f);
+  axis_pos(lgT, c.cie_x0, c.cie_dx, c.cie_idx, CIE_N, i, f);
   const R *v = tab + TAB_CIE;
   return (double)v[i * CIE_NC + col] * (1.0 - f) + (double)v[(i + 1) * CIE_NC + col] * f;
 }
@@ -98,8 +100,8 @@ __device__ __forceinline__ double co_lookup(const R *tab, double lT, double lN, 
   const CoefT<double> &c = coef64();
   int i, j;
   double f, g;
-  axis_pos(lT, c.co_x0, c.co_dx, CO_NX, i, f);
-  axis_pos(lN, c.co_y0, c.co_dy, CO_NY, j, g);
+  axis_pos(lT, c.co_x0, c.co_dx, c.co_idx, CO_NX, i, f);
+  axis_pos(lN, c.co_y0, c.co_dy, c.co_idy, CO_NY, j, g);
   const R *v = tab + TAB_CO;
   const double v00 = v[(i * CO_NY + j) * CO_NC + col], v01 = v[(i * CO_NY + j + 1) * CO_NC + col];
   const double v10 = v[((i + 1) * CO_NY + j) * CO_NC + col], v11 = v[((i + 1) * CO_NY + j + 1) * CO_NC + col];
@@ -167,7 +169,7 @@ __device__ __forceinline__ R alpha_gr(const Tq &q, double lnpsi, const double *k
 // Grain charging parameter G0 T^1/2 / n_e + 50 (Sec. 4.1.1), n_e floored at 1e-20 n.
 template <class R>
 __device__ __forceinline__ R psi_charge(R sqrtT, R n, R xe, R chiPE, R chiLW, const CoefT<R> &c) {
-  const R G0 = c.G0_per_chi * ((c.J_PE * chiPE + c.J_LW * chiLW) / c.J_FUV);
+  const R G0 = c.G0_per_chi * ((c.J_PE * chiPE + c.J_LW * chiLW) * c.inv_J_FUV);
   return G0 * sqrtT / (n * rmax(xe, R(1e-20))) + c.psi_off;
 }
 
@@ -190,7 +192,7 @@ __device__ EqS<R> eq_species(double T, R n, double xH2_d, double xHp_d, const Ra
   const R kch = R(cd.k_CpH2[0]) * Mx<R>::ex(cd.k_CpH2[1] * q.lnT - cd.k_CpH2[2] * q.invT) * n * xH2;
   R y, xe;
   if (T >= cd.xe_T_switch) {
-    const double lgT = q.lnT / LN10D;
+    const double lgT = q.lnT * INV_LN10D;
     xe = xHp + R(cie_lookup(tab, lgT, 2)) + p.Zg * R(cie_lookup(tab, lgT, 3));
     const R psi = psi_charge(sqrtT, n, xe, r.chiPE, r.chiLW, c);
     const R B = alpha_gr<R>(q, Mx<R>::ln((double)psi), cd.agr_Cp, Zd) * n + kch;
@@ -253,7 +255,7 @@ __device__ __forceinline__ void fixed_terms(Rad<R> &r, double n_d, const CoefT<R
   const CoefT<double> &cd = coef64();
   r.G = dust_heating_per_Zd(r, c, p);
   const double *qq = cd.q_cr_H2;  // values qq[0..3] at log10 n = qq[4..7], linear between, flat outside
-  const double ln = Mx<R>::ln(n_d) / LN10D;
+  const double ln = Mx<R>::ln(n_d) * INV_LN10D;
   double val;
   if (ln <= qq[4]) val = qq[0];
   else if (ln >= qq[7]) val = qq[3];
@@ -273,7 +275,7 @@ template <> struct RootTol<float> { static constexpr float v = 2e-7f; static con
 
 template <class R>
 __device__ R dust_T(R T, R sqrtT, R n, R G, R guess, R Tbb, const CoefT<R> &c, bool &bad) {
-  const R A = c.sigma_IR10 / R(100) * R(C_LIGHT) * c.a_rad;
+  const R A = c.dust_A;  // sigma_IR(10 K)/100 c a_rad
   const R B = n * c.alpha_gd * sqrtT;
   const R Tbb2 = Tbb * Tbb, Tbb4 = Tbb2 * Tbb2;
   const R rhs = G + B * T;
@@ -318,25 +320,28 @@ __device__ R dust_T(R T, R sqrtT, R n, R G, R guess, R Tbb, const CoefT<R> &c, b
 // 3-level atom (levels 0, 1, 2); H-impact de-excitation k10 follows the printed critical
 // densities as a power law in T (slope precomputed on the host), other partners and
 // transitions are stand-in ratios.  Populations by Cramer's rule with p0 = 1, normalised.
+// rat: g1/g0, g2/g0, g2/g1 and A10 / n_crit,H, formed on the host.
 template <class R>
 __device__ __forceinline__ R three_level_cool(const Tq &q, R n, R xH, R xH2, R xe, const double *lv,
-                                              const double *co, const double *nc, double slope) {
-  const R g0 = R(lv[0]), g1 = R(lv[1]), g2 = R(lv[2]), A10 = R(lv[5]), A20 = R(lv[6]), A21 = R(lv[7]);
+                                              const double *rat, const double *co, const double *nc,
+                                              double slope) {
+  const R A10 = R(lv[5]), A20 = R(lv[6]), A21 = R(lv[7]);
   const double E1 = lv[3], E2 = lv[4];
-  const R kH = R(lv[5] / nc[0]) * Mx<R>::ex(slope * (q.lnT - LN10D));
+  const R kH = R(rat[3]) * Mx<R>::ex(slope * (q.lnT - LN10D));
   const R ke = R(co[3]) * Mx<R>::ex(co[4] * q.lnT4);
   const R part = xH * kH + xH2 * R(co[2]) * kH + xe * ke;
   const R C10 = n * part, C20 = n * R(co[0]) * part, C21 = n * R(co[1]) * part;
-  const R R01 = C10 * (g1 / g0) * Mx<R>::ex(-E1 * q.invT);
-  const R R02 = C20 * (g2 / g0) * Mx<R>::ex(-E2 * q.invT);
-  const R R12 = C21 * (g2 / g1) * Mx<R>::ex(-(E2 - E1) * q.invT);
+  const R R01 = C10 * R(rat[0]) * Mx<R>::ex(-E1 * q.invT);
+  const R R02 = C20 * R(rat[1]) * Mx<R>::ex(-E2 * q.invT);
+  const R R12 = C21 * R(rat[2]) * Mx<R>::ex(-(E2 - E1) * q.invT);
   const R R10 = C10 + A10, R20 = C20 + A20, R21 = C21 + A21;
   const R det = R10 * R20 + R10 * R21 + R12 * R20;
-  R p1 = (R01 * (R20 + R21) + R21 * R02) / det;
-  R p2 = (R02 * (R10 + R12) + R12 * R01) / det;
-  const R sum = R(1) + p1 + p2;
-  p1 /= sum;
-  p2 /= sum;
+  const R idet = R(1) / det;
+  R p1 = (R01 * (R20 + R21) + R21 * R02) * idet;
+  R p2 = (R02 * (R10 + R12) + R12 * R01) * idet;
+  const R isum = R(1) / (R(1) + p1 + p2);
+  p1 *= isum;
+  p2 *= isum;
   return (p1 * A10 * R(E1) + p2 * (A20 * R(E2) + A21 * R(E2 - E1))) * R(K_B) / n;
 }
 
@@ -381,7 +386,7 @@ __device__ Eval<R> evaluate(double T, double n_d, double xH2_d, double xHp_d, co
   const R kcdH2 = c.k_cd_H2[0] * Mx<R>::ex(cd.k_cd_H2[1] * q.lnT - cd.k_cd_H2[3] * Mx<R>::ln(1.0 + cd.k_cd_H2[2] * T) -
                                            cd.k_cd_H2[4] * q.invT);
   const R zcd = n * (xH * kcdH + xH2 * kcdH2);
-  const R kci = c.k_ci_H[0] * sqrtT * Mx<R>::ex(-cd.k_ci_H[1] * q.invT) / (R(1) + Mx<R>::sq(R(T / cd.k_ci_H[2])));
+  const R kci = c.k_ci_H[0] * sqrtT * Mx<R>::ex(-cd.k_ci_H[1] * q.invT) / (R(1) + Mx<R>::sq(R(T * cd.inv_kci_T)));
   const R zci = kci * n * xe;
   const R aB = c.alpha_B[0] * Mx<R>::ex((cd.alpha_B[1] + cd.alpha_B[2] * q.lnT4) * q.lnT4);
   const R agrH = alpha_gr<R>(q, lnpsi, cd.agr_Hp, Zd);
@@ -405,7 +410,7 @@ __device__ Eval<R> evaluate(double T, double n_d, double xH2_d, double xHp_d, co
   if (CHEM_ONLY) return v;
   const R ev = R(EV);
   // heating, Sec. 4.1
-  const R G0 = c.G0_per_chi * ((c.J_PE * r.chiPE + c.J_LW * r.chiLW) / c.J_FUV);
+  const R G0 = c.G0_per_chi * ((c.J_PE * r.chiPE + c.J_LW * r.chiLW) * c.inv_J_FUV);
   const R eps = (c.pe_C[0] + c.pe_C[1] * Mx<R>::ex(cd.pe_C[4] * q.lnT)) /
                 (R(1) + c.pe_C[2] * Mx<R>::ex(cd.pe_C[5] * lnpsi) * (R(1) + c.pe_C[3] * Mx<R>::ex(cd.pe_C[6] * lnpsi)));
   const R g_pe = c.pe_pref * G0 * eps * Zd;
@@ -440,7 +445,7 @@ __device__ Eval<R> evaluate(double T, double n_d, double xH2_d, double xHp_d, co
     const R Llte = Lrot + Lvib;
     // the quartic in log10 T cancels terms of ~1e2 down to ~-24: kept in double
     const double *b = cd.rovib_low;
-    double lg = q.lnT / LN10D;
+    double lg = q.lnT * INV_LN10D;
     lg = lg < b[5] ? b[5] : (lg > b[6] ? b[6] : lg);
     const R L0 = Mx<R>::ex(LN10D * (b[0] + lg * (b[1] + lg * (b[2] + lg * (b[3] + lg * b[4])))));
     const R np_ = n * (xH + xH2);
@@ -454,22 +459,24 @@ __device__ Eval<R> evaluate(double T, double n_d, double xH2_d, double xHp_d, co
   // C+ 2-level
   R l_cp;
   {
-    const R g0 = c.cp_levels[0], g1 = c.cp_levels[1], E10 = c.cp_levels[2], A10 = c.cp_levels[3];
+    const R E10 = c.cp_levels[2], A10 = c.cp_levels[3];
     const double lnT2 = q.lnT - LN100;
-    const R k10H = (A10 / c.cp_ncrit_H[0]) * Mx<R>::ex((cd.cp_ncrit_H[1] + cd.cp_ncrit_H[2] * lnT2) * lnT2);
+    const R k10H = c.cp_rat[0] * Mx<R>::ex((cd.cp_ncrit_H[1] + cd.cp_ncrit_H[2] * lnT2) * lnT2);
     const R k10e = A10 / (c.cp_ncrit_e * Mx<R>::sq(T4));
     const R C10 = n * (xH * k10H + xH2 * c.cp_h2_over_h * k10H + xe * k10e);
-    const R C01 = C10 * (g1 / g0) * Mx<R>::ex(-cd.cp_levels[2] * q.invT);
+    const R C01 = C10 * c.cp_rat[1] * Mx<R>::ex(-cd.cp_levels[2] * q.invT);
     const R f1 = C01 / (C01 + C10 + A10);
     l_cp = e.xCp * f1 * A10 * R(K_B) * E10 / n;
   }
-  const R l_c = e.xC * three_level_cool<R>(q, n, xH, xH2, xe, cd.c_levels, cd.c_coll, cd.c_ncrit_H, cd.fs_slope_C);
-  const R l_o = e.xO * three_level_cool<R>(q, n, xH, xH2, xe, cd.o_levels, cd.o_coll, cd.o_ncrit_H, cd.fs_slope_O);
+  const R l_c = e.xC * three_level_cool<R>(q, n, xH, xH2, xe, cd.c_levels, cd.c_rat, cd.c_coll, cd.c_ncrit_H,
+                                             cd.fs_slope_C);
+  const R l_o = e.xO * three_level_cool<R>(q, n, xH, xH2, xe, cd.o_levels, cd.o_rat, cd.o_coll, cd.o_ncrit_H,
+                                             cd.fs_slope_O);
   R l_co;
   {
     const R Nt = n * e.xCO * R(PC_CM) / p.dvdr;
-    const double lT = q.lnT / LN10D;
-    const double lN = Nt > R(0) ? Mx<R>::ln((double)Nt) / LN10D : -300.0;
+    const double lT = q.lnT * INV_LN10D;
+    const double lN = Nt > R(0) ? Mx<R>::ln((double)Nt) * INV_LN10D : -300.0;
     // log10 columns are stored as log10(value) + TAB_LOG_OFFSET (see coef.h)
     const R L0 = Mx<R>::ex(LN10D * (co_lookup(tab, lT, lN, 0) - TAB_LOG_OFFSET));
     const R nh = Mx<R>::ex(LN10D * co_lookup(tab, lT, lN, 1));
@@ -485,7 +492,7 @@ __device__ Eval<R> evaluate(double T, double n_d, double xH2_d, double xHp_d, co
     for (int k = 6; k >= 0; --k) f = f * q.lnT4 + cd.neb_a[k];
     // exp(-E/T4) f_neb as one exponent: each factor alone can leave float range
     const R ef = Mx<R>::ex(LN10D * f - cd.neb[1] * 1e4 * q.invT);
-    const R ne2 = n * xe / R(100);
+    const R ne2 = n * xe * R(0.01);
     const double expo = cd.neb[3] - cd.neb[4] * q.lnT4;
     const R dens = ne2 > R(0) ? Mx<R>::ex(expo * Mx<R>::ln((double)ne2))
                               : (expo > 0.0 ? R(0) : (expo < 0.0 ? R(INFINITY) : R(1)));
@@ -499,9 +506,9 @@ __device__ Eval<R> evaluate(double T, double n_d, double xH2_d, double xHp_d, co
   v.Td = Td;
   v.td_bad = bad;
   const R l_gd = R(cd.alpha_gd * sqrtTd * (T - Td) * (double)Zd);
-  const R S = R(1) / (R(1) + Mx<R>::ex(-cd.sigmoid[0] * (T - 0.5 * (cd.sigmoid[1] + cd.sigmoid[2])) /
-                                         (cd.sigmoid[2] - cd.sigmoid[1])));
-  const double lgT = q.lnT / LN10D;
+  const R S = R(1) / (R(1) + Mx<R>::ex(-cd.sigmoid[0] * (T - 0.5 * (cd.sigmoid[1] + cd.sigmoid[2])) *
+                                         cd.sigmoid_iw));
+  const double lgT = q.lnT * INV_LN10D;
   const R l_cie = Mx<R>::ex(LN10D * (cie_lookup(tab, lgT, 0) - TAB_LOG_OFFSET)) +
                   Zg * Mx<R>::ex(LN10D * (cie_lookup(tab, lgT, 1) - TAB_LOG_OFFSET));
   const double l_hyd = (double)l_lya + (double)l_ci + (double)l_rv + (double)l_cd + (double)l_ff + (double)l_rr;
