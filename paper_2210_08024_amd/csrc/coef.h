@@ -67,7 +67,7 @@ struct CoefT {
 template <class R>
 struct ParT {
   R Zg, Zd, chi0, dvdr, eps_sub, fd_rel, T_floor, T_bb, tau_ratio;
-  R xCt, xOt, muH, lnZd;
+  R xCt, xOt, muH, lnZd, idvdr;  // idvdr = 1 / dvdr
   int32_t kgr_const, h2_rovib, max_sub, cr_mode;
 };
 

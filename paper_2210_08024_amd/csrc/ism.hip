@@ -111,6 +111,7 @@ ParT<R> make_par(const ism_params *p, const CoefT<double> &c) {
   q.xOt = (R)(c.xOt_per_Zg * p->Zg);
   q.muH = (R)(c.muH0 - c.muH_slope * (p->Zg - 1.0));
   q.lnZd = (R)std::log(p->Zd);
+  q.idvdr = (R)(1.0 / p->dvdr_kms_pc);
   q.kgr_const = p->kgr_const; q.h2_rovib = p->h2_rovib; q.max_sub = p->max_substeps; q.cr_mode = p->cr_mode;
   return q;
 }

@@ -132,8 +132,9 @@ __device__ __forceinline__ bool cell_substep(const StepArgs<R> &a, CellState<R> 
   Eval<R> vc = evaluate<R, true, false>(Tp, s.nd, s.xH2, s.xHp, s.e, s.r, c, p, tab, s.tdg, nullptr);
   const double F = vc.F, D = vc.D, I = vc.I, Rr = vc.Rr;
   const double det = 1.0 + dts * (2.0 * F + D + I + Rr) + dts * dts * (2.0 * F * Rr + D * I + D * Rr);
-  const double xa = (s.xH2 * (1.0 + dts * (I + Rr)) + F * dts * (1.0 - s.xHp) + F * dts * dts * Rr) / det;
-  const double xb = (s.xHp * (1.0 + dts * (2.0 * F + D)) + I * dts * (1.0 - 2.0 * s.xH2) + I * dts * dts * D) / det;
+  const double idet = 1.0 / det;
+  const double xa = (s.xH2 * (1.0 + dts * (I + Rr)) + F * dts * (1.0 - s.xHp) + F * dts * dts * Rr) * idet;
+  const double xb = (s.xHp * (1.0 + dts * (2.0 * F + D)) + I * dts * (1.0 - 2.0 * s.xH2) + I * dts * dts * D) * idet;
   s.e = eq_species<R>(Tp, R(s.nd), xa, xb, s.r, c, p, tab, CloseTol<R>::v, 50);
   const bool fin = isfinite(Tmu_new) && isfinite(xa) && isfinite(xb);
   if (!fin) s.st |= ISM_ST_NONFINITE;

@@ -116,6 +116,7 @@ struct Rad {
   R G;      // dust heating per Z'_d
   R qH2;    // heat per CR ionisation of H2, erg
   R ncrit;  // critical density of the CO fit
+  R qn2;    // (ncrit / n)^2
 };
 
 template <class R>
@@ -221,10 +222,10 @@ __device__ EqS<R> eq_species(double T, R n, double xH2_d, double xHp_d, const Ra
   y = y < xCt ? y : xCt;
   e.xCp = y;
   e.xe = xe;
+  // a true quotient: 1 - frac below cancels when C is nearly all ionised
   const R fr = rmax(y / xCt, xHp);
   const R frac = fr < R(1) ? fr : R(1);
-  const R qq = r.ncrit / n;
-  e.xCO = xCt * R(2) * xH2 * (R(1) - frac) / (R(1) + qq * qq);
+  e.xCO = xCt * R(2) * xH2 * (R(1) - frac) / (R(1) + r.qn2);
   e.xC = xCt - y - e.xCO;
   e.xO = R((double)xOt * (1.0 - xHp_d)) - e.xCO;  // x_O,tot - x_O+ formed in double (x_H+ -> 1)
   return e;
@@ -267,6 +268,8 @@ __device__ __forceinline__ void fixed_terms(Rad<R> &r, double n_d, const CoefT<R
   const double lxi = Mx<R>::ln((double)xi16);
   r.ncrit = Mx<R>::ex((double)Mx<R>::cb(r.chiLW) * (cd.ln_co0 + (double)p.lnZd - 2.0 * lxi)) *
             (c.co_fit[1] * xi16 / Mx<R>::ex(cd.co_fit[2] * (double)p.lnZd));
+  const R qn = r.ncrit / R(n_d);
+  r.qn2 = qn * qn;
 }
 
 template <class R> struct RootTol;
@@ -322,7 +325,7 @@ __device__ R dust_T(R T, R sqrtT, R n, R G, R guess, R Tbb, const CoefT<R> &c, b
 // transitions are stand-in ratios.  Populations by Cramer's rule with p0 = 1, normalised.
 // rat: g1/g0, g2/g0, g2/g1 and A10 / n_crit,H, formed on the host.
 template <class R>
-__device__ __forceinline__ R three_level_cool(const Tq &q, R n, R xH, R xH2, R xe, const double *lv,
+__device__ __forceinline__ R three_level_cool(const Tq &q, R n, R inv_n, R xH, R xH2, R xe, const double *lv,
                                               const double *rat, const double *co, const double *nc,
                                               double slope) {
   const R A10 = R(lv[5]), A20 = R(lv[6]), A21 = R(lv[7]);
@@ -342,7 +345,7 @@ __device__ __forceinline__ R three_level_cool(const Tq &q, R n, R xH, R xH2, R x
   const R isum = R(1) / (R(1) + p1 + p2);
   p1 *= isum;
   p2 *= isum;
-  return (p1 * A10 * R(E1) + p2 * (A20 * R(E2) + A21 * R(E2 - E1))) * R(K_B) / n;
+  return (p1 * A10 * R(E1) + p2 * (A20 * R(E2) + A21 * R(E2 - E1))) * R(K_B) * inv_n;
 }
 
 // ---------------------------------------------------------------- diagnostics layout
@@ -409,6 +412,7 @@ __device__ Eval<R> evaluate(double T, double n_d, double xH2_d, double xHp_d, co
   }
   if (CHEM_ONLY) return v;
   const R ev = R(EV);
+  const R inv_n = R(1) / n;
   // heating, Sec. 4.1
   const R G0 = c.G0_per_chi * ((c.J_PE * r.chiPE + c.J_LW * r.chiLW) * c.inv_J_FUV);
   const R eps = (c.pe_C[0] + c.pe_C[1] * Mx<R>::ex(cd.pe_C[4] * q.lnT)) /
@@ -452,7 +456,7 @@ __device__ Eval<R> evaluate(double T, double n_d, double xH2_d, double xHp_d, co
     const R nL0 = np_ * L0;
     // = Llte n L0 / (n L0 + Llte) without forming the tiny product; 0 when either rate is 0
     const R L = (nL0 > R(0) && Llte > R(0)) ? nL0 / (R(1) + nL0 / Llte) : R(0);
-    l_rv = xH2 * L / n;
+    l_rv = xH2 * L * inv_n;
   }
   const R l_ff = c.ff[0] * c.ff[1] * sqrtT * xe * xHp;
   const R l_rr = aB * R(K_B) * Tr * R(cd.rr_energy[0] + cd.rr_energy[1] * q.lnT4) * xe * xHp;
@@ -466,15 +470,15 @@ __device__ Eval<R> evaluate(double T, double n_d, double xH2_d, double xHp_d, co
     const R C10 = n * (xH * k10H + xH2 * c.cp_h2_over_h * k10H + xe * k10e);
     const R C01 = C10 * c.cp_rat[1] * Mx<R>::ex(-cd.cp_levels[2] * q.invT);
     const R f1 = C01 / (C01 + C10 + A10);
-    l_cp = e.xCp * f1 * A10 * R(K_B) * E10 / n;
+    l_cp = e.xCp * f1 * A10 * R(K_B) * E10 * inv_n;
   }
-  const R l_c = e.xC * three_level_cool<R>(q, n, xH, xH2, xe, cd.c_levels, cd.c_rat, cd.c_coll, cd.c_ncrit_H,
+  const R l_c = e.xC * three_level_cool<R>(q, n, inv_n, xH, xH2, xe, cd.c_levels, cd.c_rat, cd.c_coll, cd.c_ncrit_H,
                                              cd.fs_slope_C);
-  const R l_o = e.xO * three_level_cool<R>(q, n, xH, xH2, xe, cd.o_levels, cd.o_rat, cd.o_coll, cd.o_ncrit_H,
+  const R l_o = e.xO * three_level_cool<R>(q, n, inv_n, xH, xH2, xe, cd.o_levels, cd.o_rat, cd.o_coll, cd.o_ncrit_H,
                                              cd.fs_slope_O);
   R l_co;
   {
-    const R Nt = n * e.xCO * R(PC_CM) / p.dvdr;
+    const R Nt = n * e.xCO * R(PC_CM) * p.idvdr;
     const double lT = q.lnT * INV_LN10D;
     const double lN = Nt > R(0) ? Mx<R>::ln((double)Nt) * INV_LN10D : -300.0;
     // log10 columns are stored as log10(value) + TAB_LOG_OFFSET (see coef.h)
