@@ -2,7 +2,7 @@
 //
 // The device library's exp and log handle every corner of the IEEE range and cost about 50 and
 // 110 instructions; the source step calls them some 90 and 20 times per substep and is bound by
-// instruction issue.  These versions follow the constructions below, take about 18 and 30
+// instruction issue.  These versions follow the constructions below, take about 22 and 30
 // instructions, and stay within a few ulp over the arguments the step produces.
 #pragma once
 #include <hip/hip_runtime.h>

@@ -117,6 +117,7 @@ struct Rad {
   R qH2;    // heat per CR ionisation of H2, erg
   R ncrit;  // critical density of the CO fit
   R qn2;    // (ncrit / n)^2
+  R G0f;    // FUV field G0
 };
 
 template <class R>
@@ -167,10 +168,15 @@ __device__ __forceinline__ R alpha_gr(const Tq &q, double lnpsi, const double *k
   return R(1e-14 * k[0]) * Zd / (R(1) + R(k[1]) * a * (R(1) + R(k[3]) * b));
 }
 
+// FUV field G0 of a cell from its attenuation factors (Sec. 4.1.1).
+template <class R>
+__device__ __forceinline__ R g0_field(R chiPE, R chiLW, const CoefT<R> &c) {
+  return c.G0_per_chi * ((c.J_PE * chiPE + c.J_LW * chiLW) * c.inv_J_FUV);
+}
+
 // Grain charging parameter G0 T^1/2 / n_e + 50 (Sec. 4.1.1), n_e floored at 1e-20 n.
 template <class R>
-__device__ __forceinline__ R psi_charge(R sqrtT, R n, R xe, R chiPE, R chiLW, const CoefT<R> &c) {
-  const R G0 = c.G0_per_chi * ((c.J_PE * chiPE + c.J_LW * chiLW) * c.inv_J_FUV);
+__device__ __forceinline__ R psi_charge(R sqrtT, R n, R xe, R G0, const CoefT<R> &c) {
   return G0 * sqrtT / (n * rmax(xe, R(1e-20))) + c.psi_off;
 }
 
@@ -195,7 +201,7 @@ __device__ EqS<R> eq_species(double T, R n, double xH2_d, double xHp_d, const Ra
   if (T >= cd.xe_T_switch) {
     const double lgT = q.lnT * INV_LN10D;
     xe = xHp + R(cie_lookup(tab, lgT, 2)) + p.Zg * R(cie_lookup(tab, lgT, 3));
-    const R psi = psi_charge(sqrtT, n, xe, r.chiPE, r.chiLW, c);
+    const R psi = psi_charge(sqrtT, n, xe, r.G0f, c);
     const R B = alpha_gr<R>(q, Mx<R>::ln((double)psi), cd.agr_Cp, Zd) * n + kch;
     const R dh = a + B + cc * xe;
     y = a > R(0) ? xCt * a / (dh > R(0) ? dh : R(1)) : R(0);
@@ -206,7 +212,7 @@ __device__ EqS<R> eq_species(double T, R n, double xH2_d, double xHp_d, const Ra
     xe = xe0 + xCt;
     y = R(0);
     for (int it = 0; it < maxit; ++it) {
-      const R psi = psi_charge(sqrtT, n, xe, r.chiPE, r.chiLW, c);
+      const R psi = psi_charge(sqrtT, n, xe, r.G0f, c);
       const R B = alpha_gr<R>(q, Mx<R>::ln((double)psi), cd.agr_Cp, Zd) * n + kch;
       const R pp = a + B + cc * xe0;
       const R den = pp + Mx<R>::sq(pp * pp + R(4) * cc * xCt * a);
@@ -255,6 +261,7 @@ template <class R>
 __device__ __forceinline__ void fixed_terms(Rad<R> &r, double n_d, const CoefT<R> &c, const ParT<R> &p) {
   const CoefT<double> &cd = coef64();
   r.G = dust_heating_per_Zd(r, c, p);
+  r.G0f = g0_field(r.chiPE, r.chiLW, c);
   const double *qq = cd.q_cr_H2;  // values qq[0..3] at log10 n = qq[4..7], linear between, flat outside
   const double ln = Mx<R>::ln(n_d) * INV_LN10D;
   double val;
@@ -375,7 +382,7 @@ __device__ Eval<R> evaluate(double T, double n_d, double xH2_d, double xHp_d, co
   // x_H = 1 - 2 x_H2 - x_H+ cancels when hydrogen is nearly all molecular or ionised: formed in double
   const double xHd = 1.0 - 2.0 * xH2_d - xHp_d;
   const R xH = R(xHd > 0.0 ? xHd : 0.0);
-  const R psi = psi_charge(sqrtT, n, xe, r.chiPE, r.chiLW, c);
+  const R psi = psi_charge(sqrtT, n, xe, r.G0f, c);
   const double lnpsi = Mx<R>::ln((double)psi);
   // chemistry, Eqs. e:HH and e:HII
   const R kgr = k_gr(q, c, p);
@@ -414,7 +421,7 @@ __device__ Eval<R> evaluate(double T, double n_d, double xH2_d, double xHp_d, co
   const R ev = R(EV);
   const R inv_n = R(1) / n;
   // heating, Sec. 4.1
-  const R G0 = c.G0_per_chi * ((c.J_PE * r.chiPE + c.J_LW * r.chiLW) * c.inv_J_FUV);
+  const R G0 = r.G0f;
   const R eps = (c.pe_C[0] + c.pe_C[1] * Mx<R>::ex(cd.pe_C[4] * q.lnT)) /
                 (R(1) + c.pe_C[2] * Mx<R>::ex(cd.pe_C[5] * lnpsi) * (R(1) + c.pe_C[3] * Mx<R>::ex(cd.pe_C[6] * lnpsi)));
   const R g_pe = c.pe_pref * G0 * eps * Zd;
