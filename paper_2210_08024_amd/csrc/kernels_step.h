@@ -103,7 +103,7 @@ __device__ __forceinline__ bool cell_substep(const StepArgs<R> &a, CellState<R> 
 #pragma unroll 1
   for (int k = 0; k < 2; ++k) {
     const Eval<R> w = evaluate<R, false, false>(k == 0 ? Ta : Ta * (1.0 + delta), s.nd, s.xH2, s.xHp, s.e, s.r, c,
-                                                p, tab, s.tdg, nullptr);
+                                                p, tab, s.tdg, nullptr, k == 0);
     td_bad = td_bad || w.td_bad;
     if (k == 0) {
       v = w;

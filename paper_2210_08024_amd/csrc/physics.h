@@ -14,6 +14,7 @@
 
 #include "coef.h"
 #include "fmath.h"
+#include <type_traits>
 
 namespace ism {
 
@@ -341,9 +342,13 @@ __device__ __forceinline__ R three_level_cool(const Tq &q, R n, R inv_n, R xH, R
   const R ke = R(co[3]) * Mx<R>::ex(co[4] * q.lnT4);
   const R part = xH * kH + xH2 * R(co[2]) * kH + xe * ke;
   const R C10 = n * part, C20 = n * R(co[0]) * part, C21 = n * R(co[1]) * part;
-  const R R01 = C10 * R(rat[0]) * Mx<R>::ex(-E1 * q.invT);
-  const R R02 = C20 * R(rat[1]) * Mx<R>::ex(-E2 * q.invT);
-  const R R12 = C21 * R(rat[2]) * Mx<R>::ex(-(E2 - E1) * q.invT);
+  const double b1 = (double)Mx<R>::ex(-E1 * q.invT), b2 = (double)Mx<R>::ex(-E2 * q.invT);
+  const R R01 = C10 * R(rat[0]) * R(b1);
+  const R R02 = C20 * R(rat[1]) * R(b2);
+  // in double the 1-2 Boltzmann factor is the quotient of the other two (both stay normal for
+  // T >= 1 K), a division in place of an exp
+  const R b12 = std::is_same<R, double>::value ? R(b2 / b1) : Mx<R>::ex(-(E2 - E1) * q.invT);
+  const R R12 = C21 * R(rat[2]) * b12;
   const R R10 = C10 + A10, R20 = C20 + A20, R21 = C21 + A21;
   const R det = R10 * R20 + R10 * R21 + R12 * R20;
   const R idet = R(1) / det;
@@ -369,7 +374,8 @@ enum Diag {
 // every term into diag[NDIAG].
 template <class R, bool CHEM_ONLY, bool DIAG>
 __device__ Eval<R> evaluate(double T, double n_d, double xH2_d, double xHp_d, const EqS<R> &e, const Rad<R> &r,
-                            const CoefT<R> &c, const ParT<R> &p, const R *tab, double td_guess, R *diag) {
+                            const CoefT<R> &c, const ParT<R> &p, const R *tab, double td_guess, R *diag,
+                            bool chem = true) {
   const CoefT<double> &cd = coef64();
   Eval<R> v;
   const Tq q = make_tq<R>(T);
@@ -399,7 +405,9 @@ __device__ Eval<R> evaluate(double T, double n_d, double xH2_d, double xHp_d, co
   const R kci = c.k_ci_H[0] * sqrtT * Mx<R>::ex(-cd.k_ci_H[1] * q.invT) / (R(1) + Mx<R>::sq(R(T * cd.inv_kci_T)));
   const R zci = kci * n * xe;
   const R aB = c.alpha_B[0] * Mx<R>::ex((cd.alpha_B[1] + cd.alpha_B[2] * q.lnT4) * q.lnT4);
-  const R agrH = alpha_gr<R>(q, lnpsi, cd.agr_Hp, Zd);
+  // H+ grain recombination enters only the rates; skipped (chem = false) where a caller takes
+  // nothing but the heating and cooling from this evaluation
+  const R agrH = chem ? alpha_gr<R>(q, lnpsi, cd.agr_Hp, Zd) : R(0);
   v.F = kgr * n;
   v.D = c.cr_destr * zcrH2 + zpd + zpiH2 + zcd;
   v.I = zpiH + zcrH + zci;
