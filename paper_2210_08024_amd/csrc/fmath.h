@@ -40,9 +40,9 @@ __host__ __device__ __forceinline__ double fexp(double x) {
 }
 
 // ln x: x = 2^e m with m in [sqrt(1/2), sqrt(2)); with f = m - 1 (exact) and s = f / (2 + f),
-// ln m = 2 atanh s = 2 (s + s^3/3 + ... + s^21/21) for |s| <= 0.1716 (remainder below 3e-19
-// relative); ln x = e ln2 + ln m.  0 gives -inf, +inf gives +inf, negative arguments and NaN
-// give NaN.
+// ln m = 2 atanh s = 2 s + s z p(z), z = s^2 <= 0.02944, with p a degree-6 Chebyshev fit of
+// 2 (atanh s - s) / s^3 on z <= 0.0295 (coefficients from fmath_fit.py; 0.04 ulp);
+// ln x = e ln2 + ln m.  0 gives -inf, +inf gives +inf, negative arguments and NaN give NaN.
 __host__ __device__ __forceinline__ double flog(double x) {
   int e;
   double m = frexp(x, &e);  // m in [0.5, 1)
@@ -52,16 +52,13 @@ __host__ __device__ __forceinline__ double flog(double x) {
   const double f = m - 1.0;
   const double s = f / (2.0 + f);
   const double z = s * s;
-  double p = 2.0 / 21.0;
-  p = fma(p, z, 2.0 / 19.0);
-  p = fma(p, z, 2.0 / 17.0);
-  p = fma(p, z, 2.0 / 15.0);
-  p = fma(p, z, 2.0 / 13.0);
-  p = fma(p, z, 2.0 / 11.0);
-  p = fma(p, z, 2.0 / 9.0);
-  p = fma(p, z, 2.0 / 7.0);
-  p = fma(p, z, 2.0 / 5.0);
-  p = fma(p, z, 2.0 / 3.0);
+  double p = 0x1.2b6776a1bf0b9p-3;
+  p = fma(p, z, 0x1.39fd25d62ab23p-3);
+  p = fma(p, z, 0x1.7462be245eae3p-3);
+  p = fma(p, z, 0x1.c71c62c42db89p-3);
+  p = fma(p, z, 0x1.2492492e0b70cp-2);
+  p = fma(p, z, 0x1.99999999951f5p-2);
+  p = fma(p, z, 0x1.5555555555558p-1);
   const double lm = fma(s * z, p, s + s);
   const double de = (double)e;
   const double r = fma(de, LN2_HEAD, fma(de, LN2_TAIL, lm));
