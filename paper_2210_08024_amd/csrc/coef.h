@@ -55,7 +55,7 @@ struct CoefT {
   R c_rat[4], o_rat[4];  // C and O atoms: g1/g0, g2/g0, g2/g1, A10/n_crit,H
   R cp_rat[2];           // C+: A10/n_crit,H, g1/g0
   R dust_A;              // sigma_IR(10 K)/100 c a_rad
-  R inv_J_FUV, inv_kci_T, sigmoid_iw;
+  R inv_J_FUV, inv_kci_T, rsqrt_kci_T, sigmoid_iw;  // 1 / k_ci_H[2] and its square root
   R cie_idx, co_idx, co_idy, cs_idx, cs_idy;  // 1 / table spacing
   // ---- table axes ----
   R cie_x0, cie_dx;

@@ -132,6 +132,7 @@ inline bool load_coefficients(const char *path, CoefT<double> &c, std::vector<do
   c.dust_A = c.sigma_IR10 / 100.0 * C_LIGHT * c.a_rad;
   c.inv_J_FUV = 1.0 / c.J_FUV;
   c.inv_kci_T = 1.0 / c.k_ci_H[2];
+  c.rsqrt_kci_T = 1.0 / std::sqrt(c.k_ci_H[2]);
   c.sigmoid_iw = 1.0 / (c.sigmoid[2] - c.sigmoid[1]);
   c.cie_idx = 1.0 / c.cie_dx;
   c.co_idx = 1.0 / c.co_dx;

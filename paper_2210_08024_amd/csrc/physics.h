@@ -153,10 +153,12 @@ __device__ __forceinline__ Tq make_tq(double T) {
 
 // ---------------------------------------------------------------- rate coefficients (Sec. 3)
 template <class R>
-__device__ __forceinline__ R k_gr(const Tq &q, const CoefT<R> &c, const ParT<R> &p) {
+__device__ __forceinline__ R k_gr(const Tq &q, R sqrtT, const CoefT<R> &c, const ParT<R> &p) {
   if (p.kgr_const) return c.kgr0 * p.Zd;
   const R T2 = R(q.T * 0.01);
-  const R s = Mx<R>::sq(T2);
+  // (T / 100)^1/2: from sqrt T in double; in float its own root (a float product there moved the
+  // mixed path's most sensitive cells past their tolerance)
+  const R s = std::is_same<R, double>::value ? sqrtT * R(0.1) : Mx<R>::sq(T2);
   return c.kgr0 * p.Zd * c.kgr_shape[0] * s /
          (R(1) + c.kgr_shape[1] * s + c.kgr_shape[2] * T2 + c.kgr_shape[3] * T2 * T2);
 }
@@ -391,7 +393,7 @@ __device__ Eval<R> evaluate(double T, double n_d, double xH2_d, double xHp_d, co
   const R psi = psi_charge(sqrtT, n, xe, r.G0f, c);
   const double lnpsi = Mx<R>::ln((double)psi);
   // chemistry, Eqs. e:HH and e:HII
-  const R kgr = k_gr(q, c, p);
+  const R kgr = k_gr(q, sqrtT, c, p);
   const R zcrH2 = c.cr_coef[0] * r.xi * (c.cr_coef[1] * xH2 + c.cr_coef[2] * xH);
   const R zcrH = R(0.5) * zcrH2;
   const R zpd = c.zeta_pd * r.chiH2;
@@ -402,7 +404,8 @@ __device__ Eval<R> evaluate(double T, double n_d, double xH2_d, double xHp_d, co
   const R kcdH2 = c.k_cd_H2[0] * Mx<R>::ex(cd.k_cd_H2[1] * q.lnT - cd.k_cd_H2[3] * Mx<R>::ln(1.0 + cd.k_cd_H2[2] * T) -
                                            cd.k_cd_H2[4] * q.invT);
   const R zcd = n * (xH * kcdH + xH2 * kcdH2);
-  const R kci = c.k_ci_H[0] * sqrtT * Mx<R>::ex(-cd.k_ci_H[1] * q.invT) / (R(1) + Mx<R>::sq(R(T * cd.inv_kci_T)));
+  const R kci = c.k_ci_H[0] * sqrtT * Mx<R>::ex(-cd.k_ci_H[1] * q.invT) /
+                (R(1) + (std::is_same<R, double>::value ? sqrtT * R(cd.rsqrt_kci_T) : Mx<R>::sq(R(T * cd.inv_kci_T))));
   const R zci = kci * n * xe;
   const R aB = c.alpha_B[0] * Mx<R>::ex((cd.alpha_B[1] + cd.alpha_B[2] * q.lnT4) * q.lnT4);
   // H+ grain recombination enters only the rates; skipped (chem = false) where a caller takes
@@ -445,7 +448,7 @@ __device__ Eval<R> evaluate(double T, double n_d, double xH2_d, double xHp_d, co
                  zpd * xH2 * c.f_pump * (c.pump_eV * ev) * eff + zpd * xH2 * (c.pd_eV * ev);
   v.Gamma = (double)g_pe + (double)g_cr + (double)g_pi + (double)g_h2;
   // cooling, Sec. 4.2
-  const R T4 = R(T * 1e-4);
+  const R sqrtT4 = std::is_same<R, double>::value ? sqrtT * R(0.01) : Mx<R>::sq(R(T * 1e-4));  // (T / 1e4)^1/2
   const R k12 = c.lya[0] * Mx<R>::ex(cd.lya[1] * q.lnT4 - cd.lya[4] * 1e4 * q.invT) /
                 (R(1) + Mx<R>::ex(cd.lya[3] * (q.lnT4 - cd.ln_lya_T)));
   const R l_lya = xH * xe * R(K_B) * c.lya_E21 * k12;
@@ -481,7 +484,7 @@ __device__ Eval<R> evaluate(double T, double n_d, double xH2_d, double xHp_d, co
     const R E10 = c.cp_levels[2], A10 = c.cp_levels[3];
     const double lnT2 = q.lnT - LN100;
     const R k10H = c.cp_rat[0] * Mx<R>::ex((cd.cp_ncrit_H[1] + cd.cp_ncrit_H[2] * lnT2) * lnT2);
-    const R k10e = A10 / (c.cp_ncrit_e * Mx<R>::sq(T4));
+    const R k10e = A10 / (c.cp_ncrit_e * sqrtT4);
     const R C10 = n * (xH * k10H + xH2 * c.cp_h2_over_h * k10H + xe * k10e);
     const R C01 = C10 * c.cp_rat[1] * Mx<R>::ex(-cd.cp_levels[2] * q.invT);
     const R f1 = C01 / (C01 + C10 + A10);
@@ -515,7 +518,7 @@ __device__ Eval<R> evaluate(double T, double n_d, double xH2_d, double xHp_d, co
     const double expo = cd.neb[3] - cd.neb[4] * q.lnT4;
     const R dens = ne2 > R(0) ? Mx<R>::ex(expo * Mx<R>::ln((double)ne2))
                               : (expo > 0.0 ? R(0) : (expo < 0.0 ? R(INFINITY) : R(1)));
-    l_neb = Zg * xe * xHp * c.neb[0] * ef / (Mx<R>::sq(T4) * (R(1) + c.neb[2] * dens));
+    l_neb = Zg * xe * xHp * c.neb[0] * ef / (sqrtT4 * (R(1) + c.neb[2] * dens));
   }
   // dust temperature in double on both paths: where gas and dust are coupled T_d -> T, and the
   // gas-dust term goes as T - T_d
