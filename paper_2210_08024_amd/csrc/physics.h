@@ -171,13 +171,13 @@ __device__ __forceinline__ R alpha_gr(const Tq &q, double lnpsi, const double *k
   return R(1e-14 * k[0]) * Zd / (R(1) + R(k[1]) * a * (R(1) + R(k[3]) * b));
 }
 
-// FUV field G0 of a cell from its attenuation factors (Sec. 4.1.1).
+// FUV field G0 of a cell from its attenuation factors (Sec. 4.2).
 template <class R>
 __device__ __forceinline__ R g0_field(R chiPE, R chiLW, const CoefT<R> &c) {
   return c.G0_per_chi * ((c.J_PE * chiPE + c.J_LW * chiLW) * c.inv_J_FUV);
 }
 
-// Grain charging parameter G0 T^1/2 / n_e + 50 (Sec. 4.1.1), n_e floored at 1e-20 n.
+// Grain charging parameter G0 T^1/2 / n_e + 50 (Sec. 4.2), n_e floored at 1e-20 n.
 template <class R>
 __device__ __forceinline__ R psi_charge(R sqrtT, R n, R xe, R G0, const CoefT<R> &c) {
   return G0 * sqrtT / (n * rmax(xe, R(1e-20))) + c.psi_off;
@@ -200,7 +200,13 @@ __device__ EqS<R> eq_species(double T, R n, double xH2_d, double xHp_d, const Ra
   const R a = c.zeta_pi_C * r.chiC + c.zeta_pi_C_cr * R(2) * xH2 * r.xi + c.zeta_cr_C * r.xi;
   const R cc = R(cd.arrdr_Cp[0]) * Mx<R>::ex(cd.arrdr_Cp[2] * (q.lnT - cd.ln_arrdr_T0)) * n;
   const R kch = R(cd.k_CpH2[0]) * Mx<R>::ex(cd.k_CpH2[1] * q.lnT - cd.k_CpH2[2] * q.invT) * n * xH2;
-  R y, xe;
+  // comp = 1 - x_C+ / x_C,tot, the neutral share of the carbon.  The float path takes it from the
+  // C+ balance itself rather than by subtraction: with the carbon nearly all ionised the quotient
+  // sits within a few ulps of 1 and the subtraction would keep none of the complement's digits.
+  //   hot:  y = x_C,tot a / (a + B + c x_e)            =>  comp = (B + c x_e) / (a + B + c x_e)
+  //   cold: c y^2 + (a + B + c x_e0) y = x_C,tot a     =>  comp = y (B + c (x_e0 + y)) / (a x_C,tot)
+  // with B the value the final root was taken with.
+  R y, xe, comp;
   if (T >= cd.xe_T_switch) {
     const double lgT = q.lnT * INV_LN10D;
     xe = xHp + R(cie_lookup(tab, lgT, 2)) + p.Zg * R(cie_lookup(tab, lgT, 3));
@@ -208,15 +214,17 @@ __device__ EqS<R> eq_species(double T, R n, double xH2_d, double xHp_d, const Ra
     const R B = alpha_gr<R>(q, Mx<R>::ln((double)psi), cd.agr_Cp, Zd) * n + kch;
     const R dh = a + B + cc * xe;
     y = a > R(0) ? xCt * a / (dh > R(0) ? dh : R(1)) : R(0);
+    comp = a > R(0) ? (B + cc * xe) / (dh > R(0) ? dh : R(1)) : R(1);
   } else {
     const R amh = R(cd.x_MH[1]) * Mx<R>::ex(cd.x_MH[3] * (q.lnT - cd.ln_xMH_T0));
     const R xmh = R(2) * xH2 * Mx<R>::sq(c.x_MH[0] * r.xi / (amh * n));
     const R xe0 = xHp + e.xOp + xmh;
     xe = xe0 + xCt;
     y = R(0);
+    R B = R(0);
     for (int it = 0; it < maxit; ++it) {
       const R psi = psi_charge(sqrtT, n, xe, r.G0f, c);
-      const R B = alpha_gr<R>(q, Mx<R>::ln((double)psi), cd.agr_Cp, Zd) * n + kch;
+      B = alpha_gr<R>(q, Mx<R>::ln((double)psi), cd.agr_Cp, Zd) * n + kch;
       const R pp = a + B + cc * xe0;
       const R den = pp + Mx<R>::sq(pp * pp + R(4) * cc * xCt * a);
       y = a > R(0) ? R(2) * xCt * a / (den > R(0) ? den : R(1)) : R(0);
@@ -225,17 +233,28 @@ __device__ EqS<R> eq_species(double T, R n, double xH2_d, double xHp_d, const Ra
       xe = xn;
       if (conv) break;
     }
+    comp = a > R(0) ? y * (B + cc * (xe0 + y)) / (a * xCt) : R(1);
   }
   // y <= x_C,tot and frac <= 1 hold exactly; in float the quotient can land one ulp above, which
   // would leave x_C and x_CO at -ulp
   y = y < xCt ? y : xCt;
   e.xCp = y;
   e.xe = xe;
-  // a true quotient: 1 - frac below cancels when C is nearly all ionised
-  const R fr = rmax(y / xCt, xHp);
-  const R frac = fr < R(1) ? fr : R(1);
-  e.xCO = xCt * R(2) * xH2 * (R(1) - frac) / (R(1) + r.qn2);
-  e.xC = xCt - y - e.xCO;
+  if (std::is_same<R, double>::value) {
+    // FP64: 1 - max(x_C+ / x_C,tot, x_H+) as a true quotient and difference (Eq. e:CO as written)
+    const R fr = rmax(y / xCt, xHp);
+    const R frac = fr < R(1) ? fr : R(1);
+    e.xCO = xCt * R(2) * xH2 * (R(1) - frac) / (R(1) + r.qn2);
+    e.xC = xCt - y - e.xCO;
+  } else {
+    // float: 1 - max(y / x_C,tot, x_H+) = min(comp, 1 - x_H+), 1 - x_H+ from the double x_H+; the
+    // neutral carbon x_C + x_CO = x_C,tot comp, so x_C needs no subtraction of x_C+ either
+    comp = comp < R(0) ? R(0) : (comp > R(1) ? R(1) : comp);
+    const R omh = R(1.0 - xHp_d);
+    const R om = comp < omh ? comp : omh;
+    e.xCO = xCt * om * (R(2) * xH2 / (R(1) + r.qn2));
+    e.xC = rmax(xCt * comp - e.xCO, R(0));
+  }
   e.xO = R((double)xOt * (1.0 - xHp_d)) - e.xCO;  // x_O,tot - x_O+ formed in double (x_H+ -> 1)
   return e;
 }
@@ -329,7 +348,7 @@ __device__ R dust_T(R T, R sqrtT, R n, R G, R guess, R Tbb, const CoefT<R> &c, b
   return x;
 }
 
-// ---------------------------------------------------------------- fine structure (Sec. 4.2.2)
+// ---------------------------------------------------------------- fine structure (Sec. 4.6.2)
 // 3-level atom (levels 0, 1, 2); H-impact de-excitation k10 follows the printed critical
 // densities as a power law in T (slope precomputed on the host), other partners and
 // transitions are stand-in ratios.  Populations by Cramer's rule with p0 = 1, normalised.
@@ -347,9 +366,10 @@ __device__ __forceinline__ R three_level_cool(const Tq &q, R n, R inv_n, R xH, R
   const double b1 = (double)Mx<R>::ex(-E1 * q.invT), b2 = (double)Mx<R>::ex(-E2 * q.invT);
   const R R01 = C10 * R(rat[0]) * R(b1);
   const R R02 = C20 * R(rat[1]) * R(b2);
-  // in double the 1-2 Boltzmann factor is the quotient of the other two (both stay normal for
-  // T >= 1 K), a division in place of an exp
-  const R b12 = std::is_same<R, double>::value ? R(b2 / b1) : Mx<R>::ex(-(E2 - E1) * q.invT);
+  // in double the 1-2 Boltzmann factor is the quotient of the other two, a division in place of an
+  // exp
+  // (below ~0.3 K b1 underflows for O I: then the factor is formed on its own)
+  const R b12 = (std::is_same<R, double>::value && b1 > 0.0) ? R(b2 / b1) : Mx<R>::ex(-(E2 - E1) * q.invT);
   const R R12 = C21 * R(rat[2]) * b12;
   const R R10 = C10 + A10, R20 = C20 + A20, R21 = C21 + A21;
   const R det = R10 * R20 + R10 * R21 + R12 * R20;
@@ -371,7 +391,7 @@ enum Diag {
 };
 
 // ---------------------------------------------------------------- full evaluation
-// Rates (Sec. 3), heating (Sec. 4.1), cooling (Sec. 4.2) at temperature T with the
+// Rates (Sec. 3), heating (Secs. 4.1-4.5), cooling (Sec. 4.6) at temperature T with the
 // abundances (xH2, xHp) and closure e.  CHEM_ONLY skips heating/cooling; DIAG writes
 // every term into diag[NDIAG].
 template <class R, bool CHEM_ONLY, bool DIAG>
@@ -431,7 +451,7 @@ __device__ Eval<R> evaluate(double T, double n_d, double xH2_d, double xHp_d, co
   if (CHEM_ONLY) return v;
   const R ev = R(EV);
   const R inv_n = R(1) / n;
-  // heating, Sec. 4.1
+  // heating, Secs. 4.1-4.5
   const R G0 = r.G0f;
   const R eps = (c.pe_C[0] + c.pe_C[1] * Mx<R>::ex(cd.pe_C[4] * q.lnT)) /
                 (R(1) + c.pe_C[2] * Mx<R>::ex(cd.pe_C[5] * lnpsi) * (R(1) + c.pe_C[3] * Mx<R>::ex(cd.pe_C[6] * lnpsi)));
@@ -447,7 +467,7 @@ __device__ Eval<R> evaluate(double T, double n_d, double xH2_d, double xHp_d, co
   const R g_h2 = kgr * n * xH * (c.h2form_eV[0] * ev + c.h2form_eV[1] * ev * eff) +
                  zpd * xH2 * c.f_pump * (c.pump_eV * ev) * eff + zpd * xH2 * (c.pd_eV * ev);
   v.Gamma = (double)g_pe + (double)g_cr + (double)g_pi + (double)g_h2;
-  // cooling, Sec. 4.2
+  // cooling, Sec. 4.6
   const R sqrtT4 = std::is_same<R, double>::value ? sqrtT * R(0.01) : Mx<R>::sq(R(T * 1e-4));  // (T / 1e4)^1/2
   const R k12 = c.lya[0] * Mx<R>::ex(cd.lya[1] * q.lnT4 - cd.lya[4] * 1e4 * q.invT) /
                 (R(1) + Mx<R>::ex(cd.lya[3] * (q.lnT4 - cd.ln_lya_T)));
