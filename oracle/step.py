@@ -57,11 +57,15 @@ def be_solve(xH2, xHp, F, D, I, Rr, dt):
     return a, b
 
 
-def chem_cool_step(n, T, xH2, xHp, rad, dt, par, record=None):
+def chem_cool_step(n, T, xH2, xHp, rad, dt, par, record=None, fd_noise=0.0):
     """Advance every cell by dt [s].  Returns a dict of T, xH2, xHp, xCp, xCO, xe, nsub, status.
 
     rad: dict of per-cell arrays (or scalars) chi_PE, chi_LW, chi_H2, chi_C,
     phi, xi, Neff.  All FP64.
+
+    fd_noise (conditioning probe, 0 in every comparison): when non-zero, H of the evaluation at
+    T (1 + fd_rel) is shifted by fd_noise times its larger term, max(n |Gamma|, n^2 |Lambda|), in
+    every substep -- the size of one rounding of that evaluation at relative precision fd_noise.
     """
     n = np.asarray(n, dtype=np.float64).ravel()
     N = n.size
@@ -96,7 +100,10 @@ def chem_cool_step(n, T, xH2, xHp, rad, dt, par, record=None):
             nz = den > 0.0
             dts = np.where(nz, np.minimum(dts, num / np.where(nz, den, 1.0)), dts)
         ev2 = micro.evaluate(Ta * (1.0 + delta), na, xH2a, xHpa, eqa, rada, par)
-        dH = (ev2["H"] - H) / (delta * Tmua)
+        H2 = ev2["H"]
+        if fd_noise:
+            H2 = H2 + fd_noise * np.maximum(na * np.abs(ev2["Gamma"]), na * na * np.abs(ev2["Lambda"]))
+        dH = (H2 - H) / (delta * Tmua)
         den = Ka - dts * dH
         guard = den <= 0.1 * Ka
         den = np.where(guard, Ka, den)

@@ -1,15 +1,12 @@
-"""The 128^3 GRF configuration across its metallicities and step lengths (Z' in {0.1, 3},
-dt in {1e3, 1e5} yr; Z' = 1, dt = 1e4 yr is in test_gpu_parity): GPU columns6 + step over the
-whole grid, the oracle on sampled cells computed one by one.
+"""The 128^3 GRF configuration across its metallicities and step lengths: Z' in {0.1, 1, 3} x
+dt in {1e3, 1e4, 1e5} yr (Z' = 1, dt = 1e4 yr also runs in test_gpu_parity with more fields).
+GPU columns6 + step over the whole grid, the oracle on 1,024 sampled cells computed one by one.
 
-Bars: FP64 within 1e-9 relative; the mixed path within 1e-3 relative in T and every
-abundance, except where the FP64 scheme itself is ill-conditioned.  The subcycled step
-amplifies small changes of its inputs (cells near the thermally unstable branch diverge
-from it exponentially, and the substep sizes follow the rates), so FP32 evaluation errors
-cannot be held to 1e-3 in every cell at long dt.  Per cell the mixed bar is
-max(1e-3, 10 S), S the relative change of the oracle's end state when the input T, x_H2 and
-x_H+ are changed by a relative 1e-6 (about ten FP32 ulps); at most 1% of the cells may use
-the widened bar."""
+Bars: FP64 within 1e-9 relative; the mixed path within a flat 1e-3 relative in T and every
+abundance on every sampled cell.  A cell may be exempt only if it is named in ILL_CONDITIONED
+with the reason: the FP64 scheme itself moves its end state by S >= 1e-4 when the input T,
+x_H2, x_H+ change by a relative 1e-6 (about ten FP32 ulps), so no float evaluation of it can be
+held to 1e-3; such a cell is still held to 10 S."""
 import numpy as np
 import pytest
 
@@ -20,7 +17,8 @@ from oracle.constants import Params
 
 pytestmark = pytest.mark.gpu
 
-FIELDS = ("T", "xH2", "xHp", "xe", "xCp", "xCO")
+# (Z', dt in yr) -> {cell index: reason}
+ILL_CONDITIONED = {}
 
 
 @pytest.fixture(scope="module")
@@ -38,12 +36,10 @@ def grf128():
     return workloads.make("grf128")
 
 
-def _rel(a, b, k, xCt):
-    fl = 0.0 if k == "T" else 1e-7 * (xCt if k in ("xCp", "xCO") else 1.0)
-    return H.rel_err(a, b, fl)
+PAIRS = [(0.1, 1e3), (0.1, 1e4), (0.1, 1e5), (1.0, 1e3), (1.0, 1e5), (3.0, 1e3), (3.0, 1e4), (3.0, 1e5)]
 
 
-@pytest.mark.parametrize("Zg,dt_yr", [(0.1, 1e3), (0.1, 1e5), (3.0, 1e3), (3.0, 1e5)])
+@pytest.mark.parametrize("Zg,dt_yr", PAIRS)
 def test_grf128_metallicity_and_step_length(ism, grf128, Zg, dt_yr):
     import torch
     s, cfg = grf128
@@ -61,15 +57,7 @@ def test_grf128_metallicity_and_step_length(ism, grf128, Zg, dt_yr):
     radi = dict(chi_PE=rc["chi_PE"], chi_LW=rc["chi_LW"], chi_H2=rc["chi_H2"], chi_C=rc["chi_C"],
                 phi=np.zeros(len(idx)), xi=rc["xi"], Neff=rc["N_eff"])
     ref = H.oracle_step(s, radi, dt, par, idx=idx)
-    # conditioning of the FP64 scheme at each sampled cell
-    sens = np.zeros(len(idx))
-    for sign in (1.0, -1.0):
-        sp = {"n": s["n"]}
-        for k in ("T", "xH2", "xHp"):
-            sp[k] = s[k] * (1.0 + sign * 1e-6)
-        alt = H.oracle_step(sp, radi, dt, par, idx=idx)
-        for k in FIELDS:
-            sens = np.maximum(sens, _rel(alt[k], ref[k], k, par.xCtot))
+    sens = H.oracle_sensitivity(s, radi, dt, par, idx, ref)
     tid = torch.from_numpy(idx).cuda()
     for prec in (0, 1):
         n = H.to_dev(s["n"])
@@ -85,14 +73,5 @@ def test_grf128_metallicity_and_step_length(ism, grf128, Zg, dt_yr):
         if prec == 0:
             H.check_fields(g, ref, 1e-9, H.FLOORS_F64, par.xCtot, label=f"F64 Z'={Zg} dt={dt_yr:g}")
             continue
-        worst = np.zeros(len(idx))
-        for k in FIELDS:
-            worst = np.maximum(worst, _rel(g[k], ref[k], k, par.xCtot))
-        bar = np.maximum(1e-3, 10.0 * sens)
-        bad = np.nonzero(worst > bar)[0]
-        assert bad.size == 0, (f"mixed Z'={Zg} dt={dt_yr:g}: {bad.size} cells over the bar; worst "
-                               f"{worst[bad].max():.2e} with sensitivity {sens[bad][np.argmax(worst[bad])]:.2e}")
-        widened = (worst > 1e-3).mean()
-        print(f"  mixed: max {worst.max():.2e}, p99 {np.percentile(worst, 99):.2e}, cells over 1e-3 "
-              f"{widened * 100:.2f}% (max oracle sensitivity {sens.max():.2e})", flush=True)
-        assert widened <= 0.01
+        H.check_mixed_flat(g, ref, idx, par.xCtot, named=ILL_CONDITIONED.get((Zg, dt_yr)), sens=sens,
+                           label=f"mixed Z'={Zg} dt={dt_yr:g}")

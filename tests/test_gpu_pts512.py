@@ -1,13 +1,12 @@
 """The 512^3 point-source configuration (134,217,728 cells, 2 pc, 16 sources, one step of
 1e4 yr) on all three paths at full size.  Checked against the oracle on sampled cells: the
 FP64 six-ray columns and straight-line source maps at a few cells, then the step of every
-path on a stride-64 subsample (8^3 cells) against the FP64 oracle step fed the GPU's FP64
-radiation at those cells.
+path on the 64^3 subsample (every 8th cell along each axis, 262,144 cells) against the FP64
+oracle step fed the GPU's FP64 radiation at those cells.
 
-Bars: F64 1e-9; mixed and surrogate 1e-3 in T and every abundance, widened per cell to
-10 S where the FP64 scheme itself amplifies a 1e-6 relative change of its inputs to S (at most
-1% of the cells; the 128^3 configuration test gives the reasoning); accepted surrogate cells
-are certified to 1e-3 and fall under the same bar."""
+Bars: F64 1e-9; mixed and surrogate a flat 1e-3 in T and every abundance on every subsample
+cell (a cell may be exempt only when named in ILL_CONDITIONED, see helpers.check_mixed_flat);
+accepted surrogate cells are certified to 1e-3 and fall under the same bar."""
 import numpy as np
 import pytest
 
@@ -31,9 +30,14 @@ def ism():
     return m
 
 
-def _rel(a, b, k, xCt):
-    fl = 0.0 if k == "T" else 1e-7 * (xCt if k in ("xCp", "xCO") else 1.0)
-    return H.rel_err(a, b, fl)
+# cell index -> reason: cells where the FP64 scheme itself cannot be held to 1e-3 by a float
+# evaluation (see helpers.check_mixed_flat and helpers.oracle_sensitivity)
+ILL_CONDITIONED = {
+    81940480: "(k, j, i) = (312, 296, 0), n = 16.8, T 133 -> 31.5 K in 21 substeps as x_H+ recombines "
+              "from 0.29 to 0.011: near thermal balance the derivative dH/dT_mu is a small difference of "
+              "two evaluations of H, and one float rounding (1e-7 of the larger term) of the second one "
+              "moves the end T by 1.9e-3 in the oracle itself (a 1e-6 input change: 1.2e-4)",
+}
 
 
 def test_c4_full_size_all_paths(ism):
@@ -65,8 +69,8 @@ def test_c4_full_size_all_paths(ism):
         g = maps[k][tf[:6]].cpu().numpy()
         err = np.abs(g - ref_maps[k]) / np.maximum(np.abs(ref_maps[k]), 1e-300)
         assert err.max() < 1e-9, ("maps", k, err.max())
-    # the sampled subsample of the step comparison
-    st = 64
+    # the step comparison on the 64^3 subsample: every 8th cell along each axis (262,144 cells)
+    st = 8
     kk, jj, ii = np.meshgrid(*(np.arange(0, m, st) for m in shape), indexing="ij")
     idx = (ii + shape[2] * (jj + shape[1] * kk)).ravel()
     tid = torch.from_numpy(idx).cuda()
@@ -110,21 +114,18 @@ def test_c4_full_size_all_paths(ism):
         torch.cuda.empty_cache()
     print(f"pts512: oracle on {len(idx)} cells", flush=True)
     ref = H.oracle_step(s, rad_sample, dt, par_o, idx=idx)
-    sens = np.zeros(len(idx))
-    for sign in (1.0, -1.0):
-        sp = {"n": s["n"]}
-        for k in ("T", "xH2", "xHp"):
-            sp[k] = s[k] * (1.0 + sign * 1e-6)
-        alt = H.oracle_step(sp, rad_sample, dt, par_o, idx=idx)
-        for k in FIELDS:
-            sens = np.maximum(sens, _rel(alt[k], ref[k], k, par_o.xCtot))
     H.check_fields(got["f64"], ref, 1e-9, H.FLOORS_F64, par_o.xCtot, label="pts512 F64")
+    worst = np.zeros(len(idx))
     for path in ("mixed", "surrogate"):
-        worst = np.zeros(len(idx))
         for k in FIELDS:
-            worst = np.maximum(worst, _rel(got[path][k], ref[k], k, par_o.xCtot))
-        bar = np.maximum(1e-3, 10.0 * sens)
-        bad = np.nonzero(worst > bar)[0]
-        print(f"  {path}: max {worst.max():.2e}, cells over 1e-3 {(worst > 1e-3).mean() * 100:.2f}%", flush=True)
-        assert bad.size == 0, (path, bad.size, worst[bad].max())
-        assert (worst > 1e-3).mean() <= 0.01
+            worst = np.maximum(worst, H.mixed_rel(got[path][k], ref[k], k, par_o.xCtot))
+    sens = None
+    over = np.nonzero(worst > 1e-3)[0]
+    if over.size:
+        # the oracle's own conditioning, at the cells over the bar only (for the report)
+        sens = np.zeros(len(idx))
+        sens[over] = H.oracle_sensitivity(s, {k: v[over] for k, v in rad_sample.items()}, dt, par_o, idx[over],
+                                          {k: v[over] for k, v in ref.items()})
+    for path in ("mixed", "surrogate"):
+        H.check_mixed_flat(got[path], ref, idx, par_o.xCtot, named=ILL_CONDITIONED, sens=sens,
+                           label=f"pts512 {path}")
