@@ -14,8 +14,17 @@ It follows Kim, Gong, Kim & Ostriker (arXiv:2210.08024):
 * ``columns``  six-ray diffuse-UV columns, shielding, N_eff and CR
                attenuation (Secs. 5.1-5.3).
 * ``steady``   independent brute-force steady states (used as a pin).
-* ``explicit`` a high-order explicit ODE reference for tiny-dt checks.
+* ``census``   the operation count of one substep (the step's roofline work).
 * ``mlp``      FP64 reference forward/backward/Adam of the surrogate MLP.
+* ``art``      adaptive ray tracing of point sources, its flux and the radiation
+               force (Secs. 5.1, 6.2).
+* ``sources``  the many-ray limit at cell centres (straight-line source maps).
+* ``shield``   local shielding-length radiation and the shielded one-zone
+               equilibrium (Sec. 7.1.2).
+* ``slab``     the plane-parallel H I -> H2 transition (Sec. 7.3).
+
+The tiny-dt checks integrate the same rate functions with scipy's DOP853 inside
+the test itself.
 
 Parity status of each function is stated in its docstring; where the paper
 only cites a process (the tabulated and stand-in microphysics), the result is
