@@ -386,7 +386,7 @@ FORCE_BYTES_MIXED = 9 * 4 + 4 * 8 + 3 * 4 + 1
 
 def bench_radiation_force(ism, par, n, init, shape, dx, sources, stream, ev, reps=20):
     """Outside the timed job: the ray trace with the flux estimator (Eq. e:Frad) on the initial
-    state, and the radiation force with the grain-destruction switch (Sec. 5.4) from it."""
+    state, and the radiation force with the grain-destruction switch (Sec. 6.2) from it."""
     import torch
     N = n.numel()
     fx = {k: torch.zeros(shape, dtype=torch.float32, device="cuda") for k in ("chi_PE", "chi_LW", "chi_H2", "chi_C", "phi")}

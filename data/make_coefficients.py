@@ -64,35 +64,35 @@ def printed():
     add("J_PE_Draine", 1.8e-4, "Sec. 2.2: J^Draine_PE = 1.8e-4 erg cm^-2 s^-1 sr^-1")
     add("J_LW_Draine", 3.0e-5, "Sec. 2.2: J^Draine_LW = 3.0e-5 erg cm^-2 s^-1 sr^-1")
     add("J_FUV_norm", 2.1e-4, "Eq. e:chi_FUV: 2.1e-4 erg cm^-2 s^-1 sr^-1")
-    add("G0_per_chiFUV", 1.7, "Sec. 4.1.1: G0 = 1.7 chi_FUV")
-    # photoelectric heating (Sec. 4.1.1)
+    add("G0_per_chiFUV", 1.7, "Sec. 4.2: G0 = 1.7 chi_FUV")
+    # photoelectric heating (Sec. 4.2)
     add("pe_prefactor", 1.0e-26, "Eq. eq:photoel_heat: 1e-26 G0 eps Z'_d erg s^-1")
     add("pe_C", [5.22, 2.25, 0.04996, 0.00430, 0.147, 0.431, 0.692], "Eq. e:PE_efficiency: C0..C6")
-    add("psi_offset", 50.0, "Sec. 4.1.1: 50 K^1/2 cm^3 added to psi")
-    # photoionisation heating (Sec. 4.1.3)
-    add("q_pi_H_eV", 3.4, "Sec. 4.1.3 / Table t:sb99 row 11")
-    add("q_pi_H2_eV", 4.4, "Sec. 4.1.3 / Table t:sb99 row 12")
-    # H2 heating (Sec. 4.1.4)
+    add("psi_offset", 50.0, "Sec. 4.2: 50 K^1/2 cm^3 added to psi")
+    # photoionisation heating (Sec. 4.4)
+    add("q_pi_H_eV", 3.4, "Sec. 4.4 / Table t:sb99 row 11")
+    add("q_pi_H2_eV", 4.4, "Sec. 4.4 / Table t:sb99 row 12")
+    # H2 heating (Sec. 4.5)
     add("h2form_heat_eV", [0.2, 4.2], "Eq. e:Gamma_H2form: 0.2 eV + 4.2 eV / (1 + n_crit/n)")
     add("f_pump", 8.0, "Eq. e:Gamma_H2pump: f_pump = 8")
     add("pump_heat_eV", 2.0, "Eq. e:Gamma_H2pump: 2 eV")
     add("pd_heat_eV", 0.4, "Eq. e:Gamma_H2diss: 0.4 eV")
-    add("A_eff", 2.0e-7, "Sec. 4.1.4: A_eff = 2e-7 s^-1")
-    # cooling assembly (Sec. 4.2)
+    add("A_eff", 2.0e-7, "Sec. 4.5: A_eff = 2e-7 s^-1")
+    # cooling assembly (Sec. 4.6)
     add("sigmoid", [10.0, 2.0e4, 3.5e4], "Eq. eq:cooling_fnct: a = 10, T_t1 = 2e4, T_t2 = 3.5e4")
     add("lya_k12", [5.31e-8, 0.15, 5.0, 0.65, 11.84], "Eq. e:k_lya")
-    add("lya_E21_K", 1.184e5, "Sec. 4.2.1: E21 / k_B = 1.184e5 K")
+    add("lya_E21_K", 1.184e5, "Sec. 4.6.1: E21 / k_B = 1.184e5 K")
     add("ci_H_eV", 13.6, "Eq. e:Lambda_ci_H: 13.6 eV per ionisation")
     add("cd_H2_eV", 4.48, "Eq. e:Lambda_cd_H2: 4.48 eV per dissociation")
     add("neb", [3.68e-23, 3.86, 0.12, 0.38, 0.12], "Eq. e:Lambda_neb prefactor, exponent, 0.12 n_e2^(0.38 - 0.12 ln T4)")
     add("neb_a", [6.92e-1, -5.86e-1, 8.16e-1, -5.05e-1, 1.18e-1, 7.66e-3, -5.08e-3], "Eq. e:Lambda_neb: log10 f_neb coefficients a0..a6")
     add("alpha_gd", 3.2e-34, "Eq. eq:gas-dust: 3.2e-34 erg cm^3 s^-1 K^-3/2")
-    add("sigma_IR_10K", 2.0e-25, "Sec. 4.2.5: sigma_IR = 2e-25 Z'_d (T_d/10 K)^2 cm^2 H^-1")
-    add("a_rad", 7.57e-15, "Sec. 4.2.5: a = 7.57e-15 erg cm^-3 K^-4")
-    add("cp_ncrit_e", 53.0, "Sec. 4.2.2: C II 158um n_e,crit = 53 T4^1/2 cm^-3")
-    add("cp_ncrit_H", [3.0e3, 0.1281, 0.0087], "Sec. 4.2.2: C II 158um n_H,crit = 3e3 T2^(-0.1281 - 0.0087 ln T2)")
-    add("o_ncrit_H", [2.5e5, 4.9e4], "Sec. 4.2.2: O I 63um n_H,crit at T = 10 K and 5000 K")
-    add("c_ncrit_H", [620.0, 150.0], "Sec. 4.2.2: C I 610um n_H,crit at T = 10 K and 5000 K")
+    add("sigma_IR_10K", 2.0e-25, "Sec. 4.6.4: sigma_IR = 2e-25 Z'_d (T_d/10 K)^2 cm^2 H^-1")
+    add("a_rad", 7.57e-15, "Sec. 4.6.4: a = 7.57e-15 erg cm^-3 K^-4")
+    add("cp_ncrit_e", 53.0, "Sec. 4.6.2: C II 158um n_e,crit = 53 T4^1/2 cm^-3")
+    add("cp_ncrit_H", [3.0e3, 0.1281, 0.0087], "Sec. 4.6.2: C II 158um n_H,crit = 3e3 T2^(-0.1281 - 0.0087 ln T2)")
+    add("o_ncrit_H", [2.5e5, 4.9e4], "Sec. 4.6.2: O I 63um n_H,crit at T = 10 K and 5000 K")
+    add("c_ncrit_H", [620.0, 150.0], "Sec. 4.6.2: C I 610um n_H,crit at T = 10 K and 5000 K")
     # dust cross sections (Sec. 2.3, Sec. 5.3)
     add("sigma_d_abs", [1.9e-21, 1.5e-21, 0.9e-21, 0.3e-21], "Sec. 2.3: absorption per H / Z'_d for LyC, LW, PE, OPT")
     add("sigma_d_Neff", 1.0e-21, "Eq. e:tau_eff: N_eff = tau_PE,eff / (1e-21 Z'_d)")

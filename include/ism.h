@@ -72,7 +72,7 @@ typedef struct {
   double Zd;            /* scaled dust abundance Z'_d (> 0)                               */
   double chi0;          /* unattenuated FUV at the domain faces, Draine units (Sec. 5.2)  */
   double xi_cr0;        /* unattenuated primary CR ionisation rate [s^-1] (Sec. 2.4)      */
-  double dvdr_kms_pc;   /* |dv/dr| for the CO LVG column (Sec. 4.2.2, default 1)          */
+  double dvdr_kms_pc;   /* |dv/dr| for the CO LVG column (Sec. 4.6.2, default 1)          */
   double eps_sub;       /* substep limiter factor (Sec. 6.1, 0.1)                         */
   double fd_rel;        /* relative step of the forward difference dH/dT_mu (1e-3)        */
   double T_floor;       /* temperature floor [K] (1)                                       */
@@ -128,7 +128,7 @@ ism_status ism_columns6(const ism_grid *g, const ism_params *p, ism_precision pr
                         void *N_eff, void *xi_cr, hipStream_t stream);
 
 /* A beam of surface intensity chi0 (params) entering every x row through the x = 0 face
- * along +x: the plane-parallel slab of Sec. 7.2.  Per cell the same terms as one six-ray
+ * along +x: the plane-parallel slab of Sec. 7.3.  Per cell the same terms as one six-ray
  * direction of ism_columns6 with weight chi0 instead of chi0/6: dust attenuation to the entry
  * face times the cell average, H2 and C shielding at mid-cell.  N_eff and xi_cr as in
  * ism_columns6.  Arguments and layout as ism_columns6 (no scratch). */
@@ -227,7 +227,7 @@ typedef struct {
   double prad_ratio_max;  /* ... or where |F| / c exceeds this multiple of 2 n k_B T (50) */
 } ism_force_options;
 
-/* Radiation force per volume on the gas-dust mixture (Sec. 5.4): f = sum_j alpha_j F_j / c
+/* Radiation force per volume on the gas-dust mixture (Sec. 6.2): f = sum_j alpha_j F_j / c
  * over the traced bands with the opacities of ism_ray_trace (PE, LW: dust; LyC: dust, H and
  * H2), h nu_LyC per LyC photon.  Grain destruction (appendix on grain destruction): where
  * T > T_destroy_K or P_rad = |F_PE + F_LW + h nu F_LyC| / c > prad_ratio_max x 2 n k_B T

@@ -33,7 +33,7 @@ deposit times the packet's direction n (Eq. e:Frad): F_j = sum dL_j n / alpha_j 
 LW are given as band energy fluxes (erg cm^-2 s^-1): a packet's FUV luminosity is shared
 between them as J^D_PE : J^D_LW, the shares of the Draine field, so that F_PE + F_LW is the
 FUV flux; LyC as a photon flux (photons cm^-2 s^-1).  radiation_force turns them into the
-force per volume on the gas-dust mixture (Sec. 5.4) with the grain-destruction switch.
+force per volume on the gas-dust mixture (Sec. 6.2) with the grain-destruction switch.
 
 The HEALPix pixel centres are taken from the continuous inverse HEALPix projection
 (Calabretta & Roukema 2007) evaluated at the centre of each base-pixel sub-square, not from
@@ -363,7 +363,7 @@ PRAD_RATIO_MAX = 50.0
 
 def radiation_force(n, T, xH2, xHp, flux, par, T_destroy=T_DESTROY, prad_ratio_max=PRAD_RATIO_MAX,
                     dt=0.0, mom=None, etot=None):
-    """Radiation force per volume on the gas-dust mixture (Sec. 5.4): the sum over bands of
+    """Radiation force per volume on the gas-dust mixture (Sec. 6.2): the sum over bands of
     alpha_j F_j / c, alpha_j the band's opacity (PE, LW: dust; LyC: dust, H and H2; the same
     opacities as the trace), with the LyC photon flux carrying h nu_LyC per photon.  Where the
     grains are destroyed the dust part of every band is dropped and only the photoionisation
@@ -371,7 +371,7 @@ def radiation_force(n, T, xH2, xHp, flux, par, T_destroy=T_DESTROY, prad_ratio_m
 
     n, T, xH2, xHp: arrays of any shape; flux: [9, *shape] as ray_trace returns it.  Returns
     dict f [3, *shape] (dyn cm^-3) and dust_off (bool).  With mom ([3, *shape] momentum
-    density, g cm^-2 s^-1) the source-term update of Sec. 5.4 is also made on copies: mom + f dt
+    density, g cm^-2 s^-1) the source-term update of Sec. 6.2 is also made on copies: mom + f dt
     and, with etot (total energy density, erg cm^-3), etot plus the change of rho v^2 / 2 at
     fixed rho = mu_H m_H n; returned as 'mom' and 'etot'."""
     n = np.asarray(n, dtype=np.float64)

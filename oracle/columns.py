@@ -107,7 +107,7 @@ def columns6(n, xH2, xC, dx, par, xi_in=None):
 
 def columns_beam(n, xH2, xC, dx, par):
     """Radiation of a beam of surface intensity chi0 entering through the x = 0 face along +x
-    (the plane-parallel slab of Sec. 7.2): the +x ray of columns6 with weight chi0 instead of
+    (the plane-parallel slab of Sec. 7.3): the +x ray of columns6 with weight chi0 instead of
     chi0 / 6.  Same cell average and mid-cell shielding columns; N_eff and xi as in columns6."""
     n = np.asarray(n, dtype=np.float64)
     xH2 = np.asarray(xH2, dtype=np.float64)

@@ -48,10 +48,10 @@ G0_PER_CHI = 1.7
 # Eq. e:PE_efficiency
 PE_C = (5.22, 2.25, 0.04996, 0.00430, 0.147, 0.431, 0.692)
 PSI_OFFSET = 50.0
-# Sec. 4.1.3
+# Sec. 4.4
 Q_PI_H = 3.4 * EV
 Q_PI_H2 = 4.4 * EV
-# Sec. 4.1.4
+# Sec. 4.5
 A_EFF = 2.0e-7
 F_PUMP = 8.0
 # Eq. eq:cooling_fnct
@@ -63,7 +63,7 @@ E_CI = 13.6 * EV
 E_CD = 4.48 * EV
 # Eq. e:Lambda_neb
 NEB_A = (6.92e-1, -5.86e-1, 8.16e-1, -5.05e-1, 1.18e-1, 7.66e-3, -5.08e-3)
-# Eq. eq:gas-dust, Sec. 4.2.5
+# Eq. eq:gas-dust, Sec. 4.6.4
 ALPHA_GD = 3.2e-34
 SIGMA_IR10 = 2.0e-25
 A_RAD = 7.57e-15
@@ -75,7 +75,7 @@ SIG_D_NEFF = 1.0e-21
 N0_CR = 9.35e20
 # Eq. e:fshld_H2_DB
 B5 = 3.0
-# Sec. 4.2.2 critical densities
+# Sec. 4.6.2 critical densities
 CP_NCRIT_E = 53.0
 CP_NCRIT_H = (3.0e3, 0.1281, 0.0087)
 O_NCRIT_H = (2.5e5, 4.9e4)

@@ -121,7 +121,7 @@ def chi_fuv(chi_PE, chi_LW):
 
 
 def psi_charge(T, n, xe, chi_PE, chi_LW):
-    """Grain charging parameter G0 T^1/2 / n_e plus 50 (Sec. 4.1.1).
+    """Grain charging parameter G0 T^1/2 / n_e plus 50 (Sec. 4.2).
 
     n_e is floored at 1e-20 n so that psi stays finite in fully neutral,
     unirradiated gas (a guard; never active on ionised or irradiated gas).
@@ -197,7 +197,7 @@ def eq_species(T, n, xH2, xHp, chi_PE, chi_LW, chi_C, xi, par, tol=1.0e-12, maxi
 
 
 # --------------------------------------------------------------------------
-# dust temperature (Sec. 4.2.5, Eq. eq:dust_en, readings of Sec. 7.1.2)
+# dust temperature (Sec. 4.6.4, Eq. eq:dust_en, readings of Sec. 7.1.2)
 # --------------------------------------------------------------------------
 def dust_heating_per_Zd(chi_PE, chi_LW, phi, Neff, par):
     """UV + optical dust heating per H divided by Z'_d [erg s^-1]."""
@@ -236,7 +236,7 @@ def dust_T(T, n, G, par, iters=64):
 
 
 # --------------------------------------------------------------------------
-# fine-structure level populations (Sec. 4.2.2)
+# fine-structure level populations (Sec. 4.6.2)
 # --------------------------------------------------------------------------
 def _two_level(g0, g1, E10, A10, C10, T):
     C01 = C10 * (g1 / g0) * np.exp(-E10 / T)
@@ -266,7 +266,7 @@ def _three_level(g, E, A10, A20, A21, C10, C20, C21, T):
 
 
 def fine_structure(T, n, xH, xH2, xe, xCp, xC, xO):
-    """Lambda_C+, Lambda_C, Lambda_O [erg cm^3 s^-1] (Sec. 4.2.2).
+    """Lambda_C+, Lambda_C, Lambda_O [erg cm^3 s^-1] (Sec. 4.6.2).
 
     Rate shapes: H-impact de-excitation of C II 158um, C I 610um and O I 63um
     follow the printed critical densities (C II: n_H,crit formula and
@@ -304,7 +304,7 @@ def fine_structure(T, n, xH, xH2, xe, xCp, xC, xO):
 
 
 def lambda_co(T, n, xCO, dvdr):
-    """CO rotational cooling with the LVG column Ntilde = n_CO / |dv/dr| (Sec. 4.2.2) -- stand-in table."""
+    """CO rotational cooling with the LVG column Ntilde = n_CO / |dv/dr| (Sec. 4.6.2) -- stand-in table."""
     Nt = n * xCO * C.PC / dvdr
     lT = np.log10(T)
     lN = np.log10(np.maximum(Nt, 1.0e-300))
@@ -314,7 +314,7 @@ def lambda_co(T, n, xCO, dvdr):
 
 
 def lambda_rovib(T, n, xH, xH2):
-    """H2 ro-vibrational cooling (Sec. 4.2.1) -- stand-in (LTE / low-density interpolation)."""
+    """H2 ro-vibrational cooling (Sec. 4.6.1) -- stand-in (LTE / low-density interpolation)."""
     sd = _sd()
     r0, r1, r2, r3, r4, r5, r6, v0, v1, v2, v3 = sd["rovib_lte"]
     T3 = T / 1.0e3
@@ -377,7 +377,7 @@ def evaluate(T, n, xH2, xHp, eq, rad, par, with_dust=True, chem_only=False):
                C_H2=F * xH - D * xH2, C_Hp=I * xH - Rr * xHp)
     if chem_only:
         return out
-    # --- heating (Sec. 4.1) ---
+    # --- heating (Secs. 4.1-4.5) ---
     cPE, c1, c2, c3, c4, c5, c6 = C.PE_C
     G0 = C.G0_PER_CHI * chi_fuv(chi_PE, chi_LW)
     eps = (cPE + c1 * T ** c4) / (1.0 + c2 * psi ** c5 * (1.0 + c3 * psi ** c6))
@@ -392,7 +392,7 @@ def evaluate(T, n, xH2, xHp, eq, rad, par, with_dust=True, chem_only=False):
             + zpd * xH2 * 0.4 * C.EV)
     Gam = g_pe + g_cr + g_pi + g_h2
     out.update(G_pe=g_pe, G_cr=g_cr, G_pi=g_pi, G_h2=g_h2, Gamma=Gam)
-    # --- cooling (Sec. 4.2) ---
+    # --- cooling (Sec. 4.6) ---
     T4 = T / 1.0e4
     k12 = 5.31e-8 * T4 ** 0.15 / (1.0 + (T4 / 5.0) ** 0.65) * np.exp(-11.84 / T4)
     l_lya = xH * xe * C.K_B * C.E21_K * k12

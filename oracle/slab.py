@@ -1,10 +1,10 @@
-"""Plane-parallel H I -> H2 transition (Sec. 7.2; test infrastructure).
+"""Plane-parallel H I -> H2 transition (Sec. 7.3; test infrastructure).
 
 A uniform slab along x, lit by a beam of surface intensity chi0 through x = 0, with a constant
 H2 formation coefficient and no cosmic rays, evolved by alternating the beamed columns and long
 steps of the source step until steady; the transition column is the total hydrogen column
 from the surface to the point where 2 x_H2 = 1/2.  The analytic approximation of Bialy &
-Sternberg quoted in Sec. 7.2 (Eqs. e:NH_trans, e:alpha, e:G) gives the same column for the
+Sternberg quoted in Sec. 7.3 (Eqs. e:NH_trans, e:alpha, e:G) gives the same column for the
 beamed, CR-free case.
 """
 import numpy as np

@@ -3,7 +3,7 @@
 A steady state is a temperature T and abundances X = (x_H2, x_H+) with
 H(T, X) = 0, C_H2 = 0 and C_H+ = 0 and the C/O/e closure consistent
 (the paper finds its equilibrium curves by root finding on thermal and
-ionisation balance, Secs. 4.2.6 and 7.1.1).
+ionisation balance, Secs. 4.6.6 and 7.1.1).
 
 Method (no use of the subcycled step):
 * for each T on a fine log grid, the chemical equilibrium X_eq(T) is the fixed

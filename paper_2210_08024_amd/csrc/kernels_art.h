@@ -20,7 +20,7 @@
 // their direction (Eq. e:Frad): nine more sums per cell, band-major (PE, LW, LyC) then x, y, z.
 // PE and LW become band energy fluxes (the packet's FUV luminosity shared as J^D_PE : J^D_LW,
 // the Draine field's shares), LyC a photon flux.  radiation_force_kernel turns them into the
-// force per volume on the gas-dust mixture (Sec. 5.4) with the grain-destruction switch.
+// force per volume on the gas-dust mixture (Sec. 6.2) with the grain-destruction switch.
 #pragma once
 #include "kernels_sources.h"
 
@@ -424,7 +424,7 @@ __global__ __launch_bounds__(256) void art_level_kernel(ArtArgs a) {
   }
 }
 
-// Radiation force per volume on the gas-dust mixture (Sec. 5.4): sum over bands of
+// Radiation force per volume on the gas-dust mixture (Sec. 6.2): sum over bands of
 // alpha_j F_j / c with the trace's opacities (PE, LW: dust; LyC: dust, H and H2) and h nu_LyC
 // per LyC photon.  Grains count as destroyed (appendix on grain destruction) where T exceeds
 // T_destroy or P_rad = |F| / c exceeds prad_ratio_max times P = 2 n k_B T, F the total flux of

@@ -199,7 +199,7 @@ def test_cells_mode_matches_the_full_trace():
             np.testing.assert_allclose(got[k], ref, rtol=1e-12, atol=0)
 
 
-# ---- flux (Eq. e:Frad) and radiation force (Sec. 5.4) ---------------------------------
+# ---- flux (Eq. e:Frad) and radiation force (Sec. 6.2) ---------------------------------
 
 def _energy_fluxes(out):
     """c E_j per band in the flux's units: 4 pi J^D_j chi_j for PE and LW, phi for LyC."""
@@ -323,7 +323,7 @@ def test_force_grain_destruction_switch():
 
 
 def test_force_momentum_update():
-    """The source-term update of Sec. 5.4: from rest the energy gains the kinetic energy of the
+    """The source-term update of Sec. 6.2: from rest the energy gains the kinetic energy of the
     acquired momentum, (f dt)^2 / (2 rho); a force that reverses the momentum (f dt = -2 p)
     leaves the energy as it was; n = 0 is left alone."""
     par = Params(Zg=1.0)

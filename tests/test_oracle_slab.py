@@ -1,9 +1,9 @@
-"""The plane-parallel H I -> H2 transition (Sec. 7.2) against the analytic transition column
+"""The plane-parallel H I -> H2 transition (Sec. 7.3) against the analytic transition column
 the paper quotes (Eqs. e:NH_trans, e:alpha, e:G): a beamed, CR-free slab with k_gr = 3e-17
 evolved to steady state.  The formula is sharp in the strong- and weak-field limits and
 approximate in between (alpha G / 2 ~ 0.5), where it is checked to 30%; the transition is
 resolved by more than 3 cells in every case (the paper's convergence condition).  With CR
-ionisation (attenuated as in Eq. e:cratt) the text of Sec. 7.2 fixes two facts without
+ionisation (attenuated as in Eq. e:cratt) the text of Sec. 7.3 fixes two facts without
 printed values: the transition column grows with xi_cr,0, and deep in the slab the H I
 fraction is linear in xi / (k_gr n) with the constant that Eqs. e:HH and eq:H2_cr give."""
 import numpy as np
@@ -47,7 +47,7 @@ def _cr_par(chi0, xi0):
 
 
 def test_cosmic_rays_raise_the_transition_column():
-    """Sec. 7.2 with CR ionisation attenuated by Eq. e:cratt: CRs destroy H2, so the transition
+    """Sec. 7.3 with CR ionisation attenuated by Eq. e:cratt: CRs destroy H2, so the transition
     column grows with xi_cr,0, and tends to the CR-free column as xi_cr,0 -> 0."""
     n, chi0, dx, nx = 1e2, 1.0, 0.02 * PC, 192
     N = []
@@ -65,7 +65,7 @@ def test_deep_hi_fraction_follows_the_cosmic_ray_balance():
     """Deep in a thick slab (photodissociation shielded away, cold gas) Eq. e:HH reduces to the
     balance of grain formation and CR destruction, k_gr n x_H = 1.65 zeta_cr,H2 x_H2 with
     zeta_cr,H2 = 2 xi (2.3 x_H2 + 1.5 x_HI) (Eq. eq:H2_cr): the H I fraction is linear in
-    xi / (k_gr n), x_HI k_gr n / xi -> 1.65 x 2.3 / 2 for x_H2 -> 1/2 (the text of Sec. 7.2).
+    xi / (k_gr n), x_HI k_gr n / xi -> 1.65 x 2.3 / 2 for x_H2 -> 1/2 (the text of Sec. 7.3).
     Checked with the local, attenuated xi of every cell beyond N_H = 5e21 cm^-2."""
     from oracle.columns import columns_beam
     n, chi0, xi0, dx, nx = 1e2, 1.0, 2e-16, 0.25 * PC, 160
