@@ -22,11 +22,16 @@
  *    launch/runtime errors return ISM_E_DEVICE.  ism_last_error() gives the message
  *    (thread-local).  Per-cell numerical trouble never fails a call: it is reported
  *    in the per-cell status bits below and the call returns ISM_OK.
- *  - Thread safety: after ism_init, ism_rates, ism_radiation_force and ism_chem_cool_step
- *    with order_cells = 0 may run concurrently on different streams.  ism_columns6,
- *    ism_chem_cool_step with order_cells = 1 or 2, ism_chem_cool_step_surrogate and
- *    ism_ray_trace use per-device scratch buffers (and the ray tracer the sources in constant
- *    memory): their calls on one device must not overlap in time.
+ *  - Scratch and thread safety: library scratch (tile sums, ordering keys, work-queue
+ *    counters, the surrogate step's predictions, ray lists) belongs to the (device, stream)
+ *    a call is enqueued on, so after ism_init every step and column entry point may run
+ *    concurrently on different streams; calls on one stream are ordered by it (make them
+ *    from one thread at a time).  Scratch grows with stream-ordered allocation
+ *    (hipMallocAsync / hipFreeAsync on that stream) and is kept until ism_stream_release or
+ *    ism_shutdown; nothing here synchronises the device.  The exceptions are stated at
+ *    each call: the point-source entry points (ism_point_sources, ism_ray_trace) copy their
+ *    sources into constant memory, so their calls on one device must not overlap in time,
+ *    and ism_ray_trace waits for its stream after each level.
  */
 #ifndef ISM_H
 #define ISM_H
@@ -101,8 +106,13 @@ void ism_params_default(ism_params *p);
  * Returns ISM_E_TABLE if the file is missing or invalid, ISM_E_DEVICE on HIP errors. */
 ism_status ism_init(int device, const char *coefficients_json_path);
 
-/* Release the library's device memory on every initialised device. */
+/* Release the library's device memory on every initialised device (synchronises them). */
 ism_status ism_shutdown(void);
+
+/* Release the scratch the library holds for `stream` on the current device (stream-ordered:
+ * the memory is returned after the work already queued on the stream).  For callers that
+ * destroy streams; the next call on the stream allocates afresh. */
+ism_status ism_stream_release(hipStream_t stream);
 
 /* Message of the last error on the calling thread ("" if none).  Library-owned. */
 const char *ism_last_error(void);
@@ -121,7 +131,9 @@ const char *ism_diag_name(int32_t k);
  *   xi_cr   = per p->cr_mode (not written when cr_mode = 2)
  * with upstream columns accumulated in double.
  * In: n, xH2 (double, ncell), xC (double or NULL = 0).  Out: chi_PE, chi_LW, chi_H2,
- * chi_C, N_eff, xi_cr (double for F64, float for MIXED).  Requires nx, ny, nz >= 1. */
+ * chi_C, N_eff, xi_cr (double for F64, float for MIXED).  Requires 1 <= nx, ny, nz <= 2^24
+ * and at most 2^40 cells.  Scratch: about 27 bytes per cell on the call's stream (tile sums
+ * and their forward / backward offsets); ISM_E_NOMEM when it cannot grow. */
 ism_status ism_columns6(const ism_grid *g, const ism_params *p, ism_precision prec,
                         const double *n, const double *xH2, const double *xC,
                         void *chi_PE, void *chi_LW, void *chi_H2, void *chi_C,
@@ -213,9 +225,9 @@ typedef struct {
  * nsrc x 6 doubles that receives per source the luminosity lost through the faces (PE, LW in
  * erg s^-1, LyC in photons s^-1) and then the luminosity dropped at tau > tau_max.
  * The call returns when the work is done: it reads the number of packets of each level back
- * to the host.  The packet lists are library memory on the current device (48 bytes a packet;
- * a level may hold up to 4x the previous one) and the sources sit in constant memory, so
- * calls on one device must not overlap in time.  ISM_E_NOMEM when a list cannot grow. */
+ * to the host.  The packet lists are scratch of the call's stream (48 bytes a packet; a level
+ * may hold up to 4x the previous one); the sources sit in constant memory, so calls on one
+ * device must not overlap in time.  ISM_E_NOMEM when a list cannot grow. */
 ism_status ism_ray_trace(const ism_grid *g, const ism_params *p, ism_precision prec, int32_t nsrc,
                          const ism_source *src, const ism_art_options *opt, const double *n,
                          const double *xH2, const double *xHp, const double *xC, void *chi_PE,
@@ -312,7 +324,8 @@ typedef struct ism_surrogate ism_surrogate;
 ism_status ism_surrogate_create(ism_surrogate **out, uint64_t seed);
 ism_status ism_surrogate_destroy(ism_surrogate *m);
 
-/* Host arrays; sd values must be finite and > 0.  Copies synchronously. */
+/* Host arrays; sd values must be finite and > 0.  Held on the host and passed with every
+ * later launch (no device work, no synchronisation). */
 ism_status ism_surrogate_set_norm(ism_surrogate *m, const float *mu_x, const float *sd_x,
                                   const float *mu_y, const float *sd_y);
 
@@ -332,10 +345,12 @@ ism_status ism_surrogate_backward(ism_surrogate *m, const float *X, const float 
 ism_status ism_surrogate_train_step(ism_surrogate *m, const float *X, const float *Y, int64_t B,
                                     float lr, float *loss_dev, hipStream_t stream);
 
-/* Host checkpoint of the whole training state (layout above).  get synchronises the
- * device; set copies synchronously and rebuilds the BF16 weight copies. */
-ism_status ism_surrogate_get_params(const ism_surrogate *m, float *flat);
-ism_status ism_surrogate_set_params(ism_surrogate *m, const float *flat);
+/* Host checkpoint of the whole training state (layout above).  get copies on `stream` and
+ * waits for that stream (the one synchronising call of the surrogate); set stages the host
+ * values in the object's pinned buffer (waiting only for the previous set's copy out of it),
+ * then copies and rebuilds the BF16 weight images on `stream`, without waiting. */
+ism_status ism_surrogate_get_params(const ism_surrogate *m, float *flat, hipStream_t stream);
+ism_status ism_surrogate_set_params(ism_surrogate *m, const float *flat, hipStream_t stream);
 
 /* Training pairs for the surrogate: X [ncell][10] network inputs from the pre-step state
  * (n, T0, xH2_0, xHp_0), radiation (chi_PE, phi_LyC (nullable = 0), xi_cr, N_eff; double for
@@ -363,7 +378,7 @@ ism_status ism_surrogate_pairs(const ism_params *p, ism_precision prec, int64_t 
  * MIXED step and has ISM_ST_FALLBACK set.  m may be NULL: the seed is then the input state
  * itself (the method without the network).  n_fallback_dev (device int64, nullable)
  * receives the number of plain-step cells.  accept_tol in (0, 1e-3]; ncell < 2^31.
- * Uses a per-device scratch buffer: calls on one device must not overlap in time. */
+ * Scratch (predictions, the rejected list, ordering keys) on the call's stream. */
 ism_status ism_chem_cool_step_surrogate(ism_surrogate *m, const ism_params *p, int64_t ncell,
                                         double dt_s, const double *n, double *T, double *xH2,
                                         double *xHp, const void *chi_PE, const void *chi_LW,

@@ -39,6 +39,24 @@ __host__ __device__ __forceinline__ double fexp(double x) {
   return ldexp(p, (int)k);
 }
 
+// e^x - 1: for |x| <= 0.35 the same fit as fexp without its leading 1 (x + x^2 g(x)), so small
+// arguments keep full relative precision; elsewhere fexp(x) - 1, where the subtraction loses at
+// most a bit (|e^x - 1| > 0.29 there).
+__host__ __device__ __forceinline__ double fexpm1(double x) {
+  if (!(fabs(x) <= 0.35)) return fexp(x) - 1.0;
+  double p = 0x1.af3cd7b3560d9p-26;
+  p = fma(p, x, 0x1.2894eb03786e2p-22);
+  p = fma(p, x, 0x1.71de0be80e7e8p-19);
+  p = fma(p, x, 0x1.a019b62aaa671p-16);
+  p = fma(p, x, 0x1.a01a01a83a3a3p-13);
+  p = fma(p, x, 0x1.6c16c1794bd5cp-10);
+  p = fma(p, x, 0x1.111111111091ap-7);
+  p = fma(p, x, 0x1.5555555553b72p-5);
+  p = fma(p, x, 0x1.5555555555556p-3);
+  p = fma(p, x, 0x1.0000000000001p-1);
+  return fma(x * x, p, x);
+}
+
 // ln x: x = 2^e m with m in [sqrt(1/2), sqrt(2)); with f = m - 1 (exact) and s = f / (2 + f),
 // ln m = 2 atanh s = 2 s + s z p(z), z = s^2 <= 0.02944, with p a degree-6 Chebyshev fit of
 // 2 (atanh s - s) / s^3 on z <= 0.0295 (coefficients from fmath_fit.py; 0.04 ulp);

@@ -38,31 +38,36 @@ ism_status fail(ism_status s, const std::string &msg) {
   return s;
 }
 
-constexpr int QUEUE_SLOTS = 1024;  // work-queue counters per device (overlapping step calls)
-
 struct DevState {
   bool ready = false;
   double *tab64 = nullptr;
   float *tab32 = nullptr;
-  void *scratch = nullptr;
-  size_t scratch_bytes = 0;
-  int64_t *queues = nullptr;
-  unsigned qnext = 0;
-  void *sscratch = nullptr;  // surrogate step: predictions + rejected list
-  size_t sscratch_bytes = 0;
-  void *oscratch = nullptr;  // cell ordering: keys, histogram, cursor, ordered list
-  size_t oscratch_bytes = 0;
-  ArtRay *art_list[2] = {nullptr, nullptr};  // ray tracing: packet lists of two levels
-  int64_t art_cap[2] = {0, 0};
-  unsigned long long *art_count = nullptr;     // children appended by a level launch
-  unsigned long long *art_count_host = nullptr;
   int num_cu = 0;
   int occ64 = 0, occ32 = 0;  // resident 256-thread blocks per CU of the persistent step kernels
   bool simple_step = false;   // ISM_STEP_KERNEL=simple selects the one-lane-per-cell grid
 };
 
+// Library scratch of one (device, stream): every call takes the scratch of the stream it is
+// enqueued on, so calls on different streams never share memory.  Buffers grow with
+// stream-ordered allocation (hipFreeAsync / hipMallocAsync on that stream): no device-wide
+// synchronisation, and a buffer is released only after the work queued before it on the stream.
+struct StreamScratch {
+  void *col = nullptr;  // six-ray columns: tile sums and offsets
+  size_t col_b = 0;
+  void *ord = nullptr;  // cell ordering: keys, histogram, cursor, ordered list
+  size_t ord_b = 0;
+  void *surr = nullptr;  // surrogate step: predictions and the rejected list
+  size_t surr_b = 0;
+  void *ctl = nullptr;  // [0] work-queue counter (int64), [1] rejected-cell count (uint64)
+  size_t ctl_b = 0;
+  void *art[2] = {nullptr, nullptr};  // ray tracing: packet lists of two levels
+  size_t art_b[2] = {0, 0};
+  unsigned long long *art_count_host = nullptr;  // pinned: children appended by a level
+};
+
 std::mutex g_mu;
 std::map<int, DevState> g_dev;
+std::map<std::pair<int, hipStream_t>, StreamScratch> g_ss;
 
 #define HIP_TRY(expr)                                                                   \
   do {                                                                                  \
@@ -118,55 +123,44 @@ ParT<R> make_par(const ism_params *p, const CoefT<double> &c) {
 
 CoefT<double> g_host_coef;  // last loaded coefficients (host copy for make_par)
 
-ism_status scratch(DevState *st, size_t bytes, void **out) {
+// The scratch record of (current device, stream); std::map keeps the address stable.
+StreamScratch *stream_scratch(int dev, hipStream_t stream) {
   std::lock_guard<std::mutex> lk(g_mu);
-  if (st->scratch_bytes < bytes) {
-    if (st->scratch) (void)hipFree(st->scratch);
-    st->scratch = nullptr;
-    st->scratch_bytes = 0;
-    hipError_t e = hipMalloc(&st->scratch, bytes);
-    if (e != hipSuccess) return fail(ISM_E_NOMEM, std::string("scratch allocation failed: ") + hipGetErrorString(e));
-    st->scratch_bytes = bytes;
+  return &g_ss[std::make_pair(dev, stream)];
+}
+
+// Make *p hold at least `bytes` (stream-ordered; contents are not kept across growth).
+ism_status grow(void **p, size_t *cap, size_t bytes, hipStream_t stream, const char *what) {
+  if (*cap >= bytes && *p) return ISM_OK;
+  if (*p) {
+    hipError_t e = hipFreeAsync(*p, stream);
+    if (e != hipSuccess) return fail(ISM_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
   }
-  *out = st->scratch;
+  *p = nullptr;
+  *cap = 0;
+  const size_t want = std::max<size_t>(bytes, 256);
+  hipError_t e = hipMallocAsync(p, want, stream);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(ISM_E_NOMEM, std::string(what) + " (" + std::to_string(want) + " bytes): " + hipGetErrorString(e));
+  }
+  *cap = want;
   return ISM_OK;
 }
 
-ism_status surr_scratch(DevState *st, size_t bytes, void **out) {
-  std::lock_guard<std::mutex> lk(g_mu);
-  if (st->sscratch_bytes < bytes) {
-    if (st->sscratch) (void)hipFree(st->sscratch);
-    st->sscratch = nullptr;
-    st->sscratch_bytes = 0;
-    hipError_t e = hipMalloc(&st->sscratch, bytes);
-    if (e != hipSuccess) return fail(ISM_E_NOMEM, std::string("surrogate scratch: ") + hipGetErrorString(e));
-    st->sscratch_bytes = bytes;
-  }
-  *out = st->sscratch;
-  return ISM_OK;
+// Scratch bytes of the cell ordering for n items.
+size_t order_bytes(int64_t n) {
+  const size_t key_b = (size_t)((n * 2 + 255) / 256 * 256), bins_b = (size_t)ORDER_BINS * 4;
+  const size_t out_b = (size_t)((n * 4 + 255) / 256 * 256);
+  return key_b + 2 * bins_b + out_b;
 }
 
 // Order `n` items (cells, or the cells listed in `items`, `*count` of them when count is set)
-// by temperature regime; *out receives the ordered cell list (library scratch).
-ism_status order_cells(DevState *st, int64_t n, const unsigned long long *count, const int32_t *items,
-                       const double *T, const float *pred, const int32_t *nsub, int32_t **out,
-                       hipStream_t stream) {
+// by temperature regime (or previous substep counts); *out receives the ordered cell list, laid
+// out in `base` (order_bytes(n) bytes of scratch).
+void order_cells(uint8_t *base, int64_t n, const unsigned long long *count, const int32_t *items, const double *T,
+                 const float *pred, const int32_t *nsub, int32_t **out, hipStream_t stream) {
   const size_t key_b = (size_t)((n * 2 + 255) / 256 * 256), bins_b = (size_t)ORDER_BINS * 4;
-  const size_t out_b = (size_t)((n * 4 + 255) / 256 * 256);
-  const size_t bytes = key_b + 2 * bins_b + out_b;
-  uint8_t *base;
-  {
-    std::lock_guard<std::mutex> lk(g_mu);
-    if (st->oscratch_bytes < bytes) {
-      if (st->oscratch) (void)hipFree(st->oscratch);
-      st->oscratch = nullptr;
-      st->oscratch_bytes = 0;
-      hipError_t e = hipMalloc(&st->oscratch, bytes);
-      if (e != hipSuccess) return fail(ISM_E_NOMEM, std::string("order scratch: ") + hipGetErrorString(e));
-      st->oscratch_bytes = bytes;
-    }
-    base = (uint8_t *)st->oscratch;
-  }
   OrderArgs a{n, count, items, T, pred, nsub, (uint16_t *)base, (uint32_t *)(base + key_b),
               (uint32_t *)(base + key_b + bins_b), (int32_t *)(base + key_b + 2 * bins_b)};
   const dim3 grid((unsigned)((n + ORDER_THREADS - 1) / ORDER_THREADS));
@@ -175,7 +169,103 @@ ism_status order_cells(DevState *st, int64_t n, const unsigned long long *count,
   hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(ORDER_THREADS), 0, stream, a);
   hipLaunchKernelGGL(order_scatter_kernel, grid, dim3(ORDER_THREADS), 0, stream, a);
   *out = a.out;
+}
+
+// Scratch bytes of the tiled six-ray pass: sums, forward and backward offsets, 3 quantities each.
+size_t columns_bytes(const ism_grid *g) {
+  const TileGeo tg = tile_geo(g->nx, g->ny, g->nz);
+  return 9 * (size_t)tg.per_q * sizeof(double);
+}
+
+// Launch the tiled six-ray pass (the three kernels of kernels_columns.h) with `buf` holding
+// columns_bytes(grid) bytes.
+ism_status launch_columns6(const DevState *st, const ism_grid *g, const ism_params *p, bool f32, const double *n,
+                           const double *xH2, const double *xC, void *chi_PE, void *chi_LW, void *chi_H2,
+                           void *chi_C, void *N_eff, void *xi_cr, void *buf, hipStream_t stream) {
+  TileArgs t{};
+  ColArgs &a = t.c;
+  a.nx = g->nx; a.ny = g->ny; a.nz = g->nz; a.dx = g->dx_cm;
+  a.n = n; a.xH2 = xH2; a.xC = xC;
+  a.chiPE = chi_PE; a.chiLW = chi_LW; a.chiH2 = chi_H2; a.chiC = chi_C; a.Neff = N_eff; a.xi = xi_cr;
+  a.cr_mode = p->cr_mode;
+  a.chi0 = p->chi0; a.Zd = p->Zd; a.xi0 = p->xi_cr0;
+  a.sPE = g_host_coef.sig_d_abs[2] * p->Zd;
+  a.sLW = g_host_coef.sig_d_abs[1] * p->Zd;
+  a.tab = st->tab64;
+  t.g = tile_geo(g->nx, g->ny, g->nz);
+  t.S = (double *)buf;
+  t.F = t.S + 3 * t.g.per_q;
+  t.B = t.F + 3 * t.g.per_q;
+  const int64_t pairs = (int64_t)((t.g.ntx + 1) / 2) * t.g.nty * t.g.ntz;
+  const int cu = std::max(st->num_cu, 1);
+  // one wave per block: the sums kernel holds no LDS, the tile kernel 36 KB (four blocks per CU)
+  const unsigned g1 = (unsigned)std::min<int64_t>(pairs, (int64_t)cu * 16);
+  const unsigned g3 = (unsigned)std::min<int64_t>(pairs, (int64_t)cu * 4);
+  hipLaunchKernelGGL(columns_tilesum_kernel, dim3(g1), dim3(CT_LANES), 0, stream, t);
+  const int64_t lines = 2 * (t.g.lx + t.g.ly + t.g.lz);
+  hipLaunchKernelGGL(columns_offsets_kernel, dim3((unsigned)((lines + 255) / 256)), dim3(256), 0, stream, t);
+  if (f32) hipLaunchKernelGGL(columns_tile_kernel<float>, dim3(g3), dim3(CT_LANES), 0, stream, t);
+  else hipLaunchKernelGGL(columns_tile_kernel<double>, dim3(g3), dim3(CT_LANES), 0, stream, t);
+  HIP_TRY(hipGetLastError());
   return ISM_OK;
+}
+
+ism_status check_step(const ism_params *p, ism_precision prec, int64_t ncell, double dt_s, const double *n,
+                      const double *T, const double *xH2, const double *xHp, const void *chi_PE, const void *chi_LW,
+                      const void *chi_H2, const void *chi_C, const void *xi_cr, const void *N_eff) {
+  if (ism_status s = check_params(p)) return s;
+  if (prec != ISM_PREC_F64 && prec != ISM_PREC_MIXED) return fail(ISM_E_ARG, "invalid precision");
+  if (ncell < 0) return fail(ISM_E_ARG, "ncell must be >= 0");
+  if (!(dt_s >= 0.0) || !std::isfinite(dt_s)) return fail(ISM_E_ARG, "dt_s must be finite and >= 0");
+  if (ncell == 0) return ISM_OK;
+  if (!n || !T || !xH2 || !xHp || !chi_PE || !chi_LW || !chi_H2 || !chi_C || !xi_cr || !N_eff)
+    return fail(ISM_E_ARG, "a required array is NULL");
+  return ISM_OK;
+}
+
+// Whether the step orders its cells (order_cells 1 or 2, the persistent kernel, int32 indices).
+bool step_orders(const DevState *st, const ism_params *p, int64_t ncell) {
+  return p->order_cells && !st->simple_step && ncell <= (int64_t)INT32_MAX;
+}
+
+// Enqueue the source step on `stream`: the cell ordering into `ord` (order_bytes(ncell) bytes;
+// null when step_orders is false), the work-queue counter `q` (set by a kernel, so the sequence
+// holds no memset), then the persistent kernel.
+void launch_step(const DevState *st, const ism_params *p, ism_precision prec, int64_t ncell, double dt_s,
+                 const double *n, double *T, double *xH2, double *xHp, const void *chi_PE, const void *chi_LW,
+                 const void *chi_H2, const void *chi_C, const void *phi_LyC, const void *xi_cr, const void *N_eff,
+                 void *xCp, void *xCO, void *xe, int32_t *nsub, uint8_t *status, int64_t *q, uint8_t *ord,
+                 hipStream_t stream) {
+  const int64_t want = (ncell + 255) / 256;
+  int32_t *order = nullptr;
+  if (ord) order_cells(ord, ncell, nullptr, nullptr, T, nullptr, p->order_cells == 2 ? nsub : nullptr, &order, stream);
+  if (prec == ISM_PREC_F64) {
+    StepArgs<double> a{ncell, dt_s, n, T, xH2, xHp, (const double *)chi_PE, (const double *)chi_LW,
+                       (const double *)chi_H2, (const double *)chi_C, (const double *)phi_LyC,
+                       (const double *)xi_cr, (const double *)N_eff, (double *)xCp, (double *)xCO, (double *)xe,
+                       nsub, status, st->tab64, make_par<double>(p, g_host_coef), make_par<double>(p, g_host_coef), q,
+                       order, nullptr, 0u};
+    if (st->simple_step) {
+      hipLaunchKernelGGL(step_simple_kernel<double>, dim3((unsigned)want), dim3(256), 0, stream, a);
+    } else {
+      const int64_t grid = std::min<int64_t>(want, (int64_t)st->num_cu * std::max(st->occ64, 1));
+      hipLaunchKernelGGL(queue_init_kernel, dim3(1), dim3(1), 0, stream, q, grid * 256);
+      hipLaunchKernelGGL(step_queue_kernel<double>, dim3((unsigned)grid), dim3(256), 0, stream, a);
+    }
+  } else {
+    StepArgs<float> a{ncell, dt_s, n, T, xH2, xHp, (const float *)chi_PE, (const float *)chi_LW,
+                      (const float *)chi_H2, (const float *)chi_C, (const float *)phi_LyC,
+                      (const float *)xi_cr, (const float *)N_eff, (float *)xCp, (float *)xCO, (float *)xe,
+                      nsub, status, st->tab32, make_par<float>(p, g_host_coef), make_par<double>(p, g_host_coef), q,
+                      order, nullptr, 0u};
+    if (st->simple_step) {
+      hipLaunchKernelGGL(step_simple_kernel<float>, dim3((unsigned)want), dim3(256), 0, stream, a);
+    } else {
+      const int64_t grid = std::min<int64_t>(want, (int64_t)st->num_cu * std::max(st->occ32, 1));
+      hipLaunchKernelGGL(queue_init_kernel, dim3(1), dim3(1), 0, stream, q, grid * 256);
+      hipLaunchKernelGGL(step_queue_kernel<float>, dim3((unsigned)grid), dim3(256), 0, stream, a);
+    }
+  }
 }
 
 const char *kDiagNames[NDIAG] = {
@@ -230,7 +320,6 @@ ism_status ism_init(int device, const char *path) {
     if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(g_coef64), &c64, sizeof(c64));
     if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(g_coef32), &c32, sizeof(c32));
     if (e == hipSuccess) e = hipDeviceGetAttribute(&st.num_cu, hipDeviceAttributeMultiprocessorCount, device);
-    if (e == hipSuccess && !st.queues) e = hipMalloc(&st.queues, QUEUE_SLOTS * sizeof(int64_t));
     if (e == hipSuccess)
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&st.occ64, step_queue_kernel<double>, 256, 0);
     if (e == hipSuccess)
@@ -256,17 +345,38 @@ ism_status ism_shutdown(void) {
     (void)hipDeviceSynchronize();
     if (kv.second.tab64) (void)hipFree(kv.second.tab64);
     if (kv.second.tab32) (void)hipFree(kv.second.tab32);
-    if (kv.second.scratch) (void)hipFree(kv.second.scratch);
-    if (kv.second.queues) (void)hipFree(kv.second.queues);
-    if (kv.second.sscratch) (void)hipFree(kv.second.sscratch);
-    if (kv.second.oscratch) (void)hipFree(kv.second.oscratch);
-    for (int b = 0; b < 2; ++b)
-      if (kv.second.art_list[b]) (void)hipFree(kv.second.art_list[b]);
-    if (kv.second.art_count) (void)hipFree(kv.second.art_count);
-    if (kv.second.art_count_host) (void)hipHostFree(kv.second.art_count_host);
+    for (auto &ss : g_ss) {
+      if (ss.first.first != kv.first) continue;
+      StreamScratch &x = ss.second;
+      for (void *q : {x.col, x.ord, x.surr, x.ctl, x.art[0], x.art[1]})
+        if (q) (void)hipFree(q);
+      if (x.art_count_host) (void)hipHostFree(x.art_count_host);
+    }
   }
+  g_ss.clear();
   g_dev.clear();
   (void)hipSetDevice(prev);
+  return ISM_OK;
+}
+
+ism_status ism_stream_release(hipStream_t stream) {
+  g_err.clear();
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  StreamScratch x;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_ss.find(std::make_pair(dev, stream));
+    if (it == g_ss.end()) return ISM_OK;
+    x = it->second;
+    g_ss.erase(it);
+  }
+  for (void *q : {x.col, x.ord, x.surr, x.ctl, x.art[0], x.art[1]})
+    if (q) HIP_TRY(hipFreeAsync(q, stream));
+  if (x.art_count_host) {
+    // the pinned count is read back only inside ism_ray_trace, after a stream synchronisation
+    HIP_TRY(hipHostFree(x.art_count_host));
+  }
   return ISM_OK;
 }
 
@@ -279,61 +389,19 @@ ism_status ism_columns6(const ism_grid *g, const ism_params *p, ism_precision pr
   if (prec != ISM_PREC_F64 && prec != ISM_PREC_MIXED) return fail(ISM_E_ARG, "invalid precision");
   if (g->nx < 1 || g->ny < 1 || g->nz < 1) return fail(ISM_E_ARG, "grid dimensions must be >= 1");
   if (!(g->dx_cm > 0.0) || !std::isfinite(g->dx_cm)) return fail(ISM_E_ARG, "dx_cm must be finite and > 0");
-  if ((int64_t)g->ny * g->nz > (int64_t)INT32_MAX * 4 || g->nx > (1 << 24))
-    return fail(ISM_E_ARG, "grid too large");
+  if (g->nx > (1 << 24) || g->ny > (1 << 24) || g->nz > (1 << 24) ||
+      (int64_t)g->nx * g->ny * g->nz > ((int64_t)1 << 40))
+    return fail(ISM_E_ARG, "grid too large (each dimension at most 2^24 cells, at most 2^40 cells)");
   if (!n || !xH2 || !chi_PE || !chi_LW || !chi_H2 || !chi_C || !N_eff)
     return fail(ISM_E_ARG, "n, xH2 and all chi/N_eff outputs must be non-NULL");
   if (p->cr_mode != 2 && !xi_cr) return fail(ISM_E_ARG, "xi_cr output is NULL (cr_mode 0/1 writes it)");
   DevState *st;
-  if (ism_status s = current_state(&st)) return s;
-  const int64_t ncell = (int64_t)g->nx * g->ny * g->nz;
-  // y/z pencils are split into segments until about 2^18 lanes march per pass
-  auto nseg_for = [&](int64_t pencils, int L) {
-    int64_t s = (262144 + pencils - 1) / pencils;
-    s = std::max<int64_t>(1, std::min<int64_t>(s, L));
-    return (int)s;
-  };
-  const int segy = nseg_for((int64_t)g->nx * g->nz, g->ny), segz = nseg_for((int64_t)g->nx * g->ny, g->nz);
-  const size_t seg_elems = 3 * (size_t)std::max((int64_t)g->nx * g->nz * segy, (int64_t)g->nx * g->ny * segz);
-  void *buf;
-  if (ism_status s = scratch(st, (size_t)ncell * sizeof(double4) + seg_elems * sizeof(double), &buf)) return s;
-  ColArgs a;
-  a.nx = g->nx; a.ny = g->ny; a.nz = g->nz; a.dx = g->dx_cm;
-  a.n = n; a.xH2 = xH2; a.xC = xC;
-  a.acc = (double4 *)buf;
-  a.seg = (double *)((char *)buf + (size_t)ncell * sizeof(double4));
-  a.chiPE = chi_PE; a.chiLW = chi_LW; a.chiH2 = chi_H2; a.chiC = chi_C; a.Neff = N_eff; a.xi = xi_cr;
-  a.cr_mode = p->cr_mode;
-  a.chi0 = p->chi0; a.Zd = p->Zd; a.xi0 = p->xi_cr0;
-  a.sPE = g_host_coef.sig_d_abs[2] * p->Zd;
-  a.sLW = g_host_coef.sig_d_abs[1] * p->Zd;
-  a.tab = st->tab64;
-  const bool f32 = prec == ISM_PREC_MIXED;
-  const int64_t rows = (int64_t)g->ny * g->nz;
-  if (f32) hipLaunchKernelGGL(columns_x_kernel<float>, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, stream, a);
-  else hipLaunchKernelGGL(columns_x_kernel<double>, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, stream, a);
-  HIP_TRY(hipGetLastError());
-  for (int ax = 1; ax <= 2; ++ax) {
-    a.nseg = ax == 1 ? segy : segz;
-    const int L = ax == 1 ? g->ny : g->nz;
-    a.seglen = (L + a.nseg - 1) / a.nseg;
-    const int64_t lanes = (int64_t)g->nx * (ax == 1 ? g->nz : g->ny) * a.nseg;
-    const dim3 grid((unsigned)((lanes + 255) / 256)), blk(256);
-    if (a.nseg > 1) {
-      if (ax == 1) hipLaunchKernelGGL(columns_segsum_kernel<1>, grid, blk, 0, stream, a);
-      else hipLaunchKernelGGL(columns_segsum_kernel<2>, grid, blk, 0, stream, a);
-      HIP_TRY(hipGetLastError());
-    }
-    if (ax == 1) {
-      if (f32) hipLaunchKernelGGL((columns_march_kernel<float, 1>), grid, blk, 0, stream, a);
-      else hipLaunchKernelGGL((columns_march_kernel<double, 1>), grid, blk, 0, stream, a);
-    } else {
-      if (f32) hipLaunchKernelGGL((columns_march_kernel<float, 2>), grid, blk, 0, stream, a);
-      else hipLaunchKernelGGL((columns_march_kernel<double, 2>), grid, blk, 0, stream, a);
-    }
-    HIP_TRY(hipGetLastError());
-  }
-  return ISM_OK;
+  int dev = 0;
+  if (ism_status s = current_state(&st, &dev)) return s;
+  StreamScratch *ss = stream_scratch(dev, stream);
+  if (ism_status s = grow(&ss->col, &ss->col_b, columns_bytes(g), stream, "columns scratch")) return s;
+  return launch_columns6(st, g, p, prec == ISM_PREC_MIXED, n, xH2, xC, chi_PE, chi_LW, chi_H2, chi_C, N_eff, xi_cr,
+                         ss->col, stream);
 }
 
 ism_status ism_rates(const ism_params *p, ism_precision prec, int64_t ncell, const double *n, const double *T,
@@ -373,57 +441,24 @@ ism_status ism_chem_cool_step(const ism_params *p, ism_precision prec, int64_t n
                               const void *N_eff, void *xCp, void *xCO, void *xe, int32_t *nsub, uint8_t *status,
                               hipStream_t stream) {
   g_err.clear();
-  if (ism_status s = check_params(p)) return s;
-  if (prec != ISM_PREC_F64 && prec != ISM_PREC_MIXED) return fail(ISM_E_ARG, "invalid precision");
-  if (ncell < 0) return fail(ISM_E_ARG, "ncell must be >= 0");
-  if (!(dt_s >= 0.0) || !std::isfinite(dt_s)) return fail(ISM_E_ARG, "dt_s must be finite and >= 0");
+  if (ism_status s = check_step(p, prec, ncell, dt_s, n, T, xH2, xHp, chi_PE, chi_LW, chi_H2, chi_C, xi_cr, N_eff))
+    return s;
   if (ncell == 0) return ISM_OK;
-  if (!n || !T || !xH2 || !xHp || !chi_PE || !chi_LW || !chi_H2 || !chi_C || !xi_cr || !N_eff)
-    return fail(ISM_E_ARG, "a required array is NULL");
   DevState *st;
-  if (ism_status s = current_state(&st)) return s;
-  int64_t *q;
-  {
-    std::lock_guard<std::mutex> lk(g_mu);
-    q = st->queues + (st->qnext++ % QUEUE_SLOTS);
+  int dev = 0;
+  if (ism_status s = current_state(&st, &dev)) return s;
+  StreamScratch *ss = stream_scratch(dev, stream);
+  if (ism_status s = grow(&ss->ctl, &ss->ctl_b, 256, stream, "work-queue counter")) return s;
+  uint8_t *ord = nullptr;
+  if (step_orders(st, p, ncell)) {
+    if (ism_status s = grow(&ss->ord, &ss->ord_b, order_bytes(ncell), stream, "order scratch")) return s;
+    ord = (uint8_t *)ss->ord;
   }
-  const int64_t want = (ncell + 255) / 256;
-  int32_t *order = nullptr;
-  if (p->order_cells && !st->simple_step && ncell <= (int64_t)INT32_MAX)
-    if (ism_status s = order_cells(st, ncell, nullptr, nullptr, T, nullptr, p->order_cells == 2 ? nsub : nullptr,
-                                   &order, stream))
-      return s;
-  if (prec == ISM_PREC_F64) {
-    StepArgs<double> a{ncell, dt_s, n, T, xH2, xHp, (const double *)chi_PE, (const double *)chi_LW,
-                       (const double *)chi_H2, (const double *)chi_C, (const double *)phi_LyC,
-                       (const double *)xi_cr, (const double *)N_eff, (double *)xCp, (double *)xCO, (double *)xe,
-                       nsub, status, st->tab64, make_par<double>(p, g_host_coef), make_par<double>(p, g_host_coef), q,
-                       order, nullptr, 0u};
-    if (st->simple_step) {
-      hipLaunchKernelGGL(step_simple_kernel<double>, dim3((unsigned)want), dim3(256), 0, stream, a);
-    } else {
-      const int64_t grid = std::min<int64_t>(want, (int64_t)st->num_cu * std::max(st->occ64, 1));
-      hipLaunchKernelGGL(queue_init_kernel, dim3(1), dim3(1), 0, stream, q, grid * 256);
-      hipLaunchKernelGGL(step_queue_kernel<double>, dim3((unsigned)grid), dim3(256), 0, stream, a);
-    }
-  } else {
-    StepArgs<float> a{ncell, dt_s, n, T, xH2, xHp, (const float *)chi_PE, (const float *)chi_LW,
-                      (const float *)chi_H2, (const float *)chi_C, (const float *)phi_LyC,
-                      (const float *)xi_cr, (const float *)N_eff, (float *)xCp, (float *)xCO, (float *)xe,
-                      nsub, status, st->tab32, make_par<float>(p, g_host_coef), make_par<double>(p, g_host_coef), q,
-                      order, nullptr, 0u};
-    if (st->simple_step) {
-      hipLaunchKernelGGL(step_simple_kernel<float>, dim3((unsigned)want), dim3(256), 0, stream, a);
-    } else {
-      const int64_t grid = std::min<int64_t>(want, (int64_t)st->num_cu * std::max(st->occ32, 1));
-      hipLaunchKernelGGL(queue_init_kernel, dim3(1), dim3(1), 0, stream, q, grid * 256);
-      hipLaunchKernelGGL(step_queue_kernel<float>, dim3((unsigned)grid), dim3(256), 0, stream, a);
-    }
-  }
+  launch_step(st, p, prec, ncell, dt_s, n, T, xH2, xHp, chi_PE, chi_LW, chi_H2, chi_C, phi_LyC, xi_cr, N_eff, xCp,
+              xCO, xe, nsub, status, (int64_t *)ss->ctl, ord, stream);
   HIP_TRY(hipGetLastError());
   return ISM_OK;
 }
-
 
 // ====================================================================== surrogate
 }  // extern "C"
@@ -433,11 +468,12 @@ struct ism_surrogate {
   int num_cu = 1;
   float *params = nullptr;  // theta | adam m | adam v | grad scratch, NPARAM floats each
   uint8_t *img = nullptr;   // forward image | backward image
-  float *norm = nullptr;    // mlp::NRM_FLOATS
-  float norm_host[26];      // mu_x sd_x mu_y sd_y
+  float norm_host[26];      // mu_x sd_x mu_y sd_y (passed by value with every launch)
   int64_t step = 0;
-  void *work = nullptr;
+  void *work = nullptr;     // training workspace, grown stream-ordered
   size_t work_bytes = 0;
+  float *staging = nullptr;  // pinned: params on their way to or from the device
+  hipEvent_t staged = nullptr;  // recorded after the last upload out of `staging`
   float *theta() const { return params; }
   float *adam_m() const { return params + mlp::NPARAM; }
   float *adam_v() const { return params + 2 * mlp::NPARAM; }
@@ -462,27 +498,27 @@ ism_status surr_check(const ism_surrogate *m) {
   return ISM_OK;
 }
 
-ism_status surr_upload_norm(ism_surrogate *m) {
-  float d[mlp::NRM_FLOATS] = {0.f};
+// The standardisation as a launch argument.
+mlp::Norm surr_norm(const ism_surrogate *m) {
+  mlp::Norm d{};
   for (int k = 0; k < mlp::NIN; ++k) {
-    d[mlp::NRM_MUX + k] = m->norm_host[k];
-    d[mlp::NRM_ISDX + k] = (float)(1.0 / (double)m->norm_host[10 + k]);
+    d.v[mlp::NRM_MUX + k] = m->norm_host[k];
+    d.v[mlp::NRM_ISDX + k] = (float)(1.0 / (double)m->norm_host[10 + k]);
   }
   for (int k = 0; k < mlp::NOUT; ++k) {
-    d[mlp::NRM_MUY + k] = m->norm_host[20 + k];
-    d[mlp::NRM_SDY + k] = m->norm_host[23 + k];
-    d[mlp::NRM_ISDY + k] = (float)(1.0 / (double)m->norm_host[23 + k]);
+    d.v[mlp::NRM_MUY + k] = m->norm_host[20 + k];
+    d.v[mlp::NRM_SDY + k] = m->norm_host[23 + k];
+    d.v[mlp::NRM_ISDY + k] = (float)(1.0 / (double)m->norm_host[23 + k]);
   }
-  HIP_TRY(hipMemcpy(m->norm, d, sizeof(d), hipMemcpyHostToDevice));
-  return ISM_OK;
+  return d;
 }
 
-ism_status surr_pack(ism_surrogate *m) {
-  HIP_TRY(hipMemset(m->img, 0, mlp::FI_BYTES + mlp::BI_BYTES));
-  hipLaunchKernelGGL(mlp::mlp_pack_kernel, dim3((mlp::NPARAM + 255) / 256), dim3(256), 0, nullptr, m->theta(),
+// BF16 weight images from the FP32 parameters, enqueued on `stream` (the images' padding is
+// zeroed once at creation and never written by the pack kernel).
+ism_status surr_pack(ism_surrogate *m, hipStream_t stream) {
+  hipLaunchKernelGGL(mlp::mlp_pack_kernel, dim3((mlp::NPARAM + 255) / 256), dim3(256), 0, stream, m->theta(),
                      m->fimg(), m->bimg());
   HIP_TRY(hipGetLastError());
-  HIP_TRY(hipDeviceSynchronize());
   return ISM_OK;
 }
 
@@ -502,7 +538,7 @@ int fwd_grid(const ism_surrogate *m, int64_t B) {
   return (int)std::max<int64_t>(1, std::min<int64_t>((B + mlp::WTILE - 1) / mlp::WTILE, m->num_cu));
 }
 
-ism_status surr_work(ism_surrogate *m, int64_t B, SurrWork &w) {
+ism_status surr_work(ism_surrogate *m, int64_t B, SurrWork &w, hipStream_t stream) {
   w.chunk = std::max<int64_t>(64, ((B + 127) / 128 + 63) / 64 * 64);
   w.nchunk = (int)((B + w.chunk - 1) / w.chunk);
   w.grid_fwd = fwd_grid(m, B);
@@ -514,17 +550,7 @@ ism_status surr_work(ism_surrogate *m, int64_t B, SurrWork &w) {
                          align256((size_t)w.grid_fwd * mlp::FWD_WAVES * 4)};
   size_t total = 0;
   for (size_t x : sz) total += x;
-  if (m->work_bytes < total) {
-    if (m->work) {
-      HIP_TRY(hipDeviceSynchronize());
-      (void)hipFree(m->work);
-    }
-    m->work = nullptr;
-    m->work_bytes = 0;
-    hipError_t e = hipMalloc(&m->work, total);
-    if (e != hipSuccess) return fail(ISM_E_NOMEM, std::string("surrogate workspace: ") + hipGetErrorString(e));
-    m->work_bytes = total;
-  }
+  if (ism_status s = grow(&m->work, &m->work_bytes, total, stream, "surrogate workspace")) return s;
   uint8_t *p = (uint8_t *)m->work;
   void *ptr[10];
   for (int i = 0; i < 10; ++i) {
@@ -541,7 +567,7 @@ ism_status surr_work(ism_surrogate *m, int64_t B, SurrWork &w) {
 void surr_fwd_bwd(ism_surrogate *m, const float *X, const float *Yt, const float *dY, int64_t B, SurrWork &w,
                   hipStream_t stream) {
   mlp::FwdArgs fa{};
-  fa.X = X; fa.B = B; fa.fimg = m->fimg(); fa.norm = m->norm;
+  fa.X = X; fa.B = B; fa.fimg = m->fimg(); fa.norm = surr_norm(m);
   fa.h0 = w.h0; fa.h1 = w.h1; fa.h2 = w.h2; fa.h3 = w.h3; fa.z1 = w.z1; fa.z2 = w.z2; fa.z3 = w.z3;
   const float *d4 = dY;
   if (Yt) {
@@ -586,12 +612,14 @@ ism_status ism_surrogate_create(ism_surrogate **out, uint64_t seed) {
   }
   hipError_t e = hipMalloc(&m->params, 4 * (size_t)mlp::NPARAM * sizeof(float));
   if (e == hipSuccess) e = hipMalloc(&m->img, mlp::FI_BYTES + mlp::BI_BYTES);
-  if (e == hipSuccess) e = hipMalloc(&m->norm, mlp::NRM_FLOATS * sizeof(float));
+  if (e == hipSuccess) e = hipHostMalloc(&m->staging, 3 * (size_t)mlp::NPARAM * sizeof(float));
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&m->staged, hipEventDisableTiming);
   if (e == hipSuccess) e = hipMemset(m->params, 0, 4 * (size_t)mlp::NPARAM * sizeof(float));
+  if (e == hipSuccess) e = hipMemset(m->img, 0, mlp::FI_BYTES + mlp::BI_BYTES);
   if (e == hipSuccess) e = hipMemcpy(m->params, theta.data(), mlp::NPARAM * sizeof(float), hipMemcpyHostToDevice);
   ism_status rc = e == hipSuccess ? ISM_OK : fail(ISM_E_NOMEM, std::string("surrogate: ") + hipGetErrorString(e));
-  if (rc == ISM_OK) rc = surr_upload_norm(m);
-  if (rc == ISM_OK) rc = surr_pack(m);
+  if (rc == ISM_OK) rc = surr_pack(m, nullptr);
+  if (rc == ISM_OK && hipDeviceSynchronize() != hipSuccess) rc = fail(ISM_E_DEVICE, "surrogate: pack failed");
   if (rc != ISM_OK) {
     ism_surrogate_destroy(m);
     return rc;
@@ -608,8 +636,9 @@ ism_status ism_surrogate_destroy(ism_surrogate *m) {
   (void)hipDeviceSynchronize();
   if (m->params) (void)hipFree(m->params);
   if (m->img) (void)hipFree(m->img);
-  if (m->norm) (void)hipFree(m->norm);
   if (m->work) (void)hipFree(m->work);
+  if (m->staging) (void)hipHostFree(m->staging);
+  if (m->staged) (void)hipEventDestroy(m->staged);
   (void)hipSetDevice(prev);
   delete m;
   return ISM_OK;
@@ -626,12 +655,11 @@ ism_status ism_surrogate_set_norm(ism_surrogate *m, const float *mu_x, const flo
   for (int k = 0; k < mlp::NOUT; ++k)
     if (!std::isfinite(mu_y[k]) || !(sd_y[k] > 0.f) || !std::isfinite(sd_y[k]))
       return fail(ISM_E_ARG, "mu_y must be finite and sd_y finite and > 0");
-  HIP_TRY(hipDeviceSynchronize());
   std::memcpy(m->norm_host, mu_x, 10 * sizeof(float));
   std::memcpy(m->norm_host + 10, sd_x, 10 * sizeof(float));
   std::memcpy(m->norm_host + 20, mu_y, 3 * sizeof(float));
   std::memcpy(m->norm_host + 23, sd_y, 3 * sizeof(float));
-  return surr_upload_norm(m);
+  return ISM_OK;
 }
 
 ism_status ism_surrogate_forward(ism_surrogate *m, const float *X, float *Y, int64_t B, hipStream_t stream) {
@@ -641,7 +669,7 @@ ism_status ism_surrogate_forward(ism_surrogate *m, const float *X, float *Y, int
   if (B == 0) return ISM_OK;
   if (!X || !Y) return fail(ISM_E_ARG, "X and Y must not be NULL");
   mlp::FwdArgs fa{};
-  fa.X = X; fa.B = B; fa.fimg = m->fimg(); fa.norm = m->norm; fa.Y = Y;
+  fa.X = X; fa.B = B; fa.fimg = m->fimg(); fa.norm = surr_norm(m); fa.Y = Y;
   hipLaunchKernelGGL(mlp::mlp_fwd_kernel<0>, dim3(fwd_grid(m, B)), dim3(mlp::FWD_THREADS), 0, stream, fa);
   HIP_TRY(hipGetLastError());
   return ISM_OK;
@@ -654,7 +682,7 @@ ism_status ism_surrogate_backward(ism_surrogate *m, const float *X, const float 
   if (B < 1) return fail(ISM_E_ARG, "B must be >= 1");
   if (!X || !dY || !grad) return fail(ISM_E_ARG, "X, dY and grad must not be NULL");
   SurrWork w;
-  if (ism_status s = surr_work(m, B, w)) return s;
+  if (ism_status s = surr_work(m, B, w, stream)) return s;
   surr_fwd_bwd(m, X, nullptr, dY, B, w, stream);
   mlp::AdamArgs aa{};
   aa.part = w.part; aa.nchunk = w.nchunk; aa.grad = grad; aa.adam = 0;
@@ -671,7 +699,7 @@ ism_status ism_surrogate_train_step(ism_surrogate *m, const float *X, const floa
   if (!X || !Y) return fail(ISM_E_ARG, "X and Y must not be NULL");
   if (!std::isfinite(lr) || lr < 0.f) return fail(ISM_E_ARG, "lr must be finite and >= 0");
   SurrWork w;
-  if (ism_status s = surr_work(m, B, w)) return s;
+  if (ism_status s = surr_work(m, B, w, stream)) return s;
   surr_fwd_bwd(m, X, Y, nullptr, B, w, stream);
   const int64_t t = m->step + 1;
   mlp::AdamArgs aa{};
@@ -689,18 +717,21 @@ ism_status ism_surrogate_train_step(ism_surrogate *m, const float *X, const floa
   return ISM_OK;
 }
 
-ism_status ism_surrogate_get_params(const ism_surrogate *m, float *flat) {
+ism_status ism_surrogate_get_params(const ism_surrogate *m, float *flat, hipStream_t stream) {
   g_err.clear();
   if (ism_status s = surr_check(m)) return s;
   if (!flat) return fail(ISM_E_ARG, "flat is NULL");
-  HIP_TRY(hipDeviceSynchronize());
-  HIP_TRY(hipMemcpy(flat, m->params, 3 * (size_t)mlp::NPARAM * sizeof(float), hipMemcpyDeviceToHost));
+  HIP_TRY(hipEventSynchronize(m->staged));
+  HIP_TRY(hipMemcpyAsync(m->staging, m->params, 3 * (size_t)mlp::NPARAM * sizeof(float), hipMemcpyDeviceToHost,
+                         stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  std::memcpy(flat, m->staging, 3 * (size_t)mlp::NPARAM * sizeof(float));
   flat[3 * mlp::NPARAM] = (float)m->step;
   std::memcpy(flat + 3 * mlp::NPARAM + 1, m->norm_host, sizeof(m->norm_host));
   return ISM_OK;
 }
 
-ism_status ism_surrogate_set_params(ism_surrogate *m, const float *flat) {
+ism_status ism_surrogate_set_params(ism_surrogate *m, const float *flat, hipStream_t stream) {
   g_err.clear();
   if (ism_status s = surr_check(m)) return s;
   if (!flat) return fail(ISM_E_ARG, "flat is NULL");
@@ -713,12 +744,15 @@ ism_status ism_surrogate_set_params(ism_surrogate *m, const float *flat) {
     if (!(nh[k] > 0.f)) return fail(ISM_E_ARG, "sd_x must be > 0");
   for (int k = 23; k < 26; ++k)
     if (!(nh[k] > 0.f)) return fail(ISM_E_ARG, "sd_y must be > 0");
-  HIP_TRY(hipDeviceSynchronize());
-  HIP_TRY(hipMemcpy(m->params, flat, 3 * (size_t)mlp::NPARAM * sizeof(float), hipMemcpyHostToDevice));
+  // the staging buffer may still feed the previous upload: wait for that copy alone
+  HIP_TRY(hipEventSynchronize(m->staged));
+  std::memcpy(m->staging, flat, 3 * (size_t)mlp::NPARAM * sizeof(float));
+  HIP_TRY(hipMemcpyAsync(m->params, m->staging, 3 * (size_t)mlp::NPARAM * sizeof(float), hipMemcpyHostToDevice,
+                         stream));
+  HIP_TRY(hipEventRecord(m->staged, stream));
   m->step = (int64_t)step;
   std::memcpy(m->norm_host, nh, sizeof(m->norm_host));
-  if (ism_status s = surr_upload_norm(m)) return s;
-  return surr_pack(m);
+  return surr_pack(m, stream);
 }
 
 ism_status ism_columns_beam(const ism_grid *g, const ism_params *p, ism_precision prec, const double *n,
@@ -826,24 +860,17 @@ ism_status ism_point_sources(const ism_grid *g, const ism_params *p, ism_precisi
 }
 
 // Packet list b with room for at least `rays` packets (grows, never shrinks).
-ism_status art_list(DevState *st, int b, int64_t rays) {
-  std::lock_guard<std::mutex> lk(g_mu);
-  if (!st->art_count) {
-    hipError_t e = hipMalloc(&st->art_count, sizeof(unsigned long long));
-    if (e != hipSuccess) return fail(ISM_E_NOMEM, std::string("ray counter: ") + hipGetErrorString(e));
-    e = hipHostMalloc(&st->art_count_host, sizeof(unsigned long long));
+// Packet list b of the stream's scratch with room for at least `rays` packets (grows, never
+// shrinks), and the pinned host word the child count is read back into.
+ism_status art_list(StreamScratch *ss, int b, int64_t rays, hipStream_t stream) {
+  if (!ss->art_count_host) {
+    hipError_t e = hipHostMalloc(&ss->art_count_host, sizeof(unsigned long long));
     if (e != hipSuccess) return fail(ISM_E_NOMEM, std::string("ray counter (host): ") + hipGetErrorString(e));
   }
-  if (st->art_cap[b] < rays) {
-    if (st->art_list[b]) (void)hipFree(st->art_list[b]);
-    st->art_list[b] = nullptr;
-    st->art_cap[b] = 0;
-    const int64_t want = std::max<int64_t>(rays, 1 << 16);
-    hipError_t e = hipMalloc(&st->art_list[b], sizeof(ArtRay) * (size_t)want);
-    if (e != hipSuccess)
-      return fail(ISM_E_NOMEM, "ray list of " + std::to_string(want) + " packets: " + hipGetErrorString(e));
-    st->art_cap[b] = want;
-  }
+  const int64_t want = std::max<int64_t>(rays, 1 << 16);
+  if (ss->art_b[b] < sizeof(ArtRay) * (size_t)rays || !ss->art[b])
+    if (ism_status s = grow(&ss->art[b], &ss->art_b[b], sizeof(ArtRay) * (size_t)want, stream, "ray list"))
+      return s;
   return ISM_OK;
 }
 
@@ -871,7 +898,11 @@ ism_status ism_ray_trace(const ism_grid *g, const ism_params *p, ism_precision p
   if (!src || !n || !xH2 || !xHp || !chi_PE || !chi_LW || !chi_H2 || !chi_C || !phi_LyC)
     return fail(ISM_E_ARG, "a required array is NULL");
   DevState *st;
-  if (ism_status s = current_state(&st)) return s;
+  int dev = 0;
+  if (ism_status s = current_state(&st, &dev)) return s;
+  StreamScratch *ss = stream_scratch(dev, stream);
+  if (ism_status s = grow(&ss->ctl, &ss->ctl_b, 256, stream, "ray counter")) return s;
+  unsigned long long *art_count = (unsigned long long *)ss->ctl + 2;
   const double box[3] = {g->nx * g->dx_cm, g->ny * g->dx_cm, g->nz * g->dx_cm};
   SrcDev h[MAX_SOURCES];
   for (int s = 0; s < nsrc; ++s) {
@@ -913,18 +944,14 @@ ism_status ism_ray_trace(const ism_grid *g, const ism_params *p, ism_precision p
   int cur = 0;
   for (int level = o.level0; nin > 0 && level <= o.max_level; ++level) {
     const int nxt = cur ^ 1;
-    if (level < o.max_level)
-      if (ism_status s = art_list(st, nxt, 4 * nin)) return s;
-    if (!st->art_count)
-      if (ism_status s = art_list(st, nxt, 0)) return s;
+    if (ism_status s = art_list(ss, nxt, level < o.max_level ? 4 * nin : 0, stream)) return s;
     a.level = level;
     a.nin = nin;
-    a.in = level == o.level0 ? nullptr : st->art_list[cur];
-    a.out = st->art_list[nxt];
-    a.nout = st->art_count;
+    a.in = level == o.level0 ? nullptr : (ArtRay *)ss->art[cur];
+    a.out = (ArtRay *)ss->art[nxt];
+    a.nout = art_count;
     a.R2split = (12.0 * std::ldexp(1.0, 2 * level)) / (4.0 * M_PI * o.rays_per_cell);
-    hipLaunchKernelGGL(art_zero_kernel, dim3(1), dim3(64), 0, stream, (double *)nullptr, (int64_t)0,
-                       st->art_count);
+    hipLaunchKernelGGL(art_zero_kernel, dim3(1), dim3(64), 0, stream, (double *)nullptr, (int64_t)0, art_count);
     const dim3 grid((unsigned)((nin + 255) / 256));
     if (prec == ISM_PREC_F64) {
       if (flux)
@@ -938,10 +965,10 @@ ism_status ism_ray_trace(const ism_grid *g, const ism_params *p, ism_precision p
         hipLaunchKernelGGL((art_level_kernel<float, false>), grid, dim3(256), lds, stream, a);
     }
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(st->art_count_host, st->art_count, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+    HIP_TRY(hipMemcpyAsync(ss->art_count_host, art_count, sizeof(unsigned long long), hipMemcpyDeviceToHost,
                            stream));
     HIP_TRY(hipStreamSynchronize(stream));
-    nin = level < o.max_level ? (int64_t)*st->art_count_host : 0;
+    nin = level < o.max_level ? (int64_t)*ss->art_count_host : 0;
     cur = nxt;
   }
   return ISM_OK;
@@ -1044,21 +1071,26 @@ ism_status ism_chem_cool_step_surrogate(ism_surrogate *m, const ism_params *p, i
   if (!n || !T || !xH2 || !xHp || !chi_PE || !chi_LW || !chi_H2 || !chi_C || !xi_cr || !N_eff)
     return fail(ISM_E_ARG, "a required array is NULL");
   DevState *st;
-  if (ism_status s = current_state(&st)) return s;
+  int dev = 0;
+  if (ism_status s = current_state(&st, &dev)) return s;
+  StreamScratch *ss = stream_scratch(dev, stream);
   const size_t pred_bytes = m ? align256((size_t)ncell * 3 * sizeof(float)) : 0;
   const size_t rej_bytes = align256((size_t)ncell * sizeof(int32_t));
-  void *buf;
-  if (ism_status s = surr_scratch(st, pred_bytes + rej_bytes + 256, &buf)) return s;
-  float *pred = m ? (float *)buf : nullptr;
-  int32_t *rej = (int32_t *)((uint8_t *)buf + pred_bytes);
-  unsigned long long *nrej = (unsigned long long *)((uint8_t *)buf + pred_bytes + rej_bytes);
+  if (ism_status s = grow(&ss->surr, &ss->surr_b, pred_bytes + rej_bytes, stream, "surrogate scratch")) return s;
+  if (ism_status s = grow(&ss->ctl, &ss->ctl_b, 256, stream, "work-queue counter")) return s;
+  if (p->order_cells)
+    if (ism_status s = grow(&ss->ord, &ss->ord_b, order_bytes(ncell), stream, "order scratch")) return s;
+  float *pred = m ? (float *)ss->surr : nullptr;
+  int32_t *rej = (int32_t *)((uint8_t *)ss->surr + pred_bytes);
+  int64_t *q = (int64_t *)ss->ctl;
+  unsigned long long *nrej = (unsigned long long *)ss->ctl + 1;
   hipLaunchKernelGGL(counter_reset_kernel, dim3(1), dim3(1), 0, stream, nrej);
   if (m) {
     mlp::FwdArgs fa{};
     fa.cin = mlp::CellIn<float>{n, T, xH2, xHp, (const float *)chi_PE, (const float *)phi_LyC,
                                 (const float *)xi_cr, (const float *)N_eff, (float)std::log10(p->Zg),
                                 (float)std::log10(std::max(dt_s, 1e-300) / 3.15576e7)};
-    fa.B = ncell; fa.fimg = m->fimg(); fa.norm = m->norm; fa.Y = pred;
+    fa.B = ncell; fa.fimg = m->fimg(); fa.norm = surr_norm(m); fa.Y = pred;
     hipLaunchKernelGGL(mlp::mlp_fwd_kernel<3>, dim3(fwd_grid(m, ncell)), dim3(mlp::FWD_THREADS), 0, stream, fa);
   }
   const ParT<float> pr = make_par<float>(p, g_host_coef);
@@ -1068,14 +1100,8 @@ ism_status ism_chem_cool_step_surrogate(ism_surrogate *m, const ism_params *p, i
                 (float *)xCp, (float *)xCO, (float *)xe, nsub, status, pred, st->tab32, pr, pd, rej, nrej,
                 20.0, accept_tol, 6, 1e-3};
   hipLaunchKernelGGL(accept_kernel, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, stream, aa);
-  int64_t *q;
-  {
-    std::lock_guard<std::mutex> lk(g_mu);
-    q = st->queues + (st->qnext++ % QUEUE_SLOTS);
-  }
   int32_t *list = rej;
-  if (p->order_cells)
-    if (ism_status s = order_cells(st, ncell, nrej, rej, T, pred, nullptr, &list, stream)) return s;
+  if (p->order_cells) order_cells((uint8_t *)ss->ord, ncell, nrej, rej, T, pred, nullptr, &list, stream);
   StepArgs<float> sa{ncell, dt_s, n, T, xH2, xHp, (const float *)chi_PE, (const float *)chi_LW,
                      (const float *)chi_H2, (const float *)chi_C, (const float *)phi_LyC,
                      (const float *)xi_cr, (const float *)N_eff, (float *)xCp, (float *)xCO, (float *)xe,

@@ -1,17 +1,12 @@
 // Six-ray diffuse-UV columns, shielding, N_eff and CR attenuation (Secs. 5.1-5.3).
 //
-// For every cell and each of +-x, +-y, +-z the exclusive upstream columns (N_H, N_H2,
-// N_C) from the face the ray enters are accumulated in double; each direction adds its
-// attenuated, shielded weight to a per-cell double4 accumulator (PE, LW, H2-weighted LW,
-// C-weighted LW) in the order +x, -x, +y, -y, +z, -z; the z pass scales by chi0/6 and
-// writes chi_PE, chi_LW, chi_H2, chi_C, N_eff and xi_cr.
-//  * x pass: one wave per x row, 64-cell chunks with wave-wide exclusive scans.
-//  * y, z passes: pencils split into segments; a first kernel sums each segment, then
-//    one lane per (pencil, segment) -- consecutive x, so loads coalesce -- starts from the
-//    exclusive sum of the segments before (or after) it and marches through its segment
-//    forward and backward with running sums in registers.
-// Templated on R, the type of the transcendental cores (double: F64 outputs, float:
-// MIXED outputs); exponents and sums stay double either way.
+// For every cell and each of +-x, +-y, +-z the exclusive upstream columns (N_H, N_H2, N_C)
+// from the face the ray enters are accumulated in double, and each ray adds its attenuated,
+// shielded weight (PE, LW, H2-weighted LW, C-weighted LW).  The grid is processed in 8^3 tiles
+// (tile sums, exclusive scans of the tile sums along each line of tiles, then one pass per tile
+// that forms all six rays of every cell and writes the results once); see the tiled pass below.
+// Templated on R, the type of the transcendental cores (double: F64 outputs, float: MIXED
+// outputs); exponents, columns and attenuation products stay double either way.
 #pragma once
 #include "physics.h"
 
@@ -21,11 +16,8 @@ struct ColArgs {
   int32_t nx, ny, nz;
   double dx;
   const double *n, *xH2, *xC;
-  double4 *acc;
-  double *seg;  // segment sums: 3 arrays of nx * other * nseg
   void *chiPE, *chiLW, *chiH2, *chiC, *Neff, *xi;
   int32_t cr_mode;
-  int32_t nseg, seglen;  // segments per pencil and their length along the axis
   double chi0, Zd, xi0, sPE, sLW;
   const double *tab;  // full double table (C shielding at TAB_CS)
 };
@@ -83,6 +75,11 @@ __device__ __forceinline__ double4 ray_term(const ColArgs &a, double NH, double 
   return r;
 }
 
+template <class O>
+__device__ __forceinline__ void store_out(void *p, int64_t i, double v) {
+  static_cast<O *>(p)[i] = (O)v;
+}
+
 __device__ __forceinline__ void load_cs(const double *g, double *s) {
   for (int k = threadIdx.x; k < CS_NX * CS_NY; k += blockDim.x) s[k] = g[TAB_CS + k];
   __syncthreads();
@@ -108,149 +105,314 @@ __device__ __forceinline__ void cell_q(const ColArgs &a, int64_t idx, double &qH
   qC = a.xC ? nn * a.xC[idx] * a.dx : 0.0;
 }
 
-template <class R>
-__global__ __launch_bounds__(256) void columns_x_kernel(ColArgs a) {
-  __shared__ double s_cs[CS_NX * CS_NY];
-  load_cs(a.tab, s_cs);
-  const int lane = threadIdx.x & 63;
-  const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (row >= (int64_t)a.ny * a.nz) return;
-  const int64_t base = row * a.nx;
-  const int nch = (a.nx + 63) >> 6;
-  for (int dir = 0; dir < 2; ++dir) {
-    double cH = 0.0, cH2 = 0.0, cC = 0.0;
-    for (int cc = 0; cc < nch; ++cc) {
-      const int ch = dir == 0 ? cc : nch - 1 - cc;
-      const int i = dir == 0 ? (ch << 6) + lane : (ch << 6) + 63 - lane;
-      const bool ok = i < a.nx;
-      double qH = 0.0, qH2 = 0.0, qC = 0.0;
-      if (ok) cell_q(a, base + i, qH, qH2, qC);
-      double tH, tH2, tC;
-      const double eH = wave_excl(qH, lane, tH) + cH;
-      const double eH2 = wave_excl(qH2, lane, tH2) + cH2;
-      const double eC = wave_excl(qC, lane, tC) + cC;
-      cH += tH;
-      cH2 += tH2;
-      cC += tC;
-      if (ok) {
-        const double4 t = ray_term<R>(a, eH, eH2, eC, qH, qH2, qC, s_cs);
-        if (dir == 0) {
-          a.acc[base + i] = t;
-        } else {
-          double4 s = a.acc[base + i];
-          s.x += t.x; s.y += t.y; s.z += t.z; s.w += t.w;
-          a.acc[base + i] = s;
+// ---------------------------------------------------------------- tiled six-ray pass
+// The grid is cut into 8 x 8 x 8 tiles.  Three kernels:
+//  1. columns_tilesum_kernel: per tile, the sums of (qH, qH2, qC) = (n, n x_H2, n x_C) dx along
+//     every pencil of the tile on each axis (64 pencils per axis).
+//  2. columns_offsets_kernel: per line of tiles (the tiles a full-length pencil crosses), the
+//     exclusive sums of the tiles before (forward) and after (backward) each tile, each summed
+//     in the direction a ray takes, so that a small column keeps its relative precision.
+//  3. columns_tile_kernel: one wave per tile stages the tile in LDS, then every lane takes one
+//     (x, y) position and walks z; per cell it forms the upstream columns of all six rays from
+//     the tile offsets plus the in-tile cells before (or after) it, adds the six terms and
+//     writes chi_PE, chi_LW, chi_H2, chi_C, N_eff and xi once.
+// The dust attenuation exp(-sigma N_in) of a ray is the offset's exp(-sigma F) times the
+// per-cell factors exp(-sigma qH) of the in-tile cells it crosses, so each cell costs two
+// exponentials (its own factors) instead of two per ray; the cell average g(sigma qH) is the
+// same for all six rays and multiplies their sum.  Columns and these products stay double.
+constexpr int CT = 8;                       // tile edge
+constexpr int CT_LANES = 64;                // one wave per tile
+constexpr int CT_NS = CT * (CT + 1) * CT;   // LDS slots per field: x + 9 y + 72 z (bank spread)
+__device__ __forceinline__ int ct_slot(int x, int y, int z) { return x + (CT + 1) * y + CT * (CT + 1) * z; }
+
+struct TileGeo {
+  int ntx, nty, ntz;
+  int64_t lx, ly, lz;     // lines per axis: ny nz, nz nx, ny nx
+  int64_t ox, oy, oz;     // offset of each axis's block in an (S, F or B) array: ntx lx, nty ly, ntz lz
+  int64_t per_q;          // doubles per quantity in one array: ox + oy + oz
+};
+
+struct TileArgs {
+  ColArgs c;
+  TileGeo g;
+  double *S, *F, *B;      // [3 quantities][per_q]: sums, forward and backward exclusive offsets
+};
+
+__host__ __device__ inline TileGeo tile_geo(int nx, int ny, int nz) {
+  TileGeo g;
+  g.ntx = (nx + CT - 1) / CT;
+  g.nty = (ny + CT - 1) / CT;
+  g.ntz = (nz + CT - 1) / CT;
+  g.lx = (int64_t)ny * nz;
+  g.ly = (int64_t)nz * nx;
+  g.lz = (int64_t)ny * nx;
+  g.ox = (int64_t)g.ntx * g.lx;
+  g.oy = (int64_t)g.nty * g.ly;
+  g.oz = (int64_t)g.ntz * g.lz;
+  g.per_q = g.ox + g.oy + g.oz;
+  return g;
+}
+
+// Index of the pencil sum of tile t along an axis, line l, in one quantity's block.
+__device__ __forceinline__ int64_t tile_ix(const TileGeo &g, int ax, int t, int64_t l) {
+  return ax == 0 ? (int64_t)t * g.lx + l : (ax == 1 ? g.ox + (int64_t)t * g.ly + l : g.ox + g.oy + (int64_t)t * g.lz + l);
+}
+
+// Work item w of a block is the pair of x-neighbouring tiles (2 px, py, pz) and (2 px + 1, py,
+// pz), taken one after the other by the same wave: a tile row is 64 bytes, so the pair shares
+// each 128-byte line and the second tile finds its lines in the CU's caches.
+__device__ __forceinline__ int64_t tile_pairs(const TileGeo &g) {
+  return (int64_t)((g.ntx + 1) / 2) * g.nty * g.ntz;
+}
+__device__ __forceinline__ bool tile_of(const TileGeo &g, int64_t w, int half, int &tx, int &ty, int &tz) {
+  const int ntx2 = (g.ntx + 1) / 2;
+  tx = 2 * (int)(w % ntx2) + half;
+  const int64_t r = w / ntx2;
+  ty = (int)(r % g.nty);
+  tz = (int)(r / g.nty);
+  return tx < g.ntx;
+}
+
+// Sum over the 8 lanes of a group: lanes l ^ m for m < 8 (x within a row) or m in {8, 16, 32}
+// (y at fixed x).
+template <int M0>
+__device__ __forceinline__ double group_sum(double v) {
+  v += __shfl_xor(v, M0, 64);
+  v += __shfl_xor(v, 2 * M0, 64);
+  v += __shfl_xor(v, 4 * M0, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(CT_LANES) void columns_tilesum_kernel(TileArgs t) {
+  const ColArgs &a = t.c;
+  const TileGeo &g = t.g;
+  const int lane = threadIdx.x;
+  const int lx = lane & 7, ly = lane >> 3;
+  const int64_t nw = tile_pairs(g);
+  for (int64_t w2 = 2 * (int64_t)blockIdx.x; w2 < 2 * nw; w2 += ((w2 & 1) ? 2 * (int64_t)gridDim.x - 1 : 1)) {
+    int tx, ty, tz;
+    if (!tile_of(g, w2 >> 1, (int)(w2 & 1), tx, ty, tz)) continue;
+    const int gx = tx * CT + lx, gy = ty * CT + ly;
+    const bool in_xy = gx < a.nx && gy < a.ny;
+    double zs[3] = {0.0, 0.0, 0.0};
+#pragma unroll 1
+    for (int z = 0; z < CT; ++z) {
+      const int gz = tz * CT + z;
+      double q[3] = {0.0, 0.0, 0.0};
+      if (in_xy && gz < a.nz) cell_q(a, ((int64_t)gz * a.ny + gy) * a.nx + gx, q[0], q[1], q[2]);
+      for (int k = 0; k < 3; ++k) {
+        zs[k] += q[k];
+        const double sx = group_sum<1>(q[k]);   // along x: the 8 lanes of row ly
+        const double sy = group_sum<8>(q[k]);   // along y: the 8 lanes at column lx
+        if (gz < a.nz) {
+          if (lx == 0 && gy < a.ny) t.S[k * g.per_q + tile_ix(g, 0, tx, (int64_t)gz * a.ny + gy)] = sx;
+          if (ly == 0 && gx < a.nx) t.S[k * g.per_q + tile_ix(g, 1, ty, (int64_t)gz * a.nx + gx)] = sy;
         }
       }
     }
+    if (in_xy)
+      for (int k = 0; k < 3; ++k) t.S[k * g.per_q + tile_ix(g, 2, tz, (int64_t)gy * a.nx + gx)] = zs[k];
   }
 }
 
-// Geometry of the y (AX = 1) and z (AX = 2) passes: lane id -> (i, segment, other index).
-struct PencilPos {
-  int i, seg, o, L;
-  int64_t stride, base;
-  bool ok;
+// One thread per (axis, line, direction): forward threads write F, backward threads write B.
+__global__ __launch_bounds__(256) void columns_offsets_kernel(TileArgs t) {
+  const TileGeo &g = t.g;
+  const int64_t nl = g.lx + g.ly + g.lz;
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= 2 * nl) return;
+  const bool fwd = id < nl;
+  int64_t l = fwd ? id : id - nl;
+  int ax, nt;
+  if (l < g.lx) { ax = 0; nt = g.ntx; }
+  else if (l < g.lx + g.ly) { ax = 1; l -= g.lx; nt = g.nty; }
+  else { ax = 2; l -= g.lx + g.ly; nt = g.ntz; }
+  double *out = fwd ? t.F : t.B;
+  double run[3] = {0.0, 0.0, 0.0};
+  for (int s = 0; s < nt; ++s) {
+    const int tt = fwd ? s : nt - 1 - s;
+    const int64_t ix = tile_ix(g, ax, tt, l);
+    for (int k = 0; k < 3; ++k) {
+      out[k * g.per_q + ix] = run[k];
+      run[k] += t.S[k * g.per_q + ix];
+    }
+  }
+}
+
+// Ray state entering a cell: dust attenuation in the two bands and the H2 and C columns.
+struct RayIn {
+  double P, L, H2, C;
 };
 
-template <int AX>
-__device__ __forceinline__ PencilPos pencil_pos(const ColArgs &a) {
-  PencilPos p;
-  const int64_t lid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t other = AX == 1 ? a.nz : a.ny;
-  p.i = (int)(lid % a.nx);
-  const int64_t r = lid / a.nx;
-  p.seg = (int)(r % a.nseg);
-  p.o = (int)(r / a.nseg);
-  p.ok = p.o < other;
-  p.L = AX == 1 ? a.ny : a.nz;
-  p.stride = AX == 1 ? (int64_t)a.nx : (int64_t)a.nx * a.ny;
-  p.base = AX == 1 ? (int64_t)p.o * a.nx * a.ny + p.i : (int64_t)p.o * a.nx + p.i;
-  return p;
+template <class R>
+__device__ __forceinline__ void add_ray(const RayIn &r, double hH2, double hC, const double *cs, double acc[4]) {
+  const double mH2 = r.H2 + hH2, mC = r.C + hC;
+  acc[0] += r.P;
+  acc[1] += r.L;
+  acc[2] += r.L * f_shld_H2<R>(mH2);
+  acc[3] += r.L * f_shld_C<R>(mC, mH2, cs);
 }
 
-// Sums of (qH, qH2, qC) over each segment of each pencil.
-template <int AX>
-__global__ __launch_bounds__(256) void columns_segsum_kernel(ColArgs a) {
-  const PencilPos p = pencil_pos<AX>(a);
-  if (!p.ok) return;
-  const int m0 = p.seg * a.seglen;
-  const int m1 = m0 + a.seglen < p.L ? m0 + a.seglen : p.L;
-  double sH = 0.0, sH2 = 0.0, sC = 0.0;
-  for (int m = m0; m < m1; ++m) {
-    double qH, qH2, qC;
-    cell_q(a, p.base + (int64_t)m * p.stride, qH, qH2, qC);
-    sH += qH;
-    sH2 += qH2;
-    sC += qC;
+// e^-y for the running products and g(y) = (1 - e^-y) / y, the cell average, from one
+// transcendental: below y = 0.35 e^-y - 1 (accurate however small y) gives both, above it e^-y
+// does (1 - e^-y >= 0.29 there, so the subtraction keeps its digits, and e^-y keeps its own
+// relative precision however thick the cell).
+template <class R>
+__device__ __forceinline__ void cell_atten(double y, double &e, double &gy) {
+  double m;
+  if (y <= 0.35) {
+    m = std::is_same<R, double>::value ? fexpm1(-y) : (double)::expm1f((float)-y);
+    e = 1.0 + m;
+  } else {
+    e = (double)Mx<R>::ex(-y);
+    m = e - 1.0;
   }
-  const int64_t nseg_all = (int64_t)a.nx * (AX == 1 ? a.nz : a.ny) * a.nseg;
-  const int64_t k = ((int64_t)p.o * a.nseg + p.seg) * a.nx + p.i;
-  a.seg[k] = sH;
-  a.seg[nseg_all + k] = sH2;
-  a.seg[2 * nseg_all + k] = sC;
+  gy = y < 1e-4 ? 1.0 - y / 2.0 + y * y / 6.0 : -m / y;
 }
 
-template <class O>
-__device__ __forceinline__ void store_out(void *p, int64_t i, double v) {
-  static_cast<O *>(p)[i] = (O)v;
-}
-
-// Forward then backward march through one segment; the z pass (AX = 2) finalises.
-template <class R, int AX>
-__global__ __launch_bounds__(256) void columns_march_kernel(ColArgs a) {
+template <class R>
+__global__ __launch_bounds__(CT_LANES) void columns_tile_kernel(TileArgs t) {
   __shared__ double s_cs[CS_NX * CS_NY];
-  load_cs(a.tab, s_cs);
-  const PencilPos p = pencil_pos<AX>(a);
-  if (!p.ok) return;
-  const int m0 = p.seg * a.seglen;
-  const int m1 = m0 + a.seglen < p.L ? m0 + a.seglen : p.L;
-  const int64_t nseg_all = (int64_t)a.nx * (AX == 1 ? a.nz : a.ny) * a.nseg;
-  const double *sH = a.seg, *sH2 = a.seg + nseg_all, *sC = a.seg + 2 * nseg_all;
-  const int64_t k0 = (int64_t)p.o * a.nseg * a.nx + p.i;  // segment s of this pencil at k0 + s nx
-  for (int dir = 0; dir < 2; ++dir) {
-    double cH = 0.0, cH2 = 0.0, cC = 0.0;
-    if (dir == 0) {
-      for (int s = 0; s < p.seg; ++s) {
-        cH += sH[k0 + (int64_t)s * a.nx];
-        cH2 += sH2[k0 + (int64_t)s * a.nx];
-        cC += sC[k0 + (int64_t)s * a.nx];
+  __shared__ double s_eP[CT_NS], s_eL[CT_NS], s_h2[CT_NS], s_c[CT_NS], s_qH[CT_NS];
+  __shared__ double s_xo[64][8], s_yo[64][8];  // x pencils (y, z) and y pencils (x, z): Pf Lf H2f Cf Pb Lb H2b Cb
+  const ColArgs &a = t.c;
+  const TileGeo &g = t.g;
+  for (int k = threadIdx.x; k < CS_NX * CS_NY; k += blockDim.x) s_cs[k] = a.tab[TAB_CS + k];
+  const int lane = threadIdx.x;
+  const int lx = lane & 7, ly = lane >> 3;
+  const double fo = a.chi0 / 6.0;
+  const int64_t nw = tile_pairs(g);
+  for (int64_t w2 = 2 * (int64_t)blockIdx.x; w2 < 2 * nw; w2 += ((w2 & 1) ? 2 * (int64_t)gridDim.x - 1 : 1)) {
+    int tx, ty, tz;
+    if (!tile_of(g, w2 >> 1, (int)(w2 & 1), tx, ty, tz)) continue;
+    const int gx = tx * CT + lx, gy = ty * CT + ly;
+    const bool in_xy = gx < a.nx && gy < a.ny;
+    __syncthreads();  // the previous tile's LDS reads are done
+    // stage the tile: per cell the two dust factors, half the own H2 and C columns, and qH
+#pragma unroll 1
+    for (int z = 0; z < CT; ++z) {
+      const int gz = tz * CT + z;
+      double qH = 0.0, qH2 = 0.0, qC = 0.0;
+      if (in_xy && gz < a.nz) cell_q(a, ((int64_t)gz * a.ny + gy) * a.nx + gx, qH, qH2, qC);
+      double eP, eL, gP, gL;
+      cell_atten<R>(a.sPE * qH, eP, gP);
+      cell_atten<R>(a.sLW * qH, eL, gL);
+      const int sl = ct_slot(lx, ly, z);
+      s_eP[sl] = eP;
+      s_eL[sl] = eL;
+      s_h2[sl] = qH2;
+      s_c[sl] = qC;
+      s_qH[sl] = qH;
+    }
+    // offsets of the x pencils (y = lane & 7, z = lane >> 3) and y pencils (x = lane & 7,
+    // z = lane >> 3), dust columns turned into attenuation factors
+    {
+      const int py = lane & 7, pz = lane >> 3;
+      const int gyy = ty * CT + py, gzz = tz * CT + pz, gxx = tx * CT + py;
+      double v[2][8];
+      for (int ax = 0; ax < 2; ++ax) {
+        const bool ok = ax == 0 ? (gyy < a.ny && gzz < a.nz) : (gxx < a.nx && gzz < a.nz);
+        const int64_t l = ax == 0 ? (int64_t)gzz * a.ny + gyy : (int64_t)gzz * a.nx + gxx;
+        const int64_t ix = ok ? tile_ix(g, ax, ax == 0 ? tx : ty, l) : 0;
+        double f[3] = {0.0, 0.0, 0.0}, b[3] = {0.0, 0.0, 0.0};
+        if (ok)
+          for (int k = 0; k < 3; ++k) {
+            f[k] = t.F[k * g.per_q + ix];
+            b[k] = t.B[k * g.per_q + ix];
+          }
+        v[ax][0] = (double)Mx<R>::ex(-a.sPE * f[0]);
+        v[ax][1] = (double)Mx<R>::ex(-a.sLW * f[0]);
+        v[ax][2] = f[1];
+        v[ax][3] = f[2];
+        v[ax][4] = (double)Mx<R>::ex(-a.sPE * b[0]);
+        v[ax][5] = (double)Mx<R>::ex(-a.sLW * b[0]);
+        v[ax][6] = b[1];
+        v[ax][7] = b[2];
       }
-    } else {
-      for (int s = a.nseg - 1; s > p.seg; --s) {
-        cH += sH[k0 + (int64_t)s * a.nx];
-        cH2 += sH2[k0 + (int64_t)s * a.nx];
-        cC += sC[k0 + (int64_t)s * a.nx];
+      for (int k = 0; k < 8; ++k) {
+        s_xo[lane][k] = v[0][k];
+        s_yo[lane][k] = v[1][k];
       }
     }
-    for (int t = m0; t < m1; ++t) {
-      const int m = dir == 0 ? t : m1 - 1 - (t - m0);
-      const int64_t idx = p.base + (int64_t)m * p.stride;
-      double qH, qH2, qC;
-      cell_q(a, idx, qH, qH2, qC);
-      const double4 w = ray_term<R>(a, cH, cH2, cC, qH, qH2, qC, s_cs);
-      cH += qH;
-      cH2 += qH2;
-      cC += qC;
-      double4 acc = a.acc[idx];
-      acc.x += w.x; acc.y += w.y; acc.z += w.z; acc.w += w.w;
-      if (AX == 2 && dir == 1) {
-        const double f = a.chi0 / 6.0;
-        const double cPE = f * acc.x;
-        const double Neff = a.chi0 > 0.0 ? -::log(cPE / a.chi0) / (g_coef64.sig_d_Neff * a.Zd) : 0.0;
+    // this lane's z pencil (x = lx, y = ly)
+    RayIn zf{1.0, 1.0, 0.0, 0.0}, zb{1.0, 1.0, 0.0, 0.0};
+    if (in_xy) {
+      const int64_t ix = tile_ix(g, 2, tz, (int64_t)gy * a.nx + gx);
+      const double f0 = t.F[ix], f1 = t.F[g.per_q + ix], f2 = t.F[2 * g.per_q + ix];
+      const double b0 = t.B[ix], b1 = t.B[g.per_q + ix], b2 = t.B[2 * g.per_q + ix];
+      zf = RayIn{(double)Mx<R>::ex(-a.sPE * f0), (double)Mx<R>::ex(-a.sLW * f0), f1, f2};
+      zb = RayIn{(double)Mx<R>::ex(-a.sPE * b0), (double)Mx<R>::ex(-a.sLW * b0), b1, b2};
+    }
+    __syncthreads();
+    RayIn zr = zf;
+#pragma unroll 1
+    for (int z = 0; z < CT; ++z) {
+      const int gz = tz * CT + z;
+      const int sl = ct_slot(lx, ly, z);
+      const double hH2 = 0.5 * s_h2[sl], hC = 0.5 * s_c[sl];
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      // +x then -x
+      {
+        const double *o = s_xo[z * 8 + ly];
+        RayIn f{o[0], o[1], o[2], o[3]}, b{o[4], o[5], o[6], o[7]};
+#pragma unroll 1
+        for (int x = 0; x < CT; ++x) {
+          const int s2 = ct_slot(x, ly, z);
+          const double eP = s_eP[s2], eL = s_eL[s2], h = s_h2[s2], c = s_c[s2];
+          if (x < lx) { f.P *= eP; f.L *= eL; f.H2 += h; f.C += c; }
+          if (x > lx) { b.P *= eP; b.L *= eL; b.H2 += h; b.C += c; }
+        }
+        add_ray<R>(f, hH2, hC, s_cs, acc);
+        add_ray<R>(b, hH2, hC, s_cs, acc);
+      }
+      // +y then -y
+      {
+        const double *o = s_yo[z * 8 + lx];
+        RayIn f{o[0], o[1], o[2], o[3]}, b{o[4], o[5], o[6], o[7]};
+#pragma unroll 1
+        for (int y = 0; y < CT; ++y) {
+          const int s2 = ct_slot(lx, y, z);
+          const double eP = s_eP[s2], eL = s_eL[s2], h = s_h2[s2], c = s_c[s2];
+          if (y < ly) { f.P *= eP; f.L *= eL; f.H2 += h; f.C += c; }
+          if (y > ly) { b.P *= eP; b.L *= eL; b.H2 += h; b.C += c; }
+        }
+        add_ray<R>(f, hH2, hC, s_cs, acc);
+        add_ray<R>(b, hH2, hC, s_cs, acc);
+      }
+      // +z (running product over the lane's own pencil) then -z
+      {
+        RayIn b = zb;
+#pragma unroll 1
+        for (int z2 = CT - 1; z2 > z; --z2) {
+          const int s2 = ct_slot(lx, ly, z2);
+          b.P *= s_eP[s2]; b.L *= s_eL[s2]; b.H2 += s_h2[s2]; b.C += s_c[s2];
+        }
+        add_ray<R>(zr, hH2, hC, s_cs, acc);
+        add_ray<R>(b, hH2, hC, s_cs, acc);
+      }
+      zr.P *= s_eP[sl];
+      zr.L *= s_eL[sl];
+      zr.H2 += s_h2[sl];
+      zr.C += s_c[sl];
+      if (in_xy && gz < a.nz) {
+        const double qH = s_qH[sl];
+        double e, gP, gL;
+        cell_atten<R>(a.sPE * qH, e, gP);
+        cell_atten<R>(a.sLW * qH, e, gL);
+        const int64_t idx = ((int64_t)gz * a.ny + gy) * a.nx + gx;
+        const double cPE = fo * gP * acc[0];
+        const double Neff = a.chi0 > 0.0 ? -Mx<double>::ln(cPE / a.chi0) / (g_coef64.sig_d_Neff * a.Zd) : 0.0;
         double xi = a.xi0;
         if (a.cr_mode == 1) {
           const double N0 = g_coef64.N0_cr;
           xi = Neff <= N0 ? a.xi0 : a.xi0 * N0 / (Neff > N0 ? Neff : N0);
         }
         store_out<R>(a.chiPE, idx, cPE);
-        store_out<R>(a.chiLW, idx, f * acc.y);
-        store_out<R>(a.chiH2, idx, f * acc.z);
-        store_out<R>(a.chiC, idx, f * acc.w);
+        store_out<R>(a.chiLW, idx, fo * gL * acc[1]);
+        store_out<R>(a.chiH2, idx, fo * gL * acc[2]);
+        store_out<R>(a.chiC, idx, fo * gL * acc[3]);
         store_out<R>(a.Neff, idx, Neff);
         if (a.cr_mode != 2) store_out<R>(a.xi, idx, xi);
-      } else {
-        a.acc[idx] = acc;
       }
     }
   }

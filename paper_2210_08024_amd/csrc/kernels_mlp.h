@@ -109,12 +109,17 @@ __device__ __forceinline__ float cell_feature(const CellIn<R> &c, int64_t i, int
   }
 }
 
+// Standardisation of inputs and outputs, passed by value with each launch (NRM_* offsets).
+struct Norm {
+  float v[NRM_FLOATS];
+};
+
 struct FwdArgs {
   const float *X;  // [B][10] raw features (modes 0-2)
   CellIn<float> cin;  // mode 3: features built from the cell arrays
   int64_t B;
   const uint8_t *fimg;
-  const float *norm;
+  Norm norm;
   float *Y;        // modes 0, 3: [B][3] de-standardised predictions
   const float *Yt; // mode 2: [B][3] raw targets
   float dscale;    // mode 2: 2 / (3B)
@@ -180,8 +185,8 @@ __global__ __launch_bounds__(FWD_THREADS) void mlp_fwd_kernel(FwdArgs a) {
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int k = 4 * g + j;
-    mux[j] = k < NIN ? a.norm[NRM_MUX + k] : 0.f;
-    isdx[j] = k < NIN ? a.norm[NRM_ISDX + k] : 0.f;
+    mux[j] = k < NIN ? a.norm.v[NRM_MUX + k] : 0.f;
+    isdx[j] = k < NIN ? a.norm.v[NRM_ISDX + k] : 0.f;
   }
   float lossacc = 0.f;
   const int64_t stride = (int64_t)gridDim.x * FWD_WAVES * WTILE;
@@ -257,9 +262,9 @@ __global__ __launch_bounds__(FWD_THREADS) void mlp_fwd_kernel(FwdArgs a) {
 #pragma unroll
           for (int j = 0; j < NOUT; ++j) {
             const float y = acc[t][j] + bias[3 * NH + j];
-            if (MODE == 0 || MODE == 3) a.Y[n * NOUT + j] = y * a.norm[NRM_SDY + j] + a.norm[NRM_MUY + j];
+            if (MODE == 0 || MODE == 3) a.Y[n * NOUT + j] = y * a.norm.v[NRM_SDY + j] + a.norm.v[NRM_MUY + j];
             if (MODE == 2) {
-              const float e = y - (a.Yt[n * NOUT + j] - a.norm[NRM_MUY + j]) * a.norm[NRM_ISDY + j];
+              const float e = y - (a.Yt[n * NOUT + j] - a.norm.v[NRM_MUY + j]) * a.norm.v[NRM_ISDY + j];
               a.d4[n * NOUT + j] = e * a.dscale;
               lossacc += e * e;
             }

@@ -90,8 +90,9 @@ def lib():
         L.ism_surrogate_forward.argtypes = [_vp, _vp, _vp, _i64, _vp]
         L.ism_surrogate_backward.argtypes = [_vp, _vp, _vp, _vp, _i64, _vp]
         L.ism_surrogate_train_step.argtypes = [_vp, _vp, _vp, _i64, ctypes.c_float, _vp, _vp]
-        L.ism_surrogate_get_params.argtypes = [_vp, _vp]
-        L.ism_surrogate_set_params.argtypes = [_vp, _vp]
+        L.ism_surrogate_get_params.argtypes = [_vp, _vp, _vp]
+        L.ism_surrogate_set_params.argtypes = [_vp, _vp, _vp]
+        L.ism_stream_release.argtypes = [_vp]
         L.ism_columns_beam.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Params), ctypes.c_int] + [_vp] * 10
         L.ism_columns_beam.restype = ctypes.c_int
         L.ism_local_shielding.argtypes = [ctypes.POINTER(_Params), ctypes.c_int, _i64] + [_vp] * 11
@@ -108,7 +109,8 @@ def lib():
         L.ism_surrogate_pairs.argtypes = [ctypes.POINTER(_Params), ctypes.c_int, _i64, _dp] + [_vp] * 14
         L.ism_chem_cool_step_surrogate.argtypes = [_vp, ctypes.POINTER(_Params), _i64, _dp] + [_vp] * 16 + \
             [_dp, _vp, _vp]
-        for name in ("ism_init", "ism_shutdown", "ism_columns6", "ism_rates", "ism_chem_cool_step") + SURROGATE_SYMBOLS:
+        for name in ("ism_init", "ism_shutdown", "ism_stream_release", "ism_columns6", "ism_rates",
+                     "ism_chem_cool_step") + SURROGATE_SYMBOLS:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -121,7 +123,8 @@ SURROGATE_SYMBOLS = ("ism_surrogate_create", "ism_surrogate_destroy", "ism_surro
 
 
 def exported_symbols():
-    return ["ism_params_default", "ism_init", "ism_shutdown", "ism_last_error", "ism_ndiag", "ism_diag_name",
+    return ["ism_params_default", "ism_init", "ism_shutdown", "ism_stream_release", "ism_last_error", "ism_ndiag",
+            "ism_diag_name",
             "ism_columns6", "ism_rates", "ism_chem_cool_step", "ism_point_sources",
             "ism_ray_trace", "ism_radiation_force", "ism_local_shielding", "ism_columns_beam"] + \
         list(SURROGATE_SYMBOLS)
@@ -137,6 +140,11 @@ def init(device=None, path=COEFF_PATH):
     dev = torch.cuda.current_device() if device is None else int(device)
     _check(lib().ism_init(dev, path.encode()))
     _inited.add(dev)
+
+
+def stream_release(stream=None):
+    """ism_stream_release: return the library scratch held for `stream` (default: torch's current)."""
+    _check(lib().ism_stream_release(_stream(stream)))
 
 
 def _ensure_init(t):
@@ -349,6 +357,10 @@ def chem_cool_step(n, T, xH2, xHp, rad, dt_s, params, prec=F64, want=("xCp", "xC
     """In-place step of T, xH2, xHp (float64 device tensors).  Returns dict of the requested extra outputs.
     With params.order_cells == 2 the entry values of out["nsub"] are the ordering key; a binding-allocated
     nsub then starts at zero."""
+    return _step("ism_chem_cool_step", n, T, xH2, xHp, rad, dt_s, params, prec, want, out, stream)
+
+
+def _step(symbol, n, T, xH2, xHp, rad, dt_s, params, prec, want, out, stream):
     _ensure_init(n)
     N = n.numel()
     rd = _rdt(prec)
@@ -360,7 +372,7 @@ def chem_cool_step(n, T, xH2, xHp, rad, dt_s, params, prec=F64, want=("xCp", "xC
             out[k] = alloc(N, dtype=dt, device=n.device)
     p = params._c()
     g = out.get
-    _check(lib().ism_chem_cool_step(
+    _check(getattr(lib(), symbol)(
         ctypes.byref(p), prec, N, float(dt_s), _ptr(n, torch.float64, N, "n"), _ptr(T, torch.float64, N, "T"),
         _ptr(xH2, torch.float64, N, "xH2"), _ptr(xHp, torch.float64, N, "xHp"),
         _ptr(rad["chi_PE"], rd, N, "chi_PE"), _ptr(rad["chi_LW"], rd, N, "chi_LW"),
@@ -432,18 +444,18 @@ class Surrogate:
                                               _stream(stream)))
         return loss
 
-    def get_params(self):
+    def get_params(self, stream=None):
         import numpy as np
         out = np.empty(SURR_STATE_FLOATS, dtype=np.float32)
-        _check(lib().ism_surrogate_get_params(self._h, out.ctypes.data))
+        _check(lib().ism_surrogate_get_params(self._h, out.ctypes.data, _stream(stream)))
         return out
 
-    def set_params(self, flat):
+    def set_params(self, flat, stream=None):
         import numpy as np
         a = np.ascontiguousarray(flat, dtype=np.float32)
         if a.size != SURR_STATE_FLOATS:
             raise ValueError(f"state has {a.size} floats, expected {SURR_STATE_FLOATS}")
-        _check(lib().ism_surrogate_set_params(self._h, a.ctypes.data))
+        _check(lib().ism_surrogate_set_params(self._h, a.ctypes.data, _stream(stream)))
 
     @staticmethod
     def state(theta, m=None, v=None, step=0, mu_x=None, sd_x=None, mu_y=None, sd_y=None):

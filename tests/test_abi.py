@@ -109,8 +109,8 @@ def test_surrogate_entry_points_reject_null_handles():
     assert "NULL" in L.ism_last_error().decode()
     assert L.ism_surrogate_backward(None, None, None, None, 4, None) == -1
     assert L.ism_surrogate_train_step(None, None, None, 4, ctypes.c_float(1e-3), None, None) == -1
-    assert L.ism_surrogate_get_params(None, None) == -1
-    assert L.ism_surrogate_set_params(None, None) == -1
+    assert L.ism_surrogate_get_params(None, None, None) == -1
+    assert L.ism_surrogate_set_params(None, None, None) == -1
 
 
 def test_surrogate_sizes_match_the_reference_network():
