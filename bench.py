@@ -1,26 +1,28 @@
 """Throughput of the ISM chemistry + cooling source step on one MI355X.
 
-A step is one pass of the hot path over the 128^3 lognormal-GRF workload (4 pc cells,
-Z' = 1, CR attenuation by N_eff, dt = 1e4 yr): six-ray columns, then the source step of
-every cell.  The cell state is restored from a device copy before each step, so every
-step does the same work.  Three forms of the step are measured in the same run:
+The metric workload (default, `--workload pts512`): the 512^3 lognormal-GRF grid with 2 pc
+cells, 16 point sources (maps made once from the initial state), a per-cell CR map, Z' = 1 and
+one step of dt = 1e4 yr.  A step is one pass of the hot path: six-ray columns, then the source
+step of every cell; the cell state is restored from a device copy before each step, so every
+step does the same work.  Three forms are measured in the same run:
 
   f64        plain method, FP64 everywhere                       (columns F64 + step F64)
   mixed      plain method, FP32 evaluation, FP64 update/sums     (columns MIXED + step MIXED)
   surrogate  FP32 + learned surrogate with certification and
              fallback to the mixed step                          (columns MIXED + surrogate step)
 
-`--path` picks the form timed over K steps for `value` (cell-updates/s of the whole step,
-inputs resident in HBM); `paths` reports all three (HIP-event medians), their per-field
-error against the FP64 oracle on the CPU sample, the surrogate's fallback fraction and the
-speedups.  Prints one JSON line.
+`value` is the cell-updates/s of `--path` (default f64) over K steps (W untimed steps first,
+synchronisations around the K), inputs resident in HBM; `paths` reports all three forms with
+their substep statistics, per-field error against the FP64 oracle on the 64^3 subsample, the
+surrogate's fallback fraction and the speedups.  `cpu_baseline` times the oracle on a bounded
+sample of the same workload, in one process and over the host's cores.  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--path f64|mixed|surrogate] [--no-cpu]
 
-Other workloads (`--workload`): pts256, the 256^3 grid with 16 point sources and ten successive
-mixed steps (`--maps lc|art`: straight-line maps or the adaptive ray trace, which also
-measures the flux trace and the radiation force); pts512, the 512^3 grid, one step on each form
-with the error against the oracle on a subsample; train, the surrogate's Adam steps.
+Other workloads (`--workload`): grf128, the 128^3 GRF grid (4 pc cells, CR attenuation by
+N_eff); pts256, the 256^3 grid with 16 point sources and ten successive mixed steps (`--maps
+lc|art`: straight-line maps or the adaptive ray trace, which also measures the flux trace and the
+radiation force); train, the surrogate's Adam steps.
 """
 import argparse
 import json
@@ -35,7 +37,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
-FP32_PEAK_TFLOPS = 157.3
+FP32_PEAK_TFLOPS = 157.3           # packed FP32 (two lanes per instruction)
+FP32_ISSUE_PEAK_TFLOPS = 78.6      # what this build can issue: packed FP32 is kept out of the code
 BF16_PEAK_TFLOPS = 2500.0
 MLP_FLOP_PER_CELL = 2 * (10 * 128 + 2 * 128 * 128 + 128 * 3)
 FIELDS = ("T", "xH2", "xHp", "xe", "xCp", "xCO")
@@ -44,13 +47,14 @@ FIELDS = ("T", "xH2", "xHp", "xe", "xCp", "xCO")
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--path", choices=("f64", "mixed", "surrogate"), default="f64")
-    ap.add_argument("--workload", choices=("grf128", "pts256", "pts512", "train"), default="grf128",
-                    help="grf128: the metric workload; pts256: 256^3 with 16 point sources, ten successive steps "
-                         "(mixed form); pts512: 512^3 with 16 point sources, one step on each path; train: surrogate "
-                         "training, one Adam step of batch 65,536 per step (use --steps of a few hundred)")
+    ap.add_argument("--workload", choices=("grf128", "pts256", "pts512", "train"), default="pts512",
+                    help="pts512: the metric workload, 512^3 with 16 point sources, K steps of each form; grf128: the "
+                         "128^3 GRF grid; pts256: 256^3 with 16 point sources, ten successive steps (mixed form); "
+                         "train: surrogate training, one Adam step of batch 65,536 per step (use --steps of a few "
+                         "hundred)")
     ap.add_argument("--pts512-stride", type=int, default=8,
                     help="pts512: error report on every s-th cell along each axis (8: a 64^3 subsample)")
     ap.add_argument("--maps", choices=("lc", "art"), default="lc",
@@ -78,11 +82,11 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_counters(kernel):
-    """Counters per launch of `kernel` from the committed summary, if it was taken on the current
-    sources: HBM bytes (FETCH_SIZE x fetch factor + WRITE_SIZE x write factor, KiB -> bytes),
-    VALU wave instructions and lane utilisation.  None when absent or stale."""
-    path = os.path.join(ROOT, "profiles", "traffic_grf128.txt")
+def measured_counters(kernel, workload="grf128"):
+    """Counters per launch of `kernel` from the committed summary of `workload`, if it was taken on
+    the current sources: HBM bytes (FETCH_SIZE x fetch factor + WRITE_SIZE x write factor, KiB ->
+    bytes), VALU wave instructions and lane utilisation.  None when absent or stale."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
     if not os.path.exists(path):
         return None
     rows, meta = {}, {}
@@ -362,8 +366,8 @@ def bench_pts256(args):
                    "maps": args.maps, "job": "point-source maps once + ten (columns6 + step)",
                    "order": "steps 2-10 by the previous step's substep counts" if args.pts256_order == "previous"
                    else "by temperature"},
-        "roofline": {"bound": "alu", "kernel": "step_queue_kernel", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
+        "roofline": {"bound": "alu", "kernel": "step_queue_kernel", "achieved": achieved, "peak": FP32_ISSUE_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_ISSUE_PEAK_TFLOPS,
                      "traffic": None, "work": f"{int(np.sum(tot_sub))} substeps over ten steps x ({arith} + {trans})"},
         "detail": {"maps_ms": times["maps"][0] * 1e3,
                    ("maps_long_characteristics_ms" if args.maps == "art" else "maps_ray_tracing_ms"): other_ms, "columns_ms_mean": float(np.mean(times["columns"])) * 1e3,
@@ -483,20 +487,37 @@ def bench_train(args):
 
 
 def _oracle_chunk(job):
-    """One chunk of the oracle step (a worker of the C4 error report)."""
+    """One chunk of the oracle step (a worker of the error report and of the parallel CPU baseline)."""
     from oracle import step as ostep
     n, T, xH2, xHp, rad, dt, par = job
     return ostep.chem_cool_step(n, T, xH2, xHp, rad, dt, par)
 
 
+def _oracle_columns_box(job):
+    """The oracle's vectorised six-ray columns over one sub-box (a worker of the parallel CPU baseline)."""
+    from oracle import columns as ocol
+    n, xH2, dx, par = job
+    ocol.columns6(n, xH2, None, dx, par)
+    return n.size
+
+
+def _sub_boxes(shape, m, k):
+    """k corner offsets of m^3 sub-boxes spread over the grid (deterministic)."""
+    offs = []
+    for q in range(k):
+        offs.append(tuple(((q * 7 + a * 3) % max(1, (d - m) // m + 1)) * m for a, d in enumerate(shape)))
+    return offs
+
+
 def bench_pts512(args):
-    """512^3, 2 pc cells, 16 point sources, CR map, one step of 1e4 yr on each path (plain F64,
-    plain mixed, FP32 + surrogate with the plain step as fallback).  The point-source maps are
-    computed once from the initial state (in double; the mixed paths take them rounded to
-    float) and are not part of the timed step.  value = cell-updates/s of the surrogate path
-    (columns6 + step).  Errors: every path against the FP64 oracle step on the stride-s
-    subsample (s = 8: 64^3 cells), fed the GPU's FP64 radiation at those cells; the oracle runs
-    in a pool of worker processes forked before the GPU is touched."""
+    """512^3, 2 pc cells, 16 point sources, CR map, one step of 1e4 yr on each form (plain F64, plain
+    mixed, FP32 + surrogate with the plain mixed step as fallback).  A step of a form is six-ray
+    columns + source step with the state restored from a device copy first.  The point-source
+    maps are computed once from the initial state (in double; the mixed forms take them rounded to
+    float) and are not part of the step.  value = cell-updates/s of --path (default f64) over K
+    timed steps.  Errors: every form against the FP64 oracle step on the stride-s subsample (s = 8:
+    64^3 cells), fed the GPU's FP64 radiation at those cells; the oracle runs in a pool of worker
+    processes forked before the GPU is touched."""
     import multiprocessing as mp
     try:
         ncores = len(os.sched_getaffinity(0))
@@ -525,7 +546,7 @@ def bench_pts512(args):
     xi64 = torch.from_numpy(s["xi"].ravel()).to(dev)
     n = init["n"]
     T, xH2, xHp = (torch.empty_like(init[k]) for k in ("T", "xH2", "xHp"))
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     # point-source maps once, in double
     maps64 = {k: torch.zeros(N, dtype=torch.float64, device=dev) for k in ("chi_PE", "chi_LW", "chi_H2", "chi_C", "phi")}
     ev[0].record(stream)
@@ -551,7 +572,9 @@ def bench_pts512(args):
 
     bufs = {torch.float64: buffers(torch.float64), torch.float32: buffers(torch.float32)}
 
-    def one_step(path, times=None):
+    def one_step(path, evs=None):
+        """One step of a form; evs = three events recorded before the columns, between columns and
+        step, and after the step (on the launch stream; no synchronisation here)."""
         f64 = path == "f64"
         prec = ism.F64 if f64 else ism.MIXED
         rad, outs = bufs[torch.float64 if f64 else torch.float32]
@@ -560,22 +583,36 @@ def bench_pts512(args):
         xH2.copy_(init["xH2"])
         xHp.copy_(init["xHp"])
         rad["xi"].copy_(xi64)
-        ev[0].record(stream)
+        if evs:
+            evs[0].record(stream)
         ism.columns6(n.view(shape), xH2.view(shape), None, dx, par, prec, out={k: v.view(shape) for k, v in rad.items()})
         for k in ("chi_PE", "chi_LW", "chi_H2", "chi_C"):
             rad[k].add_(maps[k])
         r = dict(rad)
         r["phi"] = maps["phi"]
-        ev[1].record(stream)
+        if evs:
+            evs[1].record(stream)
         if path == "surrogate":
             ism.chem_cool_step_surrogate(sur, n, T, xH2, xHp, r, dt, par, out=outs, n_fallback=nfb)
         else:
             ism.chem_cool_step(n, T, xH2, xHp, r, dt, par, prec, out=outs)
-        ev[2].record(stream)
+        if evs:
+            evs[2].record(stream)
+
+    def run_form(p, K, W):
+        """W untimed steps, then K steps bracketed by synchronisations; per-step HIP events."""
+        for _ in range(W):
+            one_step(p)
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
         torch.cuda.synchronize()
-        if times is not None:
-            times["columns"].append(ev[0].elapsed_time(ev[1]) * 1e-3)
-            times["step"].append(ev[1].elapsed_time(ev[2]) * 1e-3)
+        t0 = time.perf_counter()
+        for k in range(K):
+            one_step(p, evs[k])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        tc = [e[0].elapsed_time(e[1]) * 1e-3 for e in evs]
+        ts = [e[1].elapsed_time(e[2]) * 1e-3 for e in evs]
+        return wall, float(np.median(tc)), float(np.median(ts))
 
     # the subsample: every s-th cell along each axis
     st = args.pts512_stride
@@ -583,15 +620,11 @@ def bench_pts512(args):
                              indexing="ij")
     idx = (ii + shape[2] * (jj + shape[1] * kk)).ravel()
     tid = torch.from_numpy(idx).to(dev)
-    paths, rad_sample = {}, None
-    for p in ("f64", "mixed", "surrogate"):
-        for _ in range(args.warmup):
-            one_step(p)
-        times = {"columns": [], "step": []}
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            one_step(p, times)
-        wall = (time.perf_counter() - t0) / args.steps
+    order = [args.path] + [p for p in ("f64", "mixed", "surrogate") if p != args.path]
+    paths, rad_sample, walls = {}, None, {}
+    for p in order:
+        wall, tc, ts = run_form(p, args.steps, args.warmup)
+        walls[p] = wall
         rad, outs = bufs[torch.float64 if p == "f64" else torch.float32]
         if p == "f64":
             rad_sample = {k: rad[k][tid].double().cpu().numpy() for k in ("chi_PE", "chi_LW", "chi_H2", "chi_C", "xi")}
@@ -600,18 +633,38 @@ def bench_pts512(args):
         res = {"T": T[tid].cpu().numpy(), "xH2": xH2[tid].cpu().numpy(), "xHp": xHp[tid].cpu().numpy()}
         res.update({k: outs[k][tid].double().cpu().numpy() for k in ("xCp", "xCO", "xe")})
         nsub = outs["nsub"].to(torch.int64)
-        tc, ts = float(np.median(times["columns"])), float(np.median(times["step"]))
-        paths[p] = {"ms_per_step": (tc + ts) * 1e3, "columns_ms": tc * 1e3, "step_ms": ts * 1e3, "wall_ms": wall * 1e3,
-                    "cell_updates_per_s": N / (tc + ts), "nsub_mean": float(nsub.double().mean()),
-                    "substeps": int(nsub.sum()),
+        q = torch.quantile(nsub[::64].double(), torch.tensor([0.5, 0.99], dtype=torch.float64, device=dev))
+        paths[p] = {"ms_per_step": wall / args.steps * 1e3, "columns_ms": tc * 1e3, "step_ms": ts * 1e3,
+                    "cell_updates_per_s": N / (wall / args.steps), "step_only_cell_updates_per_s": N / ts,
+                    "nsub_mean": float(nsub.double().mean()), "nsub_p50": float(q[0]), "nsub_p99": float(q[1]),
+                    "nsub_max": int(nsub.max()), "substeps": int(nsub.sum()),
                     "status_nonzero": int(((outs["status"] & 0xEF) != 0).sum()), "_res": res}
         paths[p]["conservation"] = device_conservation(xH2, xHp, outs["xCp"], outs["xCO"], OParams(Zg=1.0))
         if p == "surrogate":
             paths[p]["fallback_fraction"] = nfb.item() / N
+            paths[p]["accepted_cells"] = int(N - nfb.item())
     for p in ("mixed", "surrogate"):
         paths[p]["speedup_vs_f64"] = paths["f64"]["ms_per_step"] / paths[p]["ms_per_step"]
     paths["surrogate"]["speedup_vs_mixed"] = paths["mixed"]["ms_per_step"] / paths["surrogate"]["ms_per_step"]
-    # the FP64 oracle on the subsample, fed the GPU's FP64 radiation there
+    # inference kernel alone (network inputs built once, then timed forwards) on 2^24 cells
+    rad32, _ = bufs[torch.float32]
+    B = 1 << 24
+    X, _ = ism.surrogate_pairs(n[:B], init["T"][:B], init["xH2"][:B], init["xHp"][:B],
+                               {k: v[:B] for k, v in rad32.items()}, dt, par, ism.MIXED)
+    Y = torch.empty((B, 3), dtype=torch.float32, device=dev)
+    sur.forward(X, Y)
+    ev[0].record(stream)
+    for _ in range(10):
+        sur.forward(X, Y)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    t_mlp = ev[0].elapsed_time(ev[1]) * 1e-3 / 10
+    mlp_tf = MLP_FLOP_PER_CELL * B / t_mlp / 1e12
+    del X, Y
+    hbm_copy = copy_bandwidth()
+
+    # the FP64 oracle on the subsample, fed the GPU's FP64 radiation there (worker pool): the error
+    # report, and the parallel leg of the CPU baseline's step
     sel = lambda a: np.ascontiguousarray(a.ravel()[idx])
     st0 = {k: sel(s[k]) for k in ("n", "T", "xH2", "xHp")}
     chunk = 4096
@@ -619,37 +672,105 @@ def bench_pts512(args):
             ({k: v[a:a + chunk] for k, v in rad_sample.items()}, dt, par_o) for a in range(0, len(idx), chunk)]
     t0 = time.perf_counter()
     parts = pool.map(_oracle_chunk, jobs)
-    t_or = time.perf_counter() - t0
-    pool.close()
+    t_or_par = time.perf_counter() - t0
     ref = {k: np.concatenate([q[k] for q in parts]) for k in FIELDS}
     xCt = par_o.xCtot
     ar = np.arange(len(idx))
     for p in paths:
         paths[p]["error_vs_oracle"] = field_errors(paths[p].pop("_res"), ref, ar, xCt)
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline_pts512(pool, procs, s, dx, par_o, st0, rad_sample, dt, t_or_par, len(idx))
+    pool.close()
+    pool.join()
+
     arith, trans = substep_census(par_o)
-    sp = paths["surrogate"]
-    achieved = sp["substeps"] * (arith + trans) / (sp["step_ms"] * 1e-3) / 1e12
+    vp = paths[args.path]
+    kname = "step_queue_kernel<double>" if args.path == "f64" else "step_queue_kernel<float>"
+    achieved = vp["substeps"] * (arith + trans) / (vp["step_ms"] * 1e-3) / 1e12
+    peak = FP64_PEAK_TFLOPS if args.path == "f64" else FP32_ISSUE_PEAK_TFLOPS
+    cnt = measured_counters(kname, "pts512")
+    cols_bytes = N * (72 if args.path == "f64" else 48)
     how = ("adaptive ray tracing (Sec. 5.1)" if args.maps == "art" else
            "straight-line 1/r^2 exp(-tau) maps with the Stromgren cap")
     out = {
-        "metric": "cell-updates/s per chem+cool step (columns6 + source step)",
-        "value": sp["cell_updates_per_s"], "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": sp["ms_per_step"], "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "bf16+f32+f64", "data": "synthetic",
+        "metric": "cell-updates/s per chem+cool step: FP64 plain vs FP32+surrogate at <=1e-3 rel err",
+        "value": vp["cell_updates_per_s"], "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": vp["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": {"f64": "f64", "mixed": "f32+f64", "surrogate": "bf16+f32+f64"}[args.path],
+        "data": "synthetic",
         "config": {"workload": "pts512: 512^3 lognormal GRF (2 pc cells, 1024 pc box), 16 point sources (Q 1.24e50 s^-1, "
                                "L_FUV 1.36e6 L_sun; maps once by " + how + "), chi0 = 1 six-ray, xi_cr log-uniform "
-                               "[1e-17, 1e-15], Z' = 1, one step of 1e4 yr", "cells": N, "path": "surrogate",
-                   "maps": args.maps},
-        "roofline": {"bound": "alu", "kernel": "step_queue_kernel", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
-                     "work": f"{sp['substeps']} substeps x ({arith} + {trans}) on the surrogate path's fallback"},
-        "cpu_baseline": {"value": len(idx) / t_or, "unit": "cell-updates/s", "cores": procs, "kind": "oracle",
-                         "sample": f"the stride-{st} subsample ({len(idx)} cells): oracle step from the GPU's FP64 "
-                                   f"radiation, {procs} worker processes, {t_or:.1f} s"},
+                               "[1e-17, 1e-15], Z' = 1, one step of 1e4 yr (six-ray columns + source step)",
+                   "cells": N, "path": args.path, "maps": args.maps},
+        "roofline": {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None if cnt is None else cnt["bytes"],
+                     "traffic_algorithmic": N * (133 if args.path == "f64" else 97),
+                     "work": f"{vp['substeps']} substeps x ({arith} flops + {trans} transcendentals counted as 1) "
+                             f"per launch (census of the oracle's substep); time = the step call (cell ordering + "
+                             f"step kernel) between HIP events on the launch stream"},
+        "roofline_issue": issue_roofline(kname, vp["step_ms"] * 1e-3, "pts512"),
+        "roofline_columns": {"bound": "hbm", "kernel": "columns6 (all passes)", "achieved": cols_bytes / (vp["columns_ms"] * 1e-3) / 1e9,
+                             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": cols_bytes / (vp["columns_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                             "traffic": columns_traffic(args.path, "pts512"),
+                             "work": f"{N} cells x {72 if args.path == 'f64' else 48} B (n, x_H2, x_C in; chi_PE, chi_LW, "
+                                     f"chi_H2, chi_C, N_eff, xi out)"},
+        "roofline_mlp": {"bound": "mfma", "kernel": "mlp_fwd_kernel", "achieved": mlp_tf, "peak": BF16_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": mlp_tf / BF16_PEAK_TFLOPS, "ms": t_mlp * 1e3,
+                         "work": f"{MLP_FLOP_PER_CELL} FLOP/cell x {B} cells per launch"},
         "paths": paths,
-        "detail": {"maps_ms": maps_ms, "generate_s": t_gen, "subsample_cells": int(len(idx))},
+        "detail": {"maps_ms": maps_ms, "generate_s": t_gen, "subsample_cells": int(len(idx)),
+                   "hbm_copy_GBs_measured": hbm_copy,
+                   "fp32_peak_note": "FP32 vector peak the build can issue: 78.6 TFLOP/s (packed FP32 instructions "
+                                     "are kept out of the generated code; 157.3 is the packed rate)"},
     }
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_pts512(pool, procs, s, dx, par_o, st0, rad_sample, dt, t_step_par, nsample):
+    """The CPU oracle as it stands on a bounded sample of the 512^3 workload: its vectorised six-ray
+    columns over 96^3 sub-boxes of the grid plus its step on subsample cells (fed the GPU's FP64
+    radiation).  One process: one sub-box and 65,536 cells; all cores: 16 sub-boxes over the pool
+    and the whole subsample (the error report's run).  cell-updates/s = 1 / (columns time per cell
+    + step time per cell)."""
+    from oracle import columns as ocol
+    from oracle import step as ostep
+    m = 96
+    shape = s["n"].shape
+    boxes = _sub_boxes(shape, m, 16)
+    box = lambda o, k: np.ascontiguousarray(s[k][o[0]:o[0] + m, o[1]:o[1] + m, o[2]:o[2] + m])
+    t0 = time.perf_counter()
+    ocol.columns6(box(boxes[0], "n"), box(boxes[0], "xH2"), None, dx, par_o)
+    t_col1 = time.perf_counter() - t0
+    ns = min(65536, nsample)
+    t0 = time.perf_counter()
+    ostep.chem_cool_step(st0["n"][:ns], st0["T"][:ns], st0["xH2"][:ns], st0["xHp"][:ns],
+                         {k: v[:ns] for k, v in rad_sample.items()}, dt, par_o)
+    t_step1 = time.perf_counter() - t0
+    jobs = [(box(o, "n"), box(o, "xH2"), dx, par_o) for o in boxes]
+    t0 = time.perf_counter()
+    ncol = sum(pool.map(_oracle_columns_box, jobs))
+    t_colp = time.perf_counter() - t0
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    one = 1.0 / (t_col1 / m ** 3 + t_step1 / ns)
+    par_v = 1.0 / (t_colp / ncol + t_step_par / nsample)
+    return {"value": one, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"the oracle (numpy, FP64) on the 512^3 workload, one process: vectorised six-ray columns over a "
+                      f"96^3 sub-box ({t_col1:.2f} s) + the step of {ns} subsample cells ({t_step1:.1f} s); "
+                      f"CPU {model}",
+            "parallel": {"value": par_v, "unit": "cell-updates/s", "cores": procs, "kind": "oracle",
+                         "sample": f"columns over 16 sub-boxes of 96^3 ({t_colp:.2f} s) + the step of the "
+                                   f"{nsample}-cell subsample in chunks of 4,096 ({t_step_par:.1f} s), "
+                                   f"{procs} worker processes"}}
 
 
 # VALU issue slots: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4 cycles at 2.4 GHz
@@ -658,16 +779,29 @@ def bench_pts512(args):
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
 
-def issue_roofline(kernel, t_launch):
+def issue_roofline(kernel, t_launch, workload="grf128"):
     """VALU wave instructions per second of the kernel (counters from the committed summary over
     the measured launch time) against the chip's issue rate; None when the counters are stale."""
-    c = measured_counters(kernel)
+    c = measured_counters(kernel, workload)
     if c is None or "valu_insts" not in c:
         return None
     rate = c["valu_insts"] / t_launch
     return {"bound": "alu-issue", "kernel": kernel, "achieved": rate, "peak": VALU_ISSUE_PEAK,
             "unit": "wave64 VALU instructions/s", "frac": rate / VALU_ISSUE_PEAK, "lane_util": c["lane_util"],
-            "counters": "SQ_INSTS_VALU per launch from profiles/traffic_grf128.txt"}
+            "counters": f"SQ_INSTS_VALU per launch from profiles/traffic_{workload}.txt"}
+
+
+def columns_traffic(path, workload):
+    """HBM bytes of one columns6 call (all its kernels) from the committed counters, or None."""
+    names = ("columns_x_kernel", "columns_segsum_kernel", "columns_march_kernel")
+    tot, found = 0.0, False
+    suffix = "<double>" if path == "f64" else "<float>"
+    for k in names:
+        c = measured_counters(k + suffix, workload) or measured_counters(k, workload)
+        if c is not None:
+            tot += c["bytes"]
+            found = True
+    return tot if found else None
 
 
 def main():
@@ -807,7 +941,7 @@ def main():
     tot_sub = int(paths[args.path]["_res"]["nsub"].astype(np.int64).sum())
     arith, trans = substep_census(OParams())
     flops = float(tot_sub) * (arith + trans)
-    peak = FP64_PEAK_TFLOPS if args.path == "f64" else FP32_PEAK_TFLOPS
+    peak = FP64_PEAK_TFLOPS if args.path == "f64" else FP32_ISSUE_PEAK_TFLOPS
     t_step = paths[args.path]["step_ms"] * 1e-3
     achieved = flops / t_step / 1e12
     ms = wall / args.steps * 1e3
