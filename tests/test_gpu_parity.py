@@ -100,7 +100,8 @@ def test_rates_parity_f64(ism, kgr_const, rovib):
     two terms: H = n Gamma - n^2 Lambda, and the gas-dust term alpha_gd T^1/2 (T - T_d) Z'_d, whose
     T_d each side takes from its own root solve (bisection and safeguarded Newton, both to 1e-14
     relative), so that T - T_d is known to about 1e-14 T_d.  C I and CO cooling are proportional
-    to x_C and x_CO and are compared on those abundances' floor.  Heating and cooling terms below
+    to x_C and x_CO and are compared on those abundances' floors (x_C, a difference at the scale of
+    x_C,tot: 1e-6 x_C,tot).  Heating and cooling terms below
     1e-250 count as zero: the two sides split products of exponentials differently (one
     exponent against two factors), so they leave the double range at different points, more
     than 200 orders of magnitude below any total the terms enter.  Four cells sit below 1 K
@@ -126,10 +127,12 @@ def test_rates_parity_f64(ism, kgr_const, rovib):
         elif name == "L_gd":
             fl = OC.ALPHA_GD * np.sqrt(T) * np.maximum(T, ev["Td"]) * par.Zd
         elif name in ("L_c", "L_co"):
-            # proportional to x_C or x_CO: on their abundance floor, 1e-10 x_C,tot times the cooling
-            # per atom or molecule
-            x = eq["xC"] if name == "L_c" else eq["xCO"]
-            fl = np.maximum(1e-10 * par.xCtot * np.abs(r) / np.maximum(np.abs(x), 1e-300), 1e-250)
+            # proportional to x_C or x_CO, on the floor of that abundance times the cooling per atom or
+            # molecule: x_CO is a product (floor 1e-10 x_C,tot, as for the abundances); x_C = x_C,tot -
+            # x_C+ - x_CO is a difference at the scale of x_C,tot, which double holds to ~2 ulp
+            # (5e-20), so at a 1e-9 bar its floor is 1e-6 x_C,tot
+            x, f = (eq["xC"], 1e-6) if name == "L_c" else (eq["xCO"], 1e-10)
+            fl = np.maximum(f * par.xCtot * np.abs(r) / np.maximum(np.abs(x), 1e-300), 1e-250)
         elif name.startswith(("L_", "G_")):
             fl = 1e-250
         else:
