@@ -291,6 +291,23 @@ ism_status ism_chem_cool_step(const ism_params *p, ism_precision prec, int64_t n
                               const void *N_eff, void *xCp, void *xCO, void *xe,
                               int32_t *nsub, uint8_t *status, hipStream_t stream);
 
+/* ism_chem_cool_step for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same arguments, results and
+ * errors as ism_chem_cool_step, but the call allocates nothing: its scratch (work-queue counter
+ * and cell-ordering keys) is a fixed ISM_NOALLOC_SCRATCH_BYTES array per device, created with
+ * the library's code object and held until the process ends.  Every call on one device shares
+ * that array, so calls that overlap in time on one device race (serialise them, e.g. one
+ * stream).  Limit: with order_cells 1 or 2 ncell <= ISM_NOALLOC_MAX_ORDERED_CELLS (ISM_E_ARG
+ * beyond); with order_cells 0 any ncell. */
+#define ISM_NOALLOC_SCRATCH_BYTES (64u << 20)
+#define ISM_NOALLOC_MAX_ORDERED_CELLS (1 << 23)
+ism_status ism_chem_cool_step_noalloc(const ism_params *p, ism_precision prec, int64_t ncell,
+                                      double dt_s, const double *n, double *T, double *xH2,
+                                      double *xHp, const void *chi_PE, const void *chi_LW,
+                                      const void *chi_H2, const void *chi_C, const void *phi_LyC,
+                                      const void *xi_cr, const void *N_eff, void *xCp, void *xCO,
+                                      void *xe, int32_t *nsub, uint8_t *status, hipStream_t stream);
+
 /* ---------------------------------------------------------------- learned surrogate
  * A small MLP maps a cell's (state, radiation, dt) to its post-step (x_H2, x_H+, log10 T):
  * 10 inputs -> 128 -> 128 -> 128 -> 3 outputs, SiLU on the hidden layers.  The products

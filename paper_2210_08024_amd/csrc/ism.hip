@@ -29,6 +29,11 @@ using namespace ism;
 using ism::host::coef_to_f32;
 using ism::host::load_coefficients;
 
+// Scratch of ism_chem_cool_step_noalloc: one copy per device, held for the life of the process.
+// Layout: [0, 256) work-queue counter; [256, ...) the cell ordering (order_bytes(ncell)).  Host
+// code never names it after init: it uses the per-device address taken there.
+static __device__ __align__(256) uint8_t scratch[ISM_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 thread_local std::string g_err;
@@ -45,6 +50,7 @@ struct DevState {
   int num_cu = 0;
   int occ64 = 0, occ32 = 0;  // resident 256-thread blocks per CU of the persistent step kernels
   bool simple_step = false;   // ISM_STEP_KERNEL=simple selects the one-lane-per-cell grid
+  uint8_t *noalloc = nullptr;  // this device's copy of `scratch` (hipGetSymbolAddress at init)
 };
 
 // Library scratch of one (device, stream): every call takes the scratch of the stream it is
@@ -324,6 +330,8 @@ ism_status ism_init(int device, const char *path) {
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&st.occ64, step_queue_kernel<double>, 256, 0);
     if (e == hipSuccess)
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&st.occ32, step_queue_kernel<float>, 256, 0);
+    // the allocation-free step's scratch: its address on this device (the device is current)
+    if (e == hipSuccess && !st.noalloc) e = hipGetSymbolAddress((void **)&st.noalloc, HIP_SYMBOL(scratch));
     if (e == hipSuccess) {
       const char *k = std::getenv("ISM_STEP_KERNEL");
       st.simple_step = k && std::string(k) == "simple";
@@ -456,6 +464,29 @@ ism_status ism_chem_cool_step(const ism_params *p, ism_precision prec, int64_t n
   }
   launch_step(st, p, prec, ncell, dt_s, n, T, xH2, xHp, chi_PE, chi_LW, chi_H2, chi_C, phi_LyC, xi_cr, N_eff, xCp,
               xCO, xe, nsub, status, (int64_t *)ss->ctl, ord, stream);
+  HIP_TRY(hipGetLastError());
+  return ISM_OK;
+}
+
+ism_status ism_chem_cool_step_noalloc(const ism_params *p, ism_precision prec, int64_t ncell, double dt_s,
+                                      const double *n, double *T, double *xH2, double *xHp, const void *chi_PE,
+                                      const void *chi_LW, const void *chi_H2, const void *chi_C,
+                                      const void *phi_LyC, const void *xi_cr, const void *N_eff, void *xCp,
+                                      void *xCO, void *xe, int32_t *nsub, uint8_t *status, hipStream_t stream) {
+  g_err.clear();
+  if (ism_status s = check_step(p, prec, ncell, dt_s, n, T, xH2, xHp, chi_PE, chi_LW, chi_H2, chi_C, xi_cr, N_eff))
+    return s;
+  if (ncell == 0) return ISM_OK;
+  DevState *st;
+  if (ism_status s = current_state(&st)) return s;
+  if (!st->noalloc) return fail(ISM_E_STATE, "no allocation-free scratch on this device");
+  const bool ordered = step_orders(st, p, ncell);
+  if (ordered && (ncell > (int64_t)ISM_NOALLOC_MAX_ORDERED_CELLS ||
+                  256 + order_bytes(ncell) > (size_t)ISM_NOALLOC_SCRATCH_BYTES))
+    return fail(ISM_E_ARG, "ism_chem_cool_step_noalloc: with order_cells 1 or 2 ncell must be at most " +
+                               std::to_string((long long)ISM_NOALLOC_MAX_ORDERED_CELLS));
+  launch_step(st, p, prec, ncell, dt_s, n, T, xH2, xHp, chi_PE, chi_LW, chi_H2, chi_C, phi_LyC, xi_cr, N_eff, xCp,
+              xCO, xe, nsub, status, (int64_t *)st->noalloc, ordered ? st->noalloc + 256 : nullptr, stream);
   HIP_TRY(hipGetLastError());
   return ISM_OK;
 }

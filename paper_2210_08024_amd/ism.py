@@ -84,6 +84,7 @@ def lib():
         L.ism_columns6.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Params), ctypes.c_int] + [_vp] * 10
         L.ism_rates.argtypes = [ctypes.POINTER(_Params), ctypes.c_int, _i64] + [_vp] * 13
         L.ism_chem_cool_step.argtypes = [ctypes.POINTER(_Params), ctypes.c_int, _i64, _dp] + [_vp] * 17
+        L.ism_chem_cool_step_noalloc.argtypes = [ctypes.POINTER(_Params), ctypes.c_int, _i64, _dp] + [_vp] * 17
         L.ism_surrogate_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_uint64]
         L.ism_surrogate_destroy.argtypes = [_vp]
         L.ism_surrogate_set_norm.argtypes = [_vp] * 5
@@ -110,7 +111,7 @@ def lib():
         L.ism_chem_cool_step_surrogate.argtypes = [_vp, ctypes.POINTER(_Params), _i64, _dp] + [_vp] * 16 + \
             [_dp, _vp, _vp]
         for name in ("ism_init", "ism_shutdown", "ism_stream_release", "ism_columns6", "ism_rates",
-                     "ism_chem_cool_step") + SURROGATE_SYMBOLS:
+                     "ism_chem_cool_step", "ism_chem_cool_step_noalloc") + SURROGATE_SYMBOLS:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -125,7 +126,7 @@ SURROGATE_SYMBOLS = ("ism_surrogate_create", "ism_surrogate_destroy", "ism_surro
 def exported_symbols():
     return ["ism_params_default", "ism_init", "ism_shutdown", "ism_stream_release", "ism_last_error", "ism_ndiag",
             "ism_diag_name",
-            "ism_columns6", "ism_rates", "ism_chem_cool_step", "ism_point_sources",
+            "ism_columns6", "ism_rates", "ism_chem_cool_step", "ism_chem_cool_step_noalloc", "ism_point_sources",
             "ism_ray_trace", "ism_radiation_force", "ism_local_shielding", "ism_columns_beam"] + \
         list(SURROGATE_SYMBOLS)
 
@@ -358,6 +359,13 @@ def chem_cool_step(n, T, xH2, xHp, rad, dt_s, params, prec=F64, want=("xCp", "xC
     With params.order_cells == 2 the entry values of out["nsub"] are the ordering key; a binding-allocated
     nsub then starts at zero."""
     return _step("ism_chem_cool_step", n, T, xH2, xHp, rad, dt_s, params, prec, want, out, stream)
+
+
+def chem_cool_step_noalloc(n, T, xH2, xHp, rad, dt_s, params, prec=F64, out=None, stream=None):
+    """ism_chem_cool_step_noalloc: as chem_cool_step, the library allocating nothing (pass `out` to
+    allocate nothing here either)."""
+    return _step("ism_chem_cool_step_noalloc", n, T, xH2, xHp, rad, dt_s, params, prec,
+                 ("xCp", "xCO", "xe", "nsub", "status"), out, stream)
 
 
 def _step(symbol, n, T, xH2, xHp, rad, dt_s, params, prec, want, out, stream):
