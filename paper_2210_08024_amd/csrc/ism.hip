@@ -49,6 +49,7 @@ struct DevState {
   float *tab32 = nullptr;
   int num_cu = 0;
   int occ64 = 0, occ32 = 0;  // resident 256-thread blocks per CU of the persistent step kernels
+  int occ_col64 = 0, occ_col32 = 0;  // resident blocks per CU of the column tile kernels
   bool simple_step = false;   // ISM_STEP_KERNEL=simple selects the one-lane-per-cell grid
   uint8_t *noalloc = nullptr;  // this device's copy of `scratch` (hipGetSymbolAddress at init)
 };
@@ -204,14 +205,16 @@ ism_status launch_columns6(const DevState *st, const ism_grid *g, const ism_para
   t.B = t.F + 3 * t.g.per_q;
   const int64_t pairs = (int64_t)((t.g.ntx + 1) / 2) * t.g.nty * t.g.ntz;
   const int cu = std::max(st->num_cu, 1);
-  // one wave per block: the sums kernel holds no LDS, the tile kernel 36 KB (four blocks per CU)
+  // the sums kernel: one wave per block, no LDS; the tile kernel's grid is what stays resident
+  // (its LDS and registers set the count), each block taking an equal share of the tile pairs
+  const int occ = std::max(f32 ? st->occ_col32 : st->occ_col64, 1);
   const unsigned g1 = (unsigned)std::min<int64_t>(pairs, (int64_t)cu * 16);
-  const unsigned g3 = (unsigned)std::min<int64_t>(pairs, (int64_t)cu * 4);
+  const unsigned g3 = (unsigned)std::min<int64_t>(pairs, (int64_t)cu * occ);
   hipLaunchKernelGGL(columns_tilesum_kernel, dim3(g1), dim3(CT_LANES), 0, stream, t);
   const int64_t lines = 2 * (t.g.lx + t.g.ly + t.g.lz);
   hipLaunchKernelGGL(columns_offsets_kernel, dim3((unsigned)((lines + 255) / 256)), dim3(256), 0, stream, t);
-  if (f32) hipLaunchKernelGGL(columns_tile_kernel<float>, dim3(g3), dim3(CT_LANES), 0, stream, t);
-  else hipLaunchKernelGGL(columns_tile_kernel<double>, dim3(g3), dim3(CT_LANES), 0, stream, t);
+  if (f32) hipLaunchKernelGGL(columns_tile_kernel<float>, dim3(g3), dim3(CT_THREADS), 0, stream, t);
+  else hipLaunchKernelGGL(columns_tile_kernel<double>, dim3(g3), dim3(CT_THREADS), 0, stream, t);
   HIP_TRY(hipGetLastError());
   return ISM_OK;
 }
@@ -330,6 +333,10 @@ ism_status ism_init(int device, const char *path) {
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&st.occ64, step_queue_kernel<double>, 256, 0);
     if (e == hipSuccess)
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&st.occ32, step_queue_kernel<float>, 256, 0);
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&st.occ_col64, columns_tile_kernel<double>, CT_THREADS, 0);
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&st.occ_col32, columns_tile_kernel<float>, CT_THREADS, 0);
     // the allocation-free step's scratch: its address on this device (the device is current)
     if (e == hipSuccess && !st.noalloc) e = hipGetSymbolAddress((void **)&st.noalloc, HIP_SYMBOL(scratch));
     if (e == hipSuccess) {

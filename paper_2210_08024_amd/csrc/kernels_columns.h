@@ -112,8 +112,8 @@ __device__ __forceinline__ void cell_q(const ColArgs &a, int64_t idx, double &qH
 //  2. columns_offsets_kernel: per line of tiles (the tiles a full-length pencil crosses), the
 //     exclusive sums of the tiles before (forward) and after (backward) each tile, each summed
 //     in the direction a ray takes, so that a small column keeps its relative precision.
-//  3. columns_tile_kernel: one wave per tile stages the tile in LDS, then every lane takes one
-//     (x, y) position and walks z; per cell it forms the upstream columns of all six rays from
+//  3. columns_tile_kernel: four waves per tile stage it in LDS (each wave two z-planes, each
+//     lane one (x, y) position); per cell a lane forms the upstream columns of all six rays from
 //     the tile offsets plus the in-tile cells before (or after) it, adds the six terms and
 //     writes chi_PE, chi_LW, chi_H2, chi_C, N_eff and xi once.
 // The dust attenuation exp(-sigma N_in) of a ray is the offset's exp(-sigma F) times the
@@ -121,7 +121,8 @@ __device__ __forceinline__ void cell_q(const ColArgs &a, int64_t idx, double &qH
 // exponentials (its own factors) instead of two per ray; the cell average g(sigma qH) is the
 // same for all six rays and multiplies their sum.  Columns and these products stay double.
 constexpr int CT = 8;                       // tile edge
-constexpr int CT_LANES = 64;                // one wave per tile
+constexpr int CT_LANES = 64;                // tile sums: one wave per tile
+constexpr int CT_THREADS = 256;             // tile pass: four waves per tile, two z-planes each
 constexpr int CT_NS = CT * (CT + 1) * CT;   // LDS slots per field: x + 9 y + 72 z (bank spread)
 __device__ __forceinline__ int ct_slot(int x, int y, int z) { return x + (CT + 1) * y + CT * (CT + 1) * z; }
 
@@ -271,14 +272,16 @@ __device__ __forceinline__ void cell_atten(double y, double &e, double &gy) {
 }
 
 template <class R>
-__global__ __launch_bounds__(CT_LANES) void columns_tile_kernel(TileArgs t) {
+__global__ __launch_bounds__(CT_THREADS) void columns_tile_kernel(TileArgs t) {
   __shared__ double s_cs[CS_NX * CS_NY];
-  __shared__ double s_eP[CT_NS], s_eL[CT_NS], s_h2[CT_NS], s_c[CT_NS], s_qH[CT_NS];
-  __shared__ double s_xo[64][8], s_yo[64][8];  // x pencils (y, z) and y pencils (x, z): Pf Lf H2f Cf Pb Lb H2b Cb
+  __shared__ double s_eP[CT_NS], s_eL[CT_NS], s_h2[CT_NS], s_c[CT_NS];
+  // per axis and pencil of the tile: Pf Lf H2f Cf (forward ray at the tile's entry face) and
+  // Pb Lb H2b Cb (backward ray); pencils x: (y, z), y: (x, z), z: (x, y), index a + 8 b
+  __shared__ double s_off[3][64][8];
   const ColArgs &a = t.c;
   const TileGeo &g = t.g;
   for (int k = threadIdx.x; k < CS_NX * CS_NY; k += blockDim.x) s_cs[k] = a.tab[TAB_CS + k];
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int lx = lane & 7, ly = lane >> 3;
   const double fo = a.chi0 / 6.0;
   const int64_t nw = tile_pairs(g);
@@ -288,10 +291,10 @@ __global__ __launch_bounds__(CT_LANES) void columns_tile_kernel(TileArgs t) {
     const int gx = tx * CT + lx, gy = ty * CT + ly;
     const bool in_xy = gx < a.nx && gy < a.ny;
     __syncthreads();  // the previous tile's LDS reads are done
-    // stage the tile: per cell the two dust factors, half the own H2 and C columns, and qH
-#pragma unroll 1
-    for (int z = 0; z < CT; ++z) {
-      const int gz = tz * CT + z;
+    // stage the tile: wave wv takes the z-planes 2 wv and 2 wv + 1
+#pragma unroll
+    for (int zz = 0; zz < CT / 4; ++zz) {
+      const int z = (CT / 4) * wv + zz, gz = tz * CT + z;
       double qH = 0.0, qH2 = 0.0, qC = 0.0;
       if (in_xy && gz < a.nz) cell_q(a, ((int64_t)gz * a.ny + gy) * a.nx + gx, qH, qH2, qC);
       double eP, eL, gP, gL;
@@ -302,104 +305,85 @@ __global__ __launch_bounds__(CT_LANES) void columns_tile_kernel(TileArgs t) {
       s_eL[sl] = eL;
       s_h2[sl] = qH2;
       s_c[sl] = qC;
-      s_qH[sl] = qH;
     }
-    // offsets of the x pencils (y = lane & 7, z = lane >> 3) and y pencils (x = lane & 7,
-    // z = lane >> 3), dust columns turned into attenuation factors
-    {
-      const int py = lane & 7, pz = lane >> 3;
-      const int gyy = ty * CT + py, gzz = tz * CT + pz, gxx = tx * CT + py;
-      double v[2][8];
-      for (int ax = 0; ax < 2; ++ax) {
-        const bool ok = ax == 0 ? (gyy < a.ny && gzz < a.nz) : (gxx < a.nx && gzz < a.nz);
-        const int64_t l = ax == 0 ? (int64_t)gzz * a.ny + gyy : (int64_t)gzz * a.nx + gxx;
-        const int64_t ix = ok ? tile_ix(g, ax, ax == 0 ? tx : ty, l) : 0;
-        double f[3] = {0.0, 0.0, 0.0}, b[3] = {0.0, 0.0, 0.0};
-        if (ok)
-          for (int k = 0; k < 3; ++k) {
-            f[k] = t.F[k * g.per_q + ix];
-            b[k] = t.B[k * g.per_q + ix];
-          }
-        v[ax][0] = (double)Mx<R>::ex(-a.sPE * f[0]);
-        v[ax][1] = (double)Mx<R>::ex(-a.sLW * f[0]);
-        v[ax][2] = f[1];
-        v[ax][3] = f[2];
-        v[ax][4] = (double)Mx<R>::ex(-a.sPE * b[0]);
-        v[ax][5] = (double)Mx<R>::ex(-a.sLW * b[0]);
-        v[ax][6] = b[1];
-        v[ax][7] = b[2];
+    // the offsets of the tile's 3 x 64 pencils, dust columns turned into attenuation factors
+    if (tid < 3 * 64) {
+      const int ax = tid >> 6, p0 = lane & 7, p1 = lane >> 3;
+      bool ok;
+      int64_t l;
+      int tt;
+      if (ax == 0) {
+        const int gyy = ty * CT + p0, gzz = tz * CT + p1;
+        ok = gyy < a.ny && gzz < a.nz;
+        l = (int64_t)gzz * a.ny + gyy;
+        tt = tx;
+      } else if (ax == 1) {
+        const int gxx = tx * CT + p0, gzz = tz * CT + p1;
+        ok = gxx < a.nx && gzz < a.nz;
+        l = (int64_t)gzz * a.nx + gxx;
+        tt = ty;
+      } else {
+        const int gxx = tx * CT + p0, gyy = ty * CT + p1;
+        ok = gxx < a.nx && gyy < a.ny;
+        l = (int64_t)gyy * a.nx + gxx;
+        tt = tz;
       }
-      for (int k = 0; k < 8; ++k) {
-        s_xo[lane][k] = v[0][k];
-        s_yo[lane][k] = v[1][k];
+      double f[3] = {0.0, 0.0, 0.0}, b[3] = {0.0, 0.0, 0.0};
+      if (ok) {
+        const int64_t ix = tile_ix(g, ax, tt, l);
+        for (int k = 0; k < 3; ++k) {
+          f[k] = t.F[k * g.per_q + ix];
+          b[k] = t.B[k * g.per_q + ix];
+        }
       }
-    }
-    // this lane's z pencil (x = lx, y = ly)
-    RayIn zf{1.0, 1.0, 0.0, 0.0}, zb{1.0, 1.0, 0.0, 0.0};
-    if (in_xy) {
-      const int64_t ix = tile_ix(g, 2, tz, (int64_t)gy * a.nx + gx);
-      const double f0 = t.F[ix], f1 = t.F[g.per_q + ix], f2 = t.F[2 * g.per_q + ix];
-      const double b0 = t.B[ix], b1 = t.B[g.per_q + ix], b2 = t.B[2 * g.per_q + ix];
-      zf = RayIn{(double)Mx<R>::ex(-a.sPE * f0), (double)Mx<R>::ex(-a.sLW * f0), f1, f2};
-      zb = RayIn{(double)Mx<R>::ex(-a.sPE * b0), (double)Mx<R>::ex(-a.sLW * b0), b1, b2};
+      double *o = s_off[ax][lane];
+      o[0] = (double)Mx<R>::ex(-a.sPE * f[0]);
+      o[1] = (double)Mx<R>::ex(-a.sLW * f[0]);
+      o[2] = f[1];
+      o[3] = f[2];
+      o[4] = (double)Mx<R>::ex(-a.sPE * b[0]);
+      o[5] = (double)Mx<R>::ex(-a.sLW * b[0]);
+      o[6] = b[1];
+      o[7] = b[2];
     }
     __syncthreads();
-    RayIn zr = zf;
 #pragma unroll 1
-    for (int z = 0; z < CT; ++z) {
-      const int gz = tz * CT + z;
+    for (int zz = 0; zz < CT / 4; ++zz) {
+      const int z = (CT / 4) * wv + zz, gz = tz * CT + z;
       const int sl = ct_slot(lx, ly, z);
       const double hH2 = 0.5 * s_h2[sl], hC = 0.5 * s_c[sl];
       double acc[4] = {0.0, 0.0, 0.0, 0.0};
-      // +x then -x
-      {
-        const double *o = s_xo[z * 8 + ly];
-        RayIn f{o[0], o[1], o[2], o[3]}, b{o[4], o[5], o[6], o[7]};
+      // the six rays in the order +x, -x, +y, -y, +z, -z: the offset at the tile face times the
+      // factors of the tile's cells the ray crosses before this one
 #pragma unroll 1
-        for (int x = 0; x < CT; ++x) {
-          const int s2 = ct_slot(x, ly, z);
+      for (int d = 0; d < 6; ++d) {
+        const int ax = d >> 1;
+        const bool bwd = d & 1;
+        const int mine = ax == 0 ? lx : (ax == 1 ? ly : z);
+        const int pen = ax == 0 ? ly + 8 * z : (ax == 1 ? lx + 8 * z : lane);
+        const int stride = ax == 0 ? 1 : (ax == 1 ? CT + 1 : CT * (CT + 1));
+        const int base = ax == 0 ? ct_slot(0, ly, z) : (ax == 1 ? ct_slot(lx, 0, z) : ct_slot(lx, ly, 0));
+        const double *o = s_off[ax][pen] + (bwd ? 4 : 0);
+        RayIn r{o[0], o[1], o[2], o[3]};
+#pragma unroll
+        for (int k = 0; k < CT; ++k) {
+          const int s2 = base + k * stride;
           const double eP = s_eP[s2], eL = s_eL[s2], h = s_h2[s2], c = s_c[s2];
-          if (x < lx) { f.P *= eP; f.L *= eL; f.H2 += h; f.C += c; }
-          if (x > lx) { b.P *= eP; b.L *= eL; b.H2 += h; b.C += c; }
+          if (bwd ? k > mine : k < mine) {
+            r.P *= eP;
+            r.L *= eL;
+            r.H2 += h;
+            r.C += c;
+          }
         }
-        add_ray<R>(f, hH2, hC, s_cs, acc);
-        add_ray<R>(b, hH2, hC, s_cs, acc);
+        add_ray<R>(r, hH2, hC, s_cs, acc);
       }
-      // +y then -y
-      {
-        const double *o = s_yo[z * 8 + lx];
-        RayIn f{o[0], o[1], o[2], o[3]}, b{o[4], o[5], o[6], o[7]};
-#pragma unroll 1
-        for (int y = 0; y < CT; ++y) {
-          const int s2 = ct_slot(lx, y, z);
-          const double eP = s_eP[s2], eL = s_eL[s2], h = s_h2[s2], c = s_c[s2];
-          if (y < ly) { f.P *= eP; f.L *= eL; f.H2 += h; f.C += c; }
-          if (y > ly) { b.P *= eP; b.L *= eL; b.H2 += h; b.C += c; }
-        }
-        add_ray<R>(f, hH2, hC, s_cs, acc);
-        add_ray<R>(b, hH2, hC, s_cs, acc);
-      }
-      // +z (running product over the lane's own pencil) then -z
-      {
-        RayIn b = zb;
-#pragma unroll 1
-        for (int z2 = CT - 1; z2 > z; --z2) {
-          const int s2 = ct_slot(lx, ly, z2);
-          b.P *= s_eP[s2]; b.L *= s_eL[s2]; b.H2 += s_h2[s2]; b.C += s_c[s2];
-        }
-        add_ray<R>(zr, hH2, hC, s_cs, acc);
-        add_ray<R>(b, hH2, hC, s_cs, acc);
-      }
-      zr.P *= s_eP[sl];
-      zr.L *= s_eL[sl];
-      zr.H2 += s_h2[sl];
-      zr.C += s_c[sl];
       if (in_xy && gz < a.nz) {
-        const double qH = s_qH[sl];
+        const int64_t idx = ((int64_t)gz * a.ny + gy) * a.nx + gx;
+        const double qH = a.n[idx] * a.dx;  // staged above, so an L2 hit
         double e, gP, gL;
         cell_atten<R>(a.sPE * qH, e, gP);
         cell_atten<R>(a.sLW * qH, e, gL);
-        const int64_t idx = ((int64_t)gz * a.ny + gy) * a.nx + gx;
         const double cPE = fo * gP * acc[0];
         const double Neff = a.chi0 > 0.0 ? -Mx<double>::ln(cPE / a.chi0) / (g_coef64.sig_d_Neff * a.Zd) : 0.0;
         double xi = a.xi0;
