@@ -524,7 +524,7 @@ def bench_pts512(args):
     except Exception:
         ncores = os.cpu_count() or 1
     procs = max(1, min(16, ncores))
-    pool = mp.get_context("fork").Pool(procs)
+    pool = None if args.no_cpu else mp.get_context("fork").Pool(procs)
     import torch
     from paper_2210_08024_amd import ism, workloads, surrogate_train
     from oracle.census import substep_census
@@ -573,8 +573,9 @@ def bench_pts512(args):
     bufs = {torch.float64: buffers(torch.float64), torch.float32: buffers(torch.float32)}
 
     def one_step(path, evs=None):
-        """One step of a form; evs = three events recorded before the columns, between columns and
-        step, and after the step (on the launch stream; no synchronisation here)."""
+        """One step of a form; evs = four events recorded before the columns, after the columns,
+        after the point-source maps are added (before the step) and after the step (on the launch
+        stream; no synchronisation here)."""
         f64 = path == "f64"
         prec = ism.F64 if f64 else ism.MIXED
         rad, outs = bufs[torch.float64 if f64 else torch.float32]
@@ -586,33 +587,34 @@ def bench_pts512(args):
         if evs:
             evs[0].record(stream)
         ism.columns6(n.view(shape), xH2.view(shape), None, dx, par, prec, out={k: v.view(shape) for k, v in rad.items()})
+        if evs:
+            evs[1].record(stream)
         for k in ("chi_PE", "chi_LW", "chi_H2", "chi_C"):
             rad[k].add_(maps[k])
         r = dict(rad)
         r["phi"] = maps["phi"]
         if evs:
-            evs[1].record(stream)
+            evs[2].record(stream)
         if path == "surrogate":
             ism.chem_cool_step_surrogate(sur, n, T, xH2, xHp, r, dt, par, out=outs, n_fallback=nfb)
         else:
             ism.chem_cool_step(n, T, xH2, xHp, r, dt, par, prec, out=outs)
         if evs:
-            evs[2].record(stream)
+            evs[3].record(stream)
 
     def run_form(p, K, W):
         """W untimed steps, then K steps bracketed by synchronisations; per-step HIP events."""
         for _ in range(W):
             one_step(p)
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(K)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(K):
             one_step(p, evs[k])
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        tc = [e[0].elapsed_time(e[1]) * 1e-3 for e in evs]
-        ts = [e[1].elapsed_time(e[2]) * 1e-3 for e in evs]
-        return wall, float(np.median(tc)), float(np.median(ts))
+        med = lambda a, b: float(np.median([e[a].elapsed_time(e[b]) * 1e-3 for e in evs]))
+        return wall, med(0, 1), med(1, 2), med(2, 3)
 
     # the subsample: every s-th cell along each axis
     st = args.pts512_stride
@@ -623,7 +625,7 @@ def bench_pts512(args):
     order = [args.path] + [p for p in ("f64", "mixed", "surrogate") if p != args.path]
     paths, rad_sample, walls = {}, None, {}
     for p in order:
-        wall, tc, ts = run_form(p, args.steps, args.warmup)
+        wall, tc, tm, ts = run_form(p, args.steps, args.warmup)
         walls[p] = wall
         rad, outs = bufs[torch.float64 if p == "f64" else torch.float32]
         if p == "f64":
@@ -634,8 +636,9 @@ def bench_pts512(args):
         res.update({k: outs[k][tid].double().cpu().numpy() for k in ("xCp", "xCO", "xe")})
         nsub = outs["nsub"].to(torch.int64)
         q = torch.quantile(nsub[::64].double(), torch.tensor([0.5, 0.99], dtype=torch.float64, device=dev))
-        paths[p] = {"ms_per_step": wall / args.steps * 1e3, "columns_ms": tc * 1e3, "step_ms": ts * 1e3,
-                    "cell_updates_per_s": N / (wall / args.steps), "step_only_cell_updates_per_s": N / ts,
+        paths[p] = {"ms_per_step": wall / args.steps * 1e3, "columns_ms": tc * 1e3, "maps_add_ms": tm * 1e3,
+                    "step_ms": ts * 1e3, "cell_updates_per_s": N / (wall / args.steps),
+                    "step_only_cell_updates_per_s": N / ts,
                     "nsub_mean": float(nsub.double().mean()), "nsub_p50": float(q[0]), "nsub_p99": float(q[1]),
                     "nsub_max": int(nsub.max()), "substeps": int(nsub.sum()),
                     "status_nonzero": int(((outs["status"] & 0xEF) != 0).sum()), "_res": res}
@@ -665,24 +668,26 @@ def bench_pts512(args):
 
     # the FP64 oracle on the subsample, fed the GPU's FP64 radiation there (worker pool): the error
     # report, and the parallel leg of the CPU baseline's step
-    sel = lambda a: np.ascontiguousarray(a.ravel()[idx])
-    st0 = {k: sel(s[k]) for k in ("n", "T", "xH2", "xHp")}
-    chunk = 4096
-    jobs = [tuple(st0[k][a:a + chunk] for k in ("n", "T", "xH2", "xHp")) +
-            ({k: v[a:a + chunk] for k, v in rad_sample.items()}, dt, par_o) for a in range(0, len(idx), chunk)]
-    t0 = time.perf_counter()
-    parts = pool.map(_oracle_chunk, jobs)
-    t_or_par = time.perf_counter() - t0
-    ref = {k: np.concatenate([q[k] for q in parts]) for k in FIELDS}
-    xCt = par_o.xCtot
-    ar = np.arange(len(idx))
-    for p in paths:
-        paths[p]["error_vs_oracle"] = field_errors(paths[p].pop("_res"), ref, ar, xCt)
     cpu = None
     if not args.no_cpu:
+        sel = lambda a: np.ascontiguousarray(a.ravel()[idx])
+        st0 = {k: sel(s[k]) for k in ("n", "T", "xH2", "xHp")}
+        chunk = 4096
+        jobs = [tuple(st0[k][a:a + chunk] for k in ("n", "T", "xH2", "xHp")) +
+                ({k: v[a:a + chunk] for k, v in rad_sample.items()}, dt, par_o) for a in range(0, len(idx), chunk)]
+        t0 = time.perf_counter()
+        parts = pool.map(_oracle_chunk, jobs)
+        t_or_par = time.perf_counter() - t0
+        ref = {k: np.concatenate([q[k] for q in parts]) for k in FIELDS}
+        xCt = par_o.xCtot
+        ar = np.arange(len(idx))
+        for p in paths:
+            paths[p]["error_vs_oracle"] = field_errors(paths[p]["_res"], ref, ar, xCt)
         cpu = cpu_baseline_pts512(pool, procs, s, dx, par_o, st0, rad_sample, dt, t_or_par, len(idx))
-    pool.close()
-    pool.join()
+        pool.close()
+        pool.join()
+    for p in paths:
+        paths[p].pop("_res")
 
     arith, trans = substep_census(par_o)
     vp = paths[args.path]
@@ -793,15 +798,10 @@ def issue_roofline(kernel, t_launch, workload="grf128"):
 
 def columns_traffic(path, workload):
     """HBM bytes of one columns6 call (all its kernels) from the committed counters, or None."""
-    names = ("columns_x_kernel", "columns_segsum_kernel", "columns_march_kernel")
-    tot, found = 0.0, False
-    suffix = "<double>" if path == "f64" else "<float>"
-    for k in names:
-        c = measured_counters(k + suffix, workload) or measured_counters(k, workload)
-        if c is not None:
-            tot += c["bytes"]
-            found = True
-    return tot if found else None
+    names = ("columns_tilesum_kernel", "columns_offsets_kernel",
+             "columns_tile_kernel<double>" if path == "f64" else "columns_tile_kernel<float>")
+    cs = [measured_counters(k, workload) for k in names]
+    return None if any(c is None for c in cs) else sum(c["bytes"] for c in cs)
 
 
 def main():
