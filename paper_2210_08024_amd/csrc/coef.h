@@ -68,6 +68,7 @@ template <class R>
 struct ParT {
   R Zg, Zd, chi0, dvdr, eps_sub, fd_rel, T_floor, T_bb, tau_ratio;
   R xCt, xOt, muH, lnZd, idvdr;  // idvdr = 1 / dvdr
+  R fd_ln, fd_inv, fd_sqrt;       // ln, reciprocal and square root of 1 + fd_rel
   int32_t kgr_const, h2_rovib, max_sub, cr_mode;
 };
 

@@ -124,6 +124,10 @@ ParT<R> make_par(const ism_params *p, const CoefT<double> &c) {
   q.muH = (R)(c.muH0 - c.muH_slope * (p->Zg - 1.0));
   q.lnZd = (R)std::log(p->Zd);
   q.idvdr = (R)(1.0 / p->dvdr_kms_pc);
+  const double fd1 = 1.0 + p->fd_rel;
+  q.fd_ln = (R)std::log(fd1);
+  q.fd_inv = (R)(1.0 / fd1);
+  q.fd_sqrt = (R)std::sqrt(fd1);
   q.kgr_const = p->kgr_const; q.h2_rovib = p->h2_rovib; q.max_sub = p->max_substeps; q.cr_mode = p->cr_mode;
   return q;
 }

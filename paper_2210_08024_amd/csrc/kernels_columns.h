@@ -385,7 +385,8 @@ __global__ __launch_bounds__(CT_THREADS) void columns_tile_kernel(TileArgs t) {
         cell_atten<R>(a.sPE * qH, e, gP);
         cell_atten<R>(a.sLW * qH, e, gL);
         const double cPE = fo * gP * acc[0];
-        const double Neff = a.chi0 > 0.0 ? -Mx<double>::ln(cPE / a.chi0) / (g_coef64.sig_d_Neff * a.Zd) : 0.0;
+        // (chi_PE can underflow to 0 in a thick enough cloud: the log with its special cases)
+        const double Neff = a.chi0 > 0.0 ? -flog(cPE / a.chi0) / (g_coef64.sig_d_Neff * a.Zd) : 0.0;
         double xi = a.xi0;
         if (a.cr_mode == 1) {
           const double N0 = g_coef64.N0_cr;

@@ -58,7 +58,7 @@ struct CellState {
   double nd, K, Tmu, xH2, xHp, t;
   Rad<R> r;
   EqS<R> e;
-  double tdg;
+  double tdi, tds;  // the last dust temperature as a line in T: T_d ~ tdi + tds T
   int32_t ns;
   uint32_t st;
 };
@@ -85,7 +85,8 @@ __device__ __forceinline__ void cell_begin(const StepArgs<R> &a, int64_t i, Cell
   s.t = 0.0;
   s.ns = 0;
   s.st = 0;
-  s.tdg = 0.0;
+  s.tdi = 0.0;  // no dust temperature yet: the first solve starts cold
+  s.tds = 0.0;
 }
 
 // One substep of Sec. 6.1 for the lane's cell; returns true when the cell is finished.
@@ -96,18 +97,23 @@ __device__ __forceinline__ bool cell_substep(const StepArgs<R> &a, CellState<R> 
   const double muH = a.pd.muH, eps = a.pd.eps_sub, delta = a.pd.fd_rel, dt = a.dt;
   const double mu_den = 1.1 + (double)s.e.xe - s.xH2;
   const double Ta = muH * s.Tmu / mu_den;
-  // H at T and at T (1 + fd_rel): one instance of the evaluation, run twice
+  // H at T and at T (1 + fd_rel): one instance of the evaluation, run twice.  Each dust
+  // temperature solve starts from the last one carried along its slope.
+  Tq qk = make_tq<R>(Ta);
+  const PreLogs pre = pre_logs<R>(R(s.nd), s.e, p);
   Eval<R> v;
   double H2 = 0.0;
   bool td_bad = false;
 #pragma unroll 1
   for (int k = 0; k < 2; ++k) {
-    const Eval<R> w = evaluate<R, false, false>(k == 0 ? Ta : Ta * (1.0 + delta), s.nd, s.xH2, s.xHp, s.e, s.r, c,
-                                                p, tab, s.tdg, nullptr, k == 0);
+    const Eval<R> w = evaluate<R, false, false>(qk, s.nd, s.xH2, s.xHp, s.e, s.r, c, p, tab,
+                                                s.tdi + s.tds * qk.T, nullptr, k == 0, &pre);
     td_bad = td_bad || w.td_bad;
     if (k == 0) {
       v = w;
-      s.tdg = w.Td;
+      s.tds = w.Tds;
+      s.tdi = w.Td - w.Tds * Ta;
+      qk = shift_tq<R>(qk, a.pd);
     } else {
       H2 = w.H;
     }
@@ -129,13 +135,14 @@ __device__ __forceinline__ bool cell_substep(const StepArgs<R> &a, CellState<R> 
   if (Tmu_new < Tmu_min) { Tmu_new = Tmu_min; s.st |= ISM_ST_T_FLOOR; }
   // abundances: rate coefficients at T^{n+1} = mu^n T_mu^{n+1}, abundance factors frozen at step n
   const double Tp = muH * Tmu_new / mu_den;
-  Eval<R> vc = evaluate<R, true, false>(Tp, s.nd, s.xH2, s.xHp, s.e, s.r, c, p, tab, s.tdg, nullptr);
+  const Tq qp = make_tq<R>(Tp);  // shared by the rates and the closure at T^{n+1}
+  Eval<R> vc = evaluate<R, true, false>(qp, s.nd, s.xH2, s.xHp, s.e, s.r, c, p, tab, 0.0, nullptr);
   const double F = vc.F, D = vc.D, I = vc.I, Rr = vc.Rr;
   const double det = 1.0 + dts * (2.0 * F + D + I + Rr) + dts * dts * (2.0 * F * Rr + D * I + D * Rr);
   const double idet = 1.0 / det;
   const double xa = (s.xH2 * (1.0 + dts * (I + Rr)) + F * dts * (1.0 - s.xHp) + F * dts * dts * Rr) * idet;
   const double xb = (s.xHp * (1.0 + dts * (2.0 * F + D)) + I * dts * (1.0 - 2.0 * s.xH2) + I * dts * dts * D) * idet;
-  s.e = eq_species<R>(Tp, R(s.nd), xa, xb, s.r, c, p, tab, CloseTol<R>::v, 50);
+  s.e = eq_species<R>(qp, R(s.nd), xa, xb, s.r, c, p, tab, CloseTol<R>::v, 50);
   const bool fin = isfinite(Tmu_new) && isfinite(xa) && isfinite(xb);
   if (!fin) s.st |= ISM_ST_NONFINITE;
   const bool last = (dts == rem);

@@ -238,7 +238,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
         cs.t = 0.0;
         cs.ns = 0;
         cs.st = 0;
-        cs.tdg = tdg;
+        cs.tdi = tdg;  // a flat line through the dust temperature found at the root
+        cs.tds = 0.0;
         cell_substep(sa, cs, s_tab);
         const double o[3] = {muH * cs.Tmu / (1.1 + (double)cs.e.xe - cs.xH2), cs.xH2, cs.xHp};
         if (v < 0) {

@@ -34,19 +34,23 @@ template <class R> struct Mx;
 
 template <> struct Mx<double> {
   static __device__ __forceinline__ double ex(double x) { return fexp(x); }
-  static __device__ __forceinline__ double ln(double x) { return flog(x); }
+  // every log the step takes is of a positive finite number (T, psi >= 50, 1 + c T, guarded
+  // columns and densities, n, a floored xi)
+  static __device__ __forceinline__ double ln(double x) { return flogp(x); }
   static __device__ __forceinline__ double sq(double x) { return ::sqrt(x); }
   static __device__ __forceinline__ double cb(double x) { return ::cbrt(x); }
 };
 
 template <> struct Mx<float> {
-  // exp of a double exponent: x log2(e) = k + f, |f| <= 1/2, result 2^f (hardware) scaled by 2^k.
+  // exp of a double exponent: x log2(e) = k + f, |f| <= 1/2, result 2^f (hardware) scaled by 2^k;
+  // x clamped to +-200 ln 2 (beyond float range either way), k by the 1.5 2^52 shift (the
+  // integer is the low word of kd), f = x log2(e) - k with one rounding.
   static __device__ __forceinline__ float ex(double x) {
-    double y = x * LOG2E;
-    y = y < -200.0 ? -200.0 : (y > 200.0 ? 200.0 : y);
-    const double k = ::rint(y);
-    const float r = __builtin_amdgcn_exp2f((float)(y - k));
-    return ::ldexpf(r, (int)k);
+    x = __builtin_fmin(__builtin_fmax(x, -200.0 * LN2), 200.0 * LN2);
+    const double kd = fma(x, LOG2E, 0x1.8p52);
+    const double k = kd - 0x1.8p52;
+    const float r = __builtin_amdgcn_exp2f((float)fma(x, LOG2E, -k));
+    return ::ldexpf(r, (int)(uint32_t)__builtin_bit_cast(uint64_t, kd));
   }
   // natural log as a double: exponent from frexp, mantissa in [0.5, 1) through the hardware log2.
   static __device__ __forceinline__ double ln(double x) {
@@ -74,6 +78,15 @@ __device__ __forceinline__ const A &kernel_args() {
 }
 
 // ---------------------------------------------------------------- tables
+// a / b at a site whose denominator is a positive number in [2^-1000, 2^1000] (a sum with a
+// positive floor, a temperature, a density): in double the reciprocal-based division, in float
+// the plain one.
+template <class R>
+__device__ __forceinline__ R dvp(R a, R b) {
+  if constexpr (std::is_same<R, double>::value) return fdivp(a, b);
+  else return a / b;
+}
+
 // Clamp x to the grid [x0, x0 + (n-1) dx]; lower node index and fraction (in double).
 // idx = 1 / dx.
 __device__ __forceinline__ void axis_pos(double x, double x0, double dx, double idx, int n, int &i, double &f) {
@@ -126,17 +139,19 @@ struct EqS {
   R xCp, xCO, xC, xOp, xO, xe;
 };
 
-// Everything the update needs from one evaluation; Gamma/Lambda/H in double.
+// Everything the update needs from one evaluation; Gamma/Lambda/H in double.  Tds is dT_d/dT
+// at the dust temperature found (0 where none was), for the next solve's starting point.
 template <class R>
 struct Eval {
   R F, D, I, Rr;
-  double CH2, CHp, Td, Gamma, Lambda, H;
+  double CH2, CHp, Td, Tds, Gamma, Lambda, H;
   bool td_bad;
 };
 
-// Temperature-derived quantities shared by every term of one evaluation.
+// Temperature-derived quantities shared by every term of one evaluation (sqrtT serves the
+// double terms; the float path takes its own root of T).
 struct Tq {
-  double T, lnT, invT, lnT4;
+  double T, lnT, invT, lnT4, sqrtT;
 };
 
 // ln T in double on both paths: it feeds polynomial fits in log T whose terms cancel (the
@@ -145,10 +160,25 @@ template <class R>
 __device__ __forceinline__ Tq make_tq(double T) {
   Tq q;
   q.T = T;
-  q.lnT = flog(T);
-  q.invT = 1.0 / T;
+  q.lnT = flogp(T);
+  q.invT = fdivp(1.0, T);
   q.lnT4 = q.lnT - LN1E4;
+  q.sqrtT = Mx<double>::sq(T);
   return q;
+}
+
+// The same quantities at T (1 + fd_rel), the second point of the finite-difference derivative
+// of Sec. 6.1: ln, reciprocal and root of T there follow from those at T and the host's values
+// for 1 + fd_rel (one rounding each, against a log, a division and a root).
+template <class R>
+__device__ __forceinline__ Tq shift_tq(const Tq &q, const ParT<double> &pd) {
+  Tq s;
+  s.T = q.T * (1.0 + pd.fd_rel);
+  s.lnT = q.lnT + pd.fd_ln;
+  s.invT = q.invT * pd.fd_inv;
+  s.lnT4 = s.lnT - LN1E4;
+  s.sqrtT = q.sqrtT * pd.fd_sqrt;
+  return s;
 }
 
 // ---------------------------------------------------------------- rate coefficients (Sec. 3)
@@ -159,8 +189,8 @@ __device__ __forceinline__ R k_gr(const Tq &q, R sqrtT, const CoefT<R> &c, const
   // (T / 100)^1/2: from sqrt T in double; in float its own root (a float product there moved the
   // mixed path's most sensitive cells past their tolerance)
   const R s = std::is_same<R, double>::value ? sqrtT * R(0.1) : Mx<R>::sq(T2);
-  return c.kgr0 * p.Zd * c.kgr_shape[0] * s /
-         (R(1) + c.kgr_shape[1] * s + c.kgr_shape[2] * T2 + c.kgr_shape[3] * T2 * T2);
+  return dvp<R>(c.kgr0 * p.Zd * c.kgr_shape[0] * s,
+                R(1) + c.kgr_shape[1] * s + c.kgr_shape[2] * T2 + c.kgr_shape[3] * T2 * T2);
 }
 
 // Grain-assisted recombination 1e-14 C0 Z'_d / (1 + C1 psi^C2 (1 + C3 T^C4 psi^(-C5 - C6 ln T))).
@@ -168,7 +198,7 @@ template <class R>
 __device__ __forceinline__ R alpha_gr(const Tq &q, double lnpsi, const double *k, R Zd) {
   const R a = Mx<R>::ex(k[2] * lnpsi);
   const R b = Mx<R>::ex(k[4] * q.lnT + (-k[5] - k[6] * q.lnT) * lnpsi);
-  return R(1e-14 * k[0]) * Zd / (R(1) + R(k[1]) * a * (R(1) + R(k[3]) * b));
+  return dvp<R>(R(1e-14 * k[0]) * Zd, R(1) + R(k[1]) * a * (R(1) + R(k[3]) * b));
 }
 
 // FUV field G0 of a cell from its attenuation factors (Sec. 4.2).
@@ -180,7 +210,7 @@ __device__ __forceinline__ R g0_field(R chiPE, R chiLW, const CoefT<R> &c) {
 // Grain charging parameter G0 T^1/2 / n_e + 50 (Sec. 4.2), n_e floored at 1e-20 n.
 template <class R>
 __device__ __forceinline__ R psi_charge(R sqrtT, R n, R xe, R G0, const CoefT<R> &c) {
-  return G0 * sqrtT / (n * rmax(xe, R(1e-20))) + c.psi_off;
+  return dvp<R>(G0 * sqrtT, n * rmax(xe, R(1e-20))) + c.psi_off;
 }
 
 // ---------------------------------------------------------------- C / O / e closure
@@ -188,13 +218,13 @@ __device__ __forceinline__ R psi_charge(R sqrtT, R n, R xe, R G0, const CoefT<R>
 // (positive root of the quadratic, psi iterated to a fixed point in x_e) below 2e4 K,
 // Eq. e:xELhot above; CO from Eqs. e:CO, e:CO_fit with chi_CO = chi_LW.
 template <class R>
-__device__ EqS<R> eq_species(double T, R n, double xH2_d, double xHp_d, const Rad<R> &r, const CoefT<R> &c,
+__device__ EqS<R> eq_species(const Tq &q, R n, double xH2_d, double xHp_d, const Rad<R> &r, const CoefT<R> &c,
                              const ParT<R> &p, const R *tab, R tol, int maxit) {
   const CoefT<double> &cd = coef64();
   EqS<R> e;
-  const Tq q = make_tq<R>(T);
+  const double T = q.T;
   const R xH2 = R(xH2_d), xHp = R(xHp_d);
-  const R sqrtT = Mx<R>::sq(R(T));
+  const R sqrtT = std::is_same<R, double>::value ? R(q.sqrtT) : Mx<R>::sq(R(T));
   const R xCt = p.xCt, xOt = p.xOt, Zd = p.Zd;
   e.xOp = xOt * xHp;
   const R a = c.zeta_pi_C * r.chiC + c.zeta_pi_C_cr * R(2) * xH2 * r.xi + c.zeta_cr_C * r.xi;
@@ -217,7 +247,7 @@ __device__ EqS<R> eq_species(double T, R n, double xH2_d, double xHp_d, const Ra
     comp = a > R(0) ? (B + cc * xe) / (dh > R(0) ? dh : R(1)) : R(1);
   } else {
     const R amh = R(cd.x_MH[1]) * Mx<R>::ex(cd.x_MH[3] * (q.lnT - cd.ln_xMH_T0));
-    const R xmh = R(2) * xH2 * Mx<R>::sq(c.x_MH[0] * r.xi / (amh * n));
+    const R xmh = R(2) * xH2 * Mx<R>::sq(dvp<R>(c.x_MH[0] * r.xi, amh * n));
     const R xe0 = xHp + e.xOp + xmh;
     xe = xe0 + xCt;
     y = R(0);
@@ -227,6 +257,7 @@ __device__ EqS<R> eq_species(double T, R n, double xH2_d, double xHp_d, const Ra
       B = alpha_gr<R>(q, Mx<R>::ln((double)psi), cd.agr_Cp, Zd) * n + kch;
       const R pp = a + B + cc * xe0;
       const R den = pp + Mx<R>::sq(pp * pp + R(4) * cc * xCt * a);
+      // (a can be as small as the shielded photoionisation rate alone: the plain division)
       y = a > R(0) ? R(2) * xCt * a / (den > R(0) ? den : R(1)) : R(0);
       const R xn = xe0 + y;
       const bool conv = fabs(xn - xe) <= tol * xn;
@@ -242,8 +273,11 @@ __device__ EqS<R> eq_species(double T, R n, double xH2_d, double xHp_d, const Ra
   e.xe = xe;
   if (std::is_same<R, double>::value) {
     // FP64: 1 - max(x_C+ / x_C,tot, x_H+) as a true quotient and difference (Eq. e:CO as written)
+    // (1 - frac) cancels as the carbon ionises fully: the correctly rounded quotient
     const R fr = rmax(y / xCt, xHp);
     const R frac = fr < R(1) ? fr : R(1);
+    // (ncrit / n)^2 overflows to inf where the CO fit's critical density is huge (no cosmic
+    // rays): the plain division then gives 0
     e.xCO = xCt * R(2) * xH2 * (R(1) - frac) / (R(1) + r.qn2);
     e.xC = xCt - y - e.xCO;
   } else {
@@ -259,11 +293,20 @@ __device__ EqS<R> eq_species(double T, R n, double xH2_d, double xHp_d, const Ra
   return e;
 }
 
+template <class R>
+__device__ __forceinline__ EqS<R> eq_species(double T, R n, double xH2_d, double xHp_d, const Rad<R> &r,
+                                             const CoefT<R> &c, const ParT<R> &p, const R *tab, R tol, int maxit) {
+  return eq_species<R>(make_tq<R>(T), n, xH2_d, xHp_d, r, c, p, tab, tol, maxit);
+}
+
 // ---------------------------------------------------------------- dust temperature
 // Eq. eq:dust_en with sigma_IR(T_d) = 2e-25 Z'_d (T_d/10)^2 and Eq. eq:gas-dust, divided by
 // Z'_d:  A T_d^2 (T_d^4 - T_bb^4) + B T_d - (G + B T) = 0, increasing in T_d above T_bb.
 // Newton from `guess`, kept inside the bracket [min(T_bb, T), 1e4] and bisecting when a
-// Newton step leaves it.
+// Newton step leaves it.  A step is the last one when the error it leaves, |g''| step^2 /
+// (2 |g'|), is below 1e-16 T_d.  slope returns dT_d/dT at the root, -(dg/dT) / g' with
+// dg/dT = B (T_d / (2 T) - 3/2) (B goes as T^1/2), through the hardware reciprocal: it only
+// places the next solve's starting point.
 template <class R>
 __device__ __forceinline__ R dust_heating_per_Zd(const Rad<R> &r, const CoefT<R> &c, const ParT<R> &p) {
   const R fourpi = R(12.566370614359172954);
@@ -306,13 +349,14 @@ template <> struct RootTol<double> { static constexpr double v = 1e-14; static c
 template <> struct RootTol<float> { static constexpr float v = 2e-7f; static constexpr int it = 40; };
 
 template <class R>
-__device__ R dust_T(R T, R sqrtT, R n, R G, R guess, R Tbb, const CoefT<R> &c, bool &bad) {
+__device__ R dust_T(R T, R sqrtT, R n, R G, R guess, R Tbb, const CoefT<R> &c, bool &bad, R &slope) {
   const R A = c.dust_A;  // sigma_IR(10 K)/100 c a_rad
   const R B = n * c.alpha_gd * sqrtT;
   const R Tbb2 = Tbb * Tbb, Tbb4 = Tbb2 * Tbb2;
   const R rhs = G + B * T;
   R lo = rmin(Tbb, T), hi = R(1e4);
   const R h2 = hi * hi;
+  slope = R(0);
   if (A * h2 * (h2 * h2 - Tbb4) + B * hi - rhs < R(0)) { bad = true; return hi; }
   bad = false;
   R x = guess;
@@ -326,17 +370,20 @@ __device__ R dust_T(R T, R sqrtT, R n, R G, R guess, R Tbb, const CoefT<R> &c, b
     if (B > R(0)) x = rmin(x, rhs / B);
     if (!(x > lo && x < hi)) x = R(0.5) * (lo + hi);
   }
+  R dg = R(1);
   for (int it = 0; it < RootTol<R>::it; ++it) {
     const R x2 = x * x;
-    const R g = A * x2 * (x2 * x2 - Tbb4) + B * x - rhs;
+    const R x4 = x2 * x2;
+    const R g = A * x2 * (x4 - Tbb4) + B * x - rhs;
     if (g >= R(0)) hi = x; else lo = x;
-    const R dg = A * (R(6) * x2 * x2 * x - R(2) * Tbb4 * x) + B;
+    dg = A * (R(6) * x4 * x - R(2) * Tbb4 * x) + B;
     const R step = g / dg;
     R xn = x - step;
     // converged: tested before the bracket safeguard, which would otherwise take a root hit
     // exactly (g = 0 makes x the new upper end, so the step lands on it) for a Newton step
     // leaving the bracket and fall back to bisection
-    if (fabs(step) <= RootTol<R>::v * x) {
+    const R g2 = A * (R(30) * x4 - R(2) * Tbb4);
+    if (fabs(step) <= RootTol<R>::v * x || fabs(g2) * step * step <= R(2e-16) * x * fabs(dg)) {
       x = xn;
       break;
     }
@@ -345,6 +392,7 @@ __device__ R dust_T(R T, R sqrtT, R n, R G, R guess, R Tbb, const CoefT<R> &c, b
     x = xn;
     if (dx <= RootTol<R>::v * x || hi - lo <= RootTol<R>::v * x) break;
   }
+  slope = B * (R(1.5) - R(0.5) * x * __builtin_amdgcn_rcp(T)) * __builtin_amdgcn_rcp(dg);
   return x;
 }
 
@@ -368,15 +416,15 @@ __device__ __forceinline__ R three_level_cool(const Tq &q, R n, R inv_n, R xH, R
   const R R02 = C20 * R(rat[1]) * R(b2);
   // in double the 1-2 Boltzmann factor is the quotient of the other two, a division in place of an
   // exp
-  // (below ~0.3 K b1 underflows for O I: then the factor is formed on its own)
-  const R b12 = (std::is_same<R, double>::value && b1 > 0.0) ? R(b2 / b1) : Mx<R>::ex(-(E2 - E1) * q.invT);
+  // (below ~0.3 K b1 leaves the normal range for O I: then the factor is formed on its own)
+  const R b12 = (std::is_same<R, double>::value && b1 > 1e-300) ? R(fdivp(b2, b1)) : Mx<R>::ex(-(E2 - E1) * q.invT);
   const R R12 = C21 * R(rat[2]) * b12;
   const R R10 = C10 + A10, R20 = C20 + A20, R21 = C21 + A21;
   const R det = R10 * R20 + R10 * R21 + R12 * R20;
-  const R idet = R(1) / det;
+  const R idet = dvp<R>(R(1), det);
   R p1 = (R01 * (R20 + R21) + R21 * R02) * idet;
   R p2 = (R02 * (R10 + R12) + R12 * R01) * idet;
-  const R isum = R(1) / (R(1) + p1 + p2);
+  const R isum = dvp<R>(R(1), R(1) + p1 + p2);
   p1 *= isum;
   p2 *= isum;
   return (p1 * A10 * R(E1) + p2 * (A20 * R(E2) + A21 * R(E2 - E1))) * R(K_B) * inv_n;
@@ -394,15 +442,31 @@ enum Diag {
 // Rates (Sec. 3), heating (Secs. 4.1-4.5), cooling (Sec. 4.6) at temperature T with the
 // abundances (xH2, xHp) and closure e.  CHEM_ONLY skips heating/cooling; DIAG writes
 // every term into diag[NDIAG].
+// The logs in the cooling terms that do not depend on T: log10 of the CO column n x_CO dr/dv and
+// ln(n_e / 100), the same in every evaluation of a substep.
+struct PreLogs {
+  double lNt, lne2;
+};
+
+template <class R>
+__device__ __forceinline__ PreLogs pre_logs(R n, const EqS<R> &e, const ParT<R> &p) {
+  PreLogs g;
+  const R Nt = n * e.xCO * R(PC_CM) * p.idvdr;
+  g.lNt = Nt > R(0) ? Mx<R>::ln((double)Nt) * INV_LN10D : -300.0;
+  const R ne2 = n * e.xe * R(0.01);
+  g.lne2 = ne2 > R(0) ? Mx<R>::ln((double)ne2) : 0.0;
+  return g;
+}
+
 template <class R, bool CHEM_ONLY, bool DIAG>
-__device__ Eval<R> evaluate(double T, double n_d, double xH2_d, double xHp_d, const EqS<R> &e, const Rad<R> &r,
+__device__ Eval<R> evaluate(const Tq &q, double n_d, double xH2_d, double xHp_d, const EqS<R> &e, const Rad<R> &r,
                             const CoefT<R> &c, const ParT<R> &p, const R *tab, double td_guess, R *diag,
-                            bool chem = true) {
+                            bool chem = true, const PreLogs *pre = nullptr) {
   const CoefT<double> &cd = coef64();
   Eval<R> v;
-  const Tq q = make_tq<R>(T);
+  const double T = q.T;
   const R Tr = R(T);
-  const R sqrtT = Mx<R>::sq(Tr);
+  const R sqrtT = std::is_same<R, double>::value ? R(q.sqrtT) : Mx<R>::sq(Tr);
   const R n = R(n_d);
   const R Zd = p.Zd, Zg = p.Zg;
   const R xe = e.xe;
@@ -424,8 +488,8 @@ __device__ Eval<R> evaluate(double T, double n_d, double xH2_d, double xHp_d, co
   const R kcdH2 = c.k_cd_H2[0] * Mx<R>::ex(cd.k_cd_H2[1] * q.lnT - cd.k_cd_H2[3] * Mx<R>::ln(1.0 + cd.k_cd_H2[2] * T) -
                                            cd.k_cd_H2[4] * q.invT);
   const R zcd = n * (xH * kcdH + xH2 * kcdH2);
-  const R kci = c.k_ci_H[0] * sqrtT * Mx<R>::ex(-cd.k_ci_H[1] * q.invT) /
-                (R(1) + (std::is_same<R, double>::value ? sqrtT * R(cd.rsqrt_kci_T) : Mx<R>::sq(R(T * cd.inv_kci_T))));
+  const R kci = dvp<R>(c.k_ci_H[0] * sqrtT * Mx<R>::ex(-cd.k_ci_H[1] * q.invT),
+                       R(1) + (std::is_same<R, double>::value ? sqrtT * R(cd.rsqrt_kci_T) : Mx<R>::sq(R(T * cd.inv_kci_T))));
   const R zci = kci * n * xe;
   const R aB = c.alpha_B[0] * Mx<R>::ex((cd.alpha_B[1] + cd.alpha_B[2] * q.lnT4) * q.lnT4);
   // H+ grain recombination enters only the rates; skipped (chem = false) where a caller takes
@@ -440,6 +504,7 @@ __device__ Eval<R> evaluate(double T, double n_d, double xH2_d, double xHp_d, co
   v.CH2 = (double)v.F * (xHd > 0.0 ? xHd : 0.0) - (double)v.D * xH2_d;
   v.CHp = (double)v.I * (xHd > 0.0 ? xHd : 0.0) - (double)v.Rr * xHp_d;
   v.Td = 0.0;
+  v.Tds = 0.0;
   v.td_bad = false;
   v.Gamma = v.Lambda = v.H = 0.0;
   if (DIAG) {
@@ -450,27 +515,27 @@ __device__ Eval<R> evaluate(double T, double n_d, double xH2_d, double xHp_d, co
   }
   if (CHEM_ONLY) return v;
   const R ev = R(EV);
-  const R inv_n = R(1) / n;
+  const R inv_n = dvp<R>(R(1), n);
   // heating, Secs. 4.1-4.5
   const R G0 = r.G0f;
-  const R eps = (c.pe_C[0] + c.pe_C[1] * Mx<R>::ex(cd.pe_C[4] * q.lnT)) /
-                (R(1) + c.pe_C[2] * Mx<R>::ex(cd.pe_C[5] * lnpsi) * (R(1) + c.pe_C[3] * Mx<R>::ex(cd.pe_C[6] * lnpsi)));
+  const R eps = dvp<R>(c.pe_C[0] + c.pe_C[1] * Mx<R>::ex(cd.pe_C[4] * q.lnT),
+                       R(1) + c.pe_C[2] * Mx<R>::ex(cd.pe_C[5] * lnpsi) * (R(1) + c.pe_C[3] * Mx<R>::ex(cd.pe_C[6] * lnpsi)));
   const R g_pe = c.pe_pref * G0 * eps * Zd;
-  const R qH = (c.q_cr_H[0] + c.q_cr_H[1] * Mx<R>::sq(xe / (xe + c.q_cr_H[2]))) * ev;
+  const R qH = (c.q_cr_H[0] + c.q_cr_H[1] * Mx<R>::sq(dvp<R>(xe, xe + c.q_cr_H[2]))) * ev;
   const R qH2 = r.qH2;
   const R g_cr = r.xi * (xH * qH + R(2) * xH2 * qH2);
   const R g_pi = xH * (c.q_pi_H_eV * ev) * zpiH + xH2 * (c.q_pi_H2_eV * ev) * zpiH2;
   const R kHH = c.k_H2_H[0] * sqrtT * Mx<R>::ex(-cd.k_H2_H[1] * q.invT);
-  const R kHH2 = c.k_H2_H2[0] * sqrtT * Mx<R>::ex(-cd.k_H2_H2[1] / (T + cd.k_H2_H2[2]));
+  const R kHH2 = c.k_H2_H2[0] * sqrtT * Mx<R>::ex(-fdivp(cd.k_H2_H2[1], T + cd.k_H2_H2[2]));
   const R dcol = xH * kHH + xH2 * kHH2;
-  const R eff = n * dcol / (n * dcol + c.A_eff + zpd);
+  const R eff = dvp<R>(n * dcol, n * dcol + c.A_eff + zpd);
   const R g_h2 = kgr * n * xH * (c.h2form_eV[0] * ev + c.h2form_eV[1] * ev * eff) +
                  zpd * xH2 * c.f_pump * (c.pump_eV * ev) * eff + zpd * xH2 * (c.pd_eV * ev);
   v.Gamma = (double)g_pe + (double)g_cr + (double)g_pi + (double)g_h2;
   // cooling, Sec. 4.6
   const R sqrtT4 = std::is_same<R, double>::value ? sqrtT * R(0.01) : Mx<R>::sq(R(T * 1e-4));  // (T / 1e4)^1/2
-  const R k12 = c.lya[0] * Mx<R>::ex(cd.lya[1] * q.lnT4 - cd.lya[4] * 1e4 * q.invT) /
-                (R(1) + Mx<R>::ex(cd.lya[3] * (q.lnT4 - cd.ln_lya_T)));
+  const R k12 = dvp<R>(c.lya[0] * Mx<R>::ex(cd.lya[1] * q.lnT4 - cd.lya[4] * 1e4 * q.invT),
+                       R(1) + Mx<R>::ex(cd.lya[3] * (q.lnT4 - cd.ln_lya_T)));
   const R l_lya = xH * xe * R(K_B) * c.lya_E21 * k12;
   const R l_ci = (c.ci_eV * ev) * xH * xe * kci;
   const R l_cd = (c.cd_eV * ev) * xH2 * (xH * kcdH + xH2 * kcdH2);
@@ -480,7 +545,7 @@ __device__ Eval<R> evaluate(double T, double n_d, double xH2_d, double xHp_d, co
     const double lnT3 = q.lnT - LN1E3;
     const double iT3 = 1e3 * q.invT;
     const double q3 = a[4] * iT3;
-    const R Lrot = R(a[0]) * Mx<R>::ex(a[1] * lnT3) / (R(1) + R(a[2]) * Mx<R>::ex(a[3] * lnT3)) *
+    const R Lrot = dvp<R>(R(a[0]) * Mx<R>::ex(a[1] * lnT3), R(1) + R(a[2]) * Mx<R>::ex(a[3] * lnT3)) *
                        Mx<R>::ex(-(q3 * q3 * q3)) +
                    R(a[5]) * Mx<R>::ex(-a[6] * iT3);
     const R Lvib = R(a[7]) * Mx<R>::ex(-a[8] * iT3) + R(a[9]) * Mx<R>::ex(-a[10] * iT3);
@@ -492,8 +557,10 @@ __device__ Eval<R> evaluate(double T, double n_d, double xH2_d, double xHp_d, co
     const R L0 = Mx<R>::ex(LN10D * (b[0] + lg * (b[1] + lg * (b[2] + lg * (b[3] + lg * b[4])))));
     const R np_ = n * (xH + xH2);
     const R nL0 = np_ * L0;
-    // = Llte n L0 / (n L0 + Llte) without forming the tiny product; 0 when either rate is 0
-    const R L = (nL0 > R(0) && Llte > R(0)) ? nL0 / (R(1) + nL0 / Llte) : R(0);
+    // = Llte n L0 / (n L0 + Llte), 0 when either rate is 0: in double as one quotient (both can
+    // be tiny: the plain division), in float without forming the product, which can underflow
+    const R L = !(nL0 > R(0) && Llte > R(0)) ? R(0)
+                : std::is_same<R, double>::value ? nL0 * Llte / (nL0 + Llte) : nL0 / (R(1) + nL0 / Llte);
     l_rv = xH2 * L * inv_n;
   }
   const R l_ff = c.ff[0] * c.ff[1] * sqrtT * xe * xHp;
@@ -504,10 +571,10 @@ __device__ Eval<R> evaluate(double T, double n_d, double xH2_d, double xHp_d, co
     const R E10 = c.cp_levels[2], A10 = c.cp_levels[3];
     const double lnT2 = q.lnT - LN100;
     const R k10H = c.cp_rat[0] * Mx<R>::ex((cd.cp_ncrit_H[1] + cd.cp_ncrit_H[2] * lnT2) * lnT2);
-    const R k10e = A10 / (c.cp_ncrit_e * sqrtT4);
+    const R k10e = dvp<R>(A10, c.cp_ncrit_e * sqrtT4);
     const R C10 = n * (xH * k10H + xH2 * c.cp_h2_over_h * k10H + xe * k10e);
     const R C01 = C10 * c.cp_rat[1] * Mx<R>::ex(-cd.cp_levels[2] * q.invT);
-    const R f1 = C01 / (C01 + C10 + A10);
+    const R f1 = dvp<R>(C01, C01 + C10 + A10);
     l_cp = e.xCp * f1 * A10 * R(K_B) * E10 * inv_n;
   }
   const R l_c = e.xC * three_level_cool<R>(q, n, inv_n, xH, xH2, xe, cd.c_levels, cd.c_rat, cd.c_coll, cd.c_ncrit_H,
@@ -516,13 +583,13 @@ __device__ Eval<R> evaluate(double T, double n_d, double xH2_d, double xHp_d, co
                                              cd.fs_slope_O);
   R l_co;
   {
-    const R Nt = n * e.xCO * R(PC_CM) * p.idvdr;
     const double lT = q.lnT * INV_LN10D;
-    const double lN = Nt > R(0) ? Mx<R>::ln((double)Nt) * INV_LN10D : -300.0;
+    const double lN = (pre ? *pre : pre_logs<R>(n, e, p)).lNt;
     // log10 columns are stored as log10(value) + TAB_LOG_OFFSET (see coef.h)
     const R L0 = Mx<R>::ex(LN10D * (co_lookup(tab, lT, lN, 0) - TAB_LOG_OFFSET));
     const R nh = Mx<R>::ex(LN10D * co_lookup(tab, lT, lN, 1));
-    l_co = e.xCO * L0 / (R(1) + n / nh);
+    // L0 / (1 + n / n_half) as one division; n + n_half >= n
+    l_co = dvp<R>(e.xCO * L0 * nh, nh + n);
   }
   const R l_gr =
       c.grrec[0] * Mx<R>::ex(cd.grrec[1] * q.lnT + cd.grrec[2] * (double)Mx<R>::ex(-cd.grrec[3] * q.lnT) * lnpsi) *
@@ -535,21 +602,22 @@ __device__ Eval<R> evaluate(double T, double n_d, double xH2_d, double xHp_d, co
     // exp(-E/T4) f_neb as one exponent: each factor alone can leave float range
     const R ef = Mx<R>::ex(LN10D * f - cd.neb[1] * 1e4 * q.invT);
     const R ne2 = n * xe * R(0.01);
+    const double lne2 = (pre ? *pre : pre_logs<R>(n, e, p)).lne2;
     const double expo = cd.neb[3] - cd.neb[4] * q.lnT4;
-    const R dens = ne2 > R(0) ? Mx<R>::ex(expo * Mx<R>::ln((double)ne2))
+    const R dens = ne2 > R(0) ? Mx<R>::ex(expo * lne2)
                               : (expo > 0.0 ? R(0) : (expo < 0.0 ? R(INFINITY) : R(1)));
     l_neb = Zg * xe * xHp * c.neb[0] * ef / (sqrtT4 * (R(1) + c.neb[2] * dens));
   }
   // dust temperature in double on both paths: where gas and dust are coupled T_d -> T, and the
   // gas-dust term goes as T - T_d
   bool bad;
-  const double sqrtTd = Mx<double>::sq(T);
-  const double Td = dust_T<double>(T, sqrtTd, n_d, (double)r.G, td_guess, (double)p.T_bb, cd, bad);
+  const double sqrtTd = q.sqrtT;
+  const double Td = dust_T<double>(T, sqrtTd, n_d, (double)r.G, td_guess, (double)p.T_bb, cd, bad, v.Tds);
   v.Td = Td;
   v.td_bad = bad;
   const R l_gd = R(cd.alpha_gd * sqrtTd * (T - Td) * (double)Zd);
-  const R S = R(1) / (R(1) + Mx<R>::ex(-cd.sigmoid[0] * (T - 0.5 * (cd.sigmoid[1] + cd.sigmoid[2])) *
-                                         cd.sigmoid_iw));
+  const R S = dvp<R>(R(1), R(1) + Mx<R>::ex(-cd.sigmoid[0] * (T - 0.5 * (cd.sigmoid[1] + cd.sigmoid[2])) *
+                                              cd.sigmoid_iw));
   const double lgT = q.lnT * INV_LN10D;
   const R l_cie = Mx<R>::ex(LN10D * (cie_lookup(tab, lgT, 0) - TAB_LOG_OFFSET)) +
                   Zg * Mx<R>::ex(LN10D * (cie_lookup(tab, lgT, 1) - TAB_LOG_OFFSET));
@@ -566,6 +634,13 @@ __device__ Eval<R> evaluate(double T, double n_d, double xH2_d, double xHp_d, co
     diag[DG_LCIE] = l_cie; diag[DG_S] = S; diag[DG_LAMBDA] = R(v.Lambda); diag[DG_H] = R(v.H);
   }
   return v;
+}
+
+template <class R, bool CHEM_ONLY, bool DIAG>
+__device__ __forceinline__ Eval<R> evaluate(double T, double n_d, double xH2_d, double xHp_d, const EqS<R> &e,
+                                            const Rad<R> &r, const CoefT<R> &c, const ParT<R> &p, const R *tab,
+                                            double td_guess, R *diag, bool chem = true) {
+  return evaluate<R, CHEM_ONLY, DIAG>(make_tq<R>(T), n_d, xH2_d, xHp_d, e, r, c, p, tab, td_guess, diag, chem);
 }
 
 }  // namespace ism

@@ -1,6 +1,7 @@
-"""The library's double exp and log (csrc/fmath.h), built for the host and checked against
-long double references: at most 1.5 ulp (exp) and 2 ulp (log) over argument sweeps, and the
-special cases (saturation, exact values, non-finite arguments)."""
+"""The library's double exp, log and division (csrc/fmath.h), built for the host and checked
+against long double references: at most 1.5 ulp (exp), 2 ulp (log) and 2 ulp (division, from a
+reciprocal seed no better than float) over argument sweeps, and the special cases (saturation,
+exact values, non-finite arguments; a NaN exp argument saturates to the lower bound)."""
 import os
 import shutil
 import subprocess
@@ -27,6 +28,10 @@ def report(tmp_path_factory):
 def test_exp_accuracy(report):
     assert float(report["exp_max_ulp"]) <= 1.5, report
     assert report["exp_special"] == "1"
+
+
+def test_division_accuracy(report):
+    assert float(report["div_max_ulp"]) <= 2.0, report
 
 
 def test_log_accuracy(report):
