@@ -56,6 +56,7 @@ struct CoefT {
   R cp_rat[2];           // C+: A10/n_crit,H, g1/g0
   R dust_A;              // sigma_IR(10 K)/100 c a_rad
   R inv_J_FUV, inv_kci_T, rsqrt_kci_T, sigmoid_iw;  // 1 / k_ci_H[2] and its square root
+  R inv_fshld_N, inv_b5;  // 1 / the H2 shielding column scale, 1 / b5
   R cie_idx, co_idx, co_idy, cs_idx, cs_idy;  // 1 / table spacing
   // ---- table axes ----
   R cie_x0, cie_dx;

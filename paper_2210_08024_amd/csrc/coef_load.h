@@ -134,6 +134,8 @@ inline bool load_coefficients(const char *path, CoefT<double> &c, std::vector<do
   c.inv_kci_T = 1.0 / c.k_ci_H[2];
   c.rsqrt_kci_T = 1.0 / std::sqrt(c.k_ci_H[2]);
   c.sigmoid_iw = 1.0 / (c.sigmoid[2] - c.sigmoid[1]);
+  c.inv_fshld_N = 1.0 / c.fshld[3];
+  c.inv_b5 = 1.0 / c.b5;
   c.cie_idx = 1.0 / c.cie_dx;
   c.co_idx = 1.0 / c.co_dx;
   c.co_idy = 1.0 / c.co_dy;

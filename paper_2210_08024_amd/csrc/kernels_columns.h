@@ -30,14 +30,15 @@ __device__ __forceinline__ double g_slab(double y, float) {
   return y < 1e-4 ? 1.0 - y / 2.0 + y * y / 6.0 : (double)(-::expm1f((float)-y)) / y;
 }
 
-// Eq. e:fshld_H2_DB with b5 from the coefficient file.
+// Eq. e:fshld_H2_DB with b5 from the coefficient file.  Both denominators are at least 1, so
+// the reciprocal-based division serves; the constants' reciprocals come from the host.
 template <class R>
 __device__ __forceinline__ double f_shld_H2(double N) {
   const CoefT<double> &c = g_coef64;
-  const double x = N / c.fshld[3];
+  const double x = N * c.inv_fshld_N;
   const R s = Mx<R>::sq(R(1.0 + x));
-  const double u = 1.0 + x / c.b5;
-  return c.fshld[0] / (u * u) + c.fshld[1] / (double)s * (double)Mx<R>::ex(-c.fshld[2] * (double)s);
+  const double u = 1.0 + x * c.inv_b5;
+  return fdivp(c.fshld[0], u * u) + fdivp(c.fshld[1], (double)s) * (double)Mx<R>::ex(-c.fshld[2] * (double)s);
 }
 
 // C self- and H2 cross-shielding: bilinear in log10 f over (log10 N_C, log10 N_H2).

@@ -396,6 +396,17 @@ __device__ R dust_T(R T, R sqrtT, R n, R G, R guess, R Tbb, const CoefT<R> &c, b
   return x;
 }
 
+// One Newton step in double on the dust-temperature balance above, from x (a root found in float).
+__device__ __forceinline__ double dust_polish(double T, double sqrtT, double n, double G, double Tbb,
+                                              const CoefT<double> &c, double x) {
+  const double A = c.dust_A, B = n * c.alpha_gd * sqrtT;
+  const double Tbb2 = Tbb * Tbb, Tbb4 = Tbb2 * Tbb2;
+  const double x2 = x * x, x4 = x2 * x2;
+  const double g = A * x2 * (x4 - Tbb4) + B * x - (G + B * T);
+  const double dg = A * (6.0 * x4 * x - 2.0 * Tbb4 * x) + B;
+  return dg > 0.0 ? x - fdivp(g, dg) : x;
+}
+
 // ---------------------------------------------------------------- fine structure (Sec. 4.6.2)
 // 3-level atom (levels 0, 1, 2); H-impact de-excitation k10 follows the printed critical
 // densities as a power law in T (slope precomputed on the host), other partners and
@@ -608,11 +619,20 @@ __device__ Eval<R> evaluate(const Tq &q, double n_d, double xH2_d, double xHp_d,
                               : (expo > 0.0 ? R(0) : (expo < 0.0 ? R(INFINITY) : R(1)));
     l_neb = Zg * xe * xHp * c.neb[0] * ef / (sqrtT4 * (R(1) + c.neb[2] * dens));
   }
-  // dust temperature in double on both paths: where gas and dust are coupled T_d -> T, and the
-  // gas-dust term goes as T - T_d
+  // dust temperature to double accuracy on both paths: where gas and dust are coupled T_d -> T,
+  // and the gas-dust term goes as T - T_d.  The float path solves in float and takes one Newton
+  // step in double from the float root (relative error ~1e-7 before it, ~1e-14 after)
   bool bad;
   const double sqrtTd = q.sqrtT;
-  const double Td = dust_T<double>(T, sqrtTd, n_d, (double)r.G, td_guess, (double)p.T_bb, cd, bad, v.Tds);
+  double Td;
+  if constexpr (std::is_same<R, float>::value) {
+    float slope;
+    const float Tdf = dust_T<float>((float)T, (float)sqrtTd, (float)n_d, r.G, (float)td_guess, p.T_bb, c, bad, slope);
+    Td = bad ? (double)Tdf : dust_polish(T, sqrtTd, n_d, (double)r.G, (double)p.T_bb, cd, (double)Tdf);
+    v.Tds = slope;
+  } else {
+    Td = dust_T<double>(T, sqrtTd, n_d, (double)r.G, td_guess, (double)p.T_bb, cd, bad, v.Tds);
+  }
   v.Td = Td;
   v.td_bad = bad;
   const R l_gd = R(cd.alpha_gd * sqrtTd * (T - Td) * (double)Zd);
