@@ -384,18 +384,25 @@ ism_status ism_surrogate_pairs(const ism_params *p, ism_precision prec, int64_t 
 
 /* The source step with the surrogate in front of the plain solver (MIXED precision only:
  * radiation and x_C+, x_CO, x_e float).  Arguments as for ism_chem_cool_step.
- * For every cell the network predicts the post-step (x_H2, x_H+, T) from the inputs above;
- * the prediction seeds a Newton solve for the equilibrium of (dT/dt, C_H2, C_H+) (Eqs.
- * e:ODE1, e:HH, e:HII; Jacobian by forward differences).  The root is accepted only where
- * the plain step's result no longer depends on its substep path: Newton converged to
- * accept_tol (relative), every eigenvalue of the Jacobian at the root has real part below
- * -20/dt, the root's T is within a factor e^0.1 of the prediction, and dT/dt keeps the sign
- * of T_root - T along four temperatures from T to T_root.  Accepted cells return the root
- * with equilibrium C/O/e there, nsub = 0, status = 0; every other cell runs the plain
- * MIXED step and has ISM_ST_FALLBACK set.  m may be NULL: the seed is then the input state
- * itself (the method without the network).  n_fallback_dev (device int64, nullable)
- * receives the number of plain-step cells.  accept_tol in (0, 1e-3]; ncell < 2^31.
- * Scratch (predictions, the rejected list, ordering keys) on the call's stream. */
+ * A cell can stand in for the plain subcycled step (Sec. 6.1) only where that step's result no
+ * longer depends on its substep path, so every cell first takes a pre-test at its input state:
+ * both chemical relaxation rates fast, dt (2 k_gr n + D_H2) >= 10 and dt (I_H + R_H+) >= 10
+ * (Eqs. e:HH, e:HII), and the thermal one too, -dt (dH/dT_mu) / K >= 10 (the forward difference
+ * of Sec. 6.1, K = n mu_H k_B / (gamma - 1)).  For the cells that pass, the network predicts the
+ * post-step (x_H2, x_H+, T), and the prediction seeds a Newton solve for the equilibrium of
+ * (dT/dt, C_H2, C_H+) (Eqs. e:ODE1, e:HH, e:HII; Jacobian by forward differences).  The root is
+ * accepted only where: Newton converged to accept_tol (relative); every eigenvalue of the
+ * Jacobian at the root has real part below -20/dt; the root's T is within a factor e^0.1 of the
+ * prediction; dT/dt keeps the sign of T_root - T along four temperatures from T to T_root; and
+ * one plain substep of length dt, started at the root and at the root perturbed in each
+ * variable, bounds the plain step's own end state to within accept_tol / 2 of the root.
+ * Accepted cells return the root with equilibrium C/O/e there, nsub = 0, status = 0; every
+ * other cell runs the plain MIXED step (ordered by temperature with order_cells 1 or 2) and has
+ * ISM_ST_FALLBACK set; its outputs are those of ism_chem_cool_step(MIXED).  m may be NULL: the
+ * seed is then the input state itself (the method without the network).  n_fallback_dev
+ * (device int64, nullable) receives the number of plain-step cells.  accept_tol in (0, 1e-3];
+ * ncell < 2^31.  Scratch (the candidate and fallback lists, predictions, ordering keys) on the
+ * call's stream. */
 ism_status ism_chem_cool_step_surrogate(ism_surrogate *m, const ism_params *p, int64_t ncell,
                                         double dt_s, const double *n, double *T, double *xH2,
                                         double *xHp, const void *chi_PE, const void *chi_LW,

@@ -170,9 +170,9 @@ size_t order_bytes(int64_t n) {
 // by temperature regime (or previous substep counts); *out receives the ordered cell list, laid
 // out in `base` (order_bytes(n) bytes of scratch).
 void order_cells(uint8_t *base, int64_t n, const unsigned long long *count, const int32_t *items, const double *T,
-                 const float *pred, const int32_t *nsub, int32_t **out, hipStream_t stream) {
+                 const int32_t *nsub, int32_t **out, hipStream_t stream) {
   const size_t key_b = (size_t)((n * 2 + 255) / 256 * 256), bins_b = (size_t)ORDER_BINS * 4;
-  OrderArgs a{n, count, items, T, pred, nsub, (uint16_t *)base, (uint32_t *)(base + key_b),
+  OrderArgs a{n, count, items, T, nsub, (uint16_t *)base, (uint32_t *)(base + key_b),
               (uint32_t *)(base + key_b + bins_b), (int32_t *)(base + key_b + 2 * bins_b)};
   const dim3 grid((unsigned)((n + ORDER_THREADS - 1) / ORDER_THREADS));
   hipLaunchKernelGGL(order_zero_kernel, dim3(1), dim3(ORDER_THREADS), 0, stream, a.hist);
@@ -251,7 +251,7 @@ void launch_step(const DevState *st, const ism_params *p, ism_precision prec, in
                  hipStream_t stream) {
   const int64_t want = (ncell + 255) / 256;
   int32_t *order = nullptr;
-  if (ord) order_cells(ord, ncell, nullptr, nullptr, T, nullptr, p->order_cells == 2 ? nsub : nullptr, &order, stream);
+  if (ord) order_cells(ord, ncell, nullptr, nullptr, T, p->order_cells == 2 ? nsub : nullptr, &order, stream);
   if (prec == ISM_PREC_F64) {
     StepArgs<double> a{ncell, dt_s, n, T, xH2, xHp, (const double *)chi_PE, (const double *)chi_LW,
                        (const double *)chi_H2, (const double *)chi_C, (const double *)phi_LyC,
@@ -1116,34 +1116,56 @@ ism_status ism_chem_cool_step_surrogate(ism_surrogate *m, const ism_params *p, i
   int dev = 0;
   if (ism_status s = current_state(&st, &dev)) return s;
   StreamScratch *ss = stream_scratch(dev, stream);
+  // scratch: predictions (one per candidate), the chemistry-passing list, the candidate list,
+  // the fallback list
   const size_t pred_bytes = m ? align256((size_t)ncell * 3 * sizeof(float)) : 0;
-  const size_t rej_bytes = align256((size_t)ncell * sizeof(int32_t));
-  if (ism_status s = grow(&ss->surr, &ss->surr_b, pred_bytes + rej_bytes, stream, "surrogate scratch")) return s;
+  const size_t list_bytes = align256((size_t)ncell * sizeof(int32_t));
+  if (ism_status s = grow(&ss->surr, &ss->surr_b, pred_bytes + 3 * list_bytes, stream, "surrogate scratch")) return s;
   if (ism_status s = grow(&ss->ctl, &ss->ctl_b, 256, stream, "work-queue counter")) return s;
   if (p->order_cells)
     if (ism_status s = grow(&ss->ord, &ss->ord_b, order_bytes(ncell), stream, "order scratch")) return s;
   float *pred = m ? (float *)ss->surr : nullptr;
-  int32_t *rej = (int32_t *)((uint8_t *)ss->surr + pred_bytes);
+  int32_t *chem = (int32_t *)((uint8_t *)ss->surr + pred_bytes);
+  int32_t *cand = (int32_t *)((uint8_t *)ss->surr + pred_bytes + list_bytes);
+  int32_t *rej = (int32_t *)((uint8_t *)ss->surr + pred_bytes + 2 * list_bytes);
   int64_t *q = (int64_t *)ss->ctl;
   unsigned long long *nrej = (unsigned long long *)ss->ctl + 1;
+  unsigned long long *ncand = (unsigned long long *)ss->ctl + 2;
+  unsigned long long *nchem = (unsigned long long *)ss->ctl + 3;
   hipLaunchKernelGGL(counter_reset_kernel, dim3(1), dim3(1), 0, stream, nrej);
+  hipLaunchKernelGGL(counter_reset_kernel, dim3(1), dim3(1), 0, stream, ncand);
+  hipLaunchKernelGGL(counter_reset_kernel, dim3(1), dim3(1), 0, stream, nchem);
+  const ParT<float> pr = make_par<float>(p, g_host_coef);
+  const ParT<double> pd = make_par<double>(p, g_host_coef);
+  constexpr double FAST = 20.0;  // dt times the slowest relaxation rate an accepted cell needs
+  const int64_t lgrid = std::min<int64_t>((ncell + 255) / 256, (int64_t)std::max(st->num_cu, 1) * 4);
+  // 1. the pre-test on the input state: chemical rates on every cell, then the thermal rate on
+  //    the cells that passed; the others start the fallback list
+  PreArgs pa{ncell, dt_s, n, T, xH2, xHp, (const float *)chi_PE, (const float *)chi_LW, (const float *)chi_H2,
+             (const float *)chi_C, (const float *)phi_LyC, (const float *)xi_cr, (const float *)N_eff,
+             st->tab32, pr, pd, FAST, nullptr, nullptr, chem, rej, nchem, nrej};
+  hipLaunchKernelGGL(surr_pretest_kernel, dim3((unsigned)((ncell + PRETEST_THREADS - 1) / PRETEST_THREADS)),
+                     dim3(PRETEST_THREADS), 0, stream, pa);
+  pa.in = chem; pa.nin = nchem; pa.pass = cand; pa.npass = ncand;
+  hipLaunchKernelGGL(surr_pretest_thermal_kernel, dim3((unsigned)lgrid), dim3(256), 0, stream, pa);
+  // 2. the network on the candidates only (their count is read on the device)
   if (m) {
     mlp::FwdArgs fa{};
     fa.cin = mlp::CellIn<float>{n, T, xH2, xHp, (const float *)chi_PE, (const float *)phi_LyC,
                                 (const float *)xi_cr, (const float *)N_eff, (float)std::log10(p->Zg),
-                                (float)std::log10(std::max(dt_s, 1e-300) / 3.15576e7)};
-    fa.B = ncell; fa.fimg = m->fimg(); fa.norm = surr_norm(m); fa.Y = pred;
+                                (float)std::log10(std::max(dt_s, 1e-300) / 3.15576e7), cand};
+    fa.B = ncell; fa.count = ncand; fa.fimg = m->fimg(); fa.norm = surr_norm(m); fa.Y = pred;
     hipLaunchKernelGGL(mlp::mlp_fwd_kernel<3>, dim3(fwd_grid(m, ncell)), dim3(mlp::FWD_THREADS), 0, stream, fa);
   }
-  const ParT<float> pr = make_par<float>(p, g_host_coef);
-  const ParT<double> pd = make_par<double>(p, g_host_coef);
-  AcceptArgs aa{ncell, dt_s, n, T, xH2, xHp, (const float *)chi_PE, (const float *)chi_LW, (const float *)chi_H2,
-                (const float *)chi_C, (const float *)phi_LyC, (const float *)xi_cr, (const float *)N_eff,
-                (float *)xCp, (float *)xCO, (float *)xe, nsub, status, pred, st->tab32, pr, pd, rej, nrej,
-                20.0, accept_tol, 6, 1e-3};
-  hipLaunchKernelGGL(accept_kernel, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, stream, aa);
+  // 3. certification of the candidates; the rejected ones join the fallback list
+  AcceptArgs aa{cand, ncand, dt_s, n, T, xH2, xHp, (const float *)chi_PE, (const float *)chi_LW,
+                (const float *)chi_H2, (const float *)chi_C, (const float *)phi_LyC, (const float *)xi_cr,
+                (const float *)N_eff, (float *)xCp, (float *)xCO, (float *)xe, nsub, status, pred, st->tab32, pr, pd,
+                rej, nrej, FAST, accept_tol, 6, 1e-3};
+  hipLaunchKernelGGL(accept_kernel, dim3((unsigned)lgrid), dim3(256), 0, stream, aa);
+  // 4. the plain MIXED step on the fallback list, ordered by temperature
   int32_t *list = rej;
-  if (p->order_cells) order_cells((uint8_t *)ss->ord, ncell, nrej, rej, T, pred, nullptr, &list, stream);
+  if (p->order_cells) order_cells((uint8_t *)ss->ord, ncell, nrej, rej, T, nullptr, &list, stream);
   StepArgs<float> sa{ncell, dt_s, n, T, xH2, xHp, (const float *)chi_PE, (const float *)chi_LW,
                      (const float *)chi_H2, (const float *)chi_C, (const float *)phi_LyC,
                      (const float *)xi_cr, (const float *)N_eff, (float *)xCp, (float *)xCO, (float *)xe,

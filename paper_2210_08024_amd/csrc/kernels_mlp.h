@@ -90,6 +90,7 @@ struct CellIn {
   const double *n, *T, *xH2, *xHp;
   const R *chiPE, *phi, *xi, *Neff;  // phi may be null (= 0)
   float lZg, ldt;
+  const int32_t *idx;  // sample -> cell, or null (sample = cell)
 };
 
 template <class R>
@@ -118,6 +119,7 @@ struct FwdArgs {
   const float *X;  // [B][10] raw features (modes 0-2)
   CellIn<float> cin;  // mode 3: features built from the cell arrays
   int64_t B;
+  const unsigned long long *count;  // mode 3: device sample count (<= B), or null (= B)
   const uint8_t *fimg;
   Norm norm;
   float *Y;        // modes 0, 3: [B][3] de-standardised predictions
@@ -189,8 +191,10 @@ __global__ __launch_bounds__(FWD_THREADS) void mlp_fwd_kernel(FwdArgs a) {
     isdx[j] = k < NIN ? a.norm.v[NRM_ISDX + k] : 0.f;
   }
   float lossacc = 0.f;
+  int64_t B = a.B;
+  if (MODE == 3 && a.count) B = (int64_t)*a.count < B ? (int64_t)*a.count : B;
   const int64_t stride = (int64_t)gridDim.x * FWD_WAVES * WTILE;
-  for (int64_t base = ((int64_t)wave * gridDim.x + blockIdx.x) * WTILE; base < a.B; base += stride) {
+  for (int64_t base = ((int64_t)wave * gridDim.x + blockIdx.x) * WTILE; base < B; base += stride) {
     const uint8_t *sm = smem + opaque_zero();
     const __bf16 *W1 = (const __bf16 *)(sm + FI_W1);
     const __bf16 *W2 = (const __bf16 *)(sm + FI_W2);
@@ -201,13 +205,14 @@ __global__ __launch_bounds__(FWD_THREADS) void mlp_fwd_kernel(FwdArgs a) {
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int64_t n = base + 16 * t + r;
+      const int64_t cn = (MODE == 3 && a.cin.idx && n < B) ? (int64_t)a.cin.idx[n] : n;
       float v[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int k = 4 * g + j;
         float raw = 0.f;
-        if (n < a.B && k < NIN) raw = MODE == 3 ? cell_feature(a.cin, n, k) : a.X[n * NIN + k];
-        v[j] = (n < a.B && k < NIN) ? (raw - mux[j]) * isdx[j] : 0.f;
+        if (n < B && k < NIN) raw = MODE == 3 ? cell_feature(a.cin, cn, k) : a.X[n * NIN + k];
+        v[j] = (n < B && k < NIN) ? (raw - mux[j]) * isdx[j] : 0.f;
       }
       bf16x4 h;
       h.x = (__bf16)v[0];
@@ -215,7 +220,7 @@ __global__ __launch_bounds__(FWD_THREADS) void mlp_fwd_kernel(FwdArgs a) {
       h.z = (__bf16)v[2];
       h.w = (__bf16)v[3];
       x[t] = as_i16x4(h);
-      if ((MODE == 1 || MODE == 2) && n < a.B) *(bf16x4 *)(a.h0 + n * K1 + 4 * g) = h;
+      if ((MODE == 1 || MODE == 2) && n < B) *(bf16x4 *)(a.h0 + n * K1 + 4 * g) = h;
     }
     bf16x4 ha[8][NT], hb[8][NT];
     // layer 1 (K = 16, one 16x16x16 product per neuron block)
@@ -234,15 +239,15 @@ __global__ __launch_bounds__(FWD_THREADS) void mlp_fwd_kernel(FwdArgs a) {
         ha[m][t] = h;
         if (MODE == 1 || MODE == 2) {
           const int64_t n = base + 16 * t + r;
-          if (n < a.B) {
+          if (n < B) {
             *(f32x4 *)(a.z1 + n * NH + 16 * m + 4 * g) = z;
             *(bf16x4 *)(a.h1 + n * NH + 16 * m + 4 * g) = h;
           }
         }
       }
     }
-    fwd_hidden<MODE>(W2, bias + NH, ha, hb, r, g, base, a.B, a.z2, a.h2);
-    fwd_hidden<MODE>(W3, bias + 2 * NH, hb, ha, r, g, base, a.B, a.z3, a.h3);
+    fwd_hidden<MODE>(W2, bias + NH, ha, hb, r, g, base, B, a.z2, a.h2);
+    fwd_hidden<MODE>(W3, bias + 2 * NH, hb, ha, r, g, base, B, a.z3, a.h3);
     // output layer: rows 0..2 of a 16-row tile
     f32x4 acc[NT];
 #pragma unroll
@@ -258,7 +263,7 @@ __global__ __launch_bounds__(FWD_THREADS) void mlp_fwd_kernel(FwdArgs a) {
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         const int64_t n = base + 16 * t + r;
-        if (n < a.B) {
+        if (n < B) {
 #pragma unroll
           for (int j = 0; j < NOUT; ++j) {
             const float y = acc[t][j] + bias[3 * NH + j];

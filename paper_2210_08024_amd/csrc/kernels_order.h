@@ -4,8 +4,7 @@
 // lanes run the same instruction stream, so lanes whose cells sit in different temperature
 // regimes execute both sides of every regime branch, and lanes whose cells need different
 // numbers of substeps refill at different times.  Grouping cells with similar input
-// temperature (and, when a prediction of the end temperature is available, similar end
-// temperature) into the same waves removes most of that divergence.  When the caller holds the
+// temperature into the same waves removes most of that divergence.  When the caller holds the
 // substep counts of the previous step of the same cells, they are the better key: cells are
 // grouped by how long they will run, longest first.  The order is a
 // counting sort on a 12-bit key: a per-block LDS histogram, an exclusive scan of the 4096
@@ -25,27 +24,14 @@ __device__ __forceinline__ uint32_t order_quant(float x, float lo, float hi, int
   return (uint32_t)(u * (float)((1 << bits) - 1) + 0.5f);
 }
 
-// Key of one cell: log10 T in [0, 8) on 12 bits, or, with a prediction, the 6-bit
-// quantisations of log10 T and of the predicted log10 T interleaved (a Morton order), or, with
-// previous substep counts, log2 of the count in [0, 17] on 12 bits.  Bins are visited from
-// high to low (hot to cold, long to short).
-__device__ __forceinline__ uint32_t order_key(const double *T, const float *pred, const int32_t *nsub,
-                                              int64_t cell) {
-  uint32_t k;
+// Key of one cell: log10 T in [0, 8) on 12 bits, or, with previous substep counts, log2 of the
+// count in [0, 17] on 12 bits.  Bins are visited from high to low (hot to cold, long to short).
+__device__ __forceinline__ uint32_t order_key(const double *T, const int32_t *nsub, int64_t cell) {
   if (nsub) {
     const int32_t c = nsub[cell];
     return (uint32_t)(ORDER_BINS - 1) - order_quant(log2f((float)(c > 1 ? c : 1)), 0.f, 17.f, ORDER_BITS);
   }
-  const float lT = log10f((float)T[cell]);
-  if (pred) {
-    const uint32_t a = order_quant(lT, 0.f, 8.f, 6), b = order_quant(pred[3 * cell + 2], 0.f, 8.f, 6);
-    k = 0;
-#pragma unroll
-    for (int j = 0; j < 6; ++j) k |= (((a >> j) & 1u) << (2 * j + 1)) | (((b >> j) & 1u) << (2 * j));
-  } else {
-    k = order_quant(lT, 0.f, 8.f, ORDER_BITS);
-  }
-  return (uint32_t)(ORDER_BINS - 1) - k;
+  return (uint32_t)(ORDER_BINS - 1) - order_quant(log10f((float)T[cell]), 0.f, 8.f, ORDER_BITS);
 }
 
 struct OrderArgs {
@@ -53,7 +39,6 @@ struct OrderArgs {
   const unsigned long long *count;    // device item count, or null (= n)
   const int32_t *items;               // item -> cell, or null (item = cell)
   const double *T;
-  const float *pred;                  // [cell][3] prediction, or null
   const int32_t *nsub;                // previous substep counts per cell, or null
   uint16_t *key;                      // per item
   uint32_t *hist;                     // ORDER_BINS counts
@@ -73,7 +58,7 @@ __global__ __launch_bounds__(ORDER_THREADS) void order_key_kernel(OrderArgs a) {
   const int64_t i = (int64_t)blockIdx.x * ORDER_THREADS + threadIdx.x;
   if (i < nitem) {
     const int64_t cell = a.items ? (int64_t)a.items[i] : i;
-    const uint32_t k = order_key(a.T, a.pred, a.nsub, cell);
+    const uint32_t k = order_key(a.T, a.nsub, cell);
     a.key[i] = (uint16_t)k;
     atomicAdd(&h[k], 1u);
   }

@@ -22,16 +22,21 @@
 //      the root, so |Y_prev - Y_root| <= |Y_0 - Y_root| componentwise, and the cell is
 //      accepted when sum_v |L'_wv| |Y_0,v - Y_root,v| <= out_tol / 2 of each output's scale
 //      (and the unperturbed jump reproduces the root).
-// Accepted cells take the root (equilibrium C/O/e at the root); the others are appended to a
-// list for the plain step.  A pre-test on the chemistry diagonal, from a chemistry-only
-// probe, rejects most non-equilibrium cells before any heating/cooling evaluation.
+// Before any prediction, a pre-test on the input state (surr_pretest_kernel) requires both
+// chemical relaxation rates and the thermal one to be fast there as well: the plain step's path
+// starts at the input state, and a cell that relaxes slowly there does so along a path its end
+// state depends on.
+// Only the cells that pass are predicted and certified; the same test at the seed opens the
+// certification.  Accepted cells take the root (equilibrium C/O/e at the root); the others are
+// appended to a list for the plain step.
 #pragma once
 #include "kernels_step.h"
 
 namespace ism {
 
 struct AcceptArgs {
-  int64_t ncell;
+  const int32_t *cand;              // candidate cells (listed by surr_pretest_kernel)
+  const unsigned long long *ncand;  // their number (device counter)
   double dt;
   const double *n;
   double *T, *xH2, *xHp;
@@ -39,12 +44,12 @@ struct AcceptArgs {
   float *xCp, *xCO, *xe;
   int32_t *nsub;
   uint8_t *status;
-  const float *pred;  // [ncell][3] predicted x_H2, x_H+, log10 T; null = the input state itself
+  const float *pred;  // [candidate][3] predicted x_H2, x_H+, log10 T; null = the input state itself
   const float *tab;
   ParT<float> pr;
   ParT<double> pd;
-  int32_t *rej;                 // rejected cells, compacted (order unspecified)
-  unsigned long long *nrej;     // number of rejected cells (device counter, zeroed before)
+  int32_t *rej;                 // rejected cells, appended (order unspecified)
+  unsigned long long *nrej;     // number of rejected cells (device counter)
   double fast;                  // required dt * rate margin
   double tol;                   // relative Newton convergence tolerance
   int maxit;
@@ -88,33 +93,178 @@ __device__ __forceinline__ bool solve3(const double (&J)[3][3], const double (&g
   return isfinite(d[0]) && isfinite(d[1]) && isfinite(d[2]);
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void accept_kernel(AcceptArgs a) {
+// Both chemical relaxation rates must be fast on their own: dt (2 F + D) and dt (I + R) at
+// least fast / 2 (a NaN passes here and fails the Newton solve).
+__device__ __forceinline__ bool chem_fast(const Eval<float> &v, double dt, double fast) {
+  return !(dt * (2.0 * (double)v.F + (double)v.D) < 0.5 * fast || dt * ((double)v.I + (double)v.Rr) < 0.5 * fast);
+}
+
+__device__ __forceinline__ void load_rad(Rad<float> &r, const float *chiPE, const float *chiLW, const float *chiH2,
+                                         const float *chiC, const float *phi, const float *xi, const float *Neff,
+                                         int64_t i) {
+  r.chiPE = chiPE[i];
+  r.chiLW = chiLW[i];
+  r.chiH2 = chiH2[i];
+  r.chiC = chiC[i];
+  r.phi = phi ? phi[i] : 0.f;
+  r.xi = xi[i];
+  r.Neff = Neff[i];
+}
+
+// Append v to list for the lanes that take it: one atomic per wave, ranks by popcount.  Called
+// by every lane of the wave.
+__device__ __forceinline__ void wave_append(bool take, int32_t v, int32_t *list, unsigned long long *cnt) {
+  const uint64_t m = __ballot(take);
+  if (m == 0) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((unsigned long long)m) - 1;
+  unsigned long long base = 0;
+  if (lane == leader) base = atomicAdd(cnt, (unsigned long long)__popcll(m));
+  base = __shfl(base, leader, 64);
+  if (take) list[base + __popcll(m & ((1ull << lane) - 1ull))] = v;
+}
+
+// Append v to list a (take) or to list b (otherwise) for every live thread of the block: one
+// global atomic per block and list, ranks from the waves' ballots.  Called by every thread of the
+// block (it synchronises the block).  A single
+// counter taking one atomic from every wave of a large grid serialises them, so the lists the
+// pre-test builds from every cell are appended per block; the certification, whose lanes diverge
+// and whose list is short, appends per wave.
+template <int NT>
+__device__ __forceinline__ void block_append2(bool live, bool take, int32_t v, int32_t *la, unsigned long long *ca,
+                                              int32_t *lb, unsigned long long *cb) {
+  constexpr int NW = NT / 64;
+  __shared__ uint32_t s_cnt[2][NW];
+  __shared__ unsigned long long s_base[2];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t ma = __ballot(live && take), mb = __ballot(live && !take);
+  if (lane == 0) {
+    s_cnt[0][w] = (uint32_t)__popcll(ma);
+    s_cnt[1][w] = (uint32_t)__popcll(mb);
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    uint32_t tot = 0;
+    for (int k = 0; k < NW; ++k) tot += s_cnt[threadIdx.x][k];
+    s_base[threadIdx.x] = tot ? atomicAdd(threadIdx.x == 0 ? ca : cb, (unsigned long long)tot) : 0ull;
+  }
+  __syncthreads();
+  const int which = take ? 0 : 1;
+  unsigned long long off = s_base[which];
+  for (int k = 0; k < w; ++k) off += s_cnt[which][k];
+  const uint64_t m = take ? ma : mb;
+  if (live) (take ? la : lb)[off + __popcll(m & ((1ull << lane) - 1ull))] = v;
+  __syncthreads();  // the counts are read before a later call rewrites them
+}
+
+struct PreArgs {
+  int64_t ncell;
+  double dt;
+  const double *n, *T, *xH2, *xHp;
+  const float *chiPE, *chiLW, *chiH2, *chiC, *phi, *xi, *Neff;
+  const float *tab;
+  ParT<float> pr;
+  ParT<double> pd;
+  double fast;
+  const int32_t *in;                 // thermal test: the cells to test
+  const unsigned long long *nin;     //   and their number (device counter)
+  int32_t *pass, *rej;               // cells that pass, cells that fall back (appended, order unspecified)
+  unsigned long long *npass, *nrej;  // their counts (device counters)
+};
+
+// Closure iterations of the pre-test: the test compares rates with a threshold, so the closure
+// need not converge (x_e after four fixed-point iterations from x_e0 + x_C,tot).
+constexpr int PRETEST_CLOSE_IT = 4;
+
+__device__ __forceinline__ void pre_cell(const PreArgs &a, int64_t i, Rad<float> &r, EqS<float> &e, double &nd,
+                                         double &T0, double &x20, double &xp0, const float *s_tab) {
+  const CoefT<float> &c = coef<float>();
+  nd = a.n[i];
+  load_rad(r, a.chiPE, a.chiLW, a.chiH2, a.chiC, a.phi, a.xi, a.Neff, i);
+  fixed_terms(r, nd, c, a.pr);
+  T0 = a.T[i];
+  x20 = a.xH2[i];
+  xp0 = a.xHp[i];
+  e = eq_species<float>(T0, (float)nd, x20, xp0, r, c, a.pr, s_tab, CloseTol<float>::v, PRETEST_CLOSE_IT);
+}
+
+// The pre-test on the input state, first part, one lane per cell: both chemical relaxation rates
+// fast (a chemistry-only probe: closure and rate coefficients).  Cells that pass go to the
+// thermal test, the others to the fallback list.
+constexpr int PRETEST_THREADS = 1024;
+__global__ __launch_bounds__(PRETEST_THREADS) void surr_pretest_kernel(PreArgs a) {
   __shared__ float s_tab[TAB_STEP];
   stage_tables(a.tab, s_tab);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = i < a.ncell;
+  bool pass = false;
+  if (live) {
+    Rad<float> r;
+    EqS<float> e;
+    double nd, T0, x20, xp0;
+    pre_cell(a, i, r, e, nd, T0, x20, xp0, s_tab);
+    const Eval<float> v =
+        evaluate<float, true, false>(T0, nd, x20, xp0, e, r, coef<float>(), a.pr, s_tab, 0.f, nullptr);
+    pass = chem_fast(v, a.dt, a.fast);
+  }
+  block_append2<PRETEST_THREADS>(live, pass, (int32_t)i, a.pass, a.npass, a.rej, a.nrej);
+}
+
+// Second part, over the cells that passed the first (grid-stride over blocks): the thermal
+// relaxation rate -(dH/dT_mu) / K from the step's own forward difference (two evaluations of H,
+// Sec. 6.1) must be fast as well.  Passing cells are the candidates for the network and the
+// certification.
+__global__ __launch_bounds__(256) void surr_pretest_thermal_kernel(PreArgs a) {
+  __shared__ float s_tab[TAB_STEP];
+  stage_tables(a.tab, s_tab);
+  const int64_t nitem = (int64_t)*a.nin;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k0 = (int64_t)blockIdx.x * blockDim.x; k0 < nitem; k0 += stride) {
+    const int64_t k = k0 + threadIdx.x;
+    const bool live = k < nitem;
+    const int64_t i = live ? (int64_t)a.in[k] : 0;
+    bool pass = false;
+    if (live) {
+      Rad<float> r;
+      EqS<float> e;
+      double nd, T0, x20, xp0;
+      pre_cell(a, i, r, e, nd, T0, x20, xp0, s_tab);
+      const double muH = a.pd.muH;
+      const double K = nd * muH * K_B / (g_coef64.gamma - 1.0);
+      const double Tmu = T0 * (1.1 + (double)e.xe - x20) / muH;
+      const Tq q = make_tq<float>(T0);
+      const PreLogs pre = pre_logs<float>((float)nd, e, a.pr);
+      const Eval<float> w0 =
+          evaluate<float, false, false>(q, nd, x20, xp0, e, r, coef<float>(), a.pr, s_tab, 0.0, nullptr, false, &pre);
+      const Eval<float> w1 = evaluate<float, false, false>(shift_tq<float>(q, a.pd), nd, x20, xp0, e, r, coef<float>(),
+                                                           a.pr, s_tab, w0.Td, nullptr, false, &pre);
+      const double dH = (w1.H - w0.H) / (a.pd.fd_rel * Tmu);
+      pass = -dH * a.dt >= 0.5 * a.fast * K;  // false for a NaN as well
+    }
+    block_append2<256>(live, pass, (int32_t)i, a.pass, a.npass, a.rej, a.nrej);
+  }
+}
+
+// Certification of candidate k (cell i): true when the prediction's root is accepted (and
+// written to the cell's outputs).
+__device__ __forceinline__ bool accept_cell(const AcceptArgs &a, int64_t k, int64_t i, const float *s_tab) {
   bool ok = false;
-  if (i < a.ncell) {
+  {
     const CoefT<float> &c = coef<float>();
     const ParT<float> &p = a.pr;
     const double muH = a.pd.muH, dt = a.dt, delta = a.pd.fd_rel;
     const double nd = a.n[i];
     Rad<float> r;
-    r.chiPE = a.chiPE[i];
-    r.chiLW = a.chiLW[i];
-    r.chiH2 = a.chiH2[i];
-    r.chiC = a.chiC[i];
-    r.phi = a.phi ? a.phi[i] : 0.f;
-    r.xi = a.xi[i];
-    r.Neff = a.Neff[i];
+    load_rad(r, a.chiPE, a.chiLW, a.chiH2, a.chiC, a.phi, a.xi, a.Neff, i);
     fixed_terms(r, nd, c, p);
     const double T0 = a.T[i], x20 = a.xH2[i], xp0 = a.xHp[i];
     const double K = nd * muH * K_B / (g_coef64.gamma - 1.0);
     // seed, clamped to the physical range
     double u[3];
     if (a.pred) {
-      u[0] = exp10((double)a.pred[3 * i + 2]);
-      u[1] = (double)a.pred[3 * i + 0];
-      u[2] = (double)a.pred[3 * i + 1];
+      u[0] = exp10((double)a.pred[3 * k + 2]);
+      u[1] = (double)a.pred[3 * k + 0];
+      u[2] = (double)a.pred[3 * k + 1];
     } else {
       u[0] = T0;
       u[1] = x20;
@@ -135,7 +285,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
     {
       const EqS<float> e = eq_species<float>(u[0], (float)nd, u[1], u[2], r, c, p, s_tab, CloseTol<float>::v, 50);
       const Eval<float> v = evaluate<float, true, false>(u[0], nd, u[1], u[2], e, r, c, p, s_tab, 0.f, nullptr);
-      if (dt * (2.0 * v.F + v.D) < 0.5 * a.fast || dt * (v.I + v.Rr) < 0.5 * a.fast) u[0] = -1.0;
+      if (!chem_fast(v, dt, a.fast)) u[0] = -1.0;
     }
     double J[3][3], gb[3], h[3] = {0.0, 0.0, 0.0};
     int phase = 0, k = 0, it = 0;
@@ -167,7 +317,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
         if (k == 0) {
           gb[0] = gT; gb[1] = g1; gb[2] = g2;
           // pre-test: both chemical relaxation rates must be fast on their own
-          if (dt * (2.0 * v.F + v.D) < 0.5 * A.fast || dt * (v.I + v.Rr) < 0.5 * A.fast) break;
+          if (!chem_fast(v, dt, A.fast)) break;
           h[1] = 1e-3 * fmax(u[1], 1e-6);
           if (2.0 * (u[1] + h[1]) + u[2] > 1.0) h[1] = -h[1];
           h[2] = 1e-3 * fmax(u[2], 1e-6);
@@ -271,16 +421,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
       if (a.status) a.status[i] = 0;
     }
   }
-  // compact the rejected cells: one atomic per wave
-  const bool rej = i < a.ncell && !ok;
-  const uint64_t m = __ballot(rej);
-  if (m != 0) {
-    const int lane = threadIdx.x & 63;
-    const int leader = __ffsll((unsigned long long)m) - 1;
-    unsigned long long base = 0;
-    if (lane == leader) base = atomicAdd(a.nrej, (unsigned long long)__popcll(m));
-    base = __shfl(base, leader, 64);
-    if (rej) a.rej[base + __popcll(m & ((1ull << lane) - 1ull))] = (int32_t)i;
+  return ok;
+}
+
+// The candidates in a grid-stride loop over waves (the count is known on the device only);
+// rejected candidates are appended to the fallback list.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void accept_kernel(AcceptArgs a) {
+  __shared__ float s_tab[TAB_STEP];
+  stage_tables(a.tab, s_tab);
+  const int lane = threadIdx.x & 63;
+  const int64_t nitem = (int64_t)*a.ncand;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); k0 < nitem; k0 += stride) {
+    const int64_t k = k0 + lane;
+    const bool live = k < nitem;
+    const int64_t i = live ? (int64_t)a.cand[k] : 0;
+    const bool ok = live && accept_cell(a, k, i, s_tab);
+    wave_append(live && !ok, (int32_t)i, a.rej, a.nrej);
   }
 }
 
