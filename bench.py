@@ -239,9 +239,10 @@ def device_conservation(xH2, xHp, xCp, xCO, par_o):
             "min_abundance": float(min(xH2.min(), xHp.min(), cp.min(), co.min()))}
 
 
-def field_errors(out, ref, idx, xCt):
+def field_errors(out, ref, idx, xCt, cells=None):
     """Per-field max / p99 relative error at the sampled cells (floors: 1e-7 for abundances, carbon
-    species relative to x_C,tot), and the fraction of sampled cells over 1e-3 in any field."""
+    species relative to x_C,tot), the fraction of sampled cells over 1e-3 in any field and, with
+    `cells` (the grid index of each sampled cell), the grid indices of the first 8 such cells."""
     rep, worst = {}, np.zeros(len(idx))
     for k in FIELDS:
         fl = 0.0 if k == "T" else 1e-7 * (xCt if k in ("xCp", "xCO") else 1.0)
@@ -251,6 +252,8 @@ def field_errors(out, ref, idx, xCt):
         rep[k] = {"max": float(e.max()), "p99": float(np.percentile(e, 99))}
         worst = np.maximum(worst, e)
     rep["frac_cells_over_1e-3"] = float((worst > 1e-3).mean())
+    if cells is not None:
+        rep["cells_over_1e-3"] = [int(cells[i]) for i in np.nonzero(worst > 1e-3)[0][:8]]
     return rep
 
 
@@ -682,7 +685,7 @@ def bench_pts512(args):
         xCt = par_o.xCtot
         ar = np.arange(len(idx))
         for p in paths:
-            paths[p]["error_vs_oracle"] = field_errors(paths[p]["_res"], ref, ar, xCt)
+            paths[p]["error_vs_oracle"] = field_errors(paths[p]["_res"], ref, ar, xCt, cells=idx)
         cpu = cpu_baseline_pts512(pool, procs, s, dx, par_o, st0, rad_sample, dt, t_or_par, len(idx))
         pool.close()
         pool.join()
