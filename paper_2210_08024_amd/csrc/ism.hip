@@ -174,7 +174,7 @@ void order_cells(uint8_t *base, int64_t n, const unsigned long long *count, cons
   const size_t key_b = (size_t)((n * 2 + 255) / 256 * 256), bins_b = (size_t)ORDER_BINS * 4;
   OrderArgs a{n, count, items, T, nsub, (uint16_t *)base, (uint32_t *)(base + key_b),
               (uint32_t *)(base + key_b + bins_b), (int32_t *)(base + key_b + 2 * bins_b)};
-  const dim3 grid((unsigned)((n + ORDER_THREADS - 1) / ORDER_THREADS));
+  const dim3 grid((unsigned)((n + ORDER_CHUNK - 1) / ORDER_CHUNK));
   hipLaunchKernelGGL(order_zero_kernel, dim3(1), dim3(ORDER_THREADS), 0, stream, a.hist);
   hipLaunchKernelGGL(order_key_kernel, grid, dim3(ORDER_THREADS), 0, stream, a);
   hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(ORDER_THREADS), 0, stream, a);

@@ -9,14 +9,17 @@
 // grouped by how long they will run, longest first.  The order is a
 // counting sort on a 12-bit key: a per-block LDS histogram, an exclusive scan of the 4096
 // bins, and a scatter that reserves one range per (block, bin) with a single global atomic.
-// Within a bin the order depends on atomic timing; results do not.
+// A block takes ORDER_PER items per thread (16,384 items), so that zeroing and flushing its
+// 4096 bins, and its global atomics, are spread over many items.  Within a bin the order depends
+// on atomic timing; results do not.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace ism {
 
-constexpr int ORDER_BITS = 12, ORDER_BINS = 1 << ORDER_BITS, ORDER_THREADS = 1024;
+constexpr int ORDER_BITS = 12, ORDER_BINS = 1 << ORDER_BITS, ORDER_THREADS = 1024, ORDER_PER = 16;
+constexpr int64_t ORDER_CHUNK = (int64_t)ORDER_THREADS * ORDER_PER;  // items per block (key, scatter)
 
 __device__ __forceinline__ uint32_t order_quant(float x, float lo, float hi, int bits) {
   float u = (x - lo) / (hi - lo);
@@ -55,12 +58,16 @@ __global__ __launch_bounds__(ORDER_THREADS) void order_key_kernel(OrderArgs a) {
   for (int b = threadIdx.x; b < ORDER_BINS; b += ORDER_THREADS) h[b] = 0u;
   __syncthreads();
   const int64_t nitem = a.count ? (int64_t)*a.count : a.n;
-  const int64_t i = (int64_t)blockIdx.x * ORDER_THREADS + threadIdx.x;
-  if (i < nitem) {
-    const int64_t cell = a.items ? (int64_t)a.items[i] : i;
-    const uint32_t k = order_key(a.T, a.nsub, cell);
-    a.key[i] = (uint16_t)k;
-    atomicAdd(&h[k], 1u);
+  const int64_t i0 = (int64_t)blockIdx.x * ORDER_CHUNK + threadIdx.x;
+#pragma unroll 4
+  for (int j = 0; j < ORDER_PER; ++j) {
+    const int64_t i = i0 + (int64_t)j * ORDER_THREADS;
+    if (i < nitem) {
+      const int64_t cell = a.items ? (int64_t)a.items[i] : i;
+      const uint32_t k = order_key(a.T, a.nsub, cell);
+      a.key[i] = (uint16_t)k;
+      atomicAdd(&h[k], 1u);
+    }
   }
   __syncthreads();
   for (int b = threadIdx.x; b < ORDER_BINS; b += ORDER_THREADS)
@@ -99,18 +106,27 @@ __global__ __launch_bounds__(ORDER_THREADS) void order_scatter_kernel(OrderArgs 
   for (int b = threadIdx.x; b < ORDER_BINS; b += ORDER_THREADS) cnt[b] = 0u;
   __syncthreads();
   const int64_t nitem = a.count ? (int64_t)*a.count : a.n;
-  const int64_t i = (int64_t)blockIdx.x * ORDER_THREADS + threadIdx.x;
-  uint32_t k = 0, rank = 0;
-  const bool live = i < nitem;
-  if (live) {
-    k = a.key[i];
-    rank = atomicAdd(&cnt[k], 1u);
+  const int64_t i0 = (int64_t)blockIdx.x * ORDER_CHUNK + threadIdx.x;
+  uint32_t k[ORDER_PER], rank[ORDER_PER];
+#pragma unroll
+  for (int j = 0; j < ORDER_PER; ++j) {
+    const int64_t i = i0 + (int64_t)j * ORDER_THREADS;
+    k[j] = 0u;
+    rank[j] = 0u;
+    if (i < nitem) {
+      k[j] = a.key[i];
+      rank[j] = atomicAdd(&cnt[k[j]], 1u);
+    }
   }
   __syncthreads();
   for (int b = threadIdx.x; b < ORDER_BINS; b += ORDER_THREADS)
     if (cnt[b]) base[b] = atomicAdd(&a.cursor[b], cnt[b]);
   __syncthreads();
-  if (live) a.out[base[k] + rank] = a.items ? a.items[i] : (int32_t)i;
+#pragma unroll
+  for (int j = 0; j < ORDER_PER; ++j) {
+    const int64_t i = i0 + (int64_t)j * ORDER_THREADS;
+    if (i < nitem) a.out[base[k[j]] + rank[j]] = a.items ? a.items[i] : (int32_t)i;
+  }
 }
 
 }  // namespace ism
