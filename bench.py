@@ -146,20 +146,20 @@ def copy_bandwidth(reps=3):
 
 
 def cpu_baseline(state, cfg, ncell_sample, par_o):
-    """The CPU oracle on a seeded sample of the same workload (columns for the sampled cells + the step)."""
+    """The CPU oracle on the same workload: its vectorised six-ray columns over the whole 128^3 grid,
+    then its step on a seeded sample of the cells; cell-updates/s = 1 / (columns time per grid cell +
+    step time per sampled cell)."""
     from oracle import columns as ocol
     from oracle import step as ostep
     from oracle.constants import PC, YR
     rng = np.random.default_rng(7)
-    shape = state["n"].shape
     idx = np.sort(rng.choice(state["n"].size, ncell_sample, replace=False))
-    cells = np.stack(np.unravel_index(idx, shape), 1)
     t0 = time.perf_counter()
-    rc = ocol.columns6_cells(state["n"], state["xH2"], None, cfg["dx_pc"] * PC, par_o, cells)
+    rc = ocol.columns6(state["n"], state["xH2"], None, cfg["dx_pc"] * PC, par_o)
     t1 = time.perf_counter()
-    rad = dict(chi_PE=rc["chi_PE"], chi_LW=rc["chi_LW"], chi_H2=rc["chi_H2"], chi_C=rc["chi_C"],
-               phi=np.zeros(len(idx)), xi=rc["xi"], Neff=rc["N_eff"])
-    sel = lambda a: a.ravel()[idx]
+    sel = lambda a: np.ascontiguousarray(np.asarray(a).ravel()[idx])
+    rad = dict(chi_PE=sel(rc["chi_PE"]), chi_LW=sel(rc["chi_LW"]), chi_H2=sel(rc["chi_H2"]), chi_C=sel(rc["chi_C"]),
+               phi=np.zeros(len(idx)), xi=sel(rc["xi"]), Neff=sel(rc["N_eff"]))
     ref = ostep.chem_cool_step(sel(state["n"]), sel(state["T"]), sel(state["xH2"]), sel(state["xHp"]), rad,
                                cfg["dt_yr"] * YR, par_o)
     t2 = time.perf_counter()
@@ -167,41 +167,33 @@ def cpu_baseline(state, cfg, ncell_sample, par_o):
         threads = len(os.sched_getaffinity(0))
     except Exception:
         threads = os.cpu_count()
-    base = {"value": ncell_sample / (t2 - t0), "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{ncell_sample} seeded random cells of the 128^3 grid: oracle six-ray columns for those "
-                      f"cells ({t1 - t0:.1f} s) + oracle step ({t2 - t1:.1f} s), numpy single-threaded; host has "
+    base = {"value": 1.0 / ((t1 - t0) / state["n"].size + (t2 - t1) / ncell_sample), "unit": "cell-updates/s",
+            "cores": 1, "kind": "oracle",
+            "sample": f"the oracle's vectorised six-ray columns over the 128^3 grid ({t1 - t0:.1f} s) + its step on "
+                      f"{ncell_sample} seeded random cells ({t2 - t1:.1f} s), numpy single-threaded; host has "
                       f"{threads} threads"}
-    return base, idx, ref
+    return base, idx, ref, rad
 
 
-# The grid the oracle's worker processes read: set before they are forked, so each inherits it.
-_CPU_SHARED = {}
-
-
-def _cpu_chunk(idx):
-    """One chunk of the parallel oracle baseline: the oracle six-ray columns at the listed cells of
-    the shared 128^3 grid, then the oracle step of those cells.  Returns the cell count."""
-    from oracle import columns as ocol
-    from oracle import step as ostep
+def cpu_parallel(pool, procs, state, cfg, idx, rad, par_o, chunk=4096):
+    """The oracle over the pool of worker processes: its vectorised six-ray columns over eight 64^3
+    sub-boxes of the grid (the same work per cell as the whole grid), then its step on the sampled
+    cells in chunks of `chunk`; cell-updates/s = 1 / (columns time per cell + step time per cell)."""
     from oracle.constants import PC, YR
-    from oracle.constants import Params as OParams
-    state, cfg = _CPU_SHARED["grid"]
-    par_o = OParams(Zg=1.0, Zd=1.0, cr_mode=1)
-    cells = np.stack(np.unravel_index(idx, state["n"].shape), 1)
-    rc = ocol.columns6_cells(state["n"], state["xH2"], None, cfg["dx_pc"] * PC, par_o, cells)
-    rad = dict(chi_PE=rc["chi_PE"], chi_LW=rc["chi_LW"], chi_H2=rc["chi_H2"], chi_C=rc["chi_C"],
-               phi=np.zeros(len(idx)), xi=rc["xi"], Neff=rc["N_eff"])
-    sel = lambda a: a.ravel()[idx]
-    ostep.chem_cool_step(sel(state["n"]), sel(state["T"]), sel(state["xH2"]), sel(state["xHp"]), rad,
-                         cfg["dt_yr"] * YR, par_o)
-    return len(idx)
-
-
-def cpu_parallel(pool, procs, idx, chunk=4096):
-    """The same oracle sample in chunks of `chunk` cells over the pool of worker processes."""
+    m = 64
+    boxes = _sub_boxes(state["n"].shape, m, 8)
+    box = lambda o, k: np.ascontiguousarray(state[k][o[0]:o[0] + m, o[1]:o[1] + m, o[2]:o[2] + m])
+    dx, dt = cfg["dx_pc"] * PC, cfg["dt_yr"] * YR
     t0 = time.perf_counter()
-    done = sum(pool.map(_cpu_chunk, [idx[i:i + chunk] for i in range(0, len(idx), chunk)]))
-    t = time.perf_counter() - t0
+    ncol = sum(pool.map(_oracle_columns_box, [(box(o, "n"), box(o, "xH2"), dx, par_o) for o in boxes]))
+    t_col = time.perf_counter() - t0
+    sel = lambda a, i, j: np.ascontiguousarray(np.asarray(a).ravel()[idx[i:j]])
+    jobs = [(sel(state["n"], i, i + chunk), sel(state["T"], i, i + chunk), sel(state["xH2"], i, i + chunk),
+             sel(state["xHp"], i, i + chunk), {k: v[i:i + chunk] for k, v in rad.items()}, dt, par_o)
+            for i in range(0, len(idx), chunk)]
+    t0 = time.perf_counter()
+    pool.map(_oracle_chunk, jobs)
+    t_step = time.perf_counter() - t0
     model = "unknown"
     try:
         for line in open("/proc/cpuinfo"):
@@ -210,9 +202,10 @@ def cpu_parallel(pool, procs, idx, chunk=4096):
                 break
     except OSError:
         pass
-    return {"value": done / t, "unit": "cell-updates/s", "cores": procs, "kind": "oracle",
-            "sample": f"the same {done} cells in chunks of {chunk} over {procs} worker processes "
-                      f"({t:.1f} s); CPU {model}"}
+    return {"value": 1.0 / (t_col / ncol + t_step / len(idx)), "unit": "cell-updates/s", "cores": procs,
+            "kind": "oracle",
+            "sample": f"columns over 8 sub-boxes of 64^3 ({t_col:.2f} s) + the step of the same {len(idx)} cells in "
+                      f"chunks of {chunk} ({t_step:.1f} s), {procs} worker processes; CPU {model}"}
 
 
 def conservation(res, xCt, xOt):
@@ -739,20 +732,21 @@ def bench_pts512(args):
 
 def cpu_baseline_pts512(pool, procs, s, dx, par_o, st0, rad_sample, dt, t_step_par, nsample):
     """The CPU oracle as it stands on a bounded sample of the 512^3 workload: its vectorised six-ray
-    columns over 96^3 sub-boxes of the grid plus its step on subsample cells (fed the GPU's FP64
-    radiation).  One process: one sub-box and 65,536 cells; all cores: 16 sub-boxes over the pool
-    and the whole subsample (the error report's run).  cell-updates/s = 1 / (columns time per cell
-    + step time per cell)."""
+    columns over sub-boxes of the grid plus its step on subsample cells (fed the GPU's FP64
+    radiation).  One process: one 128^3 sub-box and the whole subsample (about 6 s); all cores: 16
+    sub-boxes of 96^3 over the pool and the whole subsample (the error report's run).
+    cell-updates/s = 1 / (columns time per cell + step time per cell)."""
     from oracle import columns as ocol
     from oracle import step as ostep
-    m = 96
+    m, m1 = 96, 128
     shape = s["n"].shape
     boxes = _sub_boxes(shape, m, 16)
-    box = lambda o, k: np.ascontiguousarray(s[k][o[0]:o[0] + m, o[1]:o[1] + m, o[2]:o[2] + m])
+    box = lambda o, k, e=m: np.ascontiguousarray(s[k][o[0]:o[0] + e, o[1]:o[1] + e, o[2]:o[2] + e])
+    b1 = _sub_boxes(shape, m1, 1)[0]
     t0 = time.perf_counter()
-    ocol.columns6(box(boxes[0], "n"), box(boxes[0], "xH2"), None, dx, par_o)
+    ocol.columns6(box(b1, "n", m1), box(b1, "xH2", m1), None, dx, par_o)
     t_col1 = time.perf_counter() - t0
-    ns = min(65536, nsample)
+    ns = nsample
     t0 = time.perf_counter()
     ostep.chem_cool_step(st0["n"][:ns], st0["T"][:ns], st0["xH2"][:ns], st0["xHp"][:ns],
                          {k: v[:ns] for k, v in rad_sample.items()}, dt, par_o)
@@ -769,11 +763,11 @@ def cpu_baseline_pts512(pool, procs, s, dx, par_o, st0, rad_sample, dt, t_step_p
                 break
     except OSError:
         pass
-    one = 1.0 / (t_col1 / m ** 3 + t_step1 / ns)
+    one = 1.0 / (t_col1 / m1 ** 3 + t_step1 / ns)
     par_v = 1.0 / (t_colp / ncol + t_step_par / nsample)
     return {"value": one, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"the oracle (numpy, FP64) on the 512^3 workload, one process: vectorised six-ray columns over a "
-                      f"96^3 sub-box ({t_col1:.2f} s) + the step of {ns} subsample cells ({t_step1:.1f} s); "
+                      f"{m1}^3 sub-box ({t_col1:.2f} s) + the step of {ns} subsample cells ({t_step1:.1f} s); "
                       f"CPU {model}",
             "parallel": {"value": par_v, "unit": "cell-updates/s", "cores": procs, "kind": "oracle",
                          "sample": f"columns over 16 sub-boxes of 96^3 ({t_colp:.2f} s) + the step of the "
@@ -825,11 +819,8 @@ def main():
         sys.exit(2)
     pool, procs = None, 0
     if not args.no_cpu:
-        # the oracle's worker processes are forked before torch is imported and the GPU touched;
-        # they inherit the grid
+        # the oracle's worker processes are forked before torch is imported and the GPU touched
         import multiprocessing as mp
-        from paper_2210_08024_amd import workloads as wl
-        _CPU_SHARED["grid"] = wl.make("grf128")
         try:
             procs = max(1, min(16, len(os.sched_getaffinity(0))))
         except Exception:
@@ -840,7 +831,7 @@ def main():
     from oracle.census import substep_census
     from oracle.constants import Params as OParams
 
-    state, cfg = _CPU_SHARED["grid"] if "grid" in _CPU_SHARED else workloads.make("grf128")
+    state, cfg = workloads.make("grf128")
     shape = state["n"].shape
     N = state["n"].size
     dev = torch.device("cuda:0")
@@ -982,8 +973,9 @@ def main():
                    "columns_hbm_GBs_algorithmic_mixed": N * 48 / (paths["mixed"]["columns_ms"] * 1e-3) / 1e9},
     }
     if not args.no_cpu:
-        base, idx, ref = cpu_baseline(state, cfg, args.cpu_cells, OParams(Zg=1.0, Zd=1.0, cr_mode=1))
-        base["parallel"] = cpu_parallel(pool, procs, idx)
+        par_cpu = OParams(Zg=1.0, Zd=1.0, cr_mode=1)
+        base, idx, ref, rad_cpu = cpu_baseline(state, cfg, args.cpu_cells, par_cpu)
+        base["parallel"] = cpu_parallel(pool, procs, state, cfg, idx, rad_cpu, par_cpu)
         pool.close()
         pool.join()
         out["cpu_baseline"] = base
