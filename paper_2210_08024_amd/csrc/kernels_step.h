@@ -196,11 +196,15 @@ __global__ __launch_bounds__(256) void step_simple_kernel(StepArgs<R> a) {
 // closure) whenever any lane takes it, so taking it for a dozen lanes at once beats taking it
 // for one or two lanes in nearly every pass.  Every lane leaves once the counter passes ncell
 // and its cell is done; *a.queue must hold the number of lanes in the grid at launch.
-// Two waves per SIMD: measured fastest for both precisions (more waves spill to scratch).
+// Waves per SIMD: two for the FP64 kernel (250 registers; three would spill to scratch), three
+// for the mixed one, which fits 168 registers without spilling and hides more latency.
 constexpr int REFILL_BATCH = 12;
+template <class R> struct StepWaves { static constexpr int v = 2; };
+template <> struct StepWaves<float> { static constexpr int v = 3; };
 
 template <class R>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void step_queue_kernel(StepArgs<R>) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StepWaves<R>::v))) void step_queue_kernel(
+    StepArgs<R>) {
   using A = StepArgs<R>;
   __shared__ R s_tab[TAB_STEP];
   stage_tables(kernel_args<A>().tab, s_tab);
