@@ -56,7 +56,8 @@ struct StepArgs {
 template <class R>
 struct CellState {
   double nd, K, Tmu, xH2, xHp, t;
-  Rad<R> r;
+  Rad<R> *r;  // the cell's radiation and fixed terms: the lane's slot in LDS (it frees 24
+              // registers a lane in FP64, read once or twice per evaluation)
   EqS<R> e;
   double tdi, tds;  // the last dust temperature as a line in T: T_d ~ tdi + tds T
   int32_t ns;
@@ -67,20 +68,22 @@ template <class R>
 __device__ __forceinline__ void cell_begin(const StepArgs<R> &a, int64_t i, CellState<R> &s, const R *tab) {
   const CoefT<R> &c = coef<R>();
   s.nd = a.n[i];
-  s.r.chiPE = a.chiPE[i];
-  s.r.chiLW = a.chiLW[i];
-  s.r.chiH2 = a.chiH2[i];
-  s.r.chiC = a.chiC[i];
-  s.r.phi = a.phi ? a.phi[i] : R(0);
-  s.r.xi = a.xi[i];
-  s.r.Neff = a.Neff[i];
-  fixed_terms(s.r, s.nd, c, a.pr);
+  Rad<R> rr;
+  rr.chiPE = a.chiPE[i];
+  rr.chiLW = a.chiLW[i];
+  rr.chiH2 = a.chiH2[i];
+  rr.chiC = a.chiC[i];
+  rr.phi = a.phi ? a.phi[i] : R(0);
+  rr.xi = a.xi[i];
+  rr.Neff = a.Neff[i];
+  fixed_terms(rr, s.nd, c, a.pr);
+  *s.r = rr;
   const double T0 = a.T[i];
   s.xH2 = a.xH2[i];
   s.xHp = a.xHp[i];
   const double muH = a.pd.muH;
   s.K = s.nd * muH * K_B / (g_coef64.gamma - 1.0);
-  s.e = eq_species<R>(T0, R(s.nd), s.xH2, s.xHp, s.r, c, a.pr, tab, CloseTol<R>::v, 50);
+  s.e = eq_species<R>(T0, R(s.nd), s.xH2, s.xHp, *s.r, c, a.pr, tab, CloseTol<R>::v, 50);
   s.Tmu = T0 * (1.1 + (double)s.e.xe - s.xH2) / muH;
   s.t = 0.0;
   s.ns = 0;
@@ -106,7 +109,7 @@ __device__ __forceinline__ bool cell_substep(const StepArgs<R> &a, CellState<R> 
   bool td_bad = false;
 #pragma unroll 1
   for (int k = 0; k < 2; ++k) {
-    const Eval<R> w = evaluate<R, false, false>(qk, s.nd, s.xH2, s.xHp, s.e, s.r, c, p, tab,
+    const Eval<R> w = evaluate<R, false, false>(qk, s.nd, s.xH2, s.xHp, s.e, *s.r, c, p, tab,
                                                 s.tdi + s.tds * qk.T, nullptr, k == 0, &pre);
     td_bad = td_bad || w.td_bad;
     if (k == 0) {
@@ -136,13 +139,13 @@ __device__ __forceinline__ bool cell_substep(const StepArgs<R> &a, CellState<R> 
   // abundances: rate coefficients at T^{n+1} = mu^n T_mu^{n+1}, abundance factors frozen at step n
   const double Tp = muH * Tmu_new / mu_den;
   const Tq qp = make_tq<R>(Tp);  // shared by the rates and the closure at T^{n+1}
-  Eval<R> vc = evaluate<R, true, false>(qp, s.nd, s.xH2, s.xHp, s.e, s.r, c, p, tab, 0.0, nullptr);
+  Eval<R> vc = evaluate<R, true, false>(qp, s.nd, s.xH2, s.xHp, s.e, *s.r, c, p, tab, 0.0, nullptr);
   const double F = vc.F, D = vc.D, I = vc.I, Rr = vc.Rr;
   const double det = 1.0 + dts * (2.0 * F + D + I + Rr) + dts * dts * (2.0 * F * Rr + D * I + D * Rr);
   const double idet = 1.0 / det;
   const double xa = (s.xH2 * (1.0 + dts * (I + Rr)) + F * dts * (1.0 - s.xHp) + F * dts * dts * Rr) * idet;
   const double xb = (s.xHp * (1.0 + dts * (2.0 * F + D)) + I * dts * (1.0 - 2.0 * s.xH2) + I * dts * dts * D) * idet;
-  s.e = eq_species<R>(qp, R(s.nd), xa, xb, s.r, c, p, tab, CloseTol<R>::v, 50);
+  s.e = eq_species<R>(qp, R(s.nd), xa, xb, *s.r, c, p, tab, CloseTol<R>::v, 50);
   const bool fin = isfinite(Tmu_new) && isfinite(xa) && isfinite(xb);
   if (!fin) s.st |= ISM_ST_NONFINITE;
   const bool last = (dts == rem);
@@ -179,9 +182,11 @@ template <class R>
 __global__ __launch_bounds__(256) void step_simple_kernel(StepArgs<R> a) {
   __shared__ R s_tab[TAB_STEP];
   stage_tables(a.tab, s_tab);
+  __shared__ Rad<R> s_rad[256];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.ncell) return;
   CellState<R> s;
+  s.r = &s_rad[threadIdx.x];
   cell_begin(a, i, s, s_tab);
   while (!cell_substep(a, s, s_tab)) {
   }
@@ -196,15 +201,14 @@ __global__ __launch_bounds__(256) void step_simple_kernel(StepArgs<R> a) {
 // closure) whenever any lane takes it, so taking it for a dozen lanes at once beats taking it
 // for one or two lanes in nearly every pass.  Every lane leaves once the counter passes ncell
 // and its cell is done; *a.queue must hold the number of lanes in the grid at launch.
-// Waves per SIMD: two for the FP64 kernel (250 registers; three would spill to scratch), three
-// for the mixed one, which fits 168 registers without spilling and hides more latency.
+// Three waves per SIMD for both precisions (168 registers a lane): the third wave hides more of
+// the long dependent transcendental sequences than two waves with more registers do.  The FP64
+// kernel fits there because the lane's radiation terms live in LDS and the cooling terms are
+// summed as they are formed.
 constexpr int REFILL_BATCH = 12;
-template <class R> struct StepWaves { static constexpr int v = 2; };
-template <> struct StepWaves<float> { static constexpr int v = 3; };
 
 template <class R>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StepWaves<R>::v))) void step_queue_kernel(
-    StepArgs<R>) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void step_queue_kernel(StepArgs<R>) {
   using A = StepArgs<R>;
   __shared__ R s_tab[TAB_STEP];
   stage_tables(kernel_args<A>().tab, s_tab);
@@ -212,7 +216,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StepWaves<R
   const int64_t nitem = kernel_args<A>().count ? (int64_t)*kernel_args<A>().count : kernel_args<A>().ncell;
   int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool active = cell < nitem;
+  __shared__ Rad<R> s_rad[256];
   CellState<R> s;
+  s.r = &s_rad[threadIdx.x];
   if (active) {
     const A &a = kernel_args<A>();
     cell_begin(a, a.idx ? (int64_t)a.idx[cell] : cell, s, s_tab);

@@ -380,7 +380,7 @@ __device__ __forceinline__ bool accept_cell(const AcceptArgs &a, int64_t k, int6
         CellState<float> cs;
         cs.nd = nd;
         cs.K = K;
-        cs.r = r;
+        cs.r = &r;
         cs.e = eq_species<float>(y0, (float)nd, y1, y2, r, c, p, s_tab, CloseTol<float>::v, 50);
         cs.Tmu = y0 * (1.1 + (double)cs.e.xe - y1) / muH;
         cs.xH2 = y1;

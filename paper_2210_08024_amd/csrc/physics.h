@@ -574,8 +574,15 @@ __device__ Eval<R> evaluate(const Tq &q, double n_d, double xH2_d, double xHp_d,
                 : std::is_same<R, double>::value ? nL0 * Llte / (nL0 + Llte) : nL0 / (R(1) + nL0 / Llte);
     l_rv = xH2 * L * inv_n;
   }
+  // the cooling terms are summed as they are formed, each partial sum pinned by an empty asm, so
+  // that a term's registers are free once it is added (holding the thirteen terms to one final
+  // sum made this the kernel's register peak)
+  double hyd = (double)l_lya + (double)l_ci + (double)l_rv + (double)l_cd;
+  asm volatile("" : "+v"(hyd));
   const R l_ff = c.ff[0] * c.ff[1] * sqrtT * xe * xHp;
   const R l_rr = aB * R(K_B) * Tr * R(cd.rr_energy[0] + cd.rr_energy[1] * q.lnT4) * xe * xHp;
+  hyd = hyd + (double)l_ff + (double)l_rr;
+  asm volatile("" : "+v"(hyd));
   // C+ 2-level
   R l_cp;
   {
@@ -588,10 +595,16 @@ __device__ Eval<R> evaluate(const Tq &q, double n_d, double xH2_d, double xHp_d,
     const R f1 = dvp<R>(C01, C01 + C10 + A10);
     l_cp = e.xCp * f1 * A10 * R(K_B) * E10 * inv_n;
   }
+  double mid = (double)l_cp;
+  asm volatile("" : "+v"(mid));
   const R l_c = e.xC * three_level_cool<R>(q, n, inv_n, xH, xH2, xe, cd.c_levels, cd.c_rat, cd.c_coll, cd.c_ncrit_H,
                                              cd.fs_slope_C);
+  mid = mid + (double)l_c;
+  asm volatile("" : "+v"(mid));
   const R l_o = e.xO * three_level_cool<R>(q, n, inv_n, xH, xH2, xe, cd.o_levels, cd.o_rat, cd.o_coll, cd.o_ncrit_H,
                                              cd.fs_slope_O);
+  mid = mid + (double)l_o;
+  asm volatile("" : "+v"(mid));
   R l_co;
   {
     const double lT = q.lnT * INV_LN10D;
@@ -602,6 +615,8 @@ __device__ Eval<R> evaluate(const Tq &q, double n_d, double xH2_d, double xHp_d,
     // L0 / (1 + n / n_half) as one division; n + n_half >= n
     l_co = dvp<R>(e.xCO * L0 * nh, nh + n);
   }
+  mid = mid + (double)l_co;
+  asm volatile("" : "+v"(mid));
   const R l_gr =
       c.grrec[0] * Mx<R>::ex(cd.grrec[1] * q.lnT + cd.grrec[2] * (double)Mx<R>::ex(-cd.grrec[3] * q.lnT) * lnpsi) *
       xe * Zd;
@@ -619,6 +634,8 @@ __device__ Eval<R> evaluate(const Tq &q, double n_d, double xH2_d, double xHp_d,
                               : (expo > 0.0 ? R(0) : (expo < 0.0 ? R(INFINITY) : R(1)));
     l_neb = Zg * xe * xHp * c.neb[0] * ef / (sqrtT4 * (R(1) + c.neb[2] * dens));
   }
+  mid = mid + (double)l_gr + (double)l_neb;
+  asm volatile("" : "+v"(mid));
   // dust temperature to double accuracy on both paths: where gas and dust are coupled T_d -> T,
   // and the gas-dust term goes as T - T_d.  The float path solves in float and takes one Newton
   // step in double from the float root (relative error ~1e-7 before it, ~1e-14 after)
@@ -641,10 +658,8 @@ __device__ Eval<R> evaluate(const Tq &q, double n_d, double xH2_d, double xHp_d,
   const double lgT = q.lnT * INV_LN10D;
   const R l_cie = Mx<R>::ex(LN10D * (cie_lookup(tab, lgT, 0) - TAB_LOG_OFFSET)) +
                   Zg * Mx<R>::ex(LN10D * (cie_lookup(tab, lgT, 1) - TAB_LOG_OFFSET));
-  const double l_hyd = (double)l_lya + (double)l_ci + (double)l_rv + (double)l_cd + (double)l_ff + (double)l_rr;
-  const double mid = (double)l_cp + (double)l_c + (double)l_o + (double)l_co + (double)l_gr + (double)l_neb +
-                     (double)l_gd;
-  v.Lambda = l_hyd + (1.0 - (double)S) * mid + (double)S * (double)l_cie;
+  mid = mid + (double)l_gd;
+  v.Lambda = hyd + (1.0 - (double)S) * mid + (double)S * (double)l_cie;
   v.H = n_d * v.Gamma - n_d * n_d * v.Lambda;
   if (DIAG) {
     diag[DG_TD] = Td; diag[DG_GPE] = g_pe; diag[DG_GCR] = g_cr; diag[DG_GPI] = g_pi; diag[DG_GH2] = g_h2;
