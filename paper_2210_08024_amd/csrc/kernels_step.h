@@ -201,14 +201,17 @@ __global__ __launch_bounds__(256) void step_simple_kernel(StepArgs<R> a) {
 // closure) whenever any lane takes it, so taking it for a dozen lanes at once beats taking it
 // for one or two lanes in nearly every pass.  Every lane leaves once the counter passes ncell
 // and its cell is done; *a.queue must hold the number of lanes in the grid at launch.
-// Three waves per SIMD for both precisions (168 registers a lane): the third wave hides more of
-// the long dependent transcendental sequences than two waves with more registers do.  The FP64
-// kernel fits there because the lane's radiation terms live in LDS and the cooling terms are
-// summed as they are formed.
+// Waves per SIMD: three for the FP64 kernel (168 registers a lane), four for the mixed one (128):
+// more waves hide more of the long dependent transcendental sequences than fewer waves with more
+// registers do.  The kernels fit there because the lane's radiation terms live in LDS and the
+// cooling terms are summed as they are formed.
 constexpr int REFILL_BATCH = 12;
+template <class R> struct StepWaves { static constexpr int v = 3; };
+template <> struct StepWaves<float> { static constexpr int v = 4; };
 
 template <class R>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void step_queue_kernel(StepArgs<R>) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StepWaves<R>::v))) void step_queue_kernel(
+    StepArgs<R>) {
   using A = StepArgs<R>;
   __shared__ R s_tab[TAB_STEP];
   stage_tables(kernel_args<A>().tab, s_tab);
