@@ -275,7 +275,8 @@ __device__ __forceinline__ void cell_atten(double y, double &e, double &gy) {
 template <class R>
 __global__ __launch_bounds__(CT_THREADS) void columns_tile_kernel(TileArgs t) {
   __shared__ double s_cs[CS_NX * CS_NY];
-  __shared__ double s_eP[CT_NS], s_eL[CT_NS], s_h2[CT_NS], s_c[CT_NS];
+  // per cell of the tile: (e^-y PE, e^-y LW) and (N_H2, N_C) of the cell, read as 16-byte pairs
+  __shared__ double2 s_e[CT_NS], s_q[CT_NS];
   // per axis and pencil of the tile: Pf Lf H2f Cf (forward ray at the tile's entry face) and
   // Pb Lb H2b Cb (backward ray); pencils x: (y, z), y: (x, z), z: (x, y), index a + 8 b
   __shared__ double s_off[3][64][8];
@@ -302,10 +303,8 @@ __global__ __launch_bounds__(CT_THREADS) void columns_tile_kernel(TileArgs t) {
       cell_atten<R>(a.sPE * qH, eP, gP);
       cell_atten<R>(a.sLW * qH, eL, gL);
       const int sl = ct_slot(lx, ly, z);
-      s_eP[sl] = eP;
-      s_eL[sl] = eL;
-      s_h2[sl] = qH2;
-      s_c[sl] = qC;
+      s_e[sl] = make_double2(eP, eL);
+      s_q[sl] = make_double2(qH2, qC);
     }
     // the offsets of the tile's 3 x 64 pencils, dust columns turned into attenuation factors
     if (tid < 3 * 64) {
@@ -352,32 +351,41 @@ __global__ __launch_bounds__(CT_THREADS) void columns_tile_kernel(TileArgs t) {
     for (int zz = 0; zz < CT / 4; ++zz) {
       const int z = (CT / 4) * wv + zz, gz = tz * CT + z;
       const int sl = ct_slot(lx, ly, z);
-      const double hH2 = 0.5 * s_h2[sl], hC = 0.5 * s_c[sl];
+      const double2 qq = s_q[sl];
+      const double hH2 = 0.5 * qq.x, hC = 0.5 * qq.y;
       double acc[4] = {0.0, 0.0, 0.0, 0.0};
       // the six rays in the order +x, -x, +y, -y, +z, -z: the offset at the tile face times the
       // factors of the tile's cells the ray crosses before this one
 #pragma unroll 1
-      for (int d = 0; d < 6; ++d) {
-        const int ax = d >> 1;
-        const bool bwd = d & 1;
+      for (int ax = 0; ax < 3; ++ax) {
         const int mine = ax == 0 ? lx : (ax == 1 ? ly : z);
         const int pen = ax == 0 ? ly + 8 * z : (ax == 1 ? lx + 8 * z : lane);
         const int stride = ax == 0 ? 1 : (ax == 1 ? CT + 1 : CT * (CT + 1));
         const int base = ax == 0 ? ct_slot(0, ly, z) : (ax == 1 ? ct_slot(lx, 0, z) : ct_slot(lx, ly, 0));
-        const double *o = s_off[ax][pen] + (bwd ? 4 : 0);
-        RayIn r{o[0], o[1], o[2], o[3]};
+        const double *o = s_off[ax][pen];
+        RayIn f{o[0], o[1], o[2], o[3]}, b{o[4], o[5], o[6], o[7]};
+        // the forward and the backward ray of the axis in one pass over the pencil: each cell's
+        // factors are read once and multiply into whichever ray has crossed the cell
 #pragma unroll
         for (int k = 0; k < CT; ++k) {
           const int s2 = base + k * stride;
-          const double eP = s_eP[s2], eL = s_eL[s2], h = s_h2[s2], c = s_c[s2];
-          if (bwd ? k > mine : k < mine) {
-            r.P *= eP;
-            r.L *= eL;
-            r.H2 += h;
-            r.C += c;
+          const double2 ee = s_e[s2], qv = s_q[s2];
+          const double eP = ee.x, eL = ee.y, h = qv.x, c = qv.y;
+          if (k < mine) {
+            f.P *= eP;
+            f.L *= eL;
+            f.H2 += h;
+            f.C += c;
+          }
+          if (k > mine) {
+            b.P *= eP;
+            b.L *= eL;
+            b.H2 += h;
+            b.C += c;
           }
         }
-        add_ray<R>(r, hH2, hC, s_cs, acc);
+        add_ray<R>(f, hH2, hC, s_cs, acc);
+        add_ray<R>(b, hH2, hC, s_cs, acc);
       }
       if (in_xy && gz < a.nz) {
         const int64_t idx = ((int64_t)gz * a.ny + gy) * a.nx + gx;
