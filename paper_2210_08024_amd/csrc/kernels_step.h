@@ -99,7 +99,9 @@ __device__ __forceinline__ bool cell_substep(const StepArgs<R> &a, CellState<R> 
   const ParT<R> &p = a.pr;
   const double muH = a.pd.muH, eps = a.pd.eps_sub, delta = a.pd.fd_rel, dt = a.dt;
   const double mu_den = 1.1 + (double)s.e.xe - s.xH2;
-  const double Ta = muH * s.Tmu / mu_den;
+  // quotients whose denominators are positive and of normal size (mu, T_mu, K, the update's
+  // determinant >= 1): the reciprocal-based division
+  const double Ta = fdivp(muH * s.Tmu, mu_den);
   // H at T and at T (1 + fd_rel): one instance of the evaluation, run twice.  Each dust
   // temperature solve starts from the last one carried along its slope.
   Tq qk = make_tq<R>(Ta);
@@ -129,20 +131,20 @@ __device__ __forceinline__ bool cell_substep(const StepArgs<R> &a, CellState<R> 
   if (aH > 0.0) dts = fmin(dts, eps * en / aH);
   if (a1 > 0.0) dts = fmin(dts, eps / a1);
   if (a2 > 0.0) dts = fmin(dts, eps / a2);
-  const double dH = (H2 - H) / (delta * s.Tmu);
+  const double dH = fdivp(H2 - H, delta * s.Tmu);
   double den = s.K - dts * dH;
   if (den <= 0.1 * s.K) { den = s.K; s.st |= ISM_ST_DENOM_GUARD; }
   if (td_bad) s.st |= ISM_ST_TD_UNBRACKETED;
-  double Tmu_new = s.Tmu + dts * H / den;
-  const double Tmu_min = a.pd.T_floor * mu_den / muH;
+  double Tmu_new = s.Tmu + fdivp(dts * H, den);
+  const double Tmu_min = fdivp(a.pd.T_floor * mu_den, muH);
   if (Tmu_new < Tmu_min) { Tmu_new = Tmu_min; s.st |= ISM_ST_T_FLOOR; }
   // abundances: rate coefficients at T^{n+1} = mu^n T_mu^{n+1}, abundance factors frozen at step n
-  const double Tp = muH * Tmu_new / mu_den;
+  const double Tp = fdivp(muH * Tmu_new, mu_den);
   const Tq qp = make_tq<R>(Tp);  // shared by the rates and the closure at T^{n+1}
   Eval<R> vc = evaluate<R, true, false>(qp, s.nd, s.xH2, s.xHp, s.e, *s.r, c, p, tab, 0.0, nullptr);
   const double F = vc.F, D = vc.D, I = vc.I, Rr = vc.Rr;
   const double det = 1.0 + dts * (2.0 * F + D + I + Rr) + dts * dts * (2.0 * F * Rr + D * I + D * Rr);
-  const double idet = 1.0 / det;
+  const double idet = fdivp(1.0, det);
   const double xa = (s.xH2 * (1.0 + dts * (I + Rr)) + F * dts * (1.0 - s.xHp) + F * dts * dts * Rr) * idet;
   const double xb = (s.xHp * (1.0 + dts * (2.0 * F + D)) + I * dts * (1.0 - 2.0 * s.xH2) + I * dts * dts * D) * idet;
   s.e = eq_species<R>(qp, R(s.nd), xa, xb, *s.r, c, p, tab, CloseTol<R>::v, 50);

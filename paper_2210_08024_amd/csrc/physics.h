@@ -377,7 +377,9 @@ __device__ R dust_T(R T, R sqrtT, R n, R G, R guess, R Tbb, const CoefT<R> &c, b
     const R g = A * x2 * (x4 - Tbb4) + B * x - rhs;
     if (g >= R(0)) hi = x; else lo = x;
     dg = A * (R(6) * x4 * x - R(2) * Tbb4 * x) + B;
-    const R step = g / dg;
+    // (dg > 0 above 0.76 T_bb; below it a step that leaves the bracket is replaced by bisection,
+    // whatever its value)
+    const R step = dvp<R>(g, dg);
     R xn = x - step;
     // converged: tested before the bracket safeguard, which would otherwise take a root hit
     // exactly (g = 0 makes x the new upper end, so the step lands on it) for a Newton step
