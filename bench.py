@@ -38,7 +38,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3           # packed FP32 (two lanes per instruction)
-FP32_ISSUE_PEAK_TFLOPS = 78.6      # what this build can issue: packed FP32 is kept out of the code
+FP32_ISSUE_PEAK_TFLOPS = 78.6      # what the library's code can issue: packed FP32 is kept out of it
 BF16_PEAK_TFLOPS = 2500.0
 MLP_FLOP_PER_CELL = 2 * (10 * 128 + 2 * 128 * 128 + 128 * 3)
 FIELDS = ("T", "xH2", "xHp", "xe", "xCp", "xCO")
@@ -71,7 +71,7 @@ def parse():
 
 
 def kernel_source_hash():
-    """SHA-256 over the HIP sources of the library: traffic counters stay valid only for this build."""
+    """SHA-256 over the HIP sources of the library: traffic counters stay valid only for these sources."""
     import hashlib
     d = os.path.join(ROOT, "paper_2210_08024_amd", "csrc")
     h = hashlib.sha256()
@@ -435,7 +435,7 @@ def bench_train(args):
     import torch
     from paper_2210_08024_amd import ism
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
+        print(json.dumps({"error": "the library runs on one GPU; --gpus above 1 is not supported"}))
         sys.exit(2)
     torch.cuda.set_device(0)
     ism.init(0)
@@ -810,11 +810,11 @@ def main():
         return bench_train(args)
     if args.workload in ("pts256", "pts512"):
         if args.gpus != 1:
-            print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
+            print(json.dumps({"error": "the library runs on one GPU; --gpus above 1 is not supported"}))
             sys.exit(2)
         return bench_pts256(args) if args.workload == "pts256" else bench_pts512(args)
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported "
+        print(json.dumps({"error": "the library runs on one GPU; --gpus above 1 is not supported "
                                    "(the source step is per-cell independent; see the sharding notes)"}))
         sys.exit(2)
     pool, procs = None, 0

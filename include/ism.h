@@ -314,7 +314,7 @@ ism_status ism_chem_cool_step_noalloc(const ism_params *p, ism_precision prec, i
  * run on the matrix cores with BF16 operands (weights, layer inputs and, backward, the
  * error signal) and FP32 accumulation; the master weights and the Adam moments are FP32.
  * The surrogate is not part of the paper's method: the plain step above is its teacher,
- * its fallback and its judge.
+ * its fallback and the reference its results are checked against.
  *
  * Parameters (flat FP32, ISM_SURR_NPARAM values, row-major W[out][in]):
  *   W1[128x10] b1[128] W2[128x128] b2[128] W3[128x128] b3[128] W4[3x128] b4[3].
