@@ -173,7 +173,12 @@ void order_cells(uint8_t *base, int64_t n, const unsigned long long *count, cons
                  const int32_t *nsub, int32_t **out, hipStream_t stream) {
   const size_t key_b = (size_t)((n * 2 + 255) / 256 * 256), bins_b = (size_t)ORDER_BINS * 4;
   OrderArgs a{n, count, items, T, nsub, (uint16_t *)base, (uint32_t *)(base + key_b),
-              (uint32_t *)(base + key_b + bins_b), (int32_t *)(base + key_b + 2 * bins_b)};
+              (uint32_t *)(base + key_b + bins_b), (int32_t *)(base + key_b + 2 * bins_b), 0};
+  // the slab of a cell: the top ORDER_BITS - ORDER_T_BITS bits of its index below n (the cells
+  // of a list are grid indices below n as well)
+  int bits = 0;
+  while (bits < 62 && ((int64_t)1 << bits) < n) ++bits;
+  a.cshift = bits > ORDER_BITS - ORDER_T_BITS ? bits - (ORDER_BITS - ORDER_T_BITS) : 0;
   const dim3 grid((unsigned)((n + ORDER_CHUNK - 1) / ORDER_CHUNK));
   hipLaunchKernelGGL(order_zero_kernel, dim3(1), dim3(ORDER_THREADS), 0, stream, a.hist);
   hipLaunchKernelGGL(order_key_kernel, grid, dim3(ORDER_THREADS), 0, stream, a);

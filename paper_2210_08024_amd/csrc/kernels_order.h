@@ -27,14 +27,23 @@ __device__ __forceinline__ uint32_t order_quant(float x, float lo, float hi, int
   return (uint32_t)(u * (float)((1 << bits) - 1) + 0.5f);
 }
 
-// Key of one cell: log10 T in [0, 8) on 12 bits, or, with previous substep counts, log2 of the
-// count in [0, 17] on 12 bits.  Bins are visited from high to low (hot to cold, long to short).
-__device__ __forceinline__ uint32_t order_key(const double *T, const int32_t *nsub, int64_t cell) {
+// Key of one cell: log10 T in [0, 8) in 16 bins of half a decade (the top 4 of the 12 bits)
+// with the cell's place in the grid below it (its index's top 8 bits: 256 slabs), or, with
+// previous substep counts, log2 of the count in [0, 17] on 12 bits.  Keys are visited from high
+// to low (hot to cold, long to short).  The temperature bins are coarse on purpose: the lanes of
+// a wave then take cells of one slab, near each other, and share the lines of their loads; with
+// 4096 temperature bins the runs of one bin and block are a few cells long and every lane's
+// load pulls its own line.  The slab bits keep that grouping also for item lists in no
+// particular order (the surrogate step's fallback list).
+constexpr int ORDER_T_BITS = 4;
+__device__ __forceinline__ uint32_t order_key(const double *T, const int32_t *nsub, int64_t cell, int cshift) {
   if (nsub) {
     const int32_t c = nsub[cell];
     return (uint32_t)(ORDER_BINS - 1) - order_quant(log2f((float)(c > 1 ? c : 1)), 0.f, 17.f, ORDER_BITS);
   }
-  return (uint32_t)(ORDER_BINS - 1) - order_quant(log10f((float)T[cell]), 0.f, 8.f, ORDER_BITS);
+  return (uint32_t)(ORDER_BINS - 1) -
+         ((order_quant(log10f((float)T[cell]), 0.f, 8.f, ORDER_T_BITS) << (ORDER_BITS - ORDER_T_BITS)) |
+          ((uint32_t)(cell >> cshift) & ((1u << (ORDER_BITS - ORDER_T_BITS)) - 1u)));
 }
 
 struct OrderArgs {
@@ -47,6 +56,7 @@ struct OrderArgs {
   uint32_t *hist;                     // ORDER_BINS counts
   uint32_t *cursor;                   // ORDER_BINS running offsets
   int32_t *out;                       // ordered cells
+  int32_t cshift;                     // cell index >> cshift: the slab (top 8 bits of the index)
 };
 
 __global__ __launch_bounds__(ORDER_THREADS) void order_zero_kernel(uint32_t *hist) {
@@ -64,7 +74,7 @@ __global__ __launch_bounds__(ORDER_THREADS) void order_key_kernel(OrderArgs a) {
     const int64_t i = i0 + (int64_t)j * ORDER_THREADS;
     if (i < nitem) {
       const int64_t cell = a.items ? (int64_t)a.items[i] : i;
-      const uint32_t k = order_key(a.T, a.nsub, cell);
+      const uint32_t k = order_key(a.T, a.nsub, cell, a.cshift);
       a.key[i] = (uint16_t)k;
       atomicAdd(&h[k], 1u);
     }
