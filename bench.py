@@ -70,15 +70,24 @@ def parse():
     return ap.parse_args()
 
 
+def _code_only(src):
+    """C++ source without its comments and blank lines (string and character literals kept)."""
+    import re
+    pat = re.compile(r'//[^\n]*|/\*.*?\*/|"(?:\\.|[^"\\])*"|\'(?:\\.|[^\'\\])*\'', re.S)
+    code = pat.sub(lambda m: "" if m.group(0).startswith("/") else m.group(0), src)
+    return "\n".join(ln.rstrip() for ln in code.splitlines() if ln.strip())
+
+
 def kernel_source_hash():
-    """SHA-256 over the HIP sources of the library: traffic counters stay valid only for these sources."""
+    """SHA-256 over the code of the library's HIP sources (comments left out): traffic counters
+    stay valid only while the code they were taken on is unchanged."""
     import hashlib
     d = os.path.join(ROOT, "paper_2210_08024_amd", "csrc")
     h = hashlib.sha256()
     for f in sorted(os.listdir(d)):
         if f.endswith((".h", ".hip")):
             h.update(f.encode())
-            h.update(open(os.path.join(d, f), "rb").read())
+            h.update(_code_only(open(os.path.join(d, f), encoding="utf-8").read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -87,8 +87,8 @@ typedef struct {
   int32_t kgr_const;    /* 1: k_gr = 3e-17 Z'_d (Sec. 7); 0: Eq. e:H2form                 */
   int32_t h2_rovib;     /* 1: include H2 ro-vibrational cooling                           */
   int32_t max_substeps; /* substep cap per cell (100000)                                   */
-  int32_t order_cells;  /* step calls: 1 (default) process cells grouped by temperature (half
-                           a decade) and, within that, by slab of the grid, so that the lanes
+  int32_t order_cells;  /* step calls: 1 (default) process cells grouped by temperature (about
+                           half a decade) and, within that, by slab of the grid, so that the lanes
                            of a wave stay in one regime and load nearby cells; 0 in index order;
                            2 (ism_chem_cool_step with an nsub array) grouped by the
                            substep counts nsub holds on entry, e.g. the previous step's

@@ -4,7 +4,8 @@
 // lanes run the same instruction stream, so lanes whose cells sit in different temperature
 // regimes execute both sides of every regime branch, and lanes whose cells need different
 // numbers of substeps refill at different times.  Grouping cells with similar input
-// temperature into the same waves removes most of that divergence.  When the caller holds the
+// temperature into the same waves removes most of that divergence, and taking the cells of a
+// group slab by slab through the grid keeps a wave's loads on nearby lines.  When the caller holds the
 // substep counts of the previous step of the same cells, they are the better key: cells are
 // grouped by how long they will run, longest first.  The order is a
 // counting sort on a 12-bit key: a per-block LDS histogram, an exclusive scan of the 4096
@@ -27,7 +28,8 @@ __device__ __forceinline__ uint32_t order_quant(float x, float lo, float hi, int
   return (uint32_t)(u * (float)((1 << bits) - 1) + 0.5f);
 }
 
-// Key of one cell: log10 T in [0, 8) in 16 bins of half a decade (the top 4 of the 12 bits)
+// Key of one cell: log10 T over [0, 8] rounded to 16 levels, about half a decade apart (the top
+// 4 of the 12 bits),
 // with the cell's place in the grid below it (its index's top 8 bits: 256 slabs), or, with
 // previous substep counts, log2 of the count in [0, 17] on 12 bits.  Keys are visited from high
 // to low (hot to cold, long to short).  The temperature bins are coarse on purpose: the lanes of
