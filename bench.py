@@ -71,11 +71,12 @@ def parse():
 
 
 def _code_only(src):
-    """C++ source without its comments and blank lines (string and character literals kept)."""
+    """C++ source without its comments, its tokens joined by single spaces (string and character
+    literals kept)."""
     import re
     pat = re.compile(r'//[^\n]*|/\*.*?\*/|"(?:\\.|[^"\\])*"|\'(?:\\.|[^\'\\])*\'', re.S)
     code = pat.sub(lambda m: "" if m.group(0).startswith("/") else m.group(0), src)
-    return "\n".join(ln.rstrip() for ln in code.splitlines() if ln.strip())
+    return " ".join(code.split())
 
 
 def kernel_source_hash():
